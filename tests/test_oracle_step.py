@@ -1,0 +1,149 @@
+"""Pins for the oracle's linear solve, material Newton and Algorithm 1 (CPU).
+
+* Linear solve: Jacobi-PCG agrees with a dense LAPACK solve.
+* Material solve (Sec. 3.2): the per-particle root agrees with a 40-digit
+  mpmath root of the same quartic.
+* Infinite medium (Sec. 4.1 set-up, dimensionless units): a uniform field makes
+  the Brookshaw sum vanish, so one backward-Euler step of the coupled system
+  is the scalar system rho (e - e0)/dt = c sigma_a (E - a T^4),
+  (E - E0)/dt = c sigma_a (a T^4 - E).  Algorithm 1 iterated to convergence
+  must reproduce its 40-digit root, conserve m e + V E (Sec. 2.5) and relax to
+  the equilibrium a T^4 + rho c_v T = rho e0 + E0 with E = B.
+* First order in time (Sec. 4.1): against SciPy's Radau IIA solution of the
+  two ODEs, halving dt halves the error.
+* Energy balance with Dirichlet ghosts: the change of sum(m e + V E) equals the
+  source term plus the flux exchanged with the ghosts, to the outer tolerance.
+"""
+import mpmath
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.integrate import solve_ivp
+
+import synth
+from oracle import linsolve, material, neighbors, operator, step
+
+mpmath.mp.dps = 40
+
+
+def _bisect(f, lo, hi, n=200):
+    """40-digit bisection for an increasing function with f(lo) <= 0 <= f(hi)."""
+    lo, hi = mpmath.mpf(lo), mpmath.mpf(hi)
+    for _ in range(n):
+        mid = (lo + hi) / 2
+        if f(mid) > 0:
+            hi = mid
+        else:
+            lo = mid
+    return (lo + hi) / 2
+
+
+def test_pcg_matches_dense():
+    p = synth.config1(n=40)
+    ptr, idx = neighbors.build(p.pos, p.h, 2.0)
+    fz = operator.frozen(p, ptr, idx)
+    s = operator.assemble(p, ptr, idx, fz)
+    b = np.random.default_rng(0).standard_normal(p.n_interior)
+    xd = np.linalg.solve(s.A.toarray(), b)
+    xc, it, rel = linsolve.pcg_jacobi(s.A, b, tol=1e-15)
+    assert np.max(np.abs(xc - xd)) / np.max(np.abs(xd)) < 1e-13
+
+
+def _quartic_root(e_prev, P, rho, cv, sig, dt, c=1.0, a=1.0):
+    f = lambda e: rho / dt * (e - e_prev) + c * sig * a * (e / cv) ** 4 - P
+    hi = e_prev + dt * P / rho
+    return _bisect(f, 0, hi)
+
+
+def test_material_newton_vs_mpmath():
+    rng = np.random.default_rng(11)
+    n = 40
+    e_prev = 10 ** rng.uniform(-4, 1, n)
+    rho = rng.uniform(0.5, 4, n)
+    cv = rng.uniform(0.5, 2, n)
+    sig = 10 ** rng.uniform(-2, 6, n)
+    dt = 10 ** rng.uniform(-5, -1, n)
+    P = 10 ** rng.uniform(-3, 2, n) * sig
+    e, its, bad = material.solve(e_prev, P, rho, cv, sig, dt, 1.0, 1.0, e_prev, tol=1e-15)
+    assert not bad.any()
+    for i in range(n):
+        ref = _quartic_root(mpmath.mpf(e_prev[i]), mpmath.mpf(P[i]), mpmath.mpf(rho[i]),
+                            mpmath.mpf(cv[i]), mpmath.mpf(sig[i]), mpmath.mpf(dt[i]))
+        assert abs(e[i] - float(ref)) <= 4e-15 * float(ref)
+
+
+def _infinite_problem(e0, E0, dt, n=6, sigma0=1.0, p=0.0):
+    prob = synth.config2_infinite(T0=e0, E0=E0, n=n, sigma0=sigma0, dt=dt)
+    prob.opacity_exponent = p
+    return prob
+
+
+def _scalar_be_step(e0, E0, dt, sig):
+    """Exact BE step of the coupled scalar system (rho = c = a = c_v = 1)."""
+    e0, E0, dt, sig = map(mpmath.mpf, (e0, E0, dt, sig))
+    f = lambda e: (e - e0) / dt - sig * (E0 + e0 - e - e ** 4)
+    e = _bisect(f, 0, e0 + dt * sig * (E0 + e0))
+    return e, E0 + e0 - e
+
+
+@pytest.mark.parametrize("e0,E0,dt", [(1.0, 1e-16, 0.1), (1.0, 1e-16, 1e-3),
+                                       (1e-4, 1.0, 0.1), (1e-4, 1.0, 1e-3)])
+def test_infinite_medium_step_closed_form(e0, E0, dt):
+    prob = _infinite_problem(e0, E0, dt)
+    r = step.time_step(prob, eps_e=1e-14, eps_E=1e-14, max_outer=200)
+    e_ref, E_ref = _scalar_be_step(e0, E0, dt, 1.0)
+    assert np.allclose(r.e, float(e_ref), rtol=1e-12, atol=0)
+    assert np.allclose(r.E, float(E_ref), rtol=1e-12, atol=0)
+    assert abs(r.energy_after - r.energy_before) <= 1e-13 * r.energy_before
+
+
+def test_infinite_medium_variable_opacity_closed_form():
+    # sigma_a = 10 T^-3 frozen at the start of the step
+    e0, E0, dt = 1.0, 0.01, 1e-3
+    prob = _infinite_problem(e0, E0, dt, sigma0=10.0, p=-3.0)
+    r = step.time_step(prob, eps_e=1e-14, eps_E=1e-14, max_outer=200)
+    e_ref, E_ref = _scalar_be_step(e0, E0, dt, 10.0 * e0 ** -3)
+    assert np.allclose(r.e, float(e_ref), rtol=1e-12, atol=0)
+    assert np.allclose(r.E, float(E_ref), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("e0,E0", [(1.0, 1e-16), (1e-4, 1.0)])
+def test_equilibrium(e0, E0):
+    prob = _infinite_problem(e0, E0, 10.0, n=4)
+    for _ in range(40):
+        r = step.time_step(prob, eps_e=1e-14, eps_E=1e-14, max_outer=200)
+        step.advance(prob, r)
+    T = _bisect(lambda T: T ** 4 + T - (e0 + E0), 0, 2)
+    assert np.allclose(r.e, float(T), rtol=1e-12)
+    assert np.allclose(r.E, float(T) ** 4, rtol=1e-12)
+
+
+def test_first_order_in_time_vs_radau():
+    e0, E0, t_end = 1.0, 1e-16, 1.0
+    ref = solve_ivp(lambda t, y: [y[1] - y[0] ** 4, y[0] ** 4 - y[1]], (0, t_end), [e0, E0],
+                    method="Radau", rtol=1e-13, atol=1e-16)
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        prob = _infinite_problem(e0, E0, dt, n=3)
+        for _ in range(int(round(t_end / dt))):
+            r = step.time_step(prob, eps_e=1e-14, eps_E=1e-14, max_outer=200)
+            step.advance(prob, r)
+        errs.append(abs(r.e[0] - ref.y[0, -1]))
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2
+
+
+def test_energy_balance_with_ghosts():
+    prob = synth.config1(n=24)
+    r = step.time_step(prob, eps_e=1e-13, eps_E=1e-13)
+    lhs = r.energy_after - r.energy_before
+    rhs = r.source_energy + r.boundary_flux
+    assert abs(lhs - rhs) <= 1e-12 * r.energy_before
+
+
+def test_manufactured_step_close_to_exact():
+    prob = synth.config1(n=32)
+    r = step.time_step(prob)
+    e_x, E_x, _, _ = prob.mms(prob.dt)
+    nin = prob.n_interior
+    assert np.max(np.abs(r.e - e_x[:nin]) / e_x[:nin]) < 1e-4
+    assert np.max(np.abs(r.E - E_x[:nin]) / E_x[:nin]) < 2e-3
