@@ -1,0 +1,251 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) implicit SPH radiation-diffusion library.
+ *
+ * Paper: Bassett, Owen & Brunner, "Efficient smoothed particle radiation
+ * hydrodynamics I: Thermal radiative transfer", arXiv:2001.11606.
+ *
+ * The library implements one time step of the paper's implicit scheme for grey
+ * thermal radiative transfer with a stationary material: the nonlinear
+ * elimination iteration of Algorithm 1, in which every outer iteration solves
+ * one linear SPH diffusion system for the radiation energy E (Sec. 3.2, the
+ * diffusion-solve operator D^-1) and then a per-particle nonlinear equation
+ * for the material energy e (Sec. 3.2, the material operator M^-1).
+ *
+ * Conventions (all entry points):
+ *   - Array arguments are DEVICE pointers owned by the caller; the library
+ *     never frees or retains them beyond the call.  double = IEEE binary64.
+ *   - Particles are in the caller's ("user") order.  Interior particles are
+ *     [0, n_interior); constant-value (Dirichlet) ghost particles, the
+ *     boundary treatment of Sec. 3.1, are [n_interior, n_total).
+ *   - Positions are structure-of-arrays: pos[alpha * n_total + i].
+ *   - Library objects (rt_ctx, rt_neighbors, rt_matrix) are opaque handles,
+ *     created by the library and released with the matching *_free/destroy.
+ *   - Every call is ordered on the context's HIP stream.  Calls that return
+ *     counts or statistics synchronise that stream before returning.
+ *   - Return value: RT_OK (0); a positive soft status (outputs valid); or a
+ *     negative hard error (outputs undefined).  rt_last_error() returns a
+ *     message for the last failing call on the calling thread.
+ *   - Nothing here allocates or frees caller memory; library-owned device
+ *     memory is released by the *_free/destroy calls.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RT_OK 0
+#define RT_NOT_CONVERGED 1   /* tolerance not reached within max iterations  */
+#define RT_NONPHYSICAL 2     /* a material root was negative (clamped to 0)  */
+#define RT_E_ARG (-1)        /* invalid argument (null, size, NaN, option)   */
+#define RT_E_OOM (-2)        /* device allocation failed                     */
+#define RT_E_DEVICE (-3)     /* HIP runtime error                            */
+#define RT_E_STATE (-4)      /* objects do not belong together               */
+
+/* ---- kernels (Sec. 2.3) -------------------------------------------------- */
+#define RT_KERNEL_CUBIC_SPLINE 0  /* M4 cubic B-spline, support 2h           */
+#define RT_KERNEL_WENDLAND_C4 1   /* the paper's Wendland C4, support h      */
+
+/* ---- flux limiters (Sec. 2.1) ------------------------------------------- */
+#define RT_LIMITER_NONE 0         /* lambda = 1/3 (Fick's law)               */
+#define RT_LIMITER_LARSEN 1       /* lambda = (3^k + R^k)^(-1/k)             */
+#define RT_LIMITER_LEVERMORE 2    /* lambda = (2 + R)/(6 + 3R + R^2)         */
+
+/* ---- solver precision ---------------------------------------------------- */
+#define RT_PREC_FP64 0   /* FP64 preconditioned CG                          */
+#define RT_PREC_MIXED 1  /* FP32 inner PCG + FP64 iterative refinement       */
+
+typedef struct rt_ctx rt_ctx;
+typedef struct rt_neighbors rt_neighbors;
+typedef struct rt_matrix rt_matrix;
+
+/* ---- context --------------------------------------------------------------
+ * rt_create: bind the calling thread's HIP device `device` and stream
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  *ctx receives a new
+ * context.  Errors: RT_E_ARG (ctx NULL), RT_E_DEVICE.                        */
+int rt_create(rt_ctx** ctx, int device, void* hip_stream);
+void rt_destroy(rt_ctx* ctx);
+int rt_set_stream(rt_ctx* ctx, void* hip_stream);
+/* Record HIP events around every sparse matrix-vector product launch so that
+ * rt_solve_stats.spmv_* report per-launch device time (on = 1).             */
+int rt_set_profiling(rt_ctx* ctx, int on);
+const char* rt_last_error(void);
+const char* rt_version(void);
+
+/* ---- neighbour lists (Sec. 2.3, Sec. 3.1) ----------------------------------
+ * Particles i != j are neighbours when r_ij^2 < (kappa * max(h_i, h_j))^2,
+ * r_ij^2 accumulated in axis order without fused multiply-add, kappa = 2
+ * (cubic spline) or 1 (Wendland C4): every pair on which either term of the
+ * symmetrised kernel W_ij = 1/2 [W(x_ij,h_i) + W(x_ij,h_j)] is non-zero.
+ *
+ * dim in {2, 3}; n_total >= 1; 0 <= n_interior <= n_total;
+ * pos: dim x n_total (SoA); h: n_total, h > 0.  The particles are sorted
+ * internally by a uniform cell grid; the result *out is library-owned.
+ * Errors: RT_E_ARG (bad sizes, non-finite pos/h, h <= 0, grid too large).  */
+int rt_build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
+                       const double* pos, const double* h, int kernel,
+                       rt_neighbors** out);
+
+typedef struct {
+  int dim;
+  int kernel;
+  int64_t n_total;
+  int64_t n_interior;
+  int64_t npairs;        /* directed pairs (each unordered pair counted twice) */
+  int64_t ncells;        /* cells of the sorting grid                        */
+  double cell_size;
+} rt_neighbors_info;
+
+int rt_neighbors_get_info(const rt_neighbors* nb, rt_neighbors_info* info);
+
+/* Neighbour lists in user order, ascending neighbour index per row:
+ * nbr_ptr (n_total + 1, int64) and nbr_idx (npairs, int32), device memory
+ * provided by the caller.                                                  */
+int rt_neighbors_export(rt_ctx* ctx, const rt_neighbors* nb, int64_t* nbr_ptr,
+                        int32_t* nbr_idx);
+
+/* perm[s] = user index of the particle at internal (cell-sorted) position s
+ * (n_total int32, device).                                                 */
+int rt_neighbors_order(rt_ctx* ctx, const rt_neighbors* nb, int32_t* perm);
+void rt_neighbors_free(rt_neighbors* nb);
+
+/* ---- per-step assembly (Sec. 2.2, 2.4, 3.2) --------------------------------
+ * Material data is frozen at the start of the step (Sec. 3.2):
+ *   T = e/c_v, sigma_a = sigma0_a T^opacity_exponent, sigma_t = sigma_a + sigma_s,
+ *   f = 1/(1 + c sigma_a dt 4 a T^3/(rho c_v))      (Fleck factor, Sec. 2.2)
+ *   V = m/rho                                        (Sec. 2.3)
+ *   D = c lambda / sigma_t                           (Sec. 2.4)
+ * with lambda = 1/3 or a flux limiter of R = |grad E|/(sigma_t E) using the
+ * SPH first derivative of E (Sec. 2.1, 2.3); ghosts always use lambda = 1/3.
+ * The diffusion system of Sec. 3.2 (the D^-1 operator), each row multiplied
+ * by V_i, is assembled into CSR:
+ *   A_ii = V_i (1/dt + c sigma_a,i f_i) + V_i sum_j a_ij,
+ *   A_ij = -V_i V_j (D_i + D_j) F_ij                  (interior j),
+ *   F_ij = -1/2 [W'(r_ij,h_i) + W'(r_ij,h_j)] / r_ij,  a_ij = V_j (D_i + D_j) F_ij,
+ * which is symmetric positive definite; ghost couplings move to the
+ * right-hand side.  An aggregation-AMG hierarchy is set up for the
+ * preconditioner, once per step (Sec. 3.2 reuses the preconditioner for the
+ * whole step).
+ *
+ * All arrays are n_total long, user order, device.  sigma_s, Q_e and Q_E may
+ * be NULL (zero).  e and E hold e^{n-1}, E^{n-1} for interior particles and
+ * the boundary values of the step for ghosts.  Q_e/Q_E are the sources Q^n.
+ * *A: if non-NULL on entry and built from the same neighbour object, its
+ * storage is reused; otherwise a new matrix is created.                      */
+typedef struct {
+  double dt, c, a;
+  double opacity_exponent;
+  int limiter;
+  double limiter_k;
+  const double* m;
+  const double* rho;
+  const double* cv;
+  const double* sigma0_a;
+  const double* sigma_s;
+  const double* e;
+  const double* E;
+  const double* Q_e;
+  const double* Q_E;
+} rt_step_inputs;
+
+typedef struct {
+  int max_levels;        /* AMG levels including the fine one; 1 = Jacobi only */
+  int coarse_size;       /* stop coarsening at or below this many unknowns     */
+  double strength;       /* strength-of-connection threshold theta             */
+  int build_fp32;        /* 1: also build the FP32 copies for RT_PREC_MIXED    */
+} rt_amg_opts;
+
+int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
+                const rt_amg_opts* amg /* NULL = defaults */, rt_matrix** A);
+
+typedef struct {
+  int64_t n;             /* unknowns = interior particles                     */
+  int64_t nnz;           /* stored entries including the diagonal            */
+  int levels;
+  int64_t level_n[16];
+  int64_t level_nnz[16];
+} rt_matrix_info;
+
+int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info);
+
+/* The assembled system in user order over interior particles, ascending
+ * columns, diagonal included: row_ptr (n+1 int64), col (nnz int32), val (nnz
+ * double), ghost_rhs (n double, the ghost coupling g_i added to b).         */
+int rt_matrix_export(rt_ctx* ctx, const rt_matrix* A, int64_t* row_ptr, int32_t* col,
+                     double* val, double* ghost_rhs);
+void rt_matrix_free(rt_matrix* A);
+
+/* ---- linear solve (Sec. 3.2, the D^-1 operator) ---------------------------
+ * Solves A x = b (the V-scaled system above) by preconditioned CG, stopping
+ * when ||b - A x||_2 <= tol ||b||_2 evaluated in FP64.  b, x: n_interior
+ * doubles, user order, device; x is the initial guess on entry (the paper
+ * warm-starts with E^l) and the solution on return.
+ * precond: 0 = Jacobi, 1 = AMG V-cycle (falls back to Jacobi when the
+ * hierarchy has one level).  RT_PREC_MIXED runs FP32 PCG on the correction
+ * equation A d = r to inner_tol, adds d in FP64 and recomputes r = b - A x in
+ * FP64, until tol.  Returns RT_NOT_CONVERGED (stats valid) if max_iter
+ * (total inner iterations) is exhausted.                                     */
+typedef struct {
+  int precision;
+  int precond;
+  double tol;
+  int max_iter;
+  double inner_tol;
+  int max_refine;
+} rt_solve_opts;
+
+typedef struct {
+  int iterations;          /* Krylov iterations (inner ones in MIXED)        */
+  int refinements;         /* FP64 residual recomputations (MIXED)           */
+  double rel_residual;     /* final ||b - A x|| / ||b|| in FP64              */
+  double seconds;          /* wall time of the call (device-synchronised)    */
+  int spmv_calls;          /* SpMV launches timed (profiling on)             */
+  double spmv_seconds;     /* their summed device time                       */
+  int spmv32_calls;
+  double spmv32_seconds;
+} rt_solve_stats;
+
+int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
+             const rt_solve_opts* opts, rt_solve_stats* stats);
+
+/* ---- one outer iteration of Algorithm 1 ------------------------------------
+ * e, E: n_interior doubles, user order, device, holding the iterate
+ * (e^{n,l}, E^{n,l}) on entry and (e^{n,l+1}, E^{n,l+1}) on return.
+ * If ell == 0, first solves m(e, E^{n,0}) = 0 for e from e^{n-1} (the
+ * initial material solve of Algorithm 1).  Then: right-hand side
+ *   b_i = V_i [E_i^{n-1}/dt + c sigma_a a T(e_i^l)^4 - (1 - f_i) c sigma_a E_i^l + Q_E,i] + g_i,
+ * linear solve warm-started from E^l, and the per-particle material solve
+ *   rho/dt (e - e^{n-1}) + c sigma_a a (e/c_v)^4 = Q_e + c sigma_a E^{l+1}
+ * by bracketed Newton from e^l to |de/e| <= material_tol (Sec. 3.2).
+ * stats: delta_e = max_i |e^{l+1} - e^l|/|e^{l+1}|, delta_E likewise
+ * (Sec. 2.2 convergence test), energy = sum_i (m_i e_i + V_i E_i) (Sec. 2.5).
+ * Returns RT_NONPHYSICAL if a material root was negative, RT_NOT_CONVERGED
+ * if the linear or a material solve did not converge.                        */
+typedef struct {
+  rt_solve_opts solve;
+  double material_tol;
+  int material_max_iter;
+} rt_newton_opts;
+
+typedef struct {
+  double delta_e;
+  double delta_E;
+  double energy;
+  double energy_prev;      /* sum_i (m_i e_i^{n-1} + V_i E_i^{n-1})           */
+  int material_iterations; /* max over particles, last material solve        */
+  int64_t nonphysical;     /* particles with a negative root                 */
+  rt_solve_stats solve;
+  double seconds;
+} rt_newton_stats;
+
+int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
+                   const rt_newton_opts* opts, rt_newton_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

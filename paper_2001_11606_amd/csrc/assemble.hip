@@ -1,0 +1,389 @@
+// Per-step frozen data and assembly of the V-scaled Brookshaw diffusion system.
+//
+// Frozen data (Sec. 3.2: computed once at the start of the step), per sorted
+// particle: T = e/c_v, sigma_a = sigma0_a T^p, sigma_t = sigma_a + sigma_s,
+// Fleck factor f = 1/(1 + c sigma_a dt 4 a T^3/(rho c_v)) (Sec. 2.2),
+// V = m/rho (Sec. 2.3), D = c lambda/sigma_t (Sec. 2.4).  With a flux limiter
+// (Sec. 2.1) lambda of the interior particles uses R = |grad E|/(sigma_t E)
+// with the SPH first derivative of E^{n-1} (Sec. 2.3).
+//
+// Matrix (the D^-1 operator of Sec. 3.2 with row i multiplied by V_i):
+//   F_ij = -1/2 [W'(r,h_i) + W'(r,h_j)] / r,  a_ij = V_j (D_i + D_j) F_ij
+//   A_ij = -(V_i V_j)(D_i + D_j) F_ij      (interior j, off-diagonal CSR)
+//   A_ii = V_i (1/dt + c sigma_a,i f_i) + V_i sum_j a_ij
+//   g_i  = V_i sum_{j ghost} a_ij E_j      (ghost coupling -> right-hand side)
+// One group of G lanes per row: lanes walk the row's neighbours, so reads of
+// the neighbour list and writes of the values are contiguous.
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "kernels_sph.h"
+#include "prim.h"
+#include "reduce.h"
+
+namespace rt {
+namespace {
+
+struct FrozenArgs {
+  const int32_t* perm;
+  const double *m, *rho, *cv, *s0, *ss, *e, *E, *Qe, *Qn;
+  double dt, c, a, p;
+  double *V, *D, *sa, *st, *f, *Eall, *e_prev, *E_prev, *rho_s, *cv_s, *m_s, *Qe_s, *QE_s;
+};
+
+__global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int32_t u = A.perm[s];
+  const double cv = A.cv[u], rho = A.rho[u], e = A.e[u], E = A.E[u];
+  const double T = e / cv;
+  const double sa = A.p == 0.0 ? A.s0[u] : A.s0[u] * pow(T, A.p);
+  const double st = sa + (A.ss ? A.ss[u] : 0.0);
+  const double f = 1.0 / (1.0 + A.c * sa * A.dt * 4.0 * A.a * (T * T * T) / (rho * cv));
+  const double V = A.m[u] / rho;
+  A.V[s] = V;
+  A.sa[s] = sa;
+  A.st[s] = st;
+  A.f[s] = f;
+  A.D[s] = A.c * (1.0 / 3.0) / st;
+  A.Eall[s] = E;
+  if (s < nin) {
+    A.e_prev[s] = e;
+    A.E_prev[s] = E;
+    A.rho_s[s] = rho;
+    A.cv_s[s] = cv;
+    A.m_s[s] = A.m[u];
+    A.Qe_s[s] = A.Qe ? A.Qe[u] : 0.0;
+    A.QE_s[s] = A.Qn ? A.Qn[u] : 0.0;
+  }
+}
+
+// Flux-limited diffusion coefficient of interior particles.
+template <int DIM>
+__global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, double lk, double c,
+                          const double* __restrict__ spos, const double* __restrict__ sh,
+                          const int64_t* __restrict__ nptr, const int32_t* __restrict__ nidx,
+                          const double* __restrict__ V, const double* __restrict__ Eall,
+                          const double* __restrict__ st, double* __restrict__ D) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nin) return;
+  const double xi = spos[i], yi = spos[n + i], zi = DIM == 3 ? spos[2 * n + i] : 0.0;
+  const double hi = sh[i], Ei = Eall[i];
+  double gx = 0, gy = 0, gz = 0;
+  for (int64_t k = nptr[i]; k < nptr[i + 1]; ++k) {
+    const int32_t j = nidx[k];
+    const double dx = xi - spos[j], dy = yi - spos[n + j];
+    const double dz = DIM == 3 ? zi - spos[2 * n + j] : 0.0;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    // grad_i W_ij = 1/2 [W'(r,h_i) + W'(r,h_j)] x_ij / r
+    const double w = V[j] * (Eall[j] - Ei) * 0.5 *
+                     (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, sh[j], kernel)) / r;
+    gx += w * dx;
+    gy += w * dy;
+    gz += w * dz;
+  }
+  const double R = sqrt(gx * gx + gy * gy + gz * gz) / (st[i] * Ei);
+  double lam;
+  if (limiter == RT_LIMITER_LARSEN) lam = pow(pow(3.0, lk) + pow(R, lk), -1.0 / lk);
+  else lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  D[i] = c * lam / st[i];
+}
+
+__global__ void k_copy_prefix_cols(int64_t nin, const int64_t* __restrict__ nptr,
+                                   const int32_t* __restrict__ nidx,
+                                   const int64_t* __restrict__ rp, int32_t* __restrict__ col) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nin) return;
+  const int64_t k0 = nptr[i], o = rp[i], len = rp[i + 1] - rp[i];
+  for (int64_t k = 0; k < len; ++k) col[o + k] = nidx[k0 + k];
+}
+
+__global__ void k_int_counts(int64_t nin, const int32_t* __restrict__ cnt32,
+                             int64_t* __restrict__ cnt64) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nin) cnt64[i] = cnt32[i];
+}
+
+struct AsmArgs {
+  const int64_t *nptr, *rp;
+  const int32_t* nidx;
+  const double *spos, *sh, *V, *D, *sa, *f, *Eall;
+  double *val64, *diag64, *g;
+  float *val32, *diag32;
+};
+
+template <int DIM, int G>
+__global__ void __launch_bounds__(kBlock)
+k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  for (int64_t i = grp; i < nin; i += ngrp) {
+    const double xi = A.spos[i], yi = A.spos[n + i], zi = DIM == 3 ? A.spos[2 * n + i] : 0.0;
+    const double hi = A.sh[i], Vi = A.V[i], Di = A.D[i];
+    const int64_t k0 = A.nptr[i], k1 = A.nptr[i + 1], o = A.rp[i];
+    double suma = 0.0, gsum = 0.0;
+    for (int64_t k = k0 + lane; k < k1; k += G) {
+      const int32_t j = A.nidx[k];
+      const double dx = xi - A.spos[j], dy = yi - A.spos[n + j];
+      const double dz = DIM == 3 ? zi - A.spos[2 * n + j] : 0.0;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double F =
+          -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, A.sh[j], kernel)) / r;
+      const double Dij = Di + A.D[j];
+      const double aij = A.V[j] * Dij * F;
+      suma += aij;
+      if (j < nin) {
+        const double v = -(Vi * A.V[j]) * Dij * F;
+        A.val64[o + (k - k0)] = v;
+        if (A.val32) A.val32[o + (k - k0)] = (float)v;
+      } else {
+        gsum += aij * A.Eall[j];
+      }
+    }
+    suma = group_sum<G>(suma);
+    gsum = group_sum<G>(gsum);
+    if (lane == 0) {
+      const double d = Vi * (1.0 / dt + c * A.sa[i] * A.f[i]) + Vi * suma;
+      A.diag64[i] = d;
+      if (A.diag32) A.diag32[i] = (float)d;
+      A.g[i] = Vi * gsum;
+    }
+  }
+}
+
+// export in user order: scatter (col, val) incl. diagonal, then sort rows
+__global__ void k_export_counts(int64_t nin, const int32_t* __restrict__ iperm,
+                                const int64_t* __restrict__ rp, int64_t* __restrict__ ucnt) {
+  int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= nin) return;
+  const int32_t s = iperm[u];
+  ucnt[u] = rp[s + 1] - rp[s] + 1;
+}
+
+__global__ void k_export_scatter(int64_t nin, const int32_t* __restrict__ perm,
+                                 const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, const double* __restrict__ diag,
+                                 const double* __restrict__ g, const int64_t* __restrict__ urp,
+                                 int32_t* __restrict__ ucol, double* __restrict__ uval,
+                                 double* __restrict__ ug) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= nin) return;
+  const int32_t u = perm[s];
+  int64_t o = urp[u];
+  ucol[o] = u;
+  uval[o] = diag[s];
+  ++o;
+  for (int64_t k = rp[s]; k < rp[s + 1]; ++k, ++o) {
+    ucol[o] = perm[col[k]];
+    uval[o] = val[k];
+  }
+  if (ug) ug[u] = g[s];
+}
+
+int pick_group(double avg_row) {
+  if (avg_row > 40) return 64;
+  if (avg_row > 20) return 32;
+  if (avg_row > 10) return 16;
+  return 8;
+}
+
+}  // namespace
+
+int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_matrix* A,
+             bool new_structure) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = nb->n_total, nin = nb->n_interior;
+  A->nb = nb;
+  A->n = nin;
+  A->n_total = n;
+  A->dt = in->dt;
+  A->c = in->c;
+  A->a = in->a;
+  for (auto* b : {&A->V, &A->D, &A->sa, &A->f, &A->Eall}) RT_CHECK(b->reserve(n));
+  for (auto* b : {&A->rho, &A->cv, &A->m, &A->e_prev, &A->E_prev, &A->Qe, &A->QE, &A->g})
+    RT_CHECK(b->reserve(nin));
+  DevBuf<double> sigt;
+  RT_CHECK(sigt.reserve(n));
+  FrozenArgs fa{nb->perm.p, in->m, in->rho, in->cv, in->sigma0_a, in->sigma_s, in->e, in->E,
+                in->Q_e, in->Q_E, in->dt, in->c, in->a, in->opacity_exponent,
+                A->V.p, A->D.p, A->sa.p, sigt.p, A->f.p, A->Eall.p, A->e_prev.p, A->E_prev.p,
+                A->rho.p, A->cv.p, A->m.p, A->Qe.p, A->QE.p};
+  hipLaunchKernelGGL(k_frozen, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nin, fa);
+  RT_LAUNCH_CHECK();
+  if (in->limiter != RT_LIMITER_NONE && nin > 0) {
+    if (nb->dim == 3)
+      hipLaunchKernelGGL(k_limiter<3>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
+                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->spos.p, nb->sh.p,
+                         nb->ptr.p, nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p);
+    else
+      hipLaunchKernelGGL(k_limiter<2>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
+                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->spos.p, nb->sh.p,
+                         nb->ptr.p, nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p);
+    RT_LAUNCH_CHECK();
+  }
+
+  if (A->levels.empty()) A->levels.resize(1);
+  Level& L = A->levels[0];
+  if (new_structure) {
+    L.n = nin;
+    RT_CHECK(L.rp.reserve(nin + 1));
+    DevBuf<int64_t> cnt;
+    RT_CHECK(cnt.reserve(nin + 1));
+    RT_CHECK_HIP(hipMemsetAsync(cnt.p + nin, 0, sizeof(int64_t), st));
+    if (nin > 0) {
+      hipLaunchKernelGGL(k_int_counts, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin,
+                         nb->n_int_nbrs.p, cnt.p);
+      RT_LAUNCH_CHECK();
+    }
+    RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, L.rp.p, nin + 1, false)));
+    RT_CHECK(ctx->sync_read(L.rp.p + nin, sizeof(int64_t)));
+    int64_t nnz = 0;
+    std::memcpy(&nnz, ctx->host, sizeof(int64_t));
+    L.nnz = nnz;
+    RT_CHECK(L.col.reserve(nnz));
+    if (nin > 0) {
+      hipLaunchKernelGGL(k_copy_prefix_cols, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin,
+                         nb->ptr.p, nb->idx.p, L.rp.p, L.col.p);
+      RT_LAUNCH_CHECK();
+    }
+  }
+  RT_CHECK(L.val64.reserve(L.nnz));
+  RT_CHECK(L.diag64.reserve(nin));
+  const bool fp32 = A->amg.build_fp32 != 0;
+  if (fp32) {
+    RT_CHECK(L.val32.reserve(L.nnz));
+    RT_CHECK(L.diag32.reserve(nin));
+  }
+  A->has_fp32 = fp32;
+  if (nin > 0) {
+    AsmArgs aa{nb->ptr.p, L.rp.p, nb->idx.p, nb->spos.p, nb->sh.p, A->V.p, A->D.p, A->sa.p,
+               A->f.p, A->Eall.p, L.val64.p, L.diag64.p, A->g.p, fp32 ? L.val32.p : nullptr,
+               fp32 ? L.diag32.p : nullptr};
+    const double avg = nin ? (double)nb->npairs / (double)n : 0.0;
+    const int G = pick_group(avg);
+    const int grid = grid_for(nin * (int64_t)G, kBlock, 1 << 20);
+#define RT_ASM(D_, G_)                                                                        \
+  hipLaunchKernelGGL((k_assemble<D_, G_>), dim3(grid), dim3(kBlock), 0, st, nin, n, nb->kernel, \
+                     in->dt, in->c, aa)
+    if (nb->dim == 3) {
+      if (G == 64) RT_ASM(3, 64); else if (G == 32) RT_ASM(3, 32);
+      else if (G == 16) RT_ASM(3, 16); else RT_ASM(3, 8);
+    } else {
+      if (G == 64) RT_ASM(2, 64); else if (G == 32) RT_ASM(2, 32);
+      else if (G == 16) RT_ASM(2, 16); else RT_ASM(2, 8);
+    }
+#undef RT_ASM
+    RT_LAUNCH_CHECK();
+  }
+  return RT_OK;
+}
+
+int matrix_export(rt_ctx* ctx, const rt_matrix* A, int64_t* urp, int32_t* ucol, double* uval,
+                  double* ug) {
+  hipStream_t st = ctx->stream;
+  const rt_neighbors* nb = A->nb;
+  const Level& L = A->levels[0];
+  const int64_t nin = A->n;
+  DevBuf<int64_t> cnt;
+  RT_CHECK(cnt.reserve(nin + 1));
+  RT_CHECK_HIP(hipMemsetAsync(cnt.p + nin, 0, sizeof(int64_t), st));
+  if (nin > 0) {
+    hipLaunchKernelGGL(k_export_counts, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin,
+                       nb->iperm.p, L.rp.p, cnt.p);
+    RT_LAUNCH_CHECK();
+  }
+  RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, urp, nin + 1, false)));
+  if (nin == 0) return RT_OK;
+  hipLaunchKernelGGL(k_export_scatter, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin,
+                     nb->perm.p, L.rp.p, L.col.p, L.val64.p, L.diag64.p, A->g.p, urp, ucol, uval,
+                     ug);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((row_sort<int32_t, double>(ctx, urp, ucol, uval, nin)));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  return RT_OK;
+}
+
+}  // namespace rt
+
+extern "C" {
+
+int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
+                const rt_amg_opts* amg, rt_matrix** A) {
+  rt::clear_error();
+  if (!ctx || !nb || !in || !A) {
+    rt::set_error("rt_assemble: NULL argument");
+    return RT_E_ARG;
+  }
+  if (!in->m || !in->rho || !in->cv || !in->sigma0_a || !in->e || !in->E) {
+    rt::set_error("rt_assemble: a required per-particle array is NULL");
+    return RT_E_ARG;
+  }
+  if (!(in->dt > 0.0) || !std::isfinite(in->dt) || !(in->c > 0.0) || !(in->a > 0.0)) {
+    rt::set_error("rt_assemble: dt, c and a must be positive and finite");
+    return RT_E_ARG;
+  }
+  if (in->limiter != RT_LIMITER_NONE && in->limiter != RT_LIMITER_LARSEN &&
+      in->limiter != RT_LIMITER_LEVERMORE) {
+    rt::set_error("rt_assemble: unknown limiter %d", in->limiter);
+    return RT_E_ARG;
+  }
+  if (in->limiter == RT_LIMITER_LARSEN && !(in->limiter_k > 0.0)) {
+    rt::set_error("rt_assemble: Larsen limiter needs k > 0");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt_matrix* M = *A;
+  bool fresh = false;
+  if (M && M->nb != nb) {
+    rt::set_error("rt_assemble: matrix was built from another neighbour object");
+    return RT_E_STATE;
+  }
+  if (!M) {
+    M = new rt_matrix();
+    fresh = true;
+  }
+  rt_amg_opts d{8, 256, 0.08, 1};
+  M->amg = amg ? *amg : d;
+  if (M->amg.max_levels < 1) M->amg.max_levels = 1;
+  if (M->amg.max_levels > 16) M->amg.max_levels = 16;
+  int s = rt::assemble(ctx, nb, in, M, fresh);
+  if (s >= 0) s = rt::amg_setup(ctx, M);
+  if (s < 0) {
+    if (fresh) delete M;
+    return s;
+  }
+  *A = M;
+  return RT_OK;
+}
+
+int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info) {
+  if (!A || !info) {
+    rt::set_error("rt_matrix_get_info: NULL argument");
+    return RT_E_ARG;
+  }
+  *info = rt_matrix_info{};
+  info->n = A->n;
+  info->nnz = A->levels.empty() ? 0 : A->levels[0].nnz + A->n;
+  info->levels = (int)A->levels.size();
+  for (size_t l = 0; l < A->levels.size() && l < 16; ++l) {
+    info->level_n[l] = A->levels[l].n;
+    info->level_nnz[l] = A->levels[l].nnz + A->levels[l].n;
+  }
+  return RT_OK;
+}
+
+int rt_matrix_export(rt_ctx* ctx, const rt_matrix* A, int64_t* row_ptr, int32_t* col,
+                     double* val, double* ghost_rhs) {
+  rt::clear_error();
+  if (!ctx || !A || !row_ptr || (A->n > 0 && (!col || !val))) {
+    rt::set_error("rt_matrix_export: NULL argument");
+    return RT_E_ARG;
+  }
+  return rt::matrix_export(ctx, A, row_ptr, col, val, ghost_rhs);
+}
+
+void rt_matrix_free(rt_matrix* A) { delete A; }
+
+}  // extern "C"

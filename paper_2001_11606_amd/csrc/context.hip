@@ -1,0 +1,130 @@
+// Context, error reporting and version of the C ABI.
+#include <cstdarg>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace rt {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace rt
+
+int rt_ctx::sync_read(const void* dev, size_t bytes) {
+  RT_CHECK_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, stream));
+  RT_CHECK_HIP(hipStreamSynchronize(stream));
+  return RT_OK;
+}
+
+int rt_ctx::prof_mark(size_t* idx) {
+  if (prof_used == prof_ev.size()) {
+    hipEvent_t e;
+    RT_CHECK_HIP(hipEventCreate(&e));
+    prof_ev.push_back(e);
+  }
+  RT_CHECK_HIP(hipEventRecord(prof_ev[prof_used], stream));
+  *idx = prof_used++;
+  return RT_OK;
+}
+
+int rt_ctx::prof_collect(double* seconds, int* calls, int nkinds) {
+  for (int k = 0; k < nkinds; ++k) {
+    seconds[k] = 0.0;
+    calls[k] = 0;
+  }
+  if (prof_used) RT_CHECK_HIP(hipEventSynchronize(prof_ev[prof_used - 1]));
+  for (const Span& s : prof_spans) {
+    float ms = 0.f;
+    RT_CHECK_HIP(hipEventElapsedTime(&ms, prof_ev[s.a], prof_ev[s.b]));
+    if (s.kind >= 0 && s.kind < nkinds) {
+      seconds[s.kind] += 1e-3 * ms;
+      calls[s.kind] += 1;
+    }
+  }
+  prof_spans.clear();
+  prof_used = 0;
+  return RT_OK;
+}
+
+rt_ctx::~rt_ctx() {
+  for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+}
+
+extern "C" {
+
+const char* rt_last_error(void) { return rt::g_last_error.c_str(); }
+
+const char* rt_version(void) { return "rt-mi355x 0.1 (gfx950)"; }
+
+int rt_create(rt_ctx** ctx, int device, void* hip_stream) {
+  rt::clear_error();
+  if (!ctx) {
+    rt::set_error("rt_create: ctx is NULL");
+    return RT_E_ARG;
+  }
+  *ctx = nullptr;
+  int ndev = 0;
+  RT_CHECK_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) {
+    rt::set_error("rt_create: device %d out of range (%d devices)", device, ndev);
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(device));
+  rt_ctx* c = new rt_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    rt::set_error("rt_create: pinned host allocation failed");
+    return RT_E_OOM;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    rt::set_error("rt_create: hipEventCreate failed");
+    rt_destroy(c);
+    return RT_E_DEVICE;
+  }
+  *ctx = c;
+  return RT_OK;
+}
+
+void rt_destroy(rt_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+}
+
+int rt_set_stream(rt_ctx* ctx, void* hip_stream) {
+  if (!ctx) {
+    rt::set_error("rt_set_stream: ctx is NULL");
+    return RT_E_ARG;
+  }
+  ctx->stream = (hipStream_t)hip_stream;
+  return RT_OK;
+}
+
+int rt_set_profiling(rt_ctx* ctx, int on) {
+  if (!ctx) {
+    rt::set_error("rt_set_profiling: ctx is NULL");
+    return RT_E_ARG;
+  }
+  ctx->profiling = on != 0;
+  return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Internal declarations of the MI355X radiation-diffusion library (gfx950).
+//
+// Device layout: every per-particle array lives in the library's cell-sorted
+// order.  Interior particles occupy sorted positions [0, n_interior) and
+// ghosts [n_interior, n_total); perm[s] maps a sorted position back to the
+// caller's index.  The V-scaled diffusion matrix (rows and columns = sorted
+// interior particles) is stored as a diagonal plus an off-diagonal CSR with
+// int64 row pointers, int32 columns (ascending) and FP64 values, with FP32
+// copies for the mixed-precision solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/rt.h"
+
+namespace rt {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define RT_CHECK_HIP(expr)                                                      \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess) {                                                     \
+      ::rt::set_error("%s:%d: %s failed: %s", __FILE__, __LINE__, #expr,        \
+                      hipGetErrorString(_e));                                   \
+      return RT_E_DEVICE;                                                       \
+    }                                                                           \
+  } while (0)
+
+#define RT_CHECK(expr)                                                          \
+  do {                                                                          \
+    int _s = (expr);                                                            \
+    if (_s < 0) return _s;                                                      \
+  } while (0)
+
+#define RT_LAUNCH_CHECK() RT_CHECK_HIP(hipGetLastError())
+
+// Owning device buffer.  Not copyable; grows on demand.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  // Frees happen only in set-up paths; wait for queued work that may still
+  // read the buffer before returning it to the allocator.
+  void release() {
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
+    p = nullptr;
+    n = 0;
+  }
+  // Ensure capacity for `count` elements (contents are not preserved).
+  int reserve(size_t count) {
+    if (count <= n && p) return RT_OK;
+    release();
+    size_t bytes = (count ? count : 1) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      set_error("device allocation of %zu bytes failed", bytes);
+      return RT_E_OOM;
+    }
+    n = count;
+    return RT_OK;
+  }
+};
+
+constexpr int kBlock = 256;            // threads per block (4 wavefronts)
+constexpr int kMaxPartials = 2048;     // cap on blocks of reduction kernels
+
+inline int grid_for(int64_t work_items, int per_block = kBlock, int cap = 1 << 30) {
+  int64_t g = (work_items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace rt
+
+// ---------------------------------------------------------------------------
+struct rt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool profiling = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // small pinned host staging area for scalar read-backs
+  double* host = nullptr;     // 64 doubles
+  int sync_read(const void* dev, size_t bytes);   // async copy to host + stream sync
+  // profiling: events recorded around timed launches, resolved at the end of a call
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
+  struct Span { int kind; size_t a, b; };
+  std::vector<Span> prof_spans;
+  int prof_mark(size_t* idx);                      // record an event on the stream
+  int prof_collect(double* seconds_by_kind, int* calls_by_kind, int nkinds);
+  ~rt_ctx();
+};
+
+struct rt_neighbors {
+  int dim = 3;
+  int kernel = RT_KERNEL_CUBIC_SPLINE;
+  double kappa = 2.0;
+  int64_t n_total = 0, n_interior = 0, npairs = 0;
+  int nc[3] = {1, 1, 1};
+  int bits = 1;                 // Morton bits per axis
+  int64_t ncells = 0;
+  double lo[3] = {0, 0, 0};
+  double cell_size = 0;
+  rt::DevBuf<uint64_t> skeys;   // sorted keys: ghost flag << (dim*bits) | Morton(cell)
+  rt::DevBuf<int32_t> perm;     // sorted -> user
+  rt::DevBuf<int32_t> iperm;    // user -> sorted
+  rt::DevBuf<double> spos;      // dim x n_total, sorted order
+  rt::DevBuf<double> sh;        // n_total, sorted order
+  rt::DevBuf<int64_t> ptr;      // n_total + 1, sorted order
+  rt::DevBuf<int32_t> idx;      // npairs, sorted indices, ascending per row
+  rt::DevBuf<int32_t> n_int_nbrs;  // interior neighbours per interior row
+};
+
+namespace rt {
+// One level of the operator hierarchy.  Level 0 is the assembled fine system;
+// level l+1 aggregates contiguous runs of level-l rows (pmap is
+// non-decreasing; crange[I] is the first level-l row of aggregate I).
+struct Level {
+  int64_t n = 0, nnz = 0;       // nnz = off-diagonal entries
+  DevBuf<int64_t> rp;
+  DevBuf<int32_t> col;
+  DevBuf<double> val64, diag64, sinv64, dinv64;   // sinv = l1-Jacobi smoother, dinv = 1/diag
+  DevBuf<float> val32, diag32, sinv32, dinv32;
+  DevBuf<uint64_t> code;        // Morton code of each node's cell block
+  DevBuf<int32_t> pmap;         // node -> aggregate on the next level
+  DevBuf<int32_t> crange;       // next-level aggregate -> first node (size n_next + 1)
+  // work vectors of this level (b: right-hand side, x: result, t, r: temporaries)
+  DevBuf<double> b64, x64, t64, r64;
+  DevBuf<float> b32, x32, t32, r32;
+};
+}  // namespace rt
+
+struct rt_matrix {
+  const rt_neighbors* nb = nullptr;
+  int64_t n = 0;          // interior unknowns
+  int64_t n_total = 0;
+  double dt = 0, c = 1, a = 1;
+  bool has_fp32 = false;
+  rt_amg_opts amg{};
+  // frozen per-step data, sorted order
+  rt::DevBuf<double> V, D, sa, f, rho, cv, m, e_prev, E_prev, Qe, QE, g;
+  rt::DevBuf<double> Eall;      // E^{n-1} / ghost data for all particles (sorted)
+  // hierarchy: levels[0] is the fine operator
+  std::vector<rt::Level> levels;
+  bool coarse_direct = false;        // coarsest level solved with a dense inverse
+  rt::DevBuf<double> coarse_inv;     // dense inverse of the coarsest operator (FP64)
+  // Krylov work vectors (fine size)
+  rt::DevBuf<double> r64, p64, q64, z64, xs, bs, ecur, Ecur, enew;
+  rt::DevBuf<float> r32, p32, q32, z32, d32;
+  rt::DevBuf<double> partA, partB;   // kMaxPartials block partials each
+  rt::DevBuf<double> scal;           // device scalars (see solve.hip)
+};
+
+namespace rt {
+// neighbours
+int build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
+                    const double* pos, const double* h, int kernel, rt_neighbors* nb);
+// solve helpers used by the Newton step
+int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
+                 const rt_solve_opts* o, rt_solve_stats* st);
+int amg_setup(rt_ctx* ctx, rt_matrix* A);
+int check_solve_opts(const rt_solve_opts* o);
+int collect_profile(rt_ctx* ctx, rt_solve_stats* s);
+int gather_sorted(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* user,
+                  double* sorted);
+int scatter_user(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* sorted,
+                 double* user);
+template <typename T>
+int vcycle(rt_ctx* ctx, rt_matrix* A, const T* b, T* z);
+int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_matrix* A,
+             bool new_structure);
+}  // namespace rt

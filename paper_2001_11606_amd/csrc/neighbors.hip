@@ -1,0 +1,462 @@
+// Cell-list neighbour search over cell-sorted particles (gfx950).
+//
+// 1. bounding box and largest smoothing length (block reduction);
+// 2. uniform grid of cells no smaller than the largest support;
+// 3. stable radix sort of (key, user index) with key = ghost flag above the
+//    Morton code of the cell: interior particles first, cells in Morton order
+//    (spatially compact runs of rows for every later gather, and 2^dim-aligned
+//    blocks of cells contiguous at every level of the aggregation hierarchy);
+//    gather sorted positions and smoothing lengths (SoA);
+// 4. table of [start, end) per (flag, row-major cell index);
+// 5. count pass, scan, fill pass: one thread per sorted particle tests the
+//    candidates of the 3^dim adjacent cells, interior cells first, so the
+//    interior neighbours of every row form a prefix of the row.
+//
+// The predicate r^2 < (kappa * max(h_i, h_j))^2 is evaluated in FP64 with
+// r^2 accumulated in axis order and contraction to FMA disabled, so that it
+// decides exactly as a separately-rounded evaluation does.
+#include <cmath>
+#include <cstring>
+#include <algorithm>
+
+#include "internal.h"
+#include "prim.h"
+
+#pragma clang fp contract(off)
+
+namespace rt {
+namespace {
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_bbox(int64_t n, const double* __restrict__ pos, const double* __restrict__ h,
+       double* __restrict__ part) {
+  __shared__ double red[8][kBlock];
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double hmax = 0.0, bad = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double x = pos[a * n + i];
+      if (!isfinite(x)) {
+        bad += 1.0;
+      } else {
+        lo[a] = fmin(lo[a], x);
+        hi[a] = fmax(hi[a], x);
+      }
+    }
+    const double hh = h[i];
+    if (!(hh > 0.0) || !isfinite(hh)) bad += 1.0;
+    else hmax = fmax(hmax, hh);
+  }
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    red[a][t] = lo[a];
+    red[3 + a][t] = hi[a];
+  }
+  red[6][t] = hmax;
+  red[7][t] = bad;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        red[a][t] = fmin(red[a][t], red[a][t + s]);
+        red[3 + a][t] = fmax(red[3 + a][t], red[3 + a][t + s]);
+      }
+      red[6][t] = fmax(red[6][t], red[6][t + s]);
+      red[7][t] = red[7][t] + red[7][t + s];
+    }
+    __syncthreads();
+  }
+  if (t < 8) part[blockIdx.x * 8 + t] = red[t][0];
+}
+
+template <int DIM>
+__device__ __forceinline__ uint64_t morton(int bits, const int* c) {
+  uint64_t code = 0;
+  for (int b = 0; b < bits; ++b)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) code |= (uint64_t)((c[a] >> b) & 1) << (DIM * b + a);
+  return code;
+}
+
+template <int DIM>
+__device__ __forceinline__ void demorton(int bits, uint64_t code, int* c) {
+  c[0] = c[1] = c[2] = 0;
+  for (int b = 0; b < bits; ++b)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) c[a] |= (int)((code >> (DIM * b + a)) & 1) << b;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_keys(int bits, int64_t n, int64_t nin, const double* __restrict__ pos, double lo0, double lo1,
+       double lo2, double cs, int nc0, int nc1, int nc2, uint64_t* __restrict__ keys,
+       int32_t* __restrict__ ids) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double lo[3] = {lo0, lo1, lo2};
+  const int nc[3] = {nc0, nc1, nc2};
+  int c[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double q = floor((pos[a * n + i] - lo[a]) / cs);
+    int ci = (int)q;
+    ci = ci < 0 ? 0 : (ci >= nc[a] ? nc[a] - 1 : ci);
+    c[a] = ci;
+  }
+  const uint64_t flag = i >= nin ? 1 : 0;
+  keys[i] = (flag << (DIM * bits)) | morton<DIM>(bits, c);
+  ids[i] = (int32_t)i;
+}
+
+__global__ void k_gather_sorted(int dim, int64_t n, const int32_t* __restrict__ perm,
+                                const double* __restrict__ pos, const double* __restrict__ h,
+                                double* __restrict__ spos, double* __restrict__ sh,
+                                int32_t* __restrict__ iperm) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int32_t u = perm[s];
+  for (int a = 0; a < dim; ++a) spos[a * n + s] = pos[a * n + u];
+  sh[s] = h[u];
+  iperm[u] = (int32_t)s;
+}
+
+// Range table: start/end of the sorted particles of every (flag, row-major cell).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_cell_table(int bits, int64_t n, int nc0, int nc1, int64_t ncells,
+             const uint64_t* __restrict__ skeys, int32_t* __restrict__ cstart,
+             int32_t* __restrict__ cend) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint64_t key = skeys[s];
+  const bool first = s == 0 || skeys[s - 1] != key;
+  const bool last = s == n - 1 || skeys[s + 1] != key;
+  if (!first && !last) return;
+  const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
+  int c[3];
+  demorton<DIM>(bits, key & mask, c);
+  const int64_t flag = (int64_t)(key >> (DIM * bits));
+  const int64_t t = flag * ncells + ((int64_t)c[2] * nc1 + c[1]) * nc0 + c[0];
+  if (first) cstart[t] = (int32_t)s;
+  if (last) cend[t] = (int32_t)(s + 1);
+}
+
+template <int DIM, bool FILL>
+__global__ void __launch_bounds__(kBlock)
+k_nbr_pass(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
+           double kappa, const uint64_t* __restrict__ skeys, const double* __restrict__ spos,
+           const double* __restrict__ sh, const int32_t* __restrict__ cstart,
+           const int32_t* __restrict__ cend, int64_t* __restrict__ cnt,
+           const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
+           int32_t* __restrict__ n_int_nbrs) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
+  int c[3];
+  demorton<DIM>(bits, skeys[s] & mask, c);
+  const double xi = spos[s];
+  const double yi = spos[n + s];
+  const double zi = DIM == 3 ? spos[2 * n + s] : 0.0;
+  const double hi = sh[s];
+  int64_t count = 0;
+  int64_t out = FILL ? ptr[s] : 0;
+  int32_t interior_count = 0;
+  for (int flag = 0; flag < 2; ++flag) {
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+      const int z = c[2] + oz;
+      if (z < 0 || z >= nc2) continue;
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int y = c[1] + oy;
+        if (y < 0 || y >= nc1) continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int x = c[0] + ox;
+          if (x < 0 || x >= nc0) continue;
+          const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
+          const int32_t t1 = cend[cell];
+          for (int32_t t = cstart[cell]; t < t1; ++t) {
+            if (t == s) continue;
+            double d = xi - spos[t];
+            double r2 = d * d;
+            d = yi - spos[n + t];
+            r2 = r2 + d * d;
+            if (DIM == 3) {
+              d = zi - spos[2 * n + t];
+              r2 = r2 + d * d;
+            }
+            const double th = kappa * fmax(hi, sh[t]);
+            if (r2 < th * th) {
+              if (FILL) idx[out++] = t;
+              else ++count;
+              if (t < nin) ++interior_count;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!FILL) cnt[s] = count;
+  else n_int_nbrs[s] = interior_count;
+}
+
+// user-order export: scatter mapped rows, then sort each row
+__global__ void k_user_counts(int64_t n, const int32_t* __restrict__ iperm,
+                              const int64_t* __restrict__ ptr, int64_t* __restrict__ ucnt) {
+  int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int32_t s = iperm[u];
+  ucnt[u] = ptr[s + 1] - ptr[s];
+}
+
+__global__ void k_user_scatter(int64_t n, const int32_t* __restrict__ perm,
+                               const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                               const int64_t* __restrict__ uptr, int32_t* __restrict__ uidx) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int64_t o = uptr[perm[s]];
+  for (int64_t k = ptr[s]; k < ptr[s + 1]; ++k) uidx[o++] = perm[idx[k]];
+}
+
+}  // namespace
+
+int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* pos,
+                    const double* h, int kernel, rt_neighbors* nb) {
+  hipStream_t st = ctx->stream;
+  nb->dim = dim;
+  nb->kernel = kernel;
+  nb->kappa = kernel == RT_KERNEL_CUBIC_SPLINE ? 2.0 : 1.0;
+  nb->n_total = n;
+  nb->n_interior = nin;
+
+  // 1. bounding box
+  int gb = grid_for(n, kBlock, 1024);
+  DevBuf<double> part;
+  RT_CHECK(part.reserve((size_t)gb * 8));
+  if (dim == 3) hipLaunchKernelGGL(k_bbox<3>, dim3(gb), dim3(kBlock), 0, st, n, pos, h, part.p);
+  else hipLaunchKernelGGL(k_bbox<2>, dim3(gb), dim3(kBlock), 0, st, n, pos, h, part.p);
+  RT_LAUNCH_CHECK();
+  std::vector<double> hp((size_t)gb * 8);
+  RT_CHECK_HIP(hipMemcpyAsync(hp.data(), part.p, hp.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double hmax = 0, bad = 0;
+  for (int b = 0; b < gb; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::fmin(lo[a], hp[b * 8 + a]);
+      hi[a] = std::fmax(hi[a], hp[b * 8 + 3 + a]);
+    }
+    hmax = std::fmax(hmax, hp[b * 8 + 6]);
+    bad += hp[b * 8 + 7];
+  }
+  if (bad > 0) {
+    set_error("rt_build_neighbors: %.0f non-finite positions or non-positive/non-finite h", bad);
+    return RT_E_ARG;
+  }
+  // cells at least as large as the largest support, with a relative margin
+  // far above the rounding of (x - lo)/cs, so adjacent cells hold every pair
+  const double cs = nb->kappa * hmax * (1.0 + 1e-6);
+  int64_t ncells = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      double cnt = std::floor((hi[a] - lo[a]) / cs) + 1.0;
+      if (cnt > 2.0e9) {
+        set_error("rt_build_neighbors: grid too large along axis %d", a);
+        return RT_E_ARG;
+      }
+      nb->nc[a] = (int)cnt;
+      nb->lo[a] = lo[a];
+    } else {
+      nb->nc[a] = 1;
+      nb->lo[a] = 0.0;
+    }
+    ncells *= nb->nc[a];
+  }
+  // the cell table holds 2 * ncells int32 pairs: bound it by the
+  // particle count so that widely separated clusters fail loudly
+  if (ncells > std::max<int64_t>(16 * n, (int64_t)1 << 24)) {
+    set_error("rt_build_neighbors: %lld cells for %lld particles exceed the cell-table bound",
+              (long long)ncells, (long long)n);
+    return RT_E_ARG;
+  }
+  nb->ncells = ncells;
+  nb->cell_size = cs;
+
+  // Morton bits per axis
+  int bits = 1;
+  for (int a = 0; a < dim; ++a)
+    while (((int64_t)1 << bits) < nb->nc[a]) ++bits;
+  if (dim * bits > 62) {
+    set_error("rt_build_neighbors: grid of %d x %d x %d cells needs more than 62 key bits",
+              nb->nc[0], nb->nc[1], nb->nc[2]);
+    return RT_E_ARG;
+  }
+  nb->bits = bits;
+
+  // 2-3. keys and stable sort
+  DevBuf<uint64_t> keys;
+  DevBuf<int32_t> ids;
+  RT_CHECK(keys.reserve(n));
+  RT_CHECK(nb->skeys.reserve(n));
+  RT_CHECK(ids.reserve(n));
+  RT_CHECK(nb->perm.reserve(n));
+  RT_CHECK(nb->iperm.reserve(n));
+  RT_CHECK(nb->spos.reserve((size_t)dim * n));
+  RT_CHECK(nb->sh.reserve(n));
+#define RT_KEYS(D_)                                                                            \
+  hipLaunchKernelGGL(k_keys<D_>, dim3(grid_for(n)), dim3(kBlock), 0, st, bits, n, nin, pos,     \
+                     nb->lo[0], nb->lo[1], nb->lo[2], cs, nb->nc[0], nb->nc[1], nb->nc[2],      \
+                     keys.p, ids.p)
+  if (dim == 3) RT_KEYS(3);
+  else RT_KEYS(2);
+#undef RT_KEYS
+  RT_LAUNCH_CHECK();
+  const int end_bit = dim * bits + 1;
+  RT_CHECK(radix_sort_pairs(ctx, keys.p, nb->skeys.p, ids.p, nb->perm.p, n, end_bit));
+  keys.release();
+  ids.release();
+  hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, dim, n,
+                     nb->perm.p, pos, h, nb->spos.p, nb->sh.p, nb->iperm.p);
+  RT_LAUNCH_CHECK();
+
+  // 4. [start, end) per (flag, row-major cell); empty cells stay [0, 0)
+  DevBuf<int32_t> cstart, cend;
+  RT_CHECK(cstart.reserve((size_t)(2 * ncells)));
+  RT_CHECK(cend.reserve((size_t)(2 * ncells)));
+  RT_CHECK_HIP(hipMemsetAsync(cstart.p, 0, sizeof(int32_t) * 2 * ncells, st));
+  RT_CHECK_HIP(hipMemsetAsync(cend.p, 0, sizeof(int32_t) * 2 * ncells, st));
+  if (dim == 3)
+    hipLaunchKernelGGL(k_cell_table<3>, dim3(grid_for(n)), dim3(kBlock), 0, st, bits, n,
+                       nb->nc[0], nb->nc[1], ncells, nb->skeys.p, cstart.p, cend.p);
+  else
+    hipLaunchKernelGGL(k_cell_table<2>, dim3(grid_for(n)), dim3(kBlock), 0, st, bits, n,
+                       nb->nc[0], nb->nc[1], ncells, nb->skeys.p, cstart.p, cend.p);
+  RT_LAUNCH_CHECK();
+
+  // 5. count, scan, fill
+  DevBuf<int64_t> cnt;
+  RT_CHECK(cnt.reserve(n + 1));
+  RT_CHECK(nb->ptr.reserve(n + 1));
+  RT_CHECK(nb->n_int_nbrs.reserve(n));
+  RT_CHECK_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int64_t), st));
+#define RT_NBR(D_, F_)                                                                         \
+  hipLaunchKernelGGL((k_nbr_pass<D_, F_>), dim3(grid_for(n)), dim3(kBlock), 0, st, n, nin, bits, \
+                     ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, nb->skeys.p,           \
+                     nb->spos.p, nb->sh.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p,       \
+                     nb->n_int_nbrs.p)
+  if (dim == 3) RT_NBR(3, false);
+  else RT_NBR(2, false);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, nb->ptr.p, n + 1, false)));
+  RT_CHECK(ctx->sync_read(nb->ptr.p + n, sizeof(int64_t)));
+  int64_t npairs = 0;
+  std::memcpy(&npairs, ctx->host, sizeof(int64_t));
+  if (npairs >= ((int64_t)1 << 31)) {
+    set_error("rt_build_neighbors: %lld pairs exceed the int32 index range", (long long)npairs);
+    return RT_E_ARG;
+  }
+  nb->npairs = npairs;
+  RT_CHECK(nb->idx.reserve((size_t)npairs));
+  if (dim == 3) RT_NBR(3, true);
+  else RT_NBR(2, true);
+#undef RT_NBR
+  RT_LAUNCH_CHECK();
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  return RT_OK;
+}
+
+}  // namespace rt
+
+extern "C" {
+
+int rt_build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
+                       const double* pos, const double* h, int kernel, rt_neighbors** out) {
+  rt::clear_error();
+  if (!ctx || !out || !pos || !h) {
+    rt::set_error("rt_build_neighbors: NULL argument");
+    return RT_E_ARG;
+  }
+  *out = nullptr;
+  if (dim != 2 && dim != 3) {
+    rt::set_error("rt_build_neighbors: dim must be 2 or 3 (got %d)", dim);
+    return RT_E_ARG;
+  }
+  if (n_total < 1 || n_total >= ((int64_t)1 << 31) || n_interior < 0 || n_interior > n_total) {
+    rt::set_error("rt_build_neighbors: bad sizes n_total=%lld n_interior=%lld",
+                  (long long)n_total, (long long)n_interior);
+    return RT_E_ARG;
+  }
+  if (kernel != RT_KERNEL_CUBIC_SPLINE && kernel != RT_KERNEL_WENDLAND_C4) {
+    rt::set_error("rt_build_neighbors: unknown kernel %d", kernel);
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt_neighbors* nb = new rt_neighbors();
+  int s = rt::build_neighbors(ctx, dim, n_total, n_interior, pos, h, kernel, nb);
+  if (s < 0) {
+    delete nb;
+    return s;
+  }
+  *out = nb;
+  return RT_OK;
+}
+
+int rt_neighbors_get_info(const rt_neighbors* nb, rt_neighbors_info* info) {
+  if (!nb || !info) {
+    rt::set_error("rt_neighbors_get_info: NULL argument");
+    return RT_E_ARG;
+  }
+  info->dim = nb->dim;
+  info->kernel = nb->kernel;
+  info->n_total = nb->n_total;
+  info->n_interior = nb->n_interior;
+  info->npairs = nb->npairs;
+  info->ncells = nb->ncells;
+  info->cell_size = nb->cell_size;
+  return RT_OK;
+}
+
+int rt_neighbors_order(rt_ctx* ctx, const rt_neighbors* nb, int32_t* perm) {
+  if (!ctx || !nb || !perm) {
+    rt::set_error("rt_neighbors_order: NULL argument");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipMemcpyAsync(perm, nb->perm.p, sizeof(int32_t) * nb->n_total,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+  RT_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  return RT_OK;
+}
+
+int rt_neighbors_export(rt_ctx* ctx, const rt_neighbors* nb, int64_t* nbr_ptr, int32_t* nbr_idx) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !nb || !nbr_ptr || (!nbr_idx && nb->npairs > 0)) {
+    set_error("rt_neighbors_export: NULL argument");
+    return RT_E_ARG;
+  }
+  const int64_t n = nb->n_total;
+  hipStream_t st = ctx->stream;
+  DevBuf<int64_t> ucnt;
+  RT_CHECK(ucnt.reserve(n + 1));
+  RT_CHECK_HIP(hipMemsetAsync(ucnt.p + n, 0, sizeof(int64_t), st));
+  hipLaunchKernelGGL(k_user_counts, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nb->iperm.p,
+                     nb->ptr.p, ucnt.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((scan<int64_t, int64_t>(ctx, ucnt.p, nbr_ptr, n + 1, false)));
+  if (nb->npairs == 0) return RT_OK;
+  hipLaunchKernelGGL(k_user_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nb->perm.p,
+                     nb->ptr.p, nb->idx.p, nbr_ptr, nbr_idx);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((row_sort<int32_t, int32_t>(ctx, nbr_ptr, nbr_idx, nullptr, n)));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  return RT_OK;
+}
+
+void rt_neighbors_free(rt_neighbors* nb) { delete nb; }
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+// One outer iteration of Algorithm 1 (nonlinear elimination), on the device.
+//
+// Right-hand side of the diffusion solve (Sec. 2.2, inexact Newton equation;
+// operators S and N of Sec. 3.2), multiplied by V_i:
+//   b_i = V_i [E_i^{n-1}/dt + c sigma_a,i a T_i^4 - (1 - f_i) c sigma_a,i E_i^l + Q_E,i] + g_i
+// Material update, the operator M^-1 of Sec. 3.2: per particle solve
+//   u(e) = rho/dt (e - e^{n-1}) + c sigma_a a (e/c_v)^4 - P = 0,  P = Q_e + c sigma_a E^{l+1},
+// by Newton with J = rho/dt + 4 c sigma_a a T^3/c_v.  u is increasing and
+// convex on e >= 0 with u(0) <= 0 <= u(e^{n-1} + dt P/rho), so a Newton step
+// leaving the current bracket is replaced by bisection; a negative upper end
+// means the root is negative (reported as non-physical, e clamped to 0).
+// Convergence measures (Sec. 2.2): max_i |e^{l+1} - e^l|/|e^{l+1}| and the
+// same for E; energy (Sec. 2.5): sum_i (m_i e_i + V_i E_i).
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace rt {
+namespace {
+
+__global__ void k_rhs(int64_t n, double dt, double c, double a, const double* __restrict__ V,
+                      const double* __restrict__ sa, const double* __restrict__ f,
+                      const double* __restrict__ cv, const double* __restrict__ E_prev,
+                      const double* __restrict__ QE, const double* __restrict__ g,
+                      const double* __restrict__ e_l, const double* __restrict__ E_l,
+                      double* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double T = e_l[i] / cv[i];
+  const double T2 = T * T;
+  const double ca = c * sa[i];
+  const double P = E_prev[i] / dt + ca * (a * (T2 * T2)) - (1.0 - f[i]) * ca * E_l[i] + QE[i];
+  b[i] = V[i] * P + g[i];
+}
+
+enum { R_DE = 0, R_DEE, R_ITS, R_BAD, R_NONPHYS, R_EN, R_EN0, R_WIDTH };
+
+struct MatArgs {
+  const double *e_prev, *rho, *cv, *sa, *Qe, *m, *V, *E_prev;
+  const double *E_new, *E_old, *e_start;
+  double* e_out;
+  double dt, c, a, tol;
+  int max_iter;
+};
+
+__global__ void __launch_bounds__(kBlock) k_material(int64_t n, MatArgs A, double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double de = 0.0, dE = 0.0, its_max = 0.0, bad = 0.0, nonphys = 0.0, en = 0.0, en0 = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double rho = A.rho[i], cv = A.cv[i], sa = A.sa[i], ep = A.e_prev[i];
+    const double Enew = A.E_new[i];
+    const double ca = A.c * sa;
+    const double P = A.Qe[i] + ca * Enew;
+    const double rdt = rho / A.dt;
+    double lo = 0.0, hi = ep + A.dt * P / rho;
+    double e;
+    int it = 0;
+    bool conv = true;
+    if (hi < 0.0) {
+      e = 0.0;
+      nonphys += 1.0;
+    } else {
+      e = fmin(fmax(A.e_start[i], lo), hi);
+      conv = false;
+      while (it < A.max_iter) {
+        const double T = e / cv;
+        const double T2 = T * T;
+        const double u = rdt * (e - ep) + ca * A.a * (T2 * T2) - P;
+        const double J = rdt + 4.0 * ca * A.a * (T2 * T) / cv;
+        ++it;
+        if (u == 0.0) {
+          conv = true;
+          break;
+        }
+        if (u > 0.0) hi = e;
+        else lo = e;
+        const double en = e - u / J;
+        const bool small = fabs(en - e) <= A.tol * fabs(en);
+        const bool inside = en > lo && en < hi;
+        e = (small || inside) ? en : 0.5 * (lo + hi);
+        if (small) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    if (!conv) bad += 1.0;
+    A.e_out[i] = e;
+    de = fmax(de, fabs(e - A.e_start[i]) / fabs(e));
+    dE = fmax(dE, fabs(Enew - A.E_old[i]) / fabs(Enew));
+    its_max = fmax(its_max, (double)it);
+    en += A.m[i] * e + A.V[i] * Enew;
+    en0 += A.m[i] * ep + A.V[i] * A.E_prev[i];
+  }
+  de = block_max(de, red);
+  dE = block_max(dE, red);
+  its_max = block_max(its_max, red);
+  bad = block_sum(bad, red);
+  nonphys = block_sum(nonphys, red);
+  en = block_sum(en, red);
+  en0 = block_sum(en0, red);
+  if (threadIdx.x == 0) {
+    double* o = part + (int64_t)blockIdx.x * R_WIDTH;
+    o[R_DE] = de;
+    o[R_DEE] = dE;
+    o[R_ITS] = its_max;
+    o[R_BAD] = bad;
+    o[R_NONPHYS] = nonphys;
+    o[R_EN] = en;
+    o[R_EN0] = en0;
+  }
+}
+
+// column-wise combination of the block partials (max for the first three
+// columns, sum for the rest), one block, fixed order
+__global__ void __launch_bounds__(kBlock) k_material_final(int np, const double* __restrict__ part,
+                                                           double* __restrict__ out) {
+  __shared__ double red[kBlock / kWave];
+  for (int c = 0; c < R_WIDTH; ++c) {
+    const bool is_max = c <= R_ITS;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const double x = part[(int64_t)i * R_WIDTH + c];
+      v = is_max ? fmax(v, x) : v + x;
+    }
+    v = is_max ? block_max(v, red) : block_sum(v, red);
+    if (threadIdx.x == 0) out[c] = v;
+  }
+}
+
+int material(rt_ctx* ctx, rt_matrix* A, const double* E_new, const double* E_old,
+             const double* e_start, double* e_out, double tol, int max_iter, double* res) {
+  const int64_t n = A->n;
+  const int gv = grid_for(n, kBlock, kMaxPartials);
+  RT_CHECK(A->partA.reserve((size_t)kMaxPartials * R_WIDTH));
+  RT_CHECK(A->scal.reserve(16));
+  MatArgs ma{A->e_prev.p, A->rho.p, A->cv.p, A->sa.p, A->Qe.p, A->m.p, A->V.p, A->E_prev.p,
+             E_new, E_old, e_start, e_out, A->dt, A->c, A->a, tol, max_iter};
+  hipLaunchKernelGGL(k_material, dim3(gv), dim3(kBlock), 0, ctx->stream, n, ma, A->partA.p);
+  RT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_material_final, dim3(1), dim3(kBlock), 0, ctx->stream, gv, A->partA.p,
+                     A->scal.p + 8);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(ctx->sync_read(A->scal.p + 8, sizeof(double) * R_WIDTH));
+  for (int c = 0; c < R_WIDTH; ++c) res[c] = ctx->host[c];
+  return RT_OK;
+}
+
+}  // namespace
+}  // namespace rt
+
+extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
+                              const rt_newton_opts* opts, rt_newton_stats* stats) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !A || !opts || (A->n > 0 && (!e || !E))) {
+    set_error("rt_newton_step: NULL argument");
+    return RT_E_ARG;
+  }
+  RT_CHECK(check_solve_opts(&opts->solve));
+  if (!(opts->material_tol > 0.0) || opts->material_max_iter < 1) {
+    set_error("rt_newton_step: material_tol must be > 0 and material_max_iter >= 1");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  auto t0 = std::chrono::steady_clock::now();
+  rt_newton_stats local{};
+  rt_newton_stats* stt = stats ? stats : &local;
+  *stt = rt_newton_stats{};
+  const int64_t n = A->n;
+  if (n == 0) return RT_OK;
+  hipStream_t st = ctx->stream;
+  for (auto* b : {&A->ecur, &A->Ecur, &A->enew, &A->xs, &A->bs}) RT_CHECK(b->reserve(n));
+  RT_CHECK(gather_sorted(ctx, A->nb, n, e, A->ecur.p));
+  RT_CHECK(gather_sorted(ctx, A->nb, n, E, A->Ecur.p));
+  double res[8];
+  int status = RT_OK;
+  if (ell == 0) {
+    // initial material solve with E^{n,0} from e^{n-1} (Algorithm 1, before the loop)
+    RT_CHECK(material(ctx, A, A->Ecur.p, A->Ecur.p, A->e_prev.p, A->ecur.p, opts->material_tol,
+                      opts->material_max_iter, res));
+    if (res[3] > 0) status = RT_NOT_CONVERGED;
+    if (res[4] > 0) status = RT_NONPHYSICAL;
+  }
+  hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->dt, A->c, A->a, A->V.p,
+                     A->sa.p, A->f.p, A->cv.p, A->E_prev.p, A->QE.p, A->g.p, A->ecur.p,
+                     A->Ecur.p, A->bs.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK_HIP(hipMemcpyAsync(A->xs.p, A->Ecur.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  int s = solve_sorted(ctx, A, A->bs.p, A->xs.p, &opts->solve, &stt->solve);
+  if (s < 0) return s;
+  if (s == RT_NOT_CONVERGED) status = RT_NOT_CONVERGED;
+  RT_CHECK(material(ctx, A, A->xs.p, A->Ecur.p, A->ecur.p, A->enew.p, opts->material_tol,
+                    opts->material_max_iter, res));
+  stt->delta_e = res[0];
+  stt->delta_E = res[1];
+  stt->material_iterations = (int)res[2];
+  stt->nonphysical = (int64_t)res[4];
+  stt->energy = res[5];
+  stt->energy_prev = res[6];
+  if (res[3] > 0 && status == RT_OK) status = RT_NOT_CONVERGED;
+  if (res[4] > 0) status = RT_NONPHYSICAL;
+  RT_CHECK(scatter_user(ctx, A->nb, n, A->enew.p, e));
+  RT_CHECK(scatter_user(ctx, A->nb, n, A->xs.p, E));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  RT_CHECK(collect_profile(ctx, &stt->solve));
+  stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status == RT_NONPHYSICAL) set_error("rt_newton_step: %lld negative material roots", (long long)stt->nonphysical);
+  else if (status == RT_NOT_CONVERGED && rt_last_error()[0] == 0)
+    set_error("rt_newton_step: a material solve did not converge");
+  return status;
+}

@@ -1,0 +1,21 @@
+// Device primitives of the set-up paths (see prim.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace rt {
+
+// out[i] = sum of in[0..i) (exclusive) or in[0..i] (inclusive), n items.
+template <typename In, typename Out>
+int scan(rt_ctx* ctx, const In* in, Out* out, int64_t n, bool inclusive);
+
+// Stable sort of (key, value) pairs by the low end_bit bits of the key.
+int radix_sort_pairs(rt_ctx* ctx, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                     int32_t* vout, int64_t n, int end_bit);
+
+// In-place ascending sort of every row [off[s], off[s+1]) of keys (and the
+// matching vals, if not NULL); meant for short rows.
+template <typename K, typename V>
+int row_sort(rt_ctx* ctx, const int64_t* off, K* keys, V* vals, int64_t nseg);
+
+}  // namespace rt

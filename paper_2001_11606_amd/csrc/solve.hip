@@ -1,0 +1,464 @@
+// Preconditioned conjugate gradients for the V-scaled radiation system
+// (the D^-1 operator of Sec. 3.2), FP64 and mixed precision.
+//
+// The paper solves the diffusion equation with AMG-preconditioned GMRES; the
+// V-scaled matrix here is symmetric positive definite, so CG applies.  The
+// paper warm-starts with E^l; the caller passes the initial guess in x.
+//
+// FP64:  PCG on A x = b, stop when ||r||_2 <= tol ||b||_2 (recursive residual).
+// MIXED: r = b - A x in FP64; repeat { FP32 PCG on A d = r (FP32 matrix, FP32
+//        vectors and arithmetic) to a relative reduction inner_tol (or just
+//        enough to reach tol); x += d in FP64; r = b - A x in FP64 } until
+//        ||r||_2 <= tol ||b||_2 -- the classical iterative refinement.
+//
+// Scalars (alpha, beta, r.z, ...) stay on the device; block partials of the
+// dot products are combined in FP64 by a one-block kernel in a fixed order.
+// The host reads ||r||^2 once per iteration for the stopping test.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "reduce.h"
+#include "spmv.h"
+
+namespace rt {
+namespace {
+
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_COUNT };
+enum { FIN_ALPHA = 0, FIN_BETA, FIN_RZ, FIN_RR, FIN_BB };
+enum { PROF_SPMV64 = 0, PROF_SPMV32 = 1, PROF_RESID64 = 2, PROF_KINDS = 3 };
+
+__global__ void __launch_bounds__(kBlock)
+k_finalize(int op, int np, const double* __restrict__ pa, const double* __restrict__ pb,
+           double* __restrict__ s) {
+  __shared__ double red[kBlock / kWave];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    a += pa[i];
+    if (pb) b += pb[i];
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case FIN_ALPHA:
+      s[S_PQ] = a;
+      if (a > 0.0 && isfinite(a)) {
+        s[S_ALPHA] = s[S_RZ] / a;
+      } else {
+        s[S_ALPHA] = 0.0;
+        s[S_BAD] = 1.0;
+      }
+      break;
+    case FIN_BETA:   // a = ||r||^2, b = r.z (new)
+      s[S_RR] = a;
+      s[S_BETA] = b / s[S_RZ];
+      s[S_RZ] = b;
+      break;
+    case FIN_RZ:     // a = r.z at the start
+      s[S_RZ] = a;
+      s[S_BAD] = 0.0;
+      break;
+    case FIN_RR:
+      s[S_RR] = a;
+      break;
+    case FIN_BB:
+      s[S_BB] = a;
+      break;
+  }
+}
+
+// p = M r for Jacobi (M = diag^-1), part = r.p
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_init_jacobi(int64_t n, const T* __restrict__ dinv, const T* __restrict__ r, T* __restrict__ p,
+              double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T z = dinv[i] * r[i];
+    p[i] = z;
+    acc += (double)r[i] * (double)z;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// p = z, part = r.z
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_copy_dot(int64_t n, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ p,
+           double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    p[i] = z[i];
+    acc += (double)r[i] * (double)z[i];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_dot(int64_t n, const T* __restrict__ a, const T* __restrict__ b, double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)a[i] * (double)b[i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// x += alpha p; r -= alpha q; partA = r.r; (Jacobi) partB = r.(dinv r)
+template <typename T, bool JAC>
+__global__ void __launch_bounds__(kBlock)
+k_update(int64_t n, const double* __restrict__ s, T* __restrict__ x, T* __restrict__ r,
+         const T* __restrict__ p, const T* __restrict__ q, const T* __restrict__ dinv,
+         double* __restrict__ partA, double* __restrict__ partB) {
+  __shared__ double red[kBlock / kWave];
+  const T alpha = (T)s[S_ALPHA];
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rr += (double)ri * (double)ri;
+    if (JAC) rz += (double)ri * (double)(dinv[i] * ri);
+  }
+  rr = block_sum(rr, red);
+  if (JAC) rz = block_sum(rz, red);
+  if (threadIdx.x == 0) {
+    partA[blockIdx.x] = rr;
+    if (JAC) partB[blockIdx.x] = rz;
+  }
+}
+
+// p = z + beta p, with z = dinv r (Jacobi) or the preconditioned vector
+template <typename T, bool JAC>
+__global__ void __launch_bounds__(kBlock)
+k_pupdate(int64_t n, const double* __restrict__ s, const T* __restrict__ r,
+          const T* __restrict__ dinv, const T* __restrict__ z, T* __restrict__ p) {
+  const T beta = (T)s[S_BETA];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T zi = JAC ? dinv[i] * r[i] : z[i];
+    p[i] = zi + beta * p[i];
+  }
+}
+
+__global__ void k_add_f32(int64_t n, const float* __restrict__ d, double* __restrict__ x) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += (double)d[i];
+}
+
+template <typename T>
+__global__ void k_zero(int64_t n, T* __restrict__ x) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ in,
+                         double* __restrict__ out) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s < n) out[s] = in[perm[s]];
+}
+
+__global__ void k_scatter(int64_t n, const int32_t* __restrict__ perm,
+                          const double* __restrict__ in, double* __restrict__ out) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s < n) out[perm[s]] = in[s];
+}
+
+struct Prof {
+  rt_ctx* ctx;
+  int kind;
+  size_t a = 0;
+  Prof(rt_ctx* c, int k) : ctx(c), kind(k) {}
+  int begin() { return ctx->profiling ? ctx->prof_mark(&a) : RT_OK; }
+  int end() {
+    if (!ctx->profiling) return RT_OK;
+    size_t b;
+    RT_CHECK(ctx->prof_mark(&b));
+    ctx->prof_spans.push_back({kind, a, b});
+    return RT_OK;
+  }
+};
+
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+  static const double* val(const Level& L) { return L.val64.p; }
+  static const double* diag(const Level& L) { return L.diag64.p; }
+  static const double* dinv(const Level& L) { return L.dinv64.p; }
+  static double* p(rt_matrix* A) { return A->p64.p; }
+  static double* q(rt_matrix* A) { return A->q64.p; }
+  static double* z(rt_matrix* A) { return A->z64.p; }
+  static constexpr int kind = PROF_SPMV64;
+};
+template <> struct Sel<float> {
+  static const float* val(const Level& L) { return L.val32.p; }
+  static const float* diag(const Level& L) { return L.diag32.p; }
+  static const float* dinv(const Level& L) { return L.dinv32.p; }
+  static float* p(rt_matrix* A) { return A->p32.p; }
+  static float* q(rt_matrix* A) { return A->q32.p; }
+  static float* z(rt_matrix* A) { return A->z32.p; }
+  static constexpr int kind = PROF_SPMV32;
+};
+
+int read_scalar(rt_ctx* ctx, rt_matrix* A, int idx, double* out) {
+  RT_CHECK(ctx->sync_read(A->scal.p + idx, sizeof(double)));
+  *out = ctx->host[0];
+  return RT_OK;
+}
+
+int finalize(rt_ctx* ctx, rt_matrix* A, int op, int np, const double* pa, const double* pb) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, ctx->stream, op, np, pa, pb,
+                     A->scal.p);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
+// PCG iterations on A x = b given r = b - A x and s[S_RR] = ||r||^2 on entry.
+// Stops when ||r||^2 <= thr2 or after max_it iterations.
+template <typename T>
+int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double thr2,
+             int max_it, int* its_out, double* rr_out) {
+  using S = Sel<T>;
+  hipStream_t st = ctx->stream;
+  const Level& L = A->levels[0];
+  const int64_t n = L.n;
+  T* p = S::p(A);
+  T* q = S::q(A);
+  T* z = S::z(A);
+  const int gv = grid_for(n, kBlock, kMaxPartials);
+  *its_out = 0;
+  *rr_out = rr0;
+  if (rr0 <= thr2) return RT_OK;
+  if (amg) {
+    RT_CHECK(vcycle<T>(ctx, A, r, z));
+    hipLaunchKernelGGL(k_copy_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, p, A->partB.p);
+  } else {
+    hipLaunchKernelGGL(k_init_jacobi<T>, dim3(gv), dim3(kBlock), 0, st, n, S::dinv(L), r, p,
+                       A->partB.p);
+  }
+  RT_LAUNCH_CHECK();
+  RT_CHECK(finalize(ctx, A, FIN_RZ, gv, A->partB.p, nullptr));
+  double rr = rr0;
+  int it = 0;
+  while (it < max_it) {
+    int nbk = 0;
+    Prof pf(ctx, S::kind);
+    RT_CHECK(pf.begin());
+    RT_CHECK((launch_spmv<T, SP_DOT>(st, n, L.nnz, L.rp.p, L.col.p, S::val(L), S::diag(L), p,
+                                     nullptr, nullptr, q, nullptr, A->partA.p, &nbk)));
+    RT_CHECK(pf.end());
+    RT_CHECK(finalize(ctx, A, FIN_ALPHA, nbk, A->partA.p, nullptr));
+    if (amg) {
+      hipLaunchKernelGGL((k_update<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r,
+                         p, q, nullptr, A->partA.p, nullptr);
+      RT_LAUNCH_CHECK();
+      RT_CHECK(vcycle<T>(ctx, A, r, z));
+      hipLaunchKernelGGL(k_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, A->partB.p);
+    } else {
+      hipLaunchKernelGGL((k_update<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r,
+                         p, q, S::dinv(L), A->partA.p, A->partB.p);
+    }
+    RT_LAUNCH_CHECK();
+    RT_CHECK(finalize(ctx, A, FIN_BETA, gv, A->partA.p, A->partB.p));
+    ++it;
+    RT_CHECK(read_scalar(ctx, A, S_RR, &rr));
+    if (!std::isfinite(rr)) {
+      set_error("PCG breakdown: non-finite residual");
+      *its_out = it;
+      *rr_out = rr;
+      return RT_E_DEVICE;
+    }
+    if (rr <= thr2) break;
+    if (amg)
+      hipLaunchKernelGGL((k_pupdate<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
+                         nullptr, z, p);
+    else
+      hipLaunchKernelGGL((k_pupdate<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
+                         S::dinv(L), nullptr, p);
+    RT_LAUNCH_CHECK();
+  }
+  *its_out = it;
+  *rr_out = rr;
+  return RT_OK;
+}
+
+int ensure_work(rt_matrix* A, bool mixed) {
+  const int64_t n = A->n;
+  for (auto* b : {&A->r64, &A->p64, &A->q64, &A->z64}) RT_CHECK(b->reserve(n));
+  RT_CHECK(A->partA.reserve(kMaxPartials));
+  RT_CHECK(A->partB.reserve(kMaxPartials));
+  RT_CHECK(A->scal.reserve(S_COUNT));
+  if (mixed)
+    for (auto* b : {&A->r32, &A->p32, &A->q32, &A->z32, &A->d32}) RT_CHECK(b->reserve(n));
+  return RT_OK;
+}
+
+// r = b - A x in FP64 (optionally also r32), returns ||r||^2
+int residual64(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, float* r32,
+               double* rr) {
+  const Level& L = A->levels[0];
+  int nbk = 0;
+  Prof pf(ctx, PROF_RESID64);
+  RT_CHECK(pf.begin());
+  RT_CHECK((launch_spmv<double, SP_RESID>(ctx->stream, L.n, L.nnz, L.rp.p, L.col.p, L.val64.p,
+                                          L.diag64.p, x, b, nullptr, A->r64.p, r32, A->partA.p,
+                                          &nbk)));
+  RT_CHECK(pf.end());
+  RT_CHECK(finalize(ctx, A, FIN_RR, nbk, A->partA.p, nullptr));
+  return read_scalar(ctx, A, S_RR, rr);
+}
+
+}  // namespace
+
+int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt_solve_opts* o,
+                 rt_solve_stats* stt) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = A->n;
+  const bool mixed = o->precision == RT_PREC_MIXED;
+  if (mixed && !A->has_fp32) {
+    set_error("rt_solve: mixed precision needs a matrix assembled with build_fp32 = 1");
+    return RT_E_STATE;
+  }
+  const bool amg = o->precond == 1 && A->levels.size() > 1;
+  RT_CHECK(ensure_work(A, mixed));
+  *stt = rt_solve_stats{};
+  if (n == 0) return RT_OK;
+  const int gv = grid_for(n, kBlock, kMaxPartials);
+  hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
+  double bb = 0.0;
+  RT_CHECK(read_scalar(ctx, A, S_BB, &bb));
+  if (!std::isfinite(bb)) {
+    set_error("rt_solve: right-hand side is not finite");
+    return RT_E_ARG;
+  }
+  if (bb == 0.0) {
+    hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, x);
+    RT_LAUNCH_CHECK();
+    return RT_OK;
+  }
+  const double thr2 = o->tol * o->tol * bb;
+  double rr = 0.0;
+  int status = RT_OK;
+  if (!mixed) {
+    RT_CHECK(residual64(ctx, A, b, x, nullptr, &rr));
+    int its = 0;
+    RT_CHECK(pcg_core<double>(ctx, A, amg, x, A->r64.p, rr, thr2, o->max_iter, &its, &rr));
+    stt->iterations = its;
+    if (rr > thr2) status = RT_NOT_CONVERGED;
+  } else {
+    RT_CHECK(residual64(ctx, A, b, x, A->r32.p, &rr));
+    int total = 0, refine = 0;
+    while (rr > thr2 && total < o->max_iter && refine < o->max_refine) {
+      // reduce by inner_tol, or just enough (with margin) to reach tol
+      double red = std::max(o->inner_tol, 0.3 * std::sqrt(thr2 / rr));
+      hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->d32.p);
+      RT_LAUNCH_CHECK();
+      int its = 0;
+      double rr_in = 0.0;
+      RT_CHECK(pcg_core<float>(ctx, A, amg, A->d32.p, A->r32.p, rr, red * red * rr,
+                               o->max_iter - total, &its, &rr_in));
+      total += its;
+      hipLaunchKernelGGL(k_add_f32, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->d32.p, x);
+      RT_LAUNCH_CHECK();
+      RT_CHECK(residual64(ctx, A, b, x, A->r32.p, &rr));
+      ++refine;
+      if (its == 0) break;
+    }
+    stt->iterations = total;
+    stt->refinements = refine;
+    if (rr > thr2) status = RT_NOT_CONVERGED;
+  }
+  stt->rel_residual = std::sqrt(rr / bb);
+  if (status == RT_NOT_CONVERGED)
+    set_error("rt_solve: relative residual %.3e above tolerance %.3e", stt->rel_residual, o->tol);
+  return status;
+}
+
+int collect_profile(rt_ctx* ctx, rt_solve_stats* s) {
+  if (!ctx->profiling) return RT_OK;
+  double sec[PROF_KINDS];
+  int calls[PROF_KINDS];
+  RT_CHECK(ctx->prof_collect(sec, calls, PROF_KINDS));
+  s->spmv_calls = calls[PROF_SPMV64];
+  s->spmv_seconds = sec[PROF_SPMV64];
+  s->spmv32_calls = calls[PROF_SPMV32];
+  s->spmv32_seconds = sec[PROF_SPMV32];
+  return RT_OK;
+}
+
+int gather_sorted(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* user,
+                  double* sorted) {
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, n, nb->perm.p,
+                     user, sorted);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
+int scatter_user(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* sorted,
+                 double* user) {
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, ctx->stream, n, nb->perm.p,
+                     sorted, user);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
+int check_solve_opts(const rt_solve_opts* o) {
+  if (!o) {
+    set_error("solve options are NULL");
+    return RT_E_ARG;
+  }
+  if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED) {
+    set_error("unknown precision %d", o->precision);
+    return RT_E_ARG;
+  }
+  if (o->precond != 0 && o->precond != 1) {
+    set_error("unknown preconditioner %d", o->precond);
+    return RT_E_ARG;
+  }
+  if (!(o->tol >= 0.0) || o->max_iter < 0 ||
+      (o->precision == RT_PREC_MIXED && (!(o->inner_tol > 0.0) || o->inner_tol >= 1.0))) {
+    set_error("invalid tolerance or iteration limit");
+    return RT_E_ARG;
+  }
+  return RT_OK;
+}
+
+}  // namespace rt
+
+extern "C" int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
+                        const rt_solve_opts* opts, rt_solve_stats* stats) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !A || (A->n > 0 && (!b || !x))) {
+    set_error("rt_solve: NULL argument");
+    return RT_E_ARG;
+  }
+  RT_CHECK(check_solve_opts(opts));
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  auto t0 = std::chrono::steady_clock::now();
+  rt_solve_stats local{};
+  rt_solve_stats* stt = stats ? stats : &local;
+  RT_CHECK(A->xs.reserve(A->n));
+  RT_CHECK(A->bs.reserve(A->n));
+  RT_CHECK(gather_sorted(ctx, A->nb, A->n, b, A->bs.p));
+  RT_CHECK(gather_sorted(ctx, A->nb, A->n, x, A->xs.p));
+  int s = solve_sorted(ctx, A, A->bs.p, A->xs.p, opts, stt);
+  if (s < 0) return s;
+  RT_CHECK(scatter_user(ctx, A->nb, A->n, A->xs.p, x));
+  RT_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  RT_CHECK(collect_profile(ctx, stt));
+  stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return s;
+}

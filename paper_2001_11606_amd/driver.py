@@ -1,0 +1,104 @@
+"""Time-step driver over the C ABI (host side, argument marshalling only).
+
+Algorithm 1 of the paper as a host loop: ``rt_assemble`` once per time step
+(material data frozen, preconditioner set up once), then ``rt_newton_step``
+per outer iteration until the relative changes of e and E fall below the
+outer tolerances (Sec. 2.2) or a fixed number of outer iterations has run.
+Arrays are torch device tensors; every computation runs in librt.so.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+from . import rt
+
+FIELDS = ("m", "rho", "cv", "sigma0_a", "sigma_s", "e", "E", "Q_e", "Q_E")
+
+
+@dataclass
+class DeviceProblem:
+    dim: int
+    n_total: int
+    n_interior: int
+    pos: object
+    h: object
+    arrays: dict
+    dt: float
+    c: float
+    a: float
+    opacity_exponent: float
+    limiter: int
+    limiter_k: float
+    kernel: int
+
+
+def upload(prob, device) -> DeviceProblem:
+    """Copy a problem description (numpy arrays, see ``synth.Problem``) to the device."""
+    import torch
+    t = lambda x: torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+    return DeviceProblem(dim=prob.dim, n_total=prob.n_total, n_interior=prob.n_interior,
+                         pos=t(prob.pos), h=t(prob.h), arrays={k: t(getattr(prob, k)) for k in FIELDS},
+                         dt=prob.dt, c=prob.c, a=prob.a, opacity_exponent=prob.opacity_exponent,
+                         limiter=prob.limiter, limiter_k=prob.limiter_k, kernel=prob.kernel)
+
+
+@dataclass
+class StepReport:
+    outer: int = 0
+    status: int = 0
+    delta_e: list = field(default_factory=list)
+    delta_E: list = field(default_factory=list)
+    krylov: list = field(default_factory=list)
+    refinements: list = field(default_factory=list)
+    energy_prev: float = 0.0
+    energy: float = 0.0
+    solve_seconds: float = 0.0
+    newton_seconds: float = 0.0
+    spmv64_calls: int = 0
+    spmv64_seconds: float = 0.0
+    spmv32_calls: int = 0
+    spmv32_seconds: float = 0.0
+
+
+def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
+              amg: Optional[rt.rt_amg_opts] = None, solve: Optional[rt.rt_solve_opts] = None,
+              eps_e: float = 1e-8, eps_E: float = 1e-8, material_tol: float = 1e-14,
+              max_outer: int = 50, fixed_outer: Optional[int] = None):
+    """One backward-Euler step.  Returns (e, E, A, report) with e, E the new
+    interior energies (device tensors, user order)."""
+    A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                     dp.limiter_k, amg=amg, A=A)
+    nin = dp.n_interior
+    e = dp.arrays["e"][:nin].clone()
+    E = dp.arrays["E"][:nin].clone()
+    solve = solve or rt.solve_opts()
+    nopts = rt.newton_opts(solve, material_tol)
+    rep = StepReport()
+    n_outer = fixed_outer if fixed_outer is not None else max_outer
+    for ell in range(n_outer):
+        status, st = ctx.newton_step(A, e, E, ell, nopts)
+        rep.status = max(rep.status, status)
+        rep.outer += 1
+        rep.delta_e.append(st.delta_e)
+        rep.delta_E.append(st.delta_E)
+        rep.krylov.append(st.solve.iterations)
+        rep.refinements.append(st.solve.refinements)
+        rep.energy_prev = st.energy_prev
+        rep.energy = st.energy
+        rep.solve_seconds += st.solve.seconds
+        rep.newton_seconds += st.seconds
+        rep.spmv64_calls += st.solve.spmv_calls
+        rep.spmv64_seconds += st.solve.spmv_seconds
+        rep.spmv32_calls += st.solve.spmv32_calls
+        rep.spmv32_seconds += st.solve.spmv32_seconds
+        if fixed_outer is None and st.delta_e < eps_e and st.delta_E < eps_E:
+            break
+    return e, E, A, rep
+
+
+def advance(dp: DeviceProblem, e, E) -> None:
+    """Store the step's result as the state at the start of the next step."""
+    nin = dp.n_interior
+    dp.arrays["e"][:nin] = e
+    dp.arrays["E"][:nin] = E

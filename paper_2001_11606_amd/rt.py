@@ -1,0 +1,352 @@
+"""ctypes binding of the C ABI declared in ``include/rt.h``.
+
+Argument marshalling only: every computation runs in ``librt.so`` on the GPU.
+Functions keep the C names (``rt_build_neighbors``, ``rt_assemble``,
+``rt_solve``, ``rt_newton_step`` ...) and take device pointers as integers;
+``Context`` wraps them for torch tensors (PyTorch is used for device memory
+and streams only).  Importing this module does not need a GPU; loading the
+library does, and fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librt.so")
+
+RT_OK = 0
+RT_NOT_CONVERGED = 1
+RT_NONPHYSICAL = 2
+RT_E_ARG = -1
+RT_E_OOM = -2
+RT_E_DEVICE = -3
+RT_E_STATE = -4
+
+RT_KERNEL_CUBIC_SPLINE = 0
+RT_KERNEL_WENDLAND_C4 = 1
+RT_LIMITER_NONE = 0
+RT_LIMITER_LARSEN = 1
+RT_LIMITER_LEVERMORE = 2
+RT_PREC_FP64 = 0
+RT_PREC_MIXED = 1
+PRECOND_JACOBI = 0
+PRECOND_AMG = 1
+
+c_i64 = ctypes.c_int64
+c_dbl = ctypes.c_double
+c_int = ctypes.c_int
+c_vp = ctypes.c_void_p
+
+
+class rt_neighbors_info(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("kernel", c_int), ("n_total", c_i64), ("n_interior", c_i64),
+                ("npairs", c_i64), ("ncells", c_i64), ("cell_size", c_dbl)]
+
+
+class rt_step_inputs(ctypes.Structure):
+    _fields_ = [("dt", c_dbl), ("c", c_dbl), ("a", c_dbl), ("opacity_exponent", c_dbl),
+                ("limiter", c_int), ("limiter_k", c_dbl),
+                ("m", c_vp), ("rho", c_vp), ("cv", c_vp), ("sigma0_a", c_vp), ("sigma_s", c_vp),
+                ("e", c_vp), ("E", c_vp), ("Q_e", c_vp), ("Q_E", c_vp)]
+
+
+class rt_amg_opts(ctypes.Structure):
+    _fields_ = [("max_levels", c_int), ("coarse_size", c_int), ("strength", c_dbl),
+                ("build_fp32", c_int)]
+
+
+class rt_matrix_info(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("nnz", c_i64), ("levels", c_int),
+                ("level_n", c_i64 * 16), ("level_nnz", c_i64 * 16)]
+
+
+class rt_solve_opts(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("precond", c_int), ("tol", c_dbl), ("max_iter", c_int),
+                ("inner_tol", c_dbl), ("max_refine", c_int)]
+
+
+class rt_solve_stats(ctypes.Structure):
+    _fields_ = [("iterations", c_int), ("refinements", c_int), ("rel_residual", c_dbl),
+                ("seconds", c_dbl), ("spmv_calls", c_int), ("spmv_seconds", c_dbl),
+                ("spmv32_calls", c_int), ("spmv32_seconds", c_dbl)]
+
+
+class rt_newton_opts(ctypes.Structure):
+    _fields_ = [("solve", rt_solve_opts), ("material_tol", c_dbl), ("material_max_iter", c_int)]
+
+
+class rt_newton_stats(ctypes.Structure):
+    _fields_ = [("delta_e", c_dbl), ("delta_E", c_dbl), ("energy", c_dbl), ("energy_prev", c_dbl),
+                ("material_iterations", c_int), ("nonphysical", c_i64), ("solve", rt_solve_stats),
+                ("seconds", c_dbl)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "rt_create": (c_int, [ctypes.POINTER(c_vp), c_int, c_vp]),
+    "rt_destroy": (None, [c_vp]),
+    "rt_set_stream": (c_int, [c_vp, c_vp]),
+    "rt_set_profiling": (c_int, [c_vp, c_int]),
+    "rt_last_error": (ctypes.c_char_p, []),
+    "rt_version": (ctypes.c_char_p, []),
+    "rt_build_neighbors": (c_int, [c_vp, c_int, c_i64, c_i64, c_vp, c_vp, c_int,
+                                   ctypes.POINTER(c_vp)]),
+    "rt_neighbors_get_info": (c_int, [c_vp, ctypes.POINTER(rt_neighbors_info)]),
+    "rt_neighbors_export": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "rt_neighbors_order": (c_int, [c_vp, c_vp, c_vp]),
+    "rt_neighbors_free": (None, [c_vp]),
+    "rt_assemble": (c_int, [c_vp, c_vp, ctypes.POINTER(rt_step_inputs),
+                            ctypes.POINTER(rt_amg_opts), ctypes.POINTER(c_vp)]),
+    "rt_matrix_get_info": (c_int, [c_vp, ctypes.POINTER(rt_matrix_info)]),
+    "rt_matrix_export": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "rt_matrix_free": (None, [c_vp]),
+    "rt_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
+                         ctypes.POINTER(rt_solve_stats)]),
+    "rt_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
+                               ctypes.POINTER(rt_newton_stats)]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+class RtError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librt.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2001_11606_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, status: int) -> int:
+    if status < 0:
+        raise RtError(fn, status, load().rt_last_error().decode())
+    return status
+
+
+def rt_last_error() -> str:
+    return load().rt_last_error().decode()
+
+
+def rt_version() -> str:
+    return load().rt_version().decode()
+
+
+def rt_create(device: int = 0, stream: int = 0) -> int:
+    ctx = c_vp()
+    _check("rt_create", load().rt_create(ctypes.byref(ctx), device, stream or None))
+    return ctx.value
+
+
+def rt_destroy(ctx: int) -> None:
+    load().rt_destroy(ctx)
+
+
+def rt_set_stream(ctx: int, stream: int) -> None:
+    _check("rt_set_stream", load().rt_set_stream(ctx, stream or None))
+
+
+def rt_set_profiling(ctx: int, on: bool) -> None:
+    _check("rt_set_profiling", load().rt_set_profiling(ctx, int(bool(on))))
+
+
+def rt_build_neighbors(ctx: int, dim: int, n_total: int, n_interior: int, pos: int, h: int,
+                       kernel: int) -> int:
+    out = c_vp()
+    _check("rt_build_neighbors", load().rt_build_neighbors(ctx, dim, n_total, n_interior, pos, h,
+                                                           kernel, ctypes.byref(out)))
+    return out.value
+
+
+def rt_neighbors_get_info(nb: int) -> rt_neighbors_info:
+    info = rt_neighbors_info()
+    _check("rt_neighbors_get_info", load().rt_neighbors_get_info(nb, ctypes.byref(info)))
+    return info
+
+
+def rt_neighbors_export(ctx: int, nb: int, nbr_ptr: int, nbr_idx: int) -> None:
+    _check("rt_neighbors_export", load().rt_neighbors_export(ctx, nb, nbr_ptr, nbr_idx))
+
+
+def rt_neighbors_order(ctx: int, nb: int, perm: int) -> None:
+    _check("rt_neighbors_order", load().rt_neighbors_order(ctx, nb, perm))
+
+
+def rt_neighbors_free(nb: int) -> None:
+    load().rt_neighbors_free(nb)
+
+
+def rt_assemble(ctx: int, nb: int, inputs: rt_step_inputs, amg: Optional[rt_amg_opts],
+                A: int = 0) -> int:
+    out = c_vp(A or None)
+    _check("rt_assemble", load().rt_assemble(ctx, nb, ctypes.byref(inputs),
+                                             ctypes.byref(amg) if amg is not None else None,
+                                             ctypes.byref(out)))
+    return out.value
+
+
+def rt_matrix_get_info(A: int) -> rt_matrix_info:
+    info = rt_matrix_info()
+    _check("rt_matrix_get_info", load().rt_matrix_get_info(A, ctypes.byref(info)))
+    return info
+
+
+def rt_matrix_export(ctx: int, A: int, row_ptr: int, col: int, val: int, ghost_rhs: int) -> None:
+    _check("rt_matrix_export", load().rt_matrix_export(ctx, A, row_ptr, col, val, ghost_rhs or None))
+
+
+def rt_matrix_free(A: int) -> None:
+    load().rt_matrix_free(A)
+
+
+def rt_solve(ctx: int, A: int, b: int, x: int, opts: rt_solve_opts) -> tuple:
+    st = rt_solve_stats()
+    s = _check("rt_solve", load().rt_solve(ctx, A, b, x, ctypes.byref(opts), ctypes.byref(st)))
+    return s, st
+
+
+def rt_newton_step(ctx: int, A: int, e: int, E: int, ell: int, opts: rt_newton_opts) -> tuple:
+    st = rt_newton_stats()
+    s = _check("rt_newton_step", load().rt_newton_step(ctx, A, e, E, ell, ctypes.byref(opts),
+                                                       ctypes.byref(st)))
+    return s, st
+
+
+# ---------------------------------------------------------------------------
+# torch-tensor convenience layer (still marshalling only)
+# ---------------------------------------------------------------------------
+
+def _ptr(t, dtype=None) -> int:
+    import torch
+    if t is None:
+        return 0
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def solve_opts(precision=RT_PREC_FP64, precond=PRECOND_JACOBI, tol=1e-10, max_iter=1000,
+               inner_tol=1e-4, max_refine=20) -> rt_solve_opts:
+    return rt_solve_opts(precision, precond, tol, max_iter, inner_tol, max_refine)
+
+
+def amg_opts(max_levels=8, coarse_size=256, strength=0.08, build_fp32=1) -> rt_amg_opts:
+    return rt_amg_opts(max_levels, coarse_size, strength, build_fp32)
+
+
+def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100) -> rt_newton_opts:
+    return rt_newton_opts(solve, material_tol, material_max_iter)
+
+
+@dataclass
+class Neighbors:
+    handle: int
+    info: rt_neighbors_info
+
+
+class Context:
+    """A library context bound to torch's current stream on ``device``."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.handle = rt_create(device, stream)
+        self._owned = []
+
+    def close(self):
+        lib = load()
+        for kind, h in reversed(self._owned):
+            (lib.rt_matrix_free if kind == "A" else lib.rt_neighbors_free)(h)
+        self._owned.clear()
+        if self.handle:
+            rt_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_profiling(self, on: bool):
+        rt_set_profiling(self.handle, on)
+
+    def build_neighbors(self, pos, h, n_interior: int, kernel: int = RT_KERNEL_CUBIC_SPLINE):
+        torch = self.torch
+        dim, n = pos.shape
+        nb = rt_build_neighbors(self.handle, dim, n, n_interior, _ptr(pos, torch.float64),
+                                _ptr(h, torch.float64), kernel)
+        self._owned.append(("N", nb))
+        return Neighbors(nb, rt_neighbors_get_info(nb))
+
+    def export_neighbors(self, nb: Neighbors):
+        torch = self.torch
+        ptr = torch.empty(nb.info.n_total + 1, dtype=torch.int64, device=self.device)
+        idx = torch.empty(max(nb.info.npairs, 1), dtype=torch.int32, device=self.device)
+        rt_neighbors_export(self.handle, nb.handle, ptr.data_ptr(), idx.data_ptr())
+        return ptr, idx[:nb.info.npairs]
+
+    def order(self, nb: Neighbors):
+        torch = self.torch
+        perm = torch.empty(nb.info.n_total, dtype=torch.int32, device=self.device)
+        rt_neighbors_order(self.handle, nb.handle, perm.data_ptr())
+        return perm
+
+    def assemble(self, nb: Neighbors, arrays: dict, dt: float, c: float = 1.0, a: float = 1.0,
+                 opacity_exponent: float = 0.0, limiter: int = RT_LIMITER_NONE,
+                 limiter_k: float = 2.0, amg: Optional[rt_amg_opts] = None, A: int = 0) -> int:
+        torch = self.torch
+        p = lambda k: _ptr(arrays.get(k), torch.float64) if arrays.get(k) is not None else None
+        inp = rt_step_inputs(dt, c, a, opacity_exponent, limiter, limiter_k,
+                             p("m"), p("rho"), p("cv"), p("sigma0_a"), p("sigma_s"), p("e"),
+                             p("E"), p("Q_e"), p("Q_E"))
+        new = rt_assemble(self.handle, nb.handle, inp, amg, A)
+        if not A:
+            self._owned.append(("A", new))
+        return new
+
+    def matrix_info(self, A: int) -> rt_matrix_info:
+        return rt_matrix_get_info(A)
+
+    def export_matrix(self, A: int):
+        torch = self.torch
+        info = rt_matrix_get_info(A)
+        rp = torch.empty(info.n + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(info.nnz, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(info.nnz, 1), dtype=torch.float64, device=self.device)
+        g = torch.empty(max(info.n, 1), dtype=torch.float64, device=self.device)
+        rt_matrix_export(self.handle, A, rp.data_ptr(), col.data_ptr(), val.data_ptr(), g.data_ptr())
+        return rp, col[:info.nnz], val[:info.nnz], g[:info.n]
+
+    def solve(self, A: int, b, x, opts: rt_solve_opts):
+        torch = self.torch
+        return rt_solve(self.handle, A, _ptr(b, torch.float64), _ptr(x, torch.float64), opts)
+
+    def newton_step(self, A: int, e, E, ell: int, opts: rt_newton_opts):
+        torch = self.torch
+        return rt_newton_step(self.handle, A, _ptr(e, torch.float64), _ptr(E, torch.float64), ell,
+                              opts)

@@ -1,0 +1,147 @@
+"""Drive the CPU (AddressSanitizer) build of the library through the C ABI on
+small seeded cases and compare with the oracle.  Run in a fresh process with
+libasan preloaded (see tests/test_kernels_cpu_emulation.py).  Prints one
+line per case; exits non-zero on the first mismatch, and ASan aborts the
+process on any out-of-bounds access."""
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import synth  # noqa: E402
+from oracle import linsolve, step as ostep  # noqa: E402
+from gpu_common import oracle_system, rowwise_rel_err  # noqa: E402
+from paper_2001_11606_amd import rt  # noqa: E402
+
+FIELDS = ("m", "rho", "cv", "sigma0_a", "sigma_s", "e", "E", "Q_e", "Q_E")
+QUICK = os.environ.get("RT_CPU_QUICK") == "1"
+
+
+def p(a):
+    return a.ctypes.data
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+class Case:
+    def __init__(self, ctx, prob, amg=None):
+        self.prob = prob
+        self.pos = np.ascontiguousarray(prob.pos)
+        self.h = np.ascontiguousarray(prob.h)
+        self.arr = {k: np.ascontiguousarray(getattr(prob, k)).copy() for k in FIELDS}
+        self.ctx = ctx
+        self.nb = rt.rt_build_neighbors(ctx, prob.dim, prob.n_total, prob.n_interior, p(self.pos),
+                                        p(self.h), prob.kernel)
+        self.info = rt.rt_neighbors_get_info(self.nb)
+        self.A = self.assemble(amg)
+
+    def inputs(self):
+        a = self.arr
+        pr = self.prob
+        return rt.rt_step_inputs(pr.dt, pr.c, pr.a, pr.opacity_exponent, pr.limiter, pr.limiter_k,
+                                 *[p(a[k]) for k in FIELDS])
+
+    def assemble(self, amg, A=0):
+        return rt.rt_assemble(self.ctx, self.nb, self.inputs(), amg, A)
+
+    def neighbors(self):
+        ptr = np.zeros(self.info.n_total + 1, np.int64)
+        idx = np.zeros(max(self.info.npairs, 1), np.int32)
+        rt.rt_neighbors_export(self.ctx, self.nb, p(ptr), p(idx))
+        return ptr, idx[:self.info.npairs]
+
+    def matrix(self):
+        info = rt.rt_matrix_get_info(self.A)
+        rp = np.zeros(info.n + 1, np.int64)
+        col = np.zeros(max(info.nnz, 1), np.int32)
+        val = np.zeros(max(info.nnz, 1))
+        g = np.zeros(max(info.n, 1))
+        rt.rt_matrix_export(self.ctx, self.A, p(rp), p(col), p(val), p(g))
+        return rp, col[:info.nnz], val[:info.nnz], g[:info.n], info
+
+    def free(self):
+        rt.rt_matrix_free(self.A)
+        rt.rt_neighbors_free(self.nb)
+
+
+def check_case(ctx, name, prob):
+    ptr, idx, fz, sysm = oracle_system(prob)
+    c = Case(ctx, prob)
+    gptr, gidx = c.neighbors()
+    assert np.array_equal(gptr, ptr) and np.array_equal(gidx, idx), f"{name}: neighbours"
+    rp, col, val, g, info = c.matrix()
+    assert np.array_equal(rp, sysm.A.indptr) and np.array_equal(col, sysm.A.indices), f"{name}: CSR"
+    err = rowwise_rel_err(rp, val, sysm.A.data)
+    assert err <= 1e-13, f"{name}: values {err}"
+    nin = prob.n_interior
+    b = np.random.default_rng(3).standard_normal(nin) * sysm.A.diagonal()
+    xref = linsolve.dense(sysm.A, b) if nin <= 3000 else linsolve.pcg_jacobi(sysm.A, b, tol=1e-15)[0]
+    combos = ((0, 0, 1e-14, 1e-12), (0, 1, 1e-14, 1e-12), (1, 0, 1e-12, 1e-10), (1, 1, 1e-12, 1e-10))
+    if QUICK:
+        combos = ((0, 1, 1e-14, 1e-12), (1, 1, 1e-12, 1e-10))
+    for prec, precond, tol, bar in combos:
+        x = np.zeros(nin)
+        s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50))
+        e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+        assert s == 0 and e <= bar, f"{name}: solve prec={prec} precond={precond} err={e} its={st.iterations}"
+    # Algorithm 1, three outer iterations, FP64 + AMG
+    n_outer = 1 if QUICK else 3
+    ref = ostep.time_step(prob.copy(), fixed_outer=n_outer, solve_tol=1e-15)
+    e_ = c.arr["e"][:nin].copy()
+    E_ = c.arr["E"][:nin].copy()
+    nopts = rt.newton_opts(rt.solve_opts(0, 1, 1e-14, 3000))
+    for ell in range(n_outer):
+        s, st = rt.rt_newton_step(ctx, c.A, p(e_), p(E_), ell, nopts)
+        assert s == 0, f"{name}: newton status {s}"
+    ee = np.max(np.abs(e_ - ref.e) / ref.e)
+    eE = np.max(np.abs(E_ - ref.E) / ref.E)
+    assert ee <= 1e-12 and eE <= 1e-12, f"{name}: newton {ee} {eE}"
+    say(f"ok {name}: n={prob.n_total} pairs={info.nnz} levels={info.levels} "
+        f"err(values)={err:.1e} newton=({ee:.1e},{eE:.1e})")
+    c.free()
+
+
+def main():
+    rt.load(os.environ["RT_CPU_LIB"])
+    ctx = rt.rt_create(0, 0)
+    cases = {
+        "mms2d_16": synth.config1(n=16),
+        "mms3d_6": synth.config2_mms(n=6),
+        "densitystep3d_8": synth.config3(n=8),
+        "marshak3d_8": synth.config4(n=8),
+        "ensemble2d": synth.config5_member(0, 400.0),
+        "infinite3d_5": synth.config2_infinite(1.0, 0.01, n=5),
+    }
+    only = os.environ.get("RT_CPU_CASES")
+    for name, prob in cases.items():
+        if only and name not in only.split(","):
+            continue
+        check_case(ctx, name, prob)
+    # error contract on the host
+    pos = np.random.default_rng(0).uniform(0, 1, (3, 40))
+    h = np.full(40, 0.2)
+    try:
+        rt.rt_build_neighbors(ctx, 4, 40, 40, p(pos), p(h), 0)
+        raise AssertionError("dim=4 accepted")
+    except rt.RtError as e:
+        assert e.code == rt.RT_E_ARG
+    # empty interior, single particle
+    nb = rt.rt_build_neighbors(ctx, 3, 40, 0, p(pos), p(h), 0)
+    rt.rt_neighbors_free(nb)
+    one = np.array([[0.5], [0.5], [0.5]])
+    nb = rt.rt_build_neighbors(ctx, 3, 1, 1, p(one), p(np.array([0.1])), 0)
+    rt.rt_neighbors_free(nb)
+    rt.rt_destroy(ctx)
+    say("all cases ok")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,54 @@
+"""Shared helpers of the GPU parity tests: run a seeded problem through the
+C ABI and through the oracle on identical inputs."""
+import sys
+
+import numpy as np
+
+import synth
+from oracle import kernels, neighbors, operator
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_cases():
+    """Seeded problems of every workload family, sized so the oracle finishes in
+    seconds while still spanning many rows per block and ragged tails."""
+    return {
+        "mms2d_64": lambda: synth.config1(n=64),
+        "mms3d_12": lambda: synth.config2_mms(n=12),
+        "densitystep3d_16": lambda: synth.config3(n=16),
+        "marshak3d_16": lambda: synth.config4(n=16),
+        "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
+        "ensemble2d": lambda: synth.config5_member(0, 2500.0),
+        "ensemble3d": lambda: synth.config5_member(1, 5000.0),
+    }
+
+
+def oracle_system(prob):
+    ptr, idx = neighbors.build(prob.pos, prob.h, kernels.KAPPA[prob.kernel])
+    fz = operator.frozen(prob, ptr, idx)
+    sysm = operator.assemble(prob, ptr, idx, fz)
+    return ptr, idx, fz, sysm
+
+
+def gpu_system(ctx, prob, amg=None):
+    from paper_2001_11606_amd import driver
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+    A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                     dp.limiter_k, amg=amg)
+    return dp, nb, A
+
+
+def rowwise_rel_err(rp, val_a, val_b):
+    """max over rows of max|a - b| / max|b| within the row."""
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    scale = np.zeros(n)
+    np.maximum.at(scale, rows, np.abs(val_b))
+    err = np.zeros(n)
+    np.maximum.at(err, rows, np.abs(val_a - val_b))
+    return float(np.max(err / np.where(scale > 0, scale, 1.0))) if n else 0.0

@@ -1,0 +1,120 @@
+"""GPU edge cases and the error contract of the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import oracle_system, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2001_11606_amd import rt
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+def _t(ctx, x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).to(ctx.device)
+
+
+def test_invalid_arguments(ctx):
+    from paper_2001_11606_amd import rt
+    say("[edges] invalid arguments")
+    pos = _t(ctx, np.random.default_rng(0).uniform(0, 1, (3, 50)))
+    h = _t(ctx, np.full(50, 0.1))
+    with pytest.raises(rt.RtError) as ei:
+        rt.rt_build_neighbors(ctx.handle, 4, 50, 50, pos.data_ptr(), h.data_ptr(), 0)
+    assert ei.value.code == rt.RT_E_ARG
+    with pytest.raises(rt.RtError):
+        rt.rt_build_neighbors(ctx.handle, 3, 50, 60, pos.data_ptr(), h.data_ptr(), 0)
+    bad = pos.clone()
+    bad[1, 7] = float("nan")
+    with pytest.raises(rt.RtError) as ei:
+        ctx.build_neighbors(bad, h, 50)
+    assert "non-finite" in str(ei.value)
+    hz = h.clone()
+    hz[3] = 0.0
+    with pytest.raises(rt.RtError):
+        ctx.build_neighbors(pos, hz, 50)
+
+
+def test_mixed_needs_fp32_copy(ctx):
+    from paper_2001_11606_amd import driver, rt
+    import torch
+    say("[edges] mixed solve without FP32 matrix")
+    prob = synth.config1(n=12)
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior)
+    A = ctx.assemble(nb, dp.arrays, dp.dt, amg=rt.amg_opts(build_fp32=0))
+    b = torch.ones(prob.n_interior, dtype=torch.float64, device=ctx.device)
+    x = torch.zeros_like(b)
+    with pytest.raises(rt.RtError) as ei:
+        ctx.solve(A, b, x, rt.solve_opts(rt.RT_PREC_MIXED))
+    assert ei.value.code == rt.RT_E_STATE
+
+
+def test_not_converged_reports_stats(ctx):
+    from paper_2001_11606_amd import driver, rt
+    import torch
+    say("[edges] max_iter = 1")
+    prob = synth.config3(n=10)
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior)
+    A = ctx.assemble(nb, dp.arrays, dp.dt, limiter=prob.limiter)
+    b = torch.ones(prob.n_interior, dtype=torch.float64, device=ctx.device)
+    x = torch.zeros_like(b)
+    status, st = ctx.solve(A, b, x, rt.solve_opts(0, 0, 1e-15, 1))
+    assert status == rt.RT_NOT_CONVERGED
+    assert st.iterations == 1 and st.rel_residual > 1e-15
+
+
+def test_all_ghosts_and_single_particle(ctx):
+    from paper_2001_11606_amd import rt
+    import torch
+    say("[edges] n_interior = 0 and n_total = 1")
+    pos = _t(ctx, np.random.default_rng(1).uniform(0, 1, (2, 30)))
+    h = _t(ctx, np.full(30, 0.2))
+    nb = ctx.build_neighbors(pos, h, 0)
+    assert nb.info.n_interior == 0
+    ptr, idx = ctx.export_neighbors(nb)
+    assert ptr[-1].item() == nb.info.npairs
+    one = ctx.build_neighbors(_t(ctx, [[0.5], [0.5], [0.5]]), _t(ctx, [0.1]), 1)
+    assert one.info.npairs == 0
+
+
+def test_coincident_far_and_ragged(ctx):
+    """Clustered particles with very different h (ragged rows, empty cells)."""
+    from oracle import neighbors
+    say("[edges] clustered, variable h")
+    rng = np.random.default_rng(9)
+    pos = np.concatenate([rng.uniform(0, 0.1, (3, 400)), rng.uniform(0.6, 1.0, (3, 300))], axis=1)
+    h = np.concatenate([np.full(400, 0.01), rng.uniform(0.02, 0.09, 300)])
+    nb = ctx.build_neighbors(_t(ctx, pos), _t(ctx, h), 650)
+    gptr, gidx = ctx.export_neighbors(nb)
+    ptr, idx = neighbors.brute_force(pos, h, 2.0)
+    assert np.array_equal(gptr.cpu().numpy(), ptr) and np.array_equal(gidx.cpu().numpy(), idx)
+
+
+def test_reassemble_reuses_matrix(ctx):
+    from paper_2001_11606_amd import driver, rt
+    import torch
+    say("[edges] second step reuses the matrix object")
+    prob = synth.config2_mms(n=8)
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior)
+    e, E, A, rep = driver.time_step(ctx, dp, nb, fixed_outer=2)
+    driver.advance(dp, e, E)
+    prob.e[:prob.n_interior] = e.cpu().numpy()
+    prob.E[:prob.n_interior] = E.cpu().numpy()
+    prob.set_time(2 * prob.dt)
+    dp2 = driver.upload(prob, ctx.device)
+    A2 = ctx.assemble(nb, dp2.arrays, dp2.dt, opacity_exponent=prob.opacity_exponent, A=A)
+    assert A2 == A
+    rp, col, val, g = [t.cpu().numpy() for t in ctx.export_matrix(A)]
+    ptr, idx, fz, sysm = oracle_system(prob)
+    assert np.array_equal(col, sysm.A.indices)
+    assert np.max(np.abs(val - sysm.A.data)) <= 1e-13 * np.max(np.abs(sysm.A.data))

@@ -1,0 +1,143 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars: neighbour lists and CSR structure bit-exact; assembled values within
+1e-13 of the row's largest entry; FP64 solves and Newton steps within 1e-12
+relative, the mixed-precision path within 1e-10 relative in E and e.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_system, oracle_system, rowwise_rel_err, say, small_cases
+from oracle import linsolve, step as ostep
+
+pytestmark = pytest.mark.gpu
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2001_11606_amd import rt
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def systems():
+    return {}
+
+
+def _get(systems, name):
+    if name not in systems:
+        prob = CASES[name]()
+        systems[name] = (prob, oracle_system(prob))
+    return systems[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_neighbors_bit_exact(ctx, systems, name):
+    prob, (ptr, idx, fz, sysm) = _get(systems, name)
+    say(f"[neighbors] {name} n_total={prob.n_total} n_interior={prob.n_interior}")
+    dp, nb, A = gpu_system(ctx, prob)
+    gptr, gidx = ctx.export_neighbors(nb)
+    assert nb.info.npairs == idx.shape[0]
+    assert np.array_equal(gptr.cpu().numpy(), ptr)
+    assert np.array_equal(gidx.cpu().numpy(), idx)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_matrix_parity(ctx, systems, name):
+    prob, (ptr, idx, fz, sysm) = _get(systems, name)
+    say(f"[assemble] {name}")
+    dp, nb, A = gpu_system(ctx, prob)
+    rp, col, val, g = [t.cpu().numpy() for t in ctx.export_matrix(A)]
+    assert np.array_equal(rp, sysm.A.indptr.astype(np.int64))
+    assert np.array_equal(col, sysm.A.indices.astype(np.int32))
+    assert rowwise_rel_err(rp, val, sysm.A.data) <= 1e-13
+    gs = np.max(np.abs(sysm.A.diagonal()))
+    assert np.max(np.abs(g - sysm.g), initial=0.0) <= 1e-13 * gs
+
+
+def _solve_case(ctx, systems, name, precision, precond, tol):
+    from paper_2001_11606_amd import rt
+    import torch
+    prob, (ptr, idx, fz, sysm) = _get(systems, name)
+    nin = prob.n_interior
+    b = np.random.default_rng(17).standard_normal(nin) * sysm.A.diagonal()
+    x_ref = linsolve.dense(sysm.A, b) if nin <= 5000 else linsolve.pcg_jacobi(sysm.A, b, tol=1e-15)[0]
+    dp, nb, A = gpu_system(ctx, prob)
+    bt = torch.tensor(b, device=ctx.device)
+    xt = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
+    status, st = ctx.solve(A, bt, xt, rt.solve_opts(precision, precond, tol, 2000, 1e-4, 50))
+    assert status == rt.RT_OK, rt.rt_last_error()
+    x = xt.cpu().numpy()
+    return np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref)), st
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "densitystep3d_16", "marshak3d_16", "ensemble3d"])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_solve_fp64(ctx, systems, name, precond):
+    say(f"[solve fp64] {name} precond={precond}")
+    err, st = _solve_case(ctx, systems, name, 0, precond, 1e-14)
+    assert err <= 1e-12, (err, st.iterations)
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "densitystep3d_16", "marshak3d_16", "ensemble3d"])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_solve_mixed(ctx, systems, name, precond):
+    say(f"[solve mixed] {name} precond={precond}")
+    err, st = _solve_case(ctx, systems, name, 1, precond, 1e-12)
+    assert err <= 1e-10, (err, st.iterations, st.refinements)
+    assert st.refinements >= 1
+
+
+def _newton_case(ctx, name, precision, precond, outer):
+    from paper_2001_11606_amd import driver, rt
+    prob = CASES[name]()
+    say(f"[newton] {name} precision={precision} precond={precond} outer={outer}")
+    ref = ostep.time_step(prob.copy(), fixed_outer=outer, inner_tol_e=1e-14, solve_tol=1e-15)
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+    tol = 1e-14 if precision == 0 else 1e-12
+    e, E, A, rep = driver.time_step(ctx, dp, nb, solve=rt.solve_opts(precision, precond, tol, 2000),
+                                    fixed_outer=outer)
+    assert rep.status == rt.RT_OK
+    e, E = e.cpu().numpy(), E.cpu().numpy()
+    err_e = np.max(np.abs(e - ref.e) / np.abs(ref.e))
+    err_E = np.max(np.abs(E - ref.E) / np.abs(ref.E))
+    return err_e, err_E, rep, ref
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "mms3d_12", "densitystep3d_16", "marshak3d_16",
+                                  "infinite3d_10"])
+def test_newton_fp64(ctx, name):
+    err_e, err_E, rep, ref = _newton_case(ctx, name, 0, 1, 3)
+    assert err_e <= 1e-12 and err_E <= 1e-12, (err_e, err_E)
+    # convergence measures and energy follow the oracle
+    assert np.allclose(rep.delta_e, ref.delta_e, rtol=1e-6, atol=1e-14)
+    assert rep.energy == pytest.approx(ref.energy_after, rel=1e-13)
+    assert rep.energy_prev == pytest.approx(ref.energy_before, rel=1e-13)
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "densitystep3d_16", "marshak3d_16"])
+def test_newton_mixed(ctx, name):
+    err_e, err_E, rep, ref = _newton_case(ctx, name, 1, 1, 3)
+    assert err_e <= 1e-10 and err_E <= 1e-10, (err_e, err_E)
+
+
+def test_deterministic(ctx):
+    from paper_2001_11606_amd import driver, rt
+    prob = CASES["densitystep3d_16"]()
+    say("[determinism] densitystep3d_16 mixed AMG twice")
+    outs = []
+    for _ in range(2):
+        dp = driver.upload(prob, ctx.device)
+        nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+        e, E, A, rep = driver.time_step(ctx, dp, nb, solve=rt.solve_opts(1, 1, 1e-10, 500),
+                                        fixed_outer=2)
+        outs.append((e.cpu().numpy().tobytes(), E.cpu().numpy().tobytes()))
+    assert outs[0] == outs[1]
