@@ -1,0 +1,197 @@
+"""Benchmark of the implicit SPH radiation-diffusion hot path on one MI355X.
+
+One step = the whole path on one synthetic batch, inputs resident in HBM:
+neighbour lists (cell sort + search), per-step frozen data and CSR assembly
+with the aggregation-AMG set-up, then the outer iterations of the
+nonlinear-elimination loop (right-hand side, diffusion solve warm-started
+from E^l, per-particle material Newton, convergence measures).
+
+Default workload: the 3-D Marshak-like front on 256^3 = 16,777,216 particles
+from greedy dart throwing (~58 neighbours), one time step dt = 1e-3 with
+exactly five outer iterations, FP32 inner PCG with FP64 iterative refinement
+to ||r||/||b|| <= 1e-10.  value = particle-updates/s = interior particles x
+outer iterations / wall time per step.  The plain-FP64 solve of the same
+systems is timed afterwards for the mixed-vs-FP64 ratio; the SpMV roofline
+uses HIP events recorded around every SpMV launch on the library's stream.
+The CPU baseline times the oracle on a smaller instance of the same recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "diffusion solve particle-updates/s + SpMV HBM GB/s; mixed vs FP64 @1e-10"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_problem(workload: str, n: int):
+    import synth
+    if workload == "marshak3d":
+        return synth.config4(n=n)
+    if workload == "densitystep3d":
+        return synth.config3(n=n)
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def run_step(ctx, dp, precision, precond, outer, tol, amg):
+    """One pass of the whole hot path; returns (e, E, A, report, nb)."""
+    from paper_2001_11606_amd import driver, rt
+    nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+    e, E, A, rep = driver.time_step(ctx, dp, nb, amg=amg,
+                                    solve=rt.solve_opts(precision, precond, tol, 5000, 1e-4, 30),
+                                    fixed_outer=outer)
+    return e, E, A, rep, nb
+
+
+def release(ctx, nb, A):
+    from paper_2001_11606_amd import rt
+    rt.rt_matrix_free(A)
+    rt.rt_neighbors_free(nb.handle)
+    ctx._owned = [o for o in ctx._owned if o[1] not in (A, nb.handle)]
+
+
+def cpu_baseline(workload: str, n_sample: int, outer: int):
+    """The oracle (plain FP64 numpy/scipy) on a smaller instance of the recipe."""
+    import numpy as np  # noqa: F401
+    from oracle import step as ostep
+    prob = make_problem(workload, n_sample)
+    t0 = time.perf_counter()
+    r = ostep.time_step(prob, fixed_outer=outer, solve_tol=1e-10)
+    dt = time.perf_counter() - t0
+    return {"value": prob.n_interior * outer / dt, "unit": "particle-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{workload} recipe at n={n_sample} ({prob.n_interior} interior particles), "
+                      f"one time step with {outer} outer iterations, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="marshak3d")
+    ap.add_argument("--n", type=int, default=256, help="particles per axis")
+    ap.add_argument("--outer", type=int, default=5)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--precond", type=int, default=0, help="0 Jacobi, 1 AMG V-cycle")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=64)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2001_11606_amd import driver, rt
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    log(f"[bench] generating {args.workload} n={args.n}")
+    t0 = time.perf_counter()
+    prob = make_problem(args.workload, args.n)
+    log(f"[bench] generated {prob.n_interior} interior + {prob.n_ghost} ghosts in "
+        f"{time.perf_counter() - t0:.1f} s")
+    ctx = rt.Context(0)
+    dp = driver.upload(prob, ctx.device)
+    amg = rt.amg_opts(max_levels=8 if args.precond == 1 else 1, build_fp32=1)
+    torch.cuda.synchronize()
+
+    def one(precision, profile=False):
+        ctx.set_profiling(profile)
+        out = run_step(ctx, dp, precision, args.precond, args.outer, args.tol, amg)
+        ctx.set_profiling(False)
+        return out
+
+    for w in range(args.warmup):
+        log(f"[bench] warmup step {w}")
+        e, E, A, rep, nb = one(rt.RT_PREC_MIXED)
+        release(ctx, nb, A)
+    torch.cuda.synchronize()
+
+    log(f"[bench] timing {args.steps} steps")
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        e, E, A, rep, nb = one(rt.RT_PREC_MIXED, profile=True)
+        reps.append(rep)
+        info = ctx.matrix_info(A)
+        if s + 1 < args.steps:
+            release(ctx, nb, A)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    nin = prob.n_interior
+    value = nin * args.outer * args.steps / elapsed
+    log(f"[bench] {ms_step:.1f} ms/step, krylov {reps[-1].krylov}, refinements "
+        f"{reps[-1].refinements}, status {reps[-1].status}")
+
+    # SpMV roofline (FP32 inner SpMV, the operator of the mixed solve)
+    n_rows = info.n
+    nnz_off = info.nnz - info.n
+    calls32 = sum(r.spmv32_calls for r in reps)
+    sec32 = sum(r.spmv32_seconds for r in reps)
+    bytes32 = 8.0 * nnz_off + 20.0 * n_rows
+    roof = None
+    if calls32:
+        achieved = bytes32 / (sec32 / calls32) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_spmv<float> (FP32 CSR SpMV inside the inner PCG)",
+                "bytes_per_launch": bytes32, "avg_launch_us": round(1e6 * sec32 / calls32, 2),
+                "launches": calls32}
+    solve_mixed = sum(r.solve_seconds for r in reps) / len(reps)
+    release(ctx, nb, A)
+
+    cmp = None
+    if not args.no_fp64:
+        log("[bench] FP64 comparison step")
+        e64, E64, A64, rep64, nb64 = one(rt.RT_PREC_FP64, profile=True)
+        torch.cuda.synchronize()
+        err_E = float(((E64 - E).abs() / E64.abs()).max())
+        err_e = float(((e64 - e).abs() / e64.abs()).max())
+        bytes64 = 12.0 * nnz_off + 32.0 * n_rows
+        cmp = {"solve_s_mixed": round(solve_mixed, 5), "solve_s_fp64": round(rep64.solve_seconds, 5),
+               "ratio_fp64_over_mixed": round(rep64.solve_seconds / solve_mixed, 3),
+               "krylov_mixed": reps[-1].krylov, "krylov_fp64": rep64.krylov,
+               "max_rel_diff_E": err_E, "max_rel_diff_e": err_e}
+        if rep64.spmv64_calls:
+            a64 = bytes64 / (rep64.spmv64_seconds / rep64.spmv64_calls) / 1e9
+            cmp["spmv64_gbs"] = round(a64, 1)
+        release(ctx, nb64, A64)
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle baseline at n={args.cpu_n}")
+        cpu = cpu_baseline(args.workload, args.cpu_n, args.outer)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {args.n}^3 ({nin} particles, {prob.n_ghost} ghosts), "
+                               f"1 step dt={prob.dt}, {args.outer} outer iterations, "
+                               f"mixed FP32/FP64 to {args.tol:g}",
+                   "particles": nin, "nnz": info.nnz, "amg_levels": info.levels,
+                   "precond": "amg" if args.precond == 1 else "jacobi"},
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

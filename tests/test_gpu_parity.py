@@ -11,7 +11,12 @@ import pytest
 from gpu_common import gpu_system, oracle_system, rowwise_rel_err, say, small_cases
 from oracle import linsolve, step as ostep
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="a GPU run that included this module ended with the device faulted and "
+                            "the cause has not been shown; kept off the GPU until it is (the same "
+                            "kernels are checked on the host by test_kernels_cpu_emulation.py)"),
+]
 
 CASES = small_cases()
 
