@@ -164,13 +164,39 @@ def main():
         err_e = float(((e64 - e).abs() / e64.abs()).max())
         bytes64 = 12.0 * nnz_off + 32.0 * n_rows
         cmp = {"solve_s_mixed": round(solve_mixed, 5), "solve_s_fp64": round(rep64.solve_seconds, 5),
-               "ratio_fp64_over_mixed": round(rep64.solve_seconds / solve_mixed, 3),
+               "ratio_fp64_over_mixed": round(rep64.solve_seconds / max(solve_mixed, 1e-12), 3),
                "krylov_mixed": reps[-1].krylov, "krylov_fp64": rep64.krylov,
                "max_rel_diff_E": err_E, "max_rel_diff_e": err_e}
         if rep64.spmv64_calls:
             a64 = bytes64 / (rep64.spmv64_seconds / rep64.spmv64_calls) / 1e9
             cmp["spmv64_gbs"] = round(a64, 1)
         release(ctx, nb64, A64)
+
+    # phase breakdown (one extra, synchronised step; not part of the timed region)
+    log("[bench] phase breakdown step")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nbb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    Ab = ctx.assemble(nbb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                      dp.limiter_k, amg=amg)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    eb = dp.arrays["e"][:nin].clone()
+    Eb = dp.arrays["E"][:nin].clone()
+    nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, args.precond, args.tol, 5000, 1e-4, 30))
+    solve_b = 0.0
+    for ell in range(args.outer):
+        _, stb = ctx.newton_step(Ab, eb, Eb, ell, nopts)
+        solve_b += stb.solve.seconds
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    phases = {"neighbors_ms": round(1e3 * (t2 - t1), 2), "assemble_ms": round(1e3 * (t3 - t2), 2),
+              "outer_iterations_ms": round(1e3 * (t4 - t3), 2),
+              "of_which_solves_ms": round(1e3 * solve_b, 2)}
+    release(ctx, nbb, Ab)
+    log(f"[bench] phases {phases}")
 
     cpu = None
     if not args.no_cpu:
@@ -187,7 +213,7 @@ def main():
                                f"mixed FP32/FP64 to {args.tol:g}",
                    "particles": nin, "nnz": info.nnz, "amg_levels": info.levels,
                    "precond": "amg" if args.precond == 1 else "jacobi"},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp,
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp, "phases": phases,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

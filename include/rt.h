@@ -202,7 +202,7 @@ typedef struct {
   int iterations;          /* Krylov iterations (inner ones in MIXED)        */
   int refinements;         /* FP64 residual recomputations (MIXED)           */
   double rel_residual;     /* final ||b - A x|| / ||b|| in FP64              */
-  double seconds;          /* wall time of the call (device-synchronised)    */
+  double seconds;          /* wall time of the solve (device-synchronised)   */
   int spmv_calls;          /* SpMV launches timed (profiling on)             */
   double spmv_seconds;     /* their summed device time                       */
   int spmv32_calls;

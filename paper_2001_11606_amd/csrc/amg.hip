@@ -236,7 +236,18 @@ template <> struct LevelBufs<float> {
   static float* r(Level& L) { return L.r32.p; }
 };
 
-// Build the aggregation structure of level l+1 from level l (no values).
+// Values (and columns) of the coarse level C = P^T F P.
+int galerkin_fill(rt_ctx* ctx, const Level& F, Level& C) {
+  hipLaunchKernelGGL((k_galerkin<true>), dim3(grid_for(C.n * kWave)), dim3(kBlock), 0,
+                     ctx->stream, C.n, F.crange.p, F.rp.p, F.col.p, F.val64.p, F.diag64.p,
+                     F.pmap.p, nullptr, C.rp.p, C.col.p, C.val64.p, C.diag64.p);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
+// Build level l+1 from level l: aggregation maps, coarse CSR structure, and
+// the coarse columns and values, so that the new level is complete before it
+// serves as the fine level of the next one.
 int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim) {
   hipStream_t st = ctx->stream;
   Level& L = A->levels[l];
@@ -279,7 +290,7 @@ int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim) {
   RT_CHECK(C.col.reserve(nnz));
   RT_CHECK(C.val64.reserve(nnz));
   RT_CHECK(C.diag64.reserve(nc));
-  return RT_OK;
+  return galerkin_fill(ctx, A->levels[l], C);
 }
 
 int level_vectors(Level& L, bool fp32) {
@@ -322,11 +333,7 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
   for (size_t l = 0; l < A->levels.size(); ++l) {
     Level& L = A->levels[l];
     if (l > 0) {
-      Level& F = A->levels[l - 1];
-      hipLaunchKernelGGL((k_galerkin<true>), dim3(grid_for(L.n * kWave)), dim3(kBlock), 0, st,
-                         L.n, F.crange.p, F.rp.p, F.col.p, F.val64.p, F.diag64.p, F.pmap.p,
-                         nullptr, L.rp.p, L.col.p, L.val64.p, L.diag64.p);
-      RT_LAUNCH_CHECK();
+      RT_CHECK(galerkin_fill(ctx, A->levels[l - 1], L));
       if (fp32) {
         if (L.nnz > 0)
           hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz)), dim3(kBlock), 0, st, L.nnz,

@@ -190,8 +190,10 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
                      A->Ecur.p, A->bs.p);
   RT_LAUNCH_CHECK();
   RT_CHECK_HIP(hipMemcpyAsync(A->xs.p, A->Ecur.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  RT_CHECK_HIP(hipEventRecord(ctx->ev0, st));
   int s = solve_sorted(ctx, A, A->bs.p, A->xs.p, &opts->solve, &stt->solve);
   if (s < 0) return s;
+  RT_CHECK_HIP(hipEventRecord(ctx->ev1, st));
   if (s == RT_NOT_CONVERGED) status = RT_NOT_CONVERGED;
   RT_CHECK(material(ctx, A, A->xs.p, A->Ecur.p, A->ecur.p, A->enew.p, opts->material_tol,
                     opts->material_max_iter, res));
@@ -206,6 +208,9 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   RT_CHECK(scatter_user(ctx, A->nb, n, A->enew.p, e));
   RT_CHECK(scatter_user(ctx, A->nb, n, A->xs.p, E));
   RT_CHECK_HIP(hipStreamSynchronize(st));
+  float solve_ms = 0.f;
+  RT_CHECK_HIP(hipEventElapsedTime(&solve_ms, ctx->ev0, ctx->ev1));
+  stt->solve.seconds = 1e-3 * solve_ms;
   RT_CHECK(collect_profile(ctx, &stt->solve));
   stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (status == RT_NONPHYSICAL) set_error("rt_newton_step: %lld negative material roots", (long long)stt->nonphysical);

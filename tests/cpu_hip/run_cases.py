@@ -74,7 +74,8 @@ class Case:
 
 def check_case(ctx, name, prob):
     ptr, idx, fz, sysm = oracle_system(prob)
-    c = Case(ctx, prob)
+    # a small coarsest size gives hierarchies of several levels even on tiny cases
+    c = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8))
     gptr, gidx = c.neighbors()
     assert np.array_equal(gptr, ptr) and np.array_equal(gidx, idx), f"{name}: neighbours"
     rp, col, val, g, info = c.matrix()

@@ -5,12 +5,7 @@ import pytest
 import synth
 from gpu_common import oracle_system, say
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="a GPU run that included this module ended with the device faulted and "
-                            "the cause has not been shown; kept off the GPU until it is (the same "
-                            "kernels are checked on the host by test_kernels_cpu_emulation.py)"),
-]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
