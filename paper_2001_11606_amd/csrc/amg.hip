@@ -119,20 +119,26 @@ k_galerkin(int64_t nc, const int32_t* __restrict__ crange, const int64_t* __rest
   }
 }
 
-// l1-Jacobi smoother scaling and Jacobi inverse diagonal, plus FP32 copies.
-__global__ void k_smoother(int64_t n, const int64_t* __restrict__ rp, const double* __restrict__ val,
-                           const double* __restrict__ diag, double* __restrict__ sinv,
-                           double* __restrict__ dinv, float* __restrict__ sinv32,
-                           float* __restrict__ dinv32) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double l1 = diag[i];
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) l1 += fabs(val[k]);
-  sinv[i] = 1.0 / l1;
-  dinv[i] = 1.0 / diag[i];
-  if (sinv32) {
-    sinv32[i] = (float)(1.0 / l1);
-    dinv32[i] = (float)(1.0 / diag[i]);
+// l1-Jacobi smoother scaling and Jacobi inverse diagonal of a coarse level,
+// plus FP32 copies; 8 lanes per row (coarse rows hold at most 3^dim entries).
+__global__ void __launch_bounds__(kBlock)
+k_smoother(int64_t n, const int64_t* __restrict__ rp, const double* __restrict__ val,
+           const double* __restrict__ diag, double* __restrict__ sinv, double* __restrict__ dinv,
+           float* __restrict__ sinv32, float* __restrict__ dinv32) {
+  constexpr int G = 8;
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  if (i >= n) return;   // the whole group leaves together
+  double l1 = 0.0;
+  for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += G) l1 += fabs(val[k]);
+  l1 = group_sum<G>(l1) + diag[i];
+  if (lane == 0) {
+    sinv[i] = 1.0 / l1;
+    dinv[i] = 1.0 / diag[i];
+    if (sinv32) {
+      sinv32[i] = (float)(1.0 / l1);
+      dinv32[i] = (float)(1.0 / diag[i]);
+    }
   }
 }
 
@@ -342,11 +348,11 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
                            L.diag32.p);
         RT_LAUNCH_CHECK();
       }
-    }
-    hipLaunchKernelGGL(k_smoother, dim3(grid_for(L.n)), dim3(kBlock), 0, st, L.n, L.rp.p,
-                       L.val64.p, L.diag64.p, L.sinv64.p, L.dinv64.p,
-                       fp32 ? L.sinv32.p : nullptr, fp32 ? L.dinv32.p : nullptr);
-    RT_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_smoother, dim3(grid_for(L.n * 8)), dim3(kBlock), 0, st, L.n, L.rp.p,
+                         L.val64.p, L.diag64.p, L.sinv64.p, L.dinv64.p,
+                         fp32 ? L.sinv32.p : nullptr, fp32 ? L.dinv32.p : nullptr);
+      RT_LAUNCH_CHECK();
+    }   // level 0: the assembly kernel wrote its scalings
   }
   // coarsest level: dense inverse when small
   Level& Lc = A->levels.back();

@@ -90,15 +90,6 @@ __global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, doubl
   D[i] = c * lam / st[i];
 }
 
-__global__ void k_copy_prefix_cols(int64_t nin, const int64_t* __restrict__ nptr,
-                                   const int32_t* __restrict__ nidx,
-                                   const int64_t* __restrict__ rp, int32_t* __restrict__ col) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nin) return;
-  const int64_t k0 = nptr[i], o = rp[i], len = rp[i + 1] - rp[i];
-  for (int64_t k = 0; k < len; ++k) col[o + k] = nidx[k0 + k];
-}
-
 __global__ void k_int_counts(int64_t nin, const int32_t* __restrict__ cnt32,
                              int64_t* __restrict__ cnt64) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -109,8 +100,9 @@ struct AsmArgs {
   const int64_t *nptr, *rp;
   const int32_t* nidx;
   const double *spos, *sh, *V, *D, *sa, *f, *Eall;
-  double *val64, *diag64, *g;
-  float *val32, *diag32;
+  int32_t* col;                       // written when the structure is new, else NULL
+  double *val64, *diag64, *dinv64, *sinv64, *g;
+  float *val32, *diag32, *dinv32, *sinv32;
 };
 
 template <int DIM, int G>
@@ -123,7 +115,7 @@ k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A) {
     const double xi = A.spos[i], yi = A.spos[n + i], zi = DIM == 3 ? A.spos[2 * n + i] : 0.0;
     const double hi = A.sh[i], Vi = A.V[i], Di = A.D[i];
     const int64_t k0 = A.nptr[i], k1 = A.nptr[i + 1], o = A.rp[i];
-    double suma = 0.0, gsum = 0.0;
+    double suma = 0.0, gsum = 0.0, absoff = 0.0;
     for (int64_t k = k0 + lane; k < k1; k += G) {
       const int32_t j = A.nidx[k];
       const double dx = xi - A.spos[j], dy = yi - A.spos[n + j];
@@ -138,16 +130,25 @@ k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A) {
         const double v = -(Vi * A.V[j]) * Dij * F;
         A.val64[o + (k - k0)] = v;
         if (A.val32) A.val32[o + (k - k0)] = (float)v;
+        if (A.col) A.col[o + (k - k0)] = j;
+        absoff += fabs(v);
       } else {
         gsum += aij * A.Eall[j];
       }
     }
     suma = group_sum<G>(suma);
     gsum = group_sum<G>(gsum);
+    absoff = group_sum<G>(absoff);
     if (lane == 0) {
       const double d = Vi * (1.0 / dt + c * A.sa[i] * A.f[i]) + Vi * suma;
       A.diag64[i] = d;
-      if (A.diag32) A.diag32[i] = (float)d;
+      A.dinv64[i] = 1.0 / d;                 // Jacobi preconditioner
+      A.sinv64[i] = 1.0 / (d + absoff);      // l1-Jacobi smoother of the V-cycle
+      if (A.diag32) {
+        A.diag32[i] = (float)d;
+        A.dinv32[i] = (float)(1.0 / d);
+        A.sinv32[i] = (float)(1.0 / (d + absoff));
+      }
       A.g[i] = Vi * gsum;
     }
   }
@@ -243,24 +244,21 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
     std::memcpy(&nnz, ctx->host, sizeof(int64_t));
     L.nnz = nnz;
     RT_CHECK(L.col.reserve(nnz));
-    if (nin > 0) {
-      hipLaunchKernelGGL(k_copy_prefix_cols, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin,
-                         nb->ptr.p, nb->idx.p, L.rp.p, L.col.p);
-      RT_LAUNCH_CHECK();
-    }
   }
   RT_CHECK(L.val64.reserve(L.nnz));
-  RT_CHECK(L.diag64.reserve(nin));
+  for (auto* b : {&L.diag64, &L.dinv64, &L.sinv64}) RT_CHECK(b->reserve(nin));
   const bool fp32 = A->amg.build_fp32 != 0;
   if (fp32) {
     RT_CHECK(L.val32.reserve(L.nnz));
-    RT_CHECK(L.diag32.reserve(nin));
+    for (auto* b : {&L.diag32, &L.dinv32, &L.sinv32}) RT_CHECK(b->reserve(nin));
   }
   A->has_fp32 = fp32;
   if (nin > 0) {
     AsmArgs aa{nb->ptr.p, L.rp.p, nb->idx.p, nb->spos.p, nb->sh.p, A->V.p, A->D.p, A->sa.p,
-               A->f.p, A->Eall.p, L.val64.p, L.diag64.p, A->g.p, fp32 ? L.val32.p : nullptr,
-               fp32 ? L.diag32.p : nullptr};
+               A->f.p, A->Eall.p, new_structure ? L.col.p : nullptr, L.val64.p, L.diag64.p,
+               L.dinv64.p, L.sinv64.p, A->g.p, fp32 ? L.val32.p : nullptr,
+               fp32 ? L.diag32.p : nullptr, fp32 ? L.dinv32.p : nullptr,
+               fp32 ? L.sinv32.p : nullptr};
     const double avg = nin ? (double)nb->npairs / (double)n : 0.0;
     const int G = pick_group(avg);
     const int grid = grid_for(nin * (int64_t)G, kBlock, 1 << 20);

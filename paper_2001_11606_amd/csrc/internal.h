@@ -167,7 +167,8 @@ struct rt_matrix {
   // Krylov work vectors (fine size)
   rt::DevBuf<double> r64, p64, q64, z64, xs, bs, ecur, Ecur, enew;
   rt::DevBuf<float> r32, p32, q32, z32, d32;
-  rt::DevBuf<double> partA, partB;   // kMaxPartials block partials each
+  rt::DevBuf<double> partA, partB;   // block partials of the reductions
+  rt::DevBuf<double> partC;          // second level of the partial reductions
   rt::DevBuf<double> scal;           // device scalars (see solve.hip)
 };
 

@@ -11,11 +11,13 @@
 // means the root is negative (reported as non-physical, e clamped to 0).
 // Convergence measures (Sec. 2.2): max_i |e^{l+1} - e^l|/|e^{l+1}| and the
 // same for E; energy (Sec. 2.5): sum_i (m_i e_i + V_i E_i).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
 #include "internal.h"
 #include "reduce.h"
+#include "spmv.h"
 
 namespace rt {
 namespace {
@@ -135,7 +137,7 @@ int material(rt_ctx* ctx, rt_matrix* A, const double* E_new, const double* E_old
              const double* e_start, double* e_out, double tol, int max_iter, double* res) {
   const int64_t n = A->n;
   const int gv = grid_for(n, kBlock, kMaxPartials);
-  RT_CHECK(A->partA.reserve((size_t)kMaxPartials * R_WIDTH));
+  RT_CHECK(A->partA.reserve(std::max<int64_t>((int64_t)kMaxPartials * R_WIDTH, max_partials(n))));
   RT_CHECK(A->scal.reserve(16));
   MatArgs ma{A->e_prev.p, A->rho.p, A->cv.p, A->sa.p, A->Qe.p, A->m.p, A->V.p, A->E_prev.p,
              E_new, E_old, e_start, e_out, A->dt, A->c, A->a, tol, max_iter};

@@ -14,6 +14,7 @@
 // Scalars (alpha, beta, r.z, ...) stay on the device; block partials of the
 // dot products are combined in FP64 by a one-block kernel in a fixed order.
 // The host reads ||r||^2 once per iteration for the stopping test.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -69,6 +70,38 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
   }
 }
 
+// Streaming vector kernels: kVec elements per thread (coalesced per element
+// slot), one partial per block, no grid-stride loop.
+constexpr int kVec = 4;
+inline int vec_blocks(int64_t n) {
+  const int64_t per_block = (int64_t)kBlock * kVec;
+  return (int)std::max<int64_t>(1, (n + per_block - 1) / per_block);
+}
+#define RT_VEC_LOOP(i)                                                                  \
+  for (int _u = 0; _u < kVec; ++_u)                                                     \
+    for (int64_t i = (int64_t)blockIdx.x * kBlock * kVec + (int64_t)_u * kBlock + threadIdx.x; \
+         i < n; i = n)
+
+// second reduction level: nb2 blocks each sum a contiguous chunk of pa (and pb)
+__global__ void __launch_bounds__(kBlock)
+k_partial_reduce(int np, int chunk, const double* __restrict__ pa, const double* __restrict__ pb,
+                 double* __restrict__ out) {
+  __shared__ double red[kBlock / kWave];
+  const int lo = blockIdx.x * chunk;
+  const int hi = lo + chunk < np ? lo + chunk : np;
+  double a = 0.0, b = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
+    a += pa[i];
+    if (pb) b += pb[i];
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = a;
+    out[gridDim.x + blockIdx.x] = b;
+  }
+}
+
 // p = M r for Jacobi (M = diag^-1), part = r.p
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -76,8 +109,7 @@ k_init_jacobi(int64_t n, const T* __restrict__ dinv, const T* __restrict__ r, T*
               double* __restrict__ part) {
   __shared__ double red[kBlock / kWave];
   double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  RT_VEC_LOOP(i) {
     const T z = dinv[i] * r[i];
     p[i] = z;
     acc += (double)r[i] * (double)z;
@@ -93,8 +125,7 @@ k_copy_dot(int64_t n, const T* __restrict__ r, const T* __restrict__ z, T* __res
            double* __restrict__ part) {
   __shared__ double red[kBlock / kWave];
   double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  RT_VEC_LOOP(i) {
     p[i] = z[i];
     acc += (double)r[i] * (double)z[i];
   }
@@ -107,9 +138,7 @@ __global__ void __launch_bounds__(kBlock)
 k_dot(int64_t n, const T* __restrict__ a, const T* __restrict__ b, double* __restrict__ part) {
   __shared__ double red[kBlock / kWave];
   double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    acc += (double)a[i] * (double)b[i];
+  RT_VEC_LOOP(i) acc += (double)a[i] * (double)b[i];
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
@@ -123,8 +152,7 @@ k_update(int64_t n, const double* __restrict__ s, T* __restrict__ x, T* __restri
   __shared__ double red[kBlock / kWave];
   const T alpha = (T)s[S_ALPHA];
   double rr = 0.0, rz = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  RT_VEC_LOOP(i) {
     x[i] += alpha * p[i];
     const T ri = r[i] - alpha * q[i];
     r[i] = ri;
@@ -145,8 +173,7 @@ __global__ void __launch_bounds__(kBlock)
 k_pupdate(int64_t n, const double* __restrict__ s, const T* __restrict__ r,
           const T* __restrict__ dinv, const T* __restrict__ z, T* __restrict__ p) {
   const T beta = (T)s[S_BETA];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  RT_VEC_LOOP(i) {
     const T zi = JAC ? dinv[i] * r[i] : z[i];
     p[i] = zi + beta * p[i];
   }
@@ -216,7 +243,23 @@ int read_scalar(rt_ctx* ctx, rt_matrix* A, int idx, double* out) {
   return RT_OK;
 }
 
+// partial counts above which a second reduction level runs first
+#ifndef RT_PARTIAL_FOLD_MIN
+#define RT_PARTIAL_FOLD_MIN (4 * kMaxPartials)
+#endif
+
 int finalize(rt_ctx* ctx, rt_matrix* A, int op, int np, const double* pa, const double* pb) {
+  if (np > RT_PARTIAL_FOLD_MIN) {
+    // first fold the partials into at most kMaxPartials values per array
+    const int nb2 = std::min(kMaxPartials, std::max(1, np / 8));
+    const int chunk = (np + nb2 - 1) / nb2;
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nb2), dim3(kBlock), 0, ctx->stream, np, chunk, pa,
+                       pb, A->partC.p);
+    RT_LAUNCH_CHECK();
+    pa = A->partC.p;
+    pb = pb ? A->partC.p + nb2 : nullptr;
+    np = nb2;
+  }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, ctx->stream, op, np, pa, pb,
                      A->scal.p);
   RT_LAUNCH_CHECK();
@@ -235,7 +278,7 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double
   T* p = S::p(A);
   T* q = S::q(A);
   T* z = S::z(A);
-  const int gv = grid_for(n, kBlock, kMaxPartials);
+  const int gv = vec_blocks(n);
   *its_out = 0;
   *rr_out = rr0;
   if (rr0 <= thr2) return RT_OK;
@@ -295,8 +338,9 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double
 int ensure_work(rt_matrix* A, bool mixed) {
   const int64_t n = A->n;
   for (auto* b : {&A->r64, &A->p64, &A->q64, &A->z64}) RT_CHECK(b->reserve(n));
-  RT_CHECK(A->partA.reserve(kMaxPartials));
-  RT_CHECK(A->partB.reserve(kMaxPartials));
+  RT_CHECK(A->partA.reserve(max_partials(n)));
+  RT_CHECK(A->partB.reserve(max_partials(n)));
+  RT_CHECK(A->partC.reserve(2 * kMaxPartials));
   RT_CHECK(A->scal.reserve(S_COUNT));
   if (mixed)
     for (auto* b : {&A->r32, &A->p32, &A->q32, &A->z32, &A->d32}) RT_CHECK(b->reserve(n));
@@ -333,7 +377,7 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
   RT_CHECK(ensure_work(A, mixed));
   *stt = rt_solve_stats{};
   if (n == 0) return RT_OK;
-  const int gv = grid_for(n, kBlock, kMaxPartials);
+  const int gv = vec_blocks(n);
   hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p);
   RT_LAUNCH_CHECK();
   RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));

@@ -16,6 +16,8 @@ LIB = os.path.join(OUT_DIR, "librt_cpu.so")
 SOURCES = ["context.hip", "prim.hip", "neighbors.hip", "assemble.hip", "amg.hip", "solve.hip", "newton.hip"]
 FLAGS = ["-x", "c++", "-std=c++20", "-O1", "-g", "-fPIC", "-fno-omit-frame-pointer",
          "-fsanitize=address", "-ffp-contract=off", "-pthread", "-w",
+         # always take the two-level reduction path, which large GPU runs use
+         "-DRT_PARTIAL_FOLD_MIN=4",
          "-I" + HERE, "-I" + os.path.join(ROOT, "include")]
 
 

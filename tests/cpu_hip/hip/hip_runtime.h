@@ -36,6 +36,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __builtin_nontemporal_load(p) (*(p))
 
 struct dim3 {
   unsigned x, y, z;
