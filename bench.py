@@ -43,13 +43,13 @@ def make_problem(workload: str, n: int):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def run_step(ctx, dp, precision, precond, outer, tol, amg):
+def run_step(ctx, dp, precision, precond, outer, tol, amg, shapes=None):
     """One pass of the whole hot path; returns (e, E, A, report, nb)."""
     from paper_2001_11606_amd import driver, rt
     nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
     e, E, A, rep = driver.time_step(ctx, dp, nb, amg=amg,
                                     solve=rt.solve_opts(precision, precond, tol, 5000, 1e-4, 30),
-                                    fixed_outer=outer)
+                                    fixed_outer=outer, shapes=shapes)
     return e, E, A, rep, nb
 
 
@@ -60,14 +60,36 @@ def release(ctx, nb, A):
     ctx._owned = [o for o in ctx._owned if o[1] not in (A, nb.handle)]
 
 
+def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Device-to-device stream copy rate (GB/s, read + write bytes) of a plain
+    elementwise kernel over nbytes; the same launch serves as the known-size
+    reference when HBM counters are read under a profiler."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    del src, dst
+    return 2.0 * nbytes / sec / 1e9
+
+
 def cpu_baseline(workload: str, n_sample: int, outer: int):
-    """The oracle (plain FP64 numpy/scipy) on a smaller instance of the recipe."""
-    import numpy as np  # noqa: F401
+    """The oracle (plain FP64 numpy/scipy) on a smaller instance of the recipe,
+    with BLAS/OpenMP pools held to one thread."""
+    from threadpoolctl import threadpool_limits
     from oracle import step as ostep
     prob = make_problem(workload, n_sample)
-    t0 = time.perf_counter()
-    r = ostep.time_step(prob, fixed_outer=outer, solve_tol=1e-10)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ostep.time_step(prob, fixed_outer=outer, solve_tol=1e-10)
+        dt = time.perf_counter() - t0
     return {"value": prob.n_interior * outer / dt, "unit": "particle-updates/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{workload} recipe at n={n_sample} ({prob.n_interior} interior particles), "
@@ -87,6 +109,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default SpMV shapes instead of tuning them during warm-up")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -107,16 +131,28 @@ def main():
     dp = driver.upload(prob, ctx.device)
     amg = rt.amg_opts(max_levels=8 if args.precond == 1 else 1, build_fp32=1)
     torch.cuda.synchronize()
+    copy_gbs = copy_bandwidth()
+    log(f"[bench] stream copy {copy_gbs:.0f} GB/s")
+
+    shapes = None
+    tune = None
 
     def one(precision, profile=False):
         ctx.set_profiling(profile)
-        out = run_step(ctx, dp, precision, args.precond, args.outer, args.tol, amg)
+        out = run_step(ctx, dp, precision, args.precond, args.outer, args.tol, amg, shapes)
         ctx.set_profiling(False)
         return out
 
     for w in range(args.warmup):
         log(f"[bench] warmup step {w}")
         e, E, A, rep, nb = one(rt.RT_PREC_MIXED)
+        if w == 0 and not args.no_tune:
+            # SpMV shapes are tuned once per problem, outside the timed region
+            tune = ctx.tune(A, reps=5)
+            shapes = tune["chosen"]
+            log(f"[bench] tuned SpMV shapes {[(tune['shapes'][a], tune['shapes'][b]) for a, b in shapes]}")
+            log(f"[bench] level-0 us per shape fp64 {[round(t, 1) for t in tune['us'][0][0]]}")
+            log(f"[bench] level-0 us per shape fp32 {[round(t, 1) for t in tune['us'][0][1]]}")
         release(ctx, nb, A)
     torch.cuda.synchronize()
 
@@ -149,6 +185,7 @@ def main():
         achieved = bytes32 / (sec32 / calls32) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "stream_copy_gbs": round(copy_gbs, 1),
                 "kernel": "k_spmv<float> (FP32 CSR SpMV inside the inner PCG)",
                 "bytes_per_launch": bytes32, "avg_launch_us": round(1e6 * sec32 / calls32, 2),
                 "launches": calls32}
@@ -181,6 +218,9 @@ def main():
     t2 = time.perf_counter()
     Ab = ctx.assemble(nbb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                       dp.limiter_k, amg=amg)
+    for lvl, (s64, s32) in enumerate((shapes or [])[:ctx.matrix_info(Ab).levels]):
+        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_FP64, s64)
+        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_MIXED, s32)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     eb = dp.arrays["e"][:nin].clone()
@@ -214,6 +254,10 @@ def main():
                    "particles": nin, "nnz": info.nnz, "amg_levels": info.levels,
                    "precond": "amg" if args.precond == 1 else "jacobi"},
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp, "phases": phases,
+        "spmv_tune": None if tune is None else {
+            "shapes_g_e": tune["shapes"], "chosen": tune["chosen"],
+            "level0_us_fp64": [round(t, 1) for t in tune["us"][0][0]],
+            "level0_us_fp32": [round(t, 1) for t in tune["us"][0][1]]},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -157,6 +157,8 @@ typedef struct {
   int coarse_size;       /* stop coarsening at or below this many unknowns     */
   double strength;       /* strength-of-connection threshold theta             */
   int build_fp32;        /* 1: also build the FP32 copies for RT_PREC_MIXED    */
+  int tiled_spmv;        /* 1: also build the tiled product form of each level
+                            (16-bit tile-local columns, x staged in LDS)      */
 } rt_amg_opts;
 
 int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
@@ -168,6 +170,8 @@ typedef struct {
   int levels;
   int64_t level_n[16];
   int64_t level_nnz[16];
+  int64_t level_tile_cols[16]; /* distinct columns summed over the level's
+                                  256-row tiles; 0 = level not tiled          */
 } rt_matrix_info;
 
 int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info);
@@ -178,6 +182,38 @@ int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info);
 int rt_matrix_export(rt_ctx* ctx, const rt_matrix* A, int64_t* row_ptr, int32_t* col,
                      double* val, double* ghost_rhs);
 void rt_matrix_free(rt_matrix* A);
+
+/* ---- SpMV shape tuning (not in the paper; a property of this library) -----
+ * Every sparse product y = A x over a level runs with a row-group shape: G
+ * lanes per row, each holding E entries, so that one pass covers G*E entries
+ * of a row.  Tiled shapes (tiled = 1) use the level's tiled form: E = 4
+ * consecutive entries per lane loaded as one 16-byte chunk, x read from LDS;
+ * a level without a tiled form runs its default plain shape instead.
+ * rt_spmv_shapes writes the (G, E, tiled) of up to max shapes (any pointer
+ * may be NULL) and returns how many exist.  rt_matrix_tune times the Krylov-loop product on every
+ * level of A with every shape, in FP64 and, when A holds FP32 copies, FP32:
+ * one untimed launch, then reps launches between HIP events on the library
+ * stream.  It keeps the fastest shape per level and precision for all later
+ * products of A and writes the timings (microseconds per product; 0 = not
+ * timed) and choices (-1 = none) to *rep when rep is not NULL.  It
+ * synchronises the stream and allocates one temporary vector.
+ * rt_matrix_set_spmv_shape forces a shape (index into the table; -1 restores
+ * the default: the smallest shape whose one pass covers the level's longest
+ * row).  Results of a product do not depend on the shape beyond the order
+ * of floating-point additions within a row.                                  */
+#define RT_MAX_LEVELS 16
+#define RT_MAX_SHAPES 16
+typedef struct {
+  int levels;                                 /* levels timed                  */
+  int shapes;                                 /* shapes timed per level        */
+  double us[RT_MAX_LEVELS][2][RT_MAX_SHAPES]; /* [level][0 FP64, 1 FP32][shape] */
+  int chosen[RT_MAX_LEVELS][2];
+} rt_tune_report;
+
+int rt_spmv_shapes(int* g, int* ent, int* tiled, int max);
+int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep);
+/* precision: RT_PREC_FP64 selects the FP64 product, RT_PREC_MIXED the FP32 one */
+int rt_matrix_set_spmv_shape(rt_matrix* A, int level, int precision, int shape);
 
 /* ---- linear solve (Sec. 3.2, the D^-1 operator) ---------------------------
  * Solves A x = b (the V-scaled system above) by preconditioned CG, stopping

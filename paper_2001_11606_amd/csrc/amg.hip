@@ -293,8 +293,9 @@ int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim) {
   int64_t nnz = 0;
   std::memcpy(&nnz, ctx->host, sizeof(int64_t));
   C.nnz = nnz;
+  RT_CHECK(max_nonneg<int64_t>(ctx, cnt.p, nc, &C.max_row));
   RT_CHECK(C.col.reserve(nnz));
-  RT_CHECK(C.val64.reserve(nnz));
+  RT_CHECK(C.val64.reserve(nnz + kSpmvPad));
   RT_CHECK(C.diag64.reserve(nc));
   return galerkin_fill(ctx, A->levels[l], C);
 }
@@ -304,7 +305,7 @@ int level_vectors(Level& L, bool fp32) {
   if (fp32) {
     for (auto* b : {&L.b32, &L.x32, &L.t32, &L.r32, &L.sinv32, &L.dinv32})
       RT_CHECK(b->reserve(L.n));
-    RT_CHECK(L.val32.reserve(L.nnz));
+    RT_CHECK(L.val32.reserve(L.nnz + kSpmvPad));
     RT_CHECK(L.diag32.reserve(L.n));
   }
   return RT_OK;
@@ -332,6 +333,7 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
         A->levels.pop_back();
         break;
       }
+      if (A->amg.tiled_spmv) RT_CHECK(build_tiles(ctx, A->levels.back()));
     }
   }
   for (Level& L : A->levels) RT_CHECK(level_vectors(L, fp32));
@@ -390,8 +392,9 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out)
     T* src = t;
     T* dst = out;
     for (int sweep = 0; sweep < 3; ++sweep) {
-      RT_CHECK((launch_spmv<T, SP_SMOOTH>(st, n, L.nnz, L.rp.p, L.col.p, B::val(L), B::diag(L),
-                                          src, b, B::sinv(L), dst, nullptr, nullptr, nullptr)));
+      RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), src, b, B::sinv(L),
+                                                dst, nullptr, nullptr, nullptr,
+                                                level_shape<T>(L))));
       T* tmp = src;
       src = dst;
       dst = tmp;
@@ -405,8 +408,8 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out)
   T* r = B::r(L);
   hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t);
   RT_LAUNCH_CHECK();
-  RT_CHECK((launch_spmv<T, SP_RESID>(st, n, L.nnz, L.rp.p, L.col.p, B::val(L), B::diag(L), t, b,
-                                     nullptr, r, nullptr, A->partB.p, nullptr)));
+  RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
+                                           nullptr, A->partB.p, nullptr, level_shape<T>(L))));
   hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
                      r, B::b(C));
   RT_LAUNCH_CHECK();
@@ -414,8 +417,8 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out)
   hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p, B::x(C),
                      t);
   RT_LAUNCH_CHECK();
-  RT_CHECK((launch_spmv<T, SP_SMOOTH>(st, n, L.nnz, L.rp.p, L.col.p, B::val(L), B::diag(L), t, b,
-                                      B::sinv(L), out, nullptr, nullptr, nullptr)));
+  RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), t, b, B::sinv(L), out,
+                                            nullptr, nullptr, nullptr, level_shape<T>(L))));
   return RT_OK;
 }
 

@@ -243,13 +243,14 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
     int64_t nnz = 0;
     std::memcpy(&nnz, ctx->host, sizeof(int64_t));
     L.nnz = nnz;
+    RT_CHECK(max_nonneg<int64_t>(ctx, cnt.p, nin, &L.max_row));
     RT_CHECK(L.col.reserve(nnz));
   }
-  RT_CHECK(L.val64.reserve(L.nnz));
+  RT_CHECK(L.val64.reserve(L.nnz + kSpmvPad));
   for (auto* b : {&L.diag64, &L.dinv64, &L.sinv64}) RT_CHECK(b->reserve(nin));
   const bool fp32 = A->amg.build_fp32 != 0;
   if (fp32) {
-    RT_CHECK(L.val32.reserve(L.nnz));
+    RT_CHECK(L.val32.reserve(L.nnz + kSpmvPad));
     for (auto* b : {&L.diag32, &L.dinv32, &L.sinv32}) RT_CHECK(b->reserve(nin));
   }
   A->has_fp32 = fp32;
@@ -275,6 +276,7 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
 #undef RT_ASM
     RT_LAUNCH_CHECK();
   }
+  if (new_structure && A->amg.tiled_spmv) RT_CHECK(build_tiles(ctx, L));
   return RT_OK;
 }
 
@@ -342,7 +344,7 @@ int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
     M = new rt_matrix();
     fresh = true;
   }
-  rt_amg_opts d{8, 256, 0.08, 1};
+  rt_amg_opts d{8, 256, 0.08, 1, 1};
   M->amg = amg ? *amg : d;
   if (M->amg.max_levels < 1) M->amg.max_levels = 1;
   if (M->amg.max_levels > 16) M->amg.max_levels = 16;
@@ -368,6 +370,7 @@ int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info) {
   for (size_t l = 0; l < A->levels.size() && l < 16; ++l) {
     info->level_n[l] = A->levels[l].n;
     info->level_nnz[l] = A->levels[l].nnz + A->levels[l].n;
+    info->level_tile_cols[l] = A->levels[l].tiled ? A->levels[l].tile_cols_total : 0;
   }
   return RT_OK;
 }

@@ -6,7 +6,12 @@
 // caller's index.  The V-scaled diffusion matrix (rows and columns = sorted
 // interior particles) is stored as a diagonal plus an off-diagonal CSR with
 // int64 row pointers, int32 columns (ascending) and FP64 values, with FP32
-// copies for the mixed-precision solver.
+// copies for the mixed-precision solver.  For the sparse products each level
+// may also hold a tiled form of the same CSR: rows in tiles of kTileRows, the
+// ascending distinct columns of each tile (tile_cols, offsets tile_off) and,
+// per entry, the 16-bit position of its column in its tile's list (lcol).
+// Value and lcol arrays carry kSpmvPad spare entries so that 16-byte chunk
+// loads may run past the last entry.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -82,6 +87,14 @@ struct DevBuf {
 
 constexpr int kBlock = 256;            // threads per block (4 wavefronts)
 constexpr int kMaxPartials = 2048;     // cap on blocks of reduction kernels
+constexpr int kTileRows = kBlock;      // rows per tile of the tiled SpMV format
+constexpr int kTileMaxCols = 3072;     // distinct columns a tile may have
+constexpr int kSpmvPad = 8;            // spare entries after values / lcol
+
+// Dynamic LDS of a kernel (bytes set at launch).
+#ifndef RT_DYNAMIC_LDS
+#define RT_DYNAMIC_LDS(name) extern __shared__ __attribute__((aligned(16))) unsigned char name[]
+#endif
 
 inline int grid_for(int64_t work_items, int per_block = kBlock, int cap = 1 << 30) {
   int64_t g = (work_items + per_block - 1) / per_block;
@@ -137,6 +150,15 @@ namespace rt {
 // non-decreasing; crange[I] is the first level-l row of aggregate I).
 struct Level {
   int64_t n = 0, nnz = 0;       // nnz = off-diagonal entries
+  int64_t max_row = 0;          // longest off-diagonal row
+  int shape64 = -1, shape32 = -1;   // SpMV row-group shape per precision (-1: by max_row)
+  // tiled form (see the file comment); tiled == false: plain CSR products only
+  bool tiled = false;
+  int64_t ntiles = 0, tile_cols_total = 0;
+  int max_tile_cols = 0;
+  DevBuf<int64_t> tile_off;     // ntiles + 1
+  DevBuf<int32_t> tile_cols;    // tile_cols_total
+  DevBuf<uint16_t> lcol;        // nnz + kSpmvPad
   DevBuf<int64_t> rp;
   DevBuf<int32_t> col;
   DevBuf<double> val64, diag64, sinv64, dinv64;   // sinv = l1-Jacobi smoother, dinv = 1/diag
@@ -148,6 +170,10 @@ struct Level {
   DevBuf<double> b64, x64, t64, r64;
   DevBuf<float> b32, x32, t32, r32;
 };
+template <typename T>
+inline int level_shape(const Level& L) {
+  return sizeof(T) == sizeof(double) ? L.shape64 : L.shape32;
+}
 }  // namespace rt
 
 struct rt_matrix {
@@ -173,6 +199,10 @@ struct rt_matrix {
 };
 
 namespace rt {
+// tiled SpMV form of a level whose rp/col are final (tile.hip); leaves the
+// level untiled when a tile has more than kTileMaxCols distinct columns
+int build_tiles(rt_ctx* ctx, Level& L);
+
 // neighbours
 int build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
                     const double* pos, const double* h, int kernel, rt_neighbors* nb);

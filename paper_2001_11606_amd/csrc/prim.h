@@ -9,6 +9,10 @@ namespace rt {
 template <typename In, typename Out>
 int scan(rt_ctx* ctx, const In* in, Out* out, int64_t n, bool inclusive);
 
+// *out = max(0, in[0..n)) on the host (synchronises the stream).
+template <typename T>
+int max_nonneg(rt_ctx* ctx, const T* in, int64_t n, T* out);
+
 // Stable sort of (key, value) pairs by the low end_bit bits of the key.
 int radix_sort_pairs(rt_ctx* ctx, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
                      int32_t* vout, int64_t n, int end_bit);

@@ -6,6 +6,8 @@
 // sort per row for the short rows of the neighbour and matrix exports.
 #include "prim.h"
 
+#include <cstring>
+
 #include "reduce.h"
 
 namespace rt {
@@ -127,7 +129,38 @@ __global__ void k_row_sort(int64_t nseg, const int64_t* __restrict__ off, K* __r
   }
 }
 
+// per-block maximum of non-negative values (grid-stride)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_max_partial(int64_t n, const T* __restrict__ in, T* __restrict__ part) {
+  __shared__ T red[kBlock / kWave];
+  T m = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    m = in[i] > m ? in[i] : m;
+  m = block_max(m, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
 }  // namespace
+
+template <typename T>
+int max_nonneg(rt_ctx* ctx, const T* in, int64_t n, T* out) {
+  *out = 0;
+  if (n <= 0) return RT_OK;
+  const int g = grid_for(n, kBlock, kMaxPartials);
+  DevBuf<T> part;
+  RT_CHECK(part.reserve(g + 1));
+  hipLaunchKernelGGL((k_max_partial<T>), dim3(g), dim3(kBlock), 0, ctx->stream, n, in, part.p);
+  RT_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_max_partial<T>), dim3(1), dim3(kBlock), 0, ctx->stream, (int64_t)g, part.p,
+                     part.p + g);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(ctx->sync_read(part.p + g, sizeof(T)));
+  std::memcpy(out, ctx->host, sizeof(T));
+  return RT_OK;
+}
+
+template int max_nonneg<int64_t>(rt_ctx*, const int64_t*, int64_t, int64_t*);
 
 template <typename In, typename Out>
 int scan(rt_ctx* ctx, const In* in, Out* out, int64_t n, bool inclusive) {

@@ -297,8 +297,8 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double
     int nbk = 0;
     Prof pf(ctx, S::kind);
     RT_CHECK(pf.begin());
-    RT_CHECK((launch_spmv<T, SP_DOT>(st, n, L.nnz, L.rp.p, L.col.p, S::val(L), S::diag(L), p,
-                                     nullptr, nullptr, q, nullptr, A->partA.p, &nbk)));
+    RT_CHECK((launch_spmv_level<T, SP_DOT>(st, L, S::val(L), S::diag(L), p, nullptr, nullptr, q,
+                                           nullptr, A->partA.p, &nbk, level_shape<T>(L))));
     RT_CHECK(pf.end());
     RT_CHECK(finalize(ctx, A, FIN_ALPHA, nbk, A->partA.p, nullptr));
     if (amg) {
@@ -354,9 +354,9 @@ int residual64(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, floa
   int nbk = 0;
   Prof pf(ctx, PROF_RESID64);
   RT_CHECK(pf.begin());
-  RT_CHECK((launch_spmv<double, SP_RESID>(ctx->stream, L.n, L.nnz, L.rp.p, L.col.p, L.val64.p,
-                                          L.diag64.p, x, b, nullptr, A->r64.p, r32, A->partA.p,
-                                          &nbk)));
+  RT_CHECK((launch_spmv_level<double, SP_RESID>(ctx->stream, L, L.val64.p, L.diag64.p, x, b,
+                                                nullptr, A->r64.p, r32, A->partA.p, &nbk,
+                                                L.shape64)));
   RT_CHECK(pf.end());
   RT_CHECK(finalize(ctx, A, FIN_RR, nbk, A->partA.p, nullptr));
   return read_scalar(ctx, A, S_RR, rr);

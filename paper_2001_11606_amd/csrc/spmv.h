@@ -1,18 +1,24 @@
 // Sparse matrix-vector kernels over (diagonal + off-diagonal CSR) on gfx950.
 //
-// One group of G lanes (G in {4, 8, 16, 32, 64}, about four entries per lane)
-// per row and 256/G rows per block, with no grid-stride loop: the launch
-// covers every row once, so the hardware keeps as many waves resident as the
-// register file allows and each wave has one short dependency chain
-// (row pointers -> values/columns -> x gathers).  Each lane issues up to four
-// independent value/column loads before it consumes them, and values and
-// columns are streamed with non-temporal loads so that L2 keeps the gathered
-// x.  Blocks are renumbered so that each of the eight XCDs (which receive
-// blocks round-robin) works on one contiguous eighth of the rows and its L2
-// sees the x-neighbourhood of those rows.  Accumulation is in the value type
-// T (FP32 in the mixed-precision inner solve, FP64 otherwise); per-block dot
-// products are combined in FP64 in a fixed order, so results are
-// deterministic run to run.
+// A group of G lanes works on one row and each lane owns ENT entries of it
+// (entries lane, lane + G, ..., lane + (ENT-1) G of the row), so a row of up
+// to G*ENT entries is covered by one pass and 256/G rows share a block.  The
+// kernel is built so that a wave waits on memory exactly three times:
+//   1. row bounds and the row's own diagonal, x_i, b_i, s_i (independent loads),
+//   2. all ENT column indices and values of the lane (issued back to back;
+//      slots beyond the row end re-read the row's last entry, which is a cache
+//      hit, and are weighted by zero),
+//   3. all ENT gathers of x.
+// Longer rows repeat steps 2-3.  With no serial chain inside a row, the bytes
+// a wave has in flight scale with G*ENT*(rows per wave), which is what an
+// HBM-bound sweep needs.  There is no grid-stride loop: the launch covers
+// every row once.  Values and columns are streamed with non-temporal loads so
+// that L2 keeps the gathered x.  Blocks are renumbered so that each of the
+// eight XCDs (which receive blocks round-robin) works on one contiguous eighth
+// of the rows and its L2 sees the x-neighbourhood of those rows.
+// Accumulation is in the value type T (FP32 in the mixed-precision inner
+// solve, FP64 otherwise); per-block dot products are combined in FP64 in a
+// fixed order, so results are deterministic run to run.
 #pragma once
 
 #include "internal.h"
@@ -41,7 +47,7 @@ __device__ __forceinline__ T stream_load(const T* p) {
   return __builtin_nontemporal_load(p);
 }
 
-template <typename T, int G, int MODE>
+template <typename T, int G, int ENT, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
        const T* __restrict__ val, const T* __restrict__ diag, const T* __restrict__ x,
@@ -54,36 +60,45 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
   const int64_t i = (int64_t)lb * RPB + threadIdx.x / G;
   double acc = 0.0;
   if (i < n) {
-    const int64_t k1 = rp[i + 1];
-    int64_t k = rp[i] + lane;
+    const int64_t k0 = rp[i], k1 = rp[i + 1];
+    const T xi = x[i];
+    const T di = diag[i];
+    T bi = 0, si = 0;
+    if (MODE == SP_RESID || MODE == SP_SMOOTH) bi = b[i];
+    if (MODE == SP_SMOOTH) si = s[i];
     T sum = 0;
-    for (; k + 3 * G < k1; k += 4 * G) {
-      const int32_t c0 = stream_load(col + k), c1 = stream_load(col + k + G);
-      const int32_t c2 = stream_load(col + k + 2 * G), c3 = stream_load(col + k + 3 * G);
-      const T v0 = stream_load(val + k), v1 = stream_load(val + k + G);
-      const T v2 = stream_load(val + k + 2 * G), v3 = stream_load(val + k + 3 * G);
-      sum += v0 * x[c0];
-      sum += v1 * x[c1];
-      sum += v2 * x[c2];
-      sum += v3 * x[c3];
+    for (int64_t base = k0 + lane; base < k1; base += G * ENT) {
+      int32_t c[ENT];
+      T v[ENT];
+#pragma unroll
+      for (int e = 0; e < ENT; ++e) {
+        const int64_t k = base + e * G;
+        const int64_t kc = k < k1 ? k : k1 - 1;
+        c[e] = stream_load(col + kc);
+        const T w = stream_load(val + kc);
+        v[e] = k < k1 ? w : T(0);
+      }
+      T xv[ENT];
+#pragma unroll
+      for (int e = 0; e < ENT; ++e) xv[e] = x[c[e]];
+#pragma unroll
+      for (int e = 0; e < ENT; ++e) sum += v[e] * xv[e];
     }
-    for (; k < k1; k += G) sum += stream_load(val + k) * x[stream_load(col + k)];
     sum = group_sum<G>(sum);
     if (lane == 0) {
-      const T xi = x[i];
-      const T ax = diag[i] * xi + sum;
+      const T ax = di * xi + sum;
       if (MODE == SP_PLAIN) {
         y[i] = ax;
       } else if (MODE == SP_DOT) {
         y[i] = ax;
         acc = (double)xi * (double)ax;
       } else if (MODE == SP_RESID) {
-        const T r = b[i] - ax;
+        const T r = bi - ax;
         y[i] = r;
         if (y32) y32[i] = (float)r;
         acc = (double)r * (double)r;
       } else {
-        y[i] = xi + s[i] * (b[i] - ax);
+        y[i] = xi + si * (bi - ax);
       }
     }
   }
@@ -93,42 +108,234 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
   }
 }
 
-// about four entries per lane
-inline int spmv_group(double avg_row) {
-  if (avg_row > 192) return 64;
-  if (avg_row > 48) return 16;
-  if (avg_row > 20) return 8;
-  return 4;
+// 16-byte chunks of four consecutive entries
+typedef float rt_f32x4 __attribute__((vector_size(16)));
+typedef double rt_f64x2 __attribute__((vector_size(16)));
+typedef unsigned short rt_u16x4 __attribute__((vector_size(8)));
+
+template <typename T>
+struct Chunk4;
+template <>
+struct Chunk4<float> {
+  rt_f32x4 v;
+  __device__ __forceinline__ void load(const float* p) {
+    v = stream_load(reinterpret_cast<const rt_f32x4*>(p));
+  }
+  __device__ __forceinline__ float operator[](int j) const { return v[j]; }
+};
+template <>
+struct Chunk4<double> {
+  rt_f64x2 lo, hi;
+  __device__ __forceinline__ void load(const double* p) {
+    lo = stream_load(reinterpret_cast<const rt_f64x2*>(p));
+    hi = stream_load(reinterpret_cast<const rt_f64x2*>(p + 2));
+  }
+  __device__ __forceinline__ double operator[](int j) const { return j < 2 ? lo[j] : hi[j - 2]; }
+};
+
+// sum over the entries of chunk kb..kb+3 that lie in [k0, k1)
+template <typename T>
+__device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int64_t kb, int64_t k0,
+                                       int64_t k1, const T* xs) {
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool in = kb + j >= k0 && kb + j < k1;
+    const T w = in ? v[j] : T(0);
+    s += w * xs[in ? (int)lc[j] : 0];
+  }
+  return s;
 }
 
-// Blocks (= partials written) of an SpMV over n rows with group size G.
-inline int spmv_blocks(int64_t n, int G) {
-  const int64_t rpb = kBlock / G;
-  const int64_t nblk = (n + rpb - 1) / rpb;
+// Tiled product: one block per tile of kTileRows rows (one row per thread for
+// the row data and the output).  The tile's distinct columns are staged from
+// x into LDS, then groups of G lanes walk the rows, UNR rows per group at a
+// time, each lane loading four consecutive entries (values and 16-bit local
+// columns) as one aligned chunk starting at (k0 & ~3); entries of the chunk
+// outside the row get weight zero.  Row sums go through LDS so that the
+// output and the dot-product terms are written by one thread per row.
+template <typename T, int G, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t* __restrict__ lcol,
+             const T* __restrict__ val, const T* __restrict__ diag,
+             const int64_t* __restrict__ toff, const int32_t* __restrict__ tcols,
+             const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ s,
+             T* __restrict__ y, float* __restrict__ y32, double* __restrict__ part) {
+  RT_DYNAMIC_LDS(dyn_lds);
+  T* xs = reinterpret_cast<T*>(dyn_lds);
+  __shared__ int64_t srp[kTileRows + 1];
+  __shared__ T sy[kTileRows];
+  __shared__ double red[kBlock / kWave];
+  constexpr int NG = kBlock / G;   // row groups per block
+  constexpr int UNR = 4;           // rows per group in flight
+  static_assert(kTileRows % (NG * UNR) == 0, "tile rows must split evenly over the groups");
+  const int t = xcd_block(per);
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)t * kTileRows;
+  const int64_t i = r0 + tid;
+  const bool live = i < n;   // grids are padded to a multiple of the XCD count
+  T di = 0, xi = 0, bi = 0, si = 0;
+  if (r0 < n) {
+    srp[tid] = rp[live ? i : n];
+    if (tid == 0) srp[kTileRows] = rp[r0 + kTileRows < n ? r0 + kTileRows : n];
+    if (live) {
+      di = diag[i];
+      xi = x[i];
+      if (MODE == SP_RESID || MODE == SP_SMOOTH) bi = b[i];
+      if (MODE == SP_SMOOTH) si = s[i];
+    }
+    const int64_t u0 = toff[t], u1 = toff[t + 1];
+    for (int64_t k = tid; k < u1 - u0; k += kBlock) xs[k] = x[tcols[u0 + k]];
+  } else {
+    srp[tid] = 0;
+    if (tid == 0) srp[kTileRows] = 0;
+  }
+  __syncthreads();
+  const int grp = tid / G, lane = tid & (G - 1);
+  for (int base = 0; base < kTileRows; base += NG * UNR) {
+    int64_t k0[UNR], k1[UNR], kb[UNR];
+    Chunk4<T> v[UNR];
+    rt_u16x4 lc[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int rr = base + u * NG + grp;
+      k0[u] = srp[rr];
+      k1[u] = srp[rr + 1];
+      kb[u] = (k0[u] & ~(int64_t)3) + 4 * lane;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if (kb[u] < k1[u]) {
+        v[u].load(val + kb[u]);
+        lc[u] = stream_load(reinterpret_cast<const rt_u16x4*>(lcol + kb[u]));
+      }
+    }
+    T sum[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      sum[u] = kb[u] < k1[u] ? chunk_dot<T>(v[u], lc[u], kb[u], k0[u], k1[u], xs) : T(0);
+    // rows longer than one pass of the group
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      for (int64_t kk = kb[u] + 4 * G; kk < k1[u]; kk += 4 * G) {
+        Chunk4<T> w;
+        w.load(val + kk);
+        const rt_u16x4 l2 = stream_load(reinterpret_cast<const rt_u16x4*>(lcol + kk));
+        sum[u] += chunk_dot<T>(w, l2, kk, k0[u], k1[u], xs);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const T r = group_sum<G>(sum[u]);
+      if (lane == 0) sy[base + u * NG + grp] = r;
+    }
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if (live) {
+    const T ax = di * xi + sy[tid];
+    if (MODE == SP_PLAIN) {
+      y[i] = ax;
+    } else if (MODE == SP_DOT) {
+      y[i] = ax;
+      acc = (double)xi * (double)ax;
+    } else if (MODE == SP_RESID) {
+      const T r = bi - ax;
+      y[i] = r;
+      if (y32) y32[i] = (float)r;
+      acc = (double)r * (double)r;
+    } else {
+      y[i] = xi + si * (bi - ax);
+    }
+  }
+  if (MODE == SP_DOT || MODE == SP_RESID) {
+    const double tsum = block_sum(acc, red);
+    if (tid == 0 && part) part[t] = tsum;
+  }
+}
+
+// Product shapes: plain ones (G lanes per row, E entries per lane, global x
+// gathers) and tiled ones (G lanes per row, four-entry chunks, x from LDS).
+struct SpmvShape {
+  int g, ent;
+  bool tiled;
+};
+constexpr SpmvShape kSpmvShapes[] = {{4, 4, false},  {4, 8, false},  {8, 8, false},
+                                     {8, 12, false}, {16, 6, false}, {32, 6, false},
+                                     {64, 4, false}, {4, 4, true},   {8, 4, true},
+                                     {16, 4, true},  {32, 4, true},  {64, 4, true}};
+constexpr int kNumSpmvShapes = sizeof(kSpmvShapes) / sizeof(kSpmvShapes[0]);
+constexpr int kFirstTiledShape = 7;
+
+// the smallest plain shape whose one pass covers the longest row (else the widest)
+inline int spmv_plain_shape_for(int64_t max_row) {
+  for (int s = 0; s < kFirstTiledShape; ++s)
+    if ((int64_t)kSpmvShapes[s].g * kSpmvShapes[s].ent >= max_row) return s;
+  return kFirstTiledShape - 1;
+}
+// the smallest tiled shape whose one pass covers the longest row at any chunk alignment
+inline int spmv_tiled_shape_for(int64_t max_row) {
+  for (int s = kFirstTiledShape; s < kNumSpmvShapes; ++s)
+    if (4 * (int64_t)kSpmvShapes[s].g - 3 >= max_row) return s;
+  return kNumSpmvShapes - 1;
+}
+// the shape a product over L runs with, given the requested one (-1: default)
+inline int spmv_effective_shape(const Level& L, int shape) {
+  if (shape >= 0 && shape < kNumSpmvShapes && (!kSpmvShapes[shape].tiled || L.tiled)) return shape;
+  return L.tiled ? spmv_tiled_shape_for(L.max_row) : spmv_plain_shape_for(L.max_row);
+}
+
+// Blocks (= partials written) of a product over n rows, rows_per_block rows
+// per block, padded to a multiple of the XCD count.
+inline int spmv_blocks_rows(int64_t n, int64_t rows_per_block) {
+  const int64_t nblk = (n + rows_per_block - 1) / rows_per_block;
   const int64_t per = (nblk + kXcd - 1) / kXcd;
   return (int)(per * kXcd);
 }
+inline int spmv_blocks(int64_t n, int G) { return spmv_blocks_rows(n, kBlock / G); }
 
-// Launch helper; *nparts receives the number of partials written.
+// Product over level L in the precision of T; *nparts receives the number of
+// partials written.  shape: index into kSpmvShapes, -1 = the level's default.
 template <typename T, int MODE>
-int launch_spmv(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
-                const T* val, const T* diag, const T* x, const T* b, const T* s, T* y,
-                float* y32, double* part, int* nparts) {
-  const int G = spmv_group(n ? (double)nnz / (double)n : 0.0);
-  const int grid = spmv_blocks(n, G);
+int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* diag, const T* x,
+                      const T* b, const T* s, T* y, float* y32, double* part, int* nparts,
+                      int shape = -1) {
+  const int64_t n = L.n;
+  shape = spmv_effective_shape(L, shape);
+  const SpmvShape sh = kSpmvShapes[shape];
+  const int grid = sh.tiled ? spmv_blocks_rows(n, kTileRows) : spmv_blocks(n, sh.g);
   const int per = grid / kXcd;
   if (nparts) *nparts = grid;
   if (n == 0) return RT_OK;
-#define RT_SPMV_G(G_)                                                                        \
-  hipLaunchKernelGGL((k_spmv<T, G_, MODE>), dim3(grid), dim3(kBlock), 0, st, n, per, rp, col, \
-                     val, diag, x, b, s, y, y32, part)
-  switch (G) {
-    case 64: RT_SPMV_G(64); break;
-    case 16: RT_SPMV_G(16); break;
-    case 8: RT_SPMV_G(8); break;
-    default: RT_SPMV_G(4); break;
+  if (sh.tiled) {
+    const size_t lds = sizeof(T) * (size_t)(L.max_tile_cols > 0 ? L.max_tile_cols : 1);
+#define RT_SPMV_T(G_)                                                                         \
+  hipLaunchKernelGGL((k_spmv_tiled<T, G_, MODE>), dim3(grid), dim3(kBlock), lds, st, n, per,  \
+                     L.rp.p, L.lcol.p, val, diag, L.tile_off.p, L.tile_cols.p, x, b, s, y, y32, \
+                     part)
+    switch (sh.g) {
+      case 4: RT_SPMV_T(4); break;
+      case 8: RT_SPMV_T(8); break;
+      case 16: RT_SPMV_T(16); break;
+      case 32: RT_SPMV_T(32); break;
+      default: RT_SPMV_T(64); break;
+    }
+#undef RT_SPMV_T
+  } else {
+#define RT_SPMV_S(G_, E_)                                                                       \
+  hipLaunchKernelGGL((k_spmv<T, G_, E_, MODE>), dim3(grid), dim3(kBlock), 0, st, n, per, L.rp.p, \
+                     L.col.p, val, diag, x, b, s, y, y32, part)
+    switch (shape) {
+      case 0: RT_SPMV_S(4, 4); break;
+      case 1: RT_SPMV_S(4, 8); break;
+      case 2: RT_SPMV_S(8, 8); break;
+      case 3: RT_SPMV_S(8, 12); break;
+      case 4: RT_SPMV_S(16, 6); break;
+      case 5: RT_SPMV_S(32, 6); break;
+      default: RT_SPMV_S(64, 4); break;
+    }
+#undef RT_SPMV_S
   }
-#undef RT_SPMV_G
   RT_LAUNCH_CHECK();
   return RT_OK;
 }

@@ -1,0 +1,194 @@
+// Tiled form of a CSR level for the LDS-staged sparse products.
+//
+// Rows are cut into tiles of kTileRows consecutive rows.  For each tile the
+// set of distinct columns its entries reference is found with an
+// open-addressing hash set in LDS, sorted (bitonic, in LDS) and written out
+// as the tile's column list; each entry's column is then replaced by its
+// 16-bit position in that list.  A product over a tile first loads
+// x[tile_cols] into LDS (one read per distinct column instead of one gather
+// per entry) and reads x from there.  Since particles are sorted by cell and
+// rows couple only neighbouring cells, a tile of 256 rows references about
+// one to two thousand distinct columns.  Built once per matrix structure;
+// the lists and lcol are deterministic (the hash only finds the set, the
+// sort fixes the order).
+#include <climits>
+#include <cstring>
+
+#include "internal.h"
+#include "prim.h"
+
+namespace rt {
+namespace {
+
+constexpr int kHashBits = 12;
+constexpr int kHash = 1 << kHashBits;   // slots; > kTileMaxCols + kBlock, so never full
+static_assert(kHash >= kTileMaxCols + kBlock, "hash set must have room for in-flight inserts");
+static_assert(kTileRows == kBlock, "one tile per block, one row per thread");
+
+__device__ __forceinline__ int hash_slot(int32_t c) {
+  return (int)(((uint32_t)c * 2654435761u) >> (32 - kHashBits));
+}
+
+// Insert the columns of entries [e0, e1) into keys (empty = -1); *count is the
+// number of distinct columns inserted; *overflow is set once it reaches
+// kTileMaxCols (then insertion stops: at most kBlock more can land).
+__device__ void tile_insert(int64_t e0, int64_t e1, const int32_t* __restrict__ col, int* keys,
+                            int* count, int* overflow) {
+  for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock) {
+    if (*(volatile int*)overflow) break;
+    const int c = col[k];
+    int s = hash_slot(c);
+    for (;;) {
+      const int cur = ((volatile int*)keys)[s];
+      if (cur == c) break;
+      if (cur == -1) {
+        const int prev = atomicCAS(&keys[s], -1, c);
+        if (prev == -1) {
+          if (atomicAdd(count, 1) + 1 >= kTileMaxCols) *(volatile int*)overflow = 1;
+          break;
+        }
+        if (prev == c) break;
+      }
+      s = (s + 1) & (kHash - 1);
+    }
+  }
+}
+
+__device__ __forceinline__ int tile_find(const int* keys, int c) {
+  int s = hash_slot(c);
+  while (keys[s] != c) s = (s + 1) & (kHash - 1);
+  return s;
+}
+
+__device__ __forceinline__ void tile_rows(int64_t n, int64_t t, const int64_t* rp, int64_t* e0,
+                                          int64_t* e1) {
+  const int64_t r0 = t * kTileRows;
+  const int64_t r1 = r0 + kTileRows < n ? r0 + kTileRows : n;
+  *e0 = rp[r0];
+  *e1 = rp[r1];
+}
+
+// distinct-column count of every tile; *flag = 1 if a tile overflows
+__global__ void __launch_bounds__(kBlock)
+k_tile_count(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+             int64_t* __restrict__ cnt, int* __restrict__ flag) {
+  __shared__ int keys[kHash];
+  __shared__ int count, overflow;
+  for (int s = threadIdx.x; s < kHash; s += kBlock) keys[s] = -1;
+  if (threadIdx.x == 0) {
+    count = 0;
+    overflow = 0;
+  }
+  __syncthreads();
+  int64_t e0, e1;
+  tile_rows(n, blockIdx.x, rp, &e0, &e1);
+  tile_insert(e0, e1, col, keys, &count, &overflow);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cnt[blockIdx.x] = overflow ? 0 : count;
+    if (overflow) flag[0] = 1;
+  }
+}
+
+// sorted distinct columns of every tile, and each entry's position among them
+__global__ void __launch_bounds__(kBlock)
+k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+            const int64_t* __restrict__ off, int32_t* __restrict__ tcols,
+            uint16_t* __restrict__ lcol) {
+  __shared__ int keys[kHash];
+  __shared__ int pos[kHash];
+  __shared__ int sorted[kHash];
+  __shared__ int count, overflow, packed;
+  for (int s = threadIdx.x; s < kHash; s += kBlock) keys[s] = -1;
+  if (threadIdx.x == 0) {
+    count = 0;
+    overflow = 0;
+    packed = 0;
+  }
+  __syncthreads();
+  int64_t e0, e1;
+  tile_rows(n, blockIdx.x, rp, &e0, &e1);
+  tile_insert(e0, e1, col, keys, &count, &overflow);
+  __syncthreads();
+  const int m = count;   // the count pass saw no overflow, so this is the full set
+  int p2 = 1;
+  while (p2 < m) p2 <<= 1;
+  for (int s = threadIdx.x; s < kHash; s += kBlock)
+    if (keys[s] != -1) sorted[atomicAdd(&packed, 1)] = keys[s];
+  __syncthreads();
+  for (int s = m + threadIdx.x; s < p2; s += kBlock) sorted[s] = INT_MAX;
+  __syncthreads();
+  // bitonic sort of sorted[0, p2), ascending
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < p2; i += kBlock) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int a = sorted[i], b = sorted[l];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            sorted[i] = b;
+            sorted[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int64_t o = off[blockIdx.x];
+  for (int q = threadIdx.x; q < m; q += kBlock) {
+    const int c = sorted[q];
+    tcols[o + q] = c;
+    pos[tile_find(keys, c)] = q;
+  }
+  __syncthreads();
+  for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock)
+    lcol[k] = (uint16_t)pos[tile_find(keys, col[k])];
+}
+
+}  // namespace
+
+int build_tiles(rt_ctx* ctx, Level& L) {
+  hipStream_t st = ctx->stream;
+  L.tiled = false;
+  L.ntiles = 0;
+  L.tile_cols_total = 0;
+  L.max_tile_cols = 0;
+  const int64_t n = L.n;
+  if (n == 0) return RT_OK;
+  const int64_t nt = (n + kTileRows - 1) / kTileRows;
+  if (nt > INT_MAX) return RT_OK;
+  DevBuf<int64_t> cnt;
+  DevBuf<int> flag;
+  RT_CHECK(cnt.reserve(nt + 1));
+  RT_CHECK(flag.reserve(1));
+  RT_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  RT_CHECK_HIP(hipMemsetAsync(cnt.p + nt, 0, sizeof(int64_t), st));
+  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nt), dim3(kBlock), 0, st, n, L.rp.p, L.col.p,
+                     cnt.p, flag.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(ctx->sync_read(flag.p, sizeof(int)));
+  int overflow = 0;
+  std::memcpy(&overflow, ctx->host, sizeof(int));
+  if (overflow) return RT_OK;
+  int64_t maxc = 0;
+  RT_CHECK(max_nonneg<int64_t>(ctx, cnt.p, nt, &maxc));
+  RT_CHECK(L.tile_off.reserve(nt + 1));
+  RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, L.tile_off.p, nt + 1, false)));
+  RT_CHECK(ctx->sync_read(L.tile_off.p + nt, sizeof(int64_t)));
+  int64_t total = 0;
+  std::memcpy(&total, ctx->host, sizeof(int64_t));
+  RT_CHECK(L.tile_cols.reserve(total));
+  RT_CHECK(L.lcol.reserve(L.nnz + kSpmvPad));
+  RT_CHECK_HIP(hipMemsetAsync(L.lcol.p + L.nnz, 0, sizeof(uint16_t) * kSpmvPad, st));
+  hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(kBlock), 0, st, n, L.rp.p, L.col.p,
+                     L.tile_off.p, L.tile_cols.p, L.lcol.p);
+  RT_LAUNCH_CHECK();
+  L.tiled = true;
+  L.ntiles = nt;
+  L.tile_cols_total = total;
+  L.max_tile_cols = (int)maxc;
+  return RT_OK;
+}
+
+}  // namespace rt

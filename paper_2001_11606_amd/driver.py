@@ -64,11 +64,19 @@ class StepReport:
 def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
               amg: Optional[rt.rt_amg_opts] = None, solve: Optional[rt.rt_solve_opts] = None,
               eps_e: float = 1e-8, eps_E: float = 1e-8, material_tol: float = 1e-14,
-              max_outer: int = 50, fixed_outer: Optional[int] = None):
+              max_outer: int = 50, fixed_outer: Optional[int] = None,
+              shapes: Optional[list] = None):
     """One backward-Euler step.  Returns (e, E, A, report) with e, E the new
-    interior energies (device tensors, user order)."""
+    interior energies (device tensors, user order).  shapes: per-level
+    (FP64, FP32) SpMV shape indices, e.g. the "chosen" list of Context.tune on
+    an earlier matrix of the same problem, applied after assembly."""
     A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                      dp.limiter_k, amg=amg, A=A)
+    if shapes:
+        levels = ctx.matrix_info(A).levels
+        for lvl, (s64, s32) in enumerate(shapes[:levels]):
+            rt.rt_matrix_set_spmv_shape(A, lvl, rt.RT_PREC_FP64, s64)
+            rt.rt_matrix_set_spmv_shape(A, lvl, rt.RT_PREC_MIXED, s32)
     nin = dp.n_interior
     e = dp.arrays["e"][:nin].clone()
     E = dp.arrays["E"][:nin].clone()

@@ -55,12 +55,13 @@ class rt_step_inputs(ctypes.Structure):
 
 class rt_amg_opts(ctypes.Structure):
     _fields_ = [("max_levels", c_int), ("coarse_size", c_int), ("strength", c_dbl),
-                ("build_fp32", c_int)]
+                ("build_fp32", c_int), ("tiled_spmv", c_int)]
 
 
 class rt_matrix_info(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("levels", c_int),
-                ("level_n", c_i64 * 16), ("level_nnz", c_i64 * 16)]
+                ("level_n", c_i64 * 16), ("level_nnz", c_i64 * 16),
+                ("level_tile_cols", c_i64 * 16)]
 
 
 class rt_solve_opts(ctypes.Structure):
@@ -84,6 +85,16 @@ class rt_newton_stats(ctypes.Structure):
                 ("seconds", c_dbl)]
 
 
+RT_MAX_LEVELS = 16
+RT_MAX_SHAPES = 16
+
+
+class rt_tune_report(ctypes.Structure):
+    _fields_ = [("levels", c_int), ("shapes", c_int),
+                ("us", ((c_dbl * RT_MAX_SHAPES) * 2) * RT_MAX_LEVELS),
+                ("chosen", (c_int * 2) * RT_MAX_LEVELS)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "rt_create": (c_int, [ctypes.POINTER(c_vp), c_int, c_vp]),
@@ -103,6 +114,10 @@ _SIGS = {
     "rt_matrix_get_info": (c_int, [c_vp, ctypes.POINTER(rt_matrix_info)]),
     "rt_matrix_export": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "rt_matrix_free": (None, [c_vp]),
+    "rt_spmv_shapes": (c_int, [ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                               ctypes.POINTER(c_int), c_int]),
+    "rt_matrix_tune": (c_int, [c_vp, c_vp, c_int, ctypes.POINTER(rt_tune_report)]),
+    "rt_matrix_set_spmv_shape": (c_int, [c_vp, c_int, c_int, c_int]),
     "rt_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
                          ctypes.POINTER(rt_solve_stats)]),
     "rt_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
@@ -217,6 +232,25 @@ def rt_matrix_free(A: int) -> None:
     load().rt_matrix_free(A)
 
 
+def rt_spmv_shapes() -> list:
+    """[(G lanes per row, E entries per lane, tiled)] for every product shape."""
+    g = (c_int * RT_MAX_SHAPES)()
+    e = (c_int * RT_MAX_SHAPES)()
+    t = (c_int * RT_MAX_SHAPES)()
+    n = load().rt_spmv_shapes(g, e, t, RT_MAX_SHAPES)
+    return [(g[i], e[i], bool(t[i])) for i in range(min(n, RT_MAX_SHAPES))]
+
+
+def rt_matrix_tune(ctx: int, A: int, reps: int) -> rt_tune_report:
+    rep = rt_tune_report()
+    _check("rt_matrix_tune", load().rt_matrix_tune(ctx, A, reps, ctypes.byref(rep)))
+    return rep
+
+
+def rt_matrix_set_spmv_shape(A: int, level: int, precision: int, shape: int) -> None:
+    _check("rt_matrix_set_spmv_shape", load().rt_matrix_set_spmv_shape(A, level, precision, shape))
+
+
 def rt_solve(ctx: int, A: int, b: int, x: int, opts: rt_solve_opts) -> tuple:
     st = rt_solve_stats()
     s = _check("rt_solve", load().rt_solve(ctx, A, b, x, ctypes.byref(opts), ctypes.byref(st)))
@@ -252,8 +286,9 @@ def solve_opts(precision=RT_PREC_FP64, precond=PRECOND_JACOBI, tol=1e-10, max_it
     return rt_solve_opts(precision, precond, tol, max_iter, inner_tol, max_refine)
 
 
-def amg_opts(max_levels=8, coarse_size=256, strength=0.08, build_fp32=1) -> rt_amg_opts:
-    return rt_amg_opts(max_levels, coarse_size, strength, build_fp32)
+def amg_opts(max_levels=8, coarse_size=256, strength=0.08, build_fp32=1,
+             tiled_spmv=1) -> rt_amg_opts:
+    return rt_amg_opts(max_levels, coarse_size, strength, build_fp32, tiled_spmv)
 
 
 def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100) -> rt_newton_opts:
@@ -341,6 +376,16 @@ class Context:
         g = torch.empty(max(info.n, 1), dtype=torch.float64, device=self.device)
         rt_matrix_export(self.handle, A, rp.data_ptr(), col.data_ptr(), val.data_ptr(), g.data_ptr())
         return rp, col[:info.nnz], val[:info.nnz], g[:info.n]
+
+    def tune(self, A: int, reps: int = 5) -> dict:
+        """Time every SpMV shape on every level; keeps the fastest per level and
+        precision.  Returns {"shapes": [(G, E)], "us": [[fp64 list, fp32 list]],
+        "chosen": [[fp64, fp32]]}."""
+        rep = rt_matrix_tune(self.handle, A, reps)
+        return {"shapes": rt_spmv_shapes()[:rep.shapes],
+                "us": [[list(rep.us[l][p][:rep.shapes]) for p in range(2)]
+                       for l in range(rep.levels)],
+                "chosen": [[rep.chosen[l][0], rep.chosen[l][1]] for l in range(rep.levels)]}
 
     def solve(self, A: int, b, x, opts: rt_solve_opts):
         torch = self.torch

@@ -5,6 +5,7 @@ indexing can be checked against real allocation bounds on the host.
 Test infrastructure: the product library is built by paper_2001_11606_amd/build.py.
 """
 import os
+import sys
 import subprocess
 import concurrent.futures as cf
 
@@ -13,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2001_11606_amd", "csrc")
 OUT_DIR = os.path.join(ROOT, "_build", "cpu_hip")
 LIB = os.path.join(OUT_DIR, "librt_cpu.so")
-SOURCES = ["context.hip", "prim.hip", "neighbors.hip", "assemble.hip", "amg.hip", "solve.hip", "newton.hip"]
+sys.path.insert(0, ROOT)
+from paper_2001_11606_amd.build import SOURCES  # noqa: E402  (the same source list as the HIP build)
 FLAGS = ["-x", "c++", "-std=c++20", "-O1", "-g", "-fPIC", "-fno-omit-frame-pointer",
          "-fsanitize=address", "-ffp-contract=off", "-pthread", "-w",
          # always take the two-level reduction path, which large GPU runs use

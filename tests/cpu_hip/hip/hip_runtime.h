@@ -37,6 +37,8 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define __builtin_nontemporal_load(p) (*(p))
+// dynamic LDS: a heap buffer of the launch's byte count (bounds seen by ASan)
+#define RT_DYNAMIC_LDS(name) unsigned char* name = cpuhip::g_dyn_lds
 
 struct dim3 {
   unsigned x, y, z;
@@ -56,6 +58,7 @@ struct ThreadCtx {
   dim3 tid, bid, bdim, gdim;
 };
 inline thread_local ThreadCtx tctx;
+inline unsigned char* g_dyn_lds = nullptr;
 
 struct BlockState {
   int nthreads = 0;
@@ -134,7 +137,7 @@ class Pool {
 };
 
 template <typename F>
-void launch(dim3 grid, dim3 block, F&& f) {
+void launch(dim3 grid, dim3 block, F&& f, size_t shmem = 0) {
   const int nt = (int)(block.x * block.y * block.z);
   if (nt <= 0 || nt > 1024) {
     fprintf(stderr, "cpuhip: invalid block size %d\n", nt);
@@ -144,6 +147,9 @@ void launch(dim3 grid, dim3 block, F&& f) {
     for (unsigned by = 0; by < grid.y; ++by)
       for (unsigned bx = 0; bx < grid.x; ++bx) {
         g_block.reset(nt);
+        std::unique_ptr<unsigned char[]> dyn(shmem ? new unsigned char[shmem] : nullptr);
+        if (shmem) memset(dyn.get(), 0xBE, shmem);
+        g_dyn_lds = dyn.get();
         std::function<void(int)> body = [&](int t) {
           tctx.tid = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
           tctx.bid = dim3(bx, by, bz);
@@ -166,6 +172,11 @@ void launch(dim3 grid, dim3 block, F&& f) {
 #define gridDim (cpuhip::tctx.gdim)
 
 inline void __syncthreads() { cpuhip::g_block.block_bar->arrive_and_wait(); }
+inline int atomicCAS(int* p, int cmp, int v) {
+  std::atomic_ref<int>(*p).compare_exchange_strong(cmp, v);
+  return cmp;
+}
+inline int atomicAdd(int* p, int v) { return std::atomic_ref<int>(*p).fetch_add(v); }
 inline void __threadfence() {}
 
 template <typename T>
@@ -189,8 +200,8 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
 template <typename... KArgs, typename... Args>
 inline void hipLaunchKernelGGL(void (*k)(KArgs...), dim3 grid, dim3 block, size_t shmem,
                                hipStream_t, Args... args) {
-  (void)shmem;
-  cpuhip::launch(grid, block, [&] { k(args...); });
+  // a fresh dynamic-LDS buffer per block, sized exactly as requested
+  cpuhip::launch(grid, block, [&] { k(args...); }, shmem);
 }
 
 // ---- runtime API -------------------------------------------------------------

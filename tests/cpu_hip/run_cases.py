@@ -93,6 +93,26 @@ def check_case(ctx, name, prob):
         s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50))
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: solve prec={prec} precond={precond} err={e} its={st.iterations}"
+    # every SpMV shape (forced on all levels), then the autotuner's choice
+    nshapes = len(rt.rt_spmv_shapes())
+    sweep = range(nshapes) if name in ("marshak3d_8", "mms2d_16") else (0, 7, nshapes - 1)
+    # (the widest shapes are slow to emulate: every shuffle is a thread barrier here)
+    for shape in (sweep if not QUICK else (0, 7)):
+        for lvl in range(info.levels):
+            for prec in (0, 1):
+                rt.rt_matrix_set_spmv_shape(c.A, lvl, prec, shape)
+        for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
+            x = np.zeros(nin)
+            s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(prec, 1, tol, 3000, 1e-4, 50))
+            e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+            assert s == 0 and e <= bar, f"{name}: shape {shape} prec={prec} err={e}"
+    if not QUICK:
+        rep = rt.rt_matrix_tune(ctx, c.A, 1)
+        assert rep.levels == info.levels and rep.shapes == nshapes, f"{name}: tune report"
+    x = np.zeros(nin)
+    s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(1, 1, 1e-12, 3000, 1e-4, 50))
+    e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+    assert s == 0 and e <= 1e-10, f"{name}: tuned solve err={e}"
     # Algorithm 1, three outer iterations, FP64 + AMG
     n_outer = 1 if QUICK else 3
     ref = ostep.time_step(prob.copy(), fixed_outer=n_outer, solve_tol=1e-15)
