@@ -43,12 +43,13 @@ def make_problem(workload: str, n: int):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def run_step(ctx, dp, precision, precond, outer, tol, amg, shapes=None):
+def run_step(ctx, dp, precision, precond, outer, tol, amg, shapes=None, inner_tol=1e-4):
     """One pass of the whole hot path; returns (e, E, A, report, nb)."""
     from paper_2001_11606_amd import driver, rt
     nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
     e, E, A, rep = driver.time_step(ctx, dp, nb, amg=amg,
-                                    solve=rt.solve_opts(precision, precond, tol, 5000, 1e-4, 30),
+                                    solve=rt.solve_opts(precision, precond, tol, 5000, inner_tol,
+                                                        30),
                                     fixed_outer=outer, shapes=shapes)
     return e, E, A, rep, nb
 
@@ -58,6 +59,42 @@ def release(ctx, nb, A):
     rt.rt_matrix_free(A)
     rt.rt_neighbors_free(nb.handle)
     ctx._owned = [o for o in ctx._owned if o[1] not in (A, nb.handle)]
+
+
+def spmv_bytes(vbytes: int, nnz_off: int, n: int, tile_cols: int) -> float:
+    """Algorithmic bytes of one Krylov-loop product y = A x (values in vbytes
+    bytes): off-diagonal values and column indices (16-bit tile-local ones
+    plus the tiles' 32-bit column lists when tiled, else 32-bit), the row
+    pointers (8 B), diagonal, x read once and y written once."""
+    if tile_cols:
+        idx = 2.0 * nnz_off + 4.0 * tile_cols
+    else:
+        idx = 4.0 * nnz_off
+    return vbytes * nnz_off + idx + 8.0 * (n + 1) + 3.0 * vbytes * n
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "k_spmv_tiled_marshak3d_16.8M_counters.md")
+
+
+def profiled_traffic(workload: str, n: int, kernel: str):
+    """HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE,
+    each scaled by its reading for a plain copy of known size) from the
+    committed counter summary -- only for the workload it was taken on, the
+    same kernel instance, and while the kernel source is unchanged (hash).
+    Returns (traffic, request-count estimate) or (None, None)."""
+    import hashlib
+    if workload != "marshak3d" or n != 256 or not os.path.exists(COUNTERS):
+        return None, None
+    vals = {}
+    for line in open(COUNTERS):
+        k, _, v = line.strip().partition(": ")
+        if v:
+            vals[k] = v
+    src = os.path.join(ROOT, "paper_2001_11606_amd", "csrc", "spmv.h")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("spmv_source_sha256") != sha or vals.get("traffic_kernel") != kernel:
+        return None, None
+    return float(vals["traffic_bytes_per_launch"]), float(vals["traffic_rdreq128_bytes_per_launch"])
 
 
 def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
@@ -106,6 +143,8 @@ def main():
     ap.add_argument("--outer", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--precond", type=int, default=0, help="0 Jacobi, 1 AMG V-cycle")
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="relative reduction asked of each FP32 inner solve")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=64)
@@ -139,7 +178,8 @@ def main():
 
     def one(precision, profile=False):
         ctx.set_profiling(profile)
-        out = run_step(ctx, dp, precision, args.precond, args.outer, args.tol, amg, shapes)
+        out = run_step(ctx, dp, precision, args.precond, args.outer, args.tol, amg, shapes,
+                       args.inner_tol)
         ctx.set_profiling(False)
         return out
 
@@ -177,18 +217,25 @@ def main():
     # SpMV roofline (FP32 inner SpMV, the operator of the mixed solve)
     n_rows = info.n
     nnz_off = info.nnz - info.n
+    tile_cols = info.level_tile_cols[0]
+    shape32 = tune["shapes"][shapes[0][1]] if shapes else None
+    tiled32 = bool(tile_cols) and (shape32 is None or shape32[2])
     calls32 = sum(r.spmv32_calls for r in reps)
     sec32 = sum(r.spmv32_seconds for r in reps)
-    bytes32 = 8.0 * nnz_off + 20.0 * n_rows
+    bytes32 = spmv_bytes(4, nnz_off, n_rows, tile_cols if tiled32 else 0)
     roof = None
     if calls32:
         achieved = bytes32 / (sec32 / calls32) / 1e9
+        kname = (("k_spmv_tiled<float, %d, %d, SP_DOT>" % (shape32[0], shape32[1]))
+                 if tiled32 and shape32 else "k_spmv<float> (plain CSR)")
+        traffic, traffic_req = profiled_traffic(args.workload, args.n, kname)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "traffic_rdreq128": traffic_req,
                 "stream_copy_gbs": round(copy_gbs, 1),
-                "kernel": "k_spmv<float> (FP32 CSR SpMV inside the inner PCG)",
+                "kernel": kname,
                 "bytes_per_launch": bytes32, "avg_launch_us": round(1e6 * sec32 / calls32, 2),
-                "launches": calls32}
+                "launches": calls32, "tile_cols": tile_cols}
     solve_mixed = sum(r.solve_seconds for r in reps) / len(reps)
     release(ctx, nb, A)
 
@@ -199,7 +246,9 @@ def main():
         torch.cuda.synchronize()
         err_E = float(((E64 - E).abs() / E64.abs()).max())
         err_e = float(((e64 - e).abs() / e64.abs()).max())
-        bytes64 = 12.0 * nnz_off + 32.0 * n_rows
+        shape64 = tune["shapes"][shapes[0][0]] if shapes else None
+        tiled64 = bool(tile_cols) and (shape64 is None or shape64[2])
+        bytes64 = spmv_bytes(8, nnz_off, n_rows, tile_cols if tiled64 else 0)
         cmp = {"solve_s_mixed": round(solve_mixed, 5), "solve_s_fp64": round(rep64.solve_seconds, 5),
                "ratio_fp64_over_mixed": round(rep64.solve_seconds / max(solve_mixed, 1e-12), 3),
                "krylov_mixed": reps[-1].krylov, "krylov_fp64": rep64.krylov,
@@ -225,7 +274,8 @@ def main():
     t3 = time.perf_counter()
     eb = dp.arrays["e"][:nin].clone()
     Eb = dp.arrays["E"][:nin].clone()
-    nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, args.precond, args.tol, 5000, 1e-4, 30))
+    nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, args.precond, args.tol, 5000,
+                                         args.inner_tol, 30))
     solve_b = 0.0
     for ell in range(args.outer):
         _, stb = ctx.newton_step(Ab, eb, Eb, ell, nopts)
@@ -250,7 +300,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {args.n}^3 ({nin} particles, {prob.n_ghost} ghosts), "
                                f"1 step dt={prob.dt}, {args.outer} outer iterations, "
-                               f"mixed FP32/FP64 to {args.tol:g}",
+                               f"mixed FP32/FP64 to {args.tol:g} (inner {args.inner_tol:g})",
                    "particles": nin, "nnz": info.nnz, "amg_levels": info.levels,
                    "precond": "amg" if args.precond == 1 else "jacobi"},
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp, "phases": phases,

@@ -186,9 +186,11 @@ void rt_matrix_free(rt_matrix* A);
 /* ---- SpMV shape tuning (not in the paper; a property of this library) -----
  * Every sparse product y = A x over a level runs with a row-group shape: G
  * lanes per row, each holding E entries, so that one pass covers G*E entries
- * of a row.  Tiled shapes (tiled = 1) use the level's tiled form: E = 4
- * consecutive entries per lane loaded as one 16-byte chunk, x read from LDS;
- * a level without a tiled form runs its default plain shape instead.
+ * of a row.  Tiled shapes (tiled = 1) use the level's tiled form: each lane
+ * loads four consecutive entries as one 16-byte chunk (a pass covers 4*G
+ * entries), x is read from LDS, and E is the number of rows a lane group
+ * keeps in flight; a level without a tiled form runs its default plain shape
+ * instead.
  * rt_spmv_shapes writes the (G, E, tiled) of up to max shapes (any pointer
  * may be NULL) and returns how many exist.  rt_matrix_tune times the Krylov-loop product on every
  * level of A with every shape, in FP64 and, when A holds FP32 copies, FP32:

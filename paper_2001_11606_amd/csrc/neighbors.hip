@@ -8,9 +8,14 @@
 //    blocks of cells contiguous at every level of the aggregation hierarchy);
 //    gather sorted positions and smoothing lengths (SoA);
 // 4. table of [start, end) per (flag, row-major cell index);
-// 5. count pass, scan, fill pass: one thread per sorted particle tests the
-//    candidates of the 3^dim adjacent cells, interior cells first, so the
-//    interior neighbours of every row form a prefix of the row.
+// 5. list of occupied cells (runs of equal keys);
+// 6. count pass, scan, fill pass: one block per occupied cell stages the
+//    candidates of the 3^dim adjacent cells (interior cells first, then ghost
+//    cells; cells in z, y, x order; ascending index within a cell) in LDS,
+//    and each wave tests one row of the cell against 64 candidates at a time,
+//    compacting the hits with a ballot so that a row's neighbours are written
+//    as contiguous runs.  The candidate order makes the interior neighbours of
+//    every row a prefix of the row.
 //
 // The predicate r^2 < (kappa * max(h_i, h_j))^2 is evaluated in FP64 with
 // r^2 accumulated in axis order and contraction to FMA disabled, so that it
@@ -21,6 +26,7 @@
 
 #include "internal.h"
 #include "prim.h"
+#include "reduce.h"
 
 #pragma clang fp contract(off)
 
@@ -147,61 +153,138 @@ k_cell_table(int bits, int64_t n, int nc0, int nc1, int64_t ncells,
   if (last) cend[t] = (int32_t)(s + 1);
 }
 
-template <int DIM, bool FILL>
-__global__ void __launch_bounds__(kBlock)
-k_nbr_pass(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
-           double kappa, const uint64_t* __restrict__ skeys, const double* __restrict__ spos,
-           const double* __restrict__ sh, const int32_t* __restrict__ cstart,
-           const int32_t* __restrict__ cend, int64_t* __restrict__ cnt,
-           const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
-           int32_t* __restrict__ n_int_nbrs) {
+// first sorted position of every run of equal keys; runs[nruns] = n
+__global__ void k_run_flags(int64_t n, const uint64_t* __restrict__ skeys,
+                            int32_t* __restrict__ flags) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s < n) flags[s] = (s == 0 || skeys[s] != skeys[s - 1]) ? 1 : 0;
+}
+
+__global__ void k_run_starts(int64_t n, const int32_t* __restrict__ flags,
+                             const int32_t* __restrict__ rid, int32_t* __restrict__ runs) {
   int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
-  int c[3];
-  demorton<DIM>(bits, skeys[s] & mask, c);
-  const double xi = spos[s];
-  const double yi = spos[n + s];
-  const double zi = DIM == 3 ? spos[2 * n + s] : 0.0;
-  const double hi = sh[s];
-  int64_t count = 0;
-  int64_t out = FILL ? ptr[s] : 0;
-  int32_t interior_count = 0;
-  for (int flag = 0; flag < 2; ++flag) {
-    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-      const int z = c[2] + oz;
-      if (z < 0 || z >= nc2) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int y = c[1] + oy;
-        if (y < 0 || y >= nc1) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int x = c[0] + ox;
-          if (x < 0 || x >= nc0) continue;
-          const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
-          const int32_t t1 = cend[cell];
-          for (int32_t t = cstart[cell]; t < t1; ++t) {
-            if (t == s) continue;
-            double d = xi - spos[t];
-            double r2 = d * d;
-            d = yi - spos[n + t];
-            r2 = r2 + d * d;
-            if (DIM == 3) {
-              d = zi - spos[2 * n + t];
+  if (flags[s]) runs[rid[s] - 1] = (int32_t)s;
+  if (s == n - 1) runs[rid[s]] = (int32_t)n;
+}
+
+constexpr int kNbrCand = 512;   // candidates staged in LDS per pass
+constexpr int kNbrRows = 512;   // rows of one cell handled per pass
+
+template <int DIM, bool FILL>
+__global__ void __launch_bounds__(kBlock)
+k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
+            double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ skeys,
+            const double* __restrict__ spos, const double* __restrict__ sh,
+            const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend,
+            int64_t* __restrict__ cnt, const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
+            int32_t* __restrict__ n_int_nbrs) {
+  constexpr int NB = DIM == 3 ? 27 : 9;   // adjacent cells per flag
+  __shared__ double cx[kNbrCand], cy[kNbrCand], cz[kNbrCand], ch[kNbrCand];
+  __shared__ int32_t ct[kNbrCand];
+  __shared__ int32_t rlo[2 * NB], roff[2 * NB + 1];
+  __shared__ int32_t rcount[kNbrRows], rint[kNbrRows];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave, lane = tid & (kWave - 1);
+  const int64_t r0 = runs[blockIdx.x], r1 = runs[blockIdx.x + 1];
+  // candidate ranges: slot = flag * NB + (z, y, x offset), empty when outside the grid
+  if (tid < 2 * NB) {
+    const uint64_t key = skeys[r0];
+    const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
+    int c[3];
+    demorton<DIM>(bits, key & mask, c);
+    const int flag = tid / NB, o = tid % NB;
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
+    const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
+    int32_t lo = 0, len = 0;
+    if (x >= 0 && x < nc0 && y >= 0 && y < nc1 && z >= 0 && z < nc2) {
+      const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
+      lo = cstart[cell];
+      len = cend[cell] - lo;
+    }
+    rlo[tid] = lo;
+    roff[tid + 1] = len;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    roff[0] = 0;
+    for (int q = 1; q <= 2 * NB; ++q) roff[q] += roff[q - 1];
+  }
+  __syncthreads();
+  const int m = roff[2 * NB];
+  for (int64_t rb = r0; rb < r1; rb += kNbrRows) {
+    const int nrows = (int)(r1 - rb < kNbrRows ? r1 - rb : kNbrRows);
+    for (int r = tid; r < nrows; r += kBlock) {
+      rcount[r] = 0;
+      rint[r] = 0;
+    }
+    for (int c0 = 0; c0 < m; c0 += kNbrCand) {
+      const int mc = m - c0 < kNbrCand ? m - c0 : kNbrCand;
+      __syncthreads();   // the previous chunk is consumed, row counters are set
+      for (int k = tid; k < mc; k += kBlock) {
+        const int kk = c0 + k;
+        int lo = 0, hi = 2 * NB;   // roff[lo] <= kk < roff[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (roff[mid] <= kk) lo = mid;
+          else hi = mid;
+        }
+        const int32_t t = rlo[lo] + (kk - roff[lo]);
+        ct[k] = t;
+        cx[k] = spos[t];
+        cy[k] = spos[n + t];
+        cz[k] = DIM == 3 ? spos[2 * n + t] : 0.0;
+        ch[k] = sh[t];
+      }
+      __syncthreads();
+      for (int r = wave; r < nrows; r += kBlock / kWave) {
+        const int64_t s = rb + r;
+        const double xi = spos[s], yi = spos[n + s];
+        const double zi = DIM == 3 ? spos[2 * n + s] : 0.0;
+        const double hi = sh[s];
+        int found = 0, fint = 0;
+        int64_t out = FILL ? ptr[s] + rcount[r] : 0;
+        for (int k = lane; k - lane < mc; k += kWave) {
+          bool hit = false;
+          int32_t t = -1;
+          if (k < mc) {
+            t = ct[k];
+            if (t != s) {
+              double d = xi - cx[k];
+              double r2 = d * d;
+              d = yi - cy[k];
               r2 = r2 + d * d;
-            }
-            const double th = kappa * fmax(hi, sh[t]);
-            if (r2 < th * th) {
-              if (FILL) idx[out++] = t;
-              else ++count;
-              if (t < nin) ++interior_count;
+              if (DIM == 3) {
+                d = zi - cz[k];
+                r2 = r2 + d * d;
+              }
+              const double th = kappa * fmax(hi, ch[k]);
+              hit = r2 < th * th;
             }
           }
+          const unsigned long long bm = __ballot(hit);
+          const unsigned long long bi = __ballot(hit && t < nin);
+          if (FILL && hit) {
+            const unsigned long long below = lane ? (bm & (~0ull >> (kWave - lane))) : 0ull;
+            idx[out + __popcll(below)] = t;
+          }
+          out += __popcll(bm);
+          found += __popcll(bm);
+          fint += __popcll(bi);
+        }
+        if (lane == 0) {
+          rcount[r] += found;
+          rint[r] += fint;
         }
       }
     }
+    __syncthreads();
+    for (int r = tid; r < nrows; r += kBlock) {
+      if (!FILL) cnt[rb + r] = rcount[r];
+      else n_int_nbrs[rb + r] = rint[r];
+    }
+    __syncthreads();
   }
-  if (!FILL) cnt[s] = count;
-  else n_int_nbrs[s] = interior_count;
 }
 
 // user-order export: scatter mapped rows, then sort each row
@@ -338,16 +421,31 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
                        nb->nc[0], nb->nc[1], ncells, nb->skeys.p, cstart.p, cend.p);
   RT_LAUNCH_CHECK();
 
-  // 5. count, scan, fill
+  // 5. occupied cells
+  DevBuf<int32_t> rflag, rid, runs;
+  RT_CHECK(rflag.reserve(n));
+  RT_CHECK(rid.reserve(n));
+  hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nb->skeys.p, rflag.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((scan<int32_t, int32_t>(ctx, rflag.p, rid.p, n, true)));
+  RT_CHECK(ctx->sync_read(rid.p + n - 1, sizeof(int32_t)));
+  int32_t nruns = 0;
+  std::memcpy(&nruns, ctx->host, sizeof(int32_t));
+  RT_CHECK(runs.reserve((size_t)nruns + 1));
+  hipLaunchKernelGGL(k_run_starts, dim3(grid_for(n)), dim3(kBlock), 0, st, n, rflag.p, rid.p,
+                     runs.p);
+  RT_LAUNCH_CHECK();
+
+  // 6. count, scan, fill
   DevBuf<int64_t> cnt;
   RT_CHECK(cnt.reserve(n + 1));
   RT_CHECK(nb->ptr.reserve(n + 1));
   RT_CHECK(nb->n_int_nbrs.reserve(n));
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int64_t), st));
-#define RT_NBR(D_, F_)                                                                         \
-  hipLaunchKernelGGL((k_nbr_pass<D_, F_>), dim3(grid_for(n)), dim3(kBlock), 0, st, n, nin, bits, \
-                     ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, nb->skeys.p,           \
-                     nb->spos.p, nb->sh.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p,       \
+#define RT_NBR(D_, F_)                                                                          \
+  hipLaunchKernelGGL((k_nbr_cells<D_, F_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits,      \
+                     ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, runs.p, nb->skeys.p,    \
+                     nb->spos.p, nb->sh.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p,        \
                      nb->n_int_nbrs.p)
   if (dim == 3) RT_NBR(3, false);
   else RT_NBR(2, false);

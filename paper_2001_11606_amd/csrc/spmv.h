@@ -135,8 +135,8 @@ struct Chunk4<double> {
 
 // sum over the entries of chunk kb..kb+3 that lie in [k0, k1)
 template <typename T>
-__device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int64_t kb, int64_t k0,
-                                       int64_t k1, const T* xs) {
+__device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int kb, int k0, int k1,
+                                       const T* xs) {
   T s = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -150,11 +150,11 @@ __device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int64_t 
 // Tiled product: one block per tile of kTileRows rows (one row per thread for
 // the row data and the output).  The tile's distinct columns are staged from
 // x into LDS, then groups of G lanes walk the rows, UNR rows per group at a
-// time, each lane loading four consecutive entries (values and 16-bit local
+// time (their loads all in flight together), each lane loading four consecutive entries (values and 16-bit local
 // columns) as one aligned chunk starting at (k0 & ~3); entries of the chunk
 // outside the row get weight zero.  Row sums go through LDS so that the
 // output and the dot-product terms are written by one thread per row.
-template <typename T, int G, int MODE>
+template <typename T, int G, int UNR, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t* __restrict__ lcol,
              const T* __restrict__ val, const T* __restrict__ diag,
@@ -163,11 +163,11 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
              T* __restrict__ y, float* __restrict__ y32, double* __restrict__ part) {
   RT_DYNAMIC_LDS(dyn_lds);
   T* xs = reinterpret_cast<T*>(dyn_lds);
-  __shared__ int64_t srp[kTileRows + 1];
+  __shared__ int srp[kTileRows + 1];      // row bounds relative to the tile's aligned base
+  __shared__ int64_t sbase;
   __shared__ T sy[kTileRows];
   __shared__ double red[kBlock / kWave];
-  constexpr int NG = kBlock / G;   // row groups per block
-  constexpr int UNR = 4;           // rows per group in flight
+  constexpr int NG = kBlock / G;   // row groups per block; UNR rows per group in flight
   static_assert(kTileRows % (NG * UNR) == 0, "tile rows must split evenly over the groups");
   const int t = xcd_block(per);
   const int tid = threadIdx.x;
@@ -175,9 +175,12 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   const int64_t i = r0 + tid;
   const bool live = i < n;   // grids are padded to a multiple of the XCD count
   T di = 0, xi = 0, bi = 0, si = 0;
+  if (tid == 0) sbase = r0 < n ? rp[r0] & ~(int64_t)3 : 0;
+  __syncthreads();
+  const int64_t base_e = sbase;   // entries of a tile number far below 2^31
   if (r0 < n) {
-    srp[tid] = rp[live ? i : n];
-    if (tid == 0) srp[kTileRows] = rp[r0 + kTileRows < n ? r0 + kTileRows : n];
+    srp[tid] = (int)(rp[live ? i : n] - base_e);
+    if (tid == 0) srp[kTileRows] = (int)(rp[r0 + kTileRows < n ? r0 + kTileRows : n] - base_e);
     if (live) {
       di = diag[i];
       xi = x[i];
@@ -192,8 +195,10 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   }
   __syncthreads();
   const int grp = tid / G, lane = tid & (G - 1);
+  const T* vt = val + base_e;
+  const uint16_t* lt = lcol + base_e;
   for (int base = 0; base < kTileRows; base += NG * UNR) {
-    int64_t k0[UNR], k1[UNR], kb[UNR];
+    int k0[UNR], k1[UNR], kb[UNR];
     Chunk4<T> v[UNR];
     rt_u16x4 lc[UNR];
 #pragma unroll
@@ -201,13 +206,13 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
       const int rr = base + u * NG + grp;
       k0[u] = srp[rr];
       k1[u] = srp[rr + 1];
-      kb[u] = (k0[u] & ~(int64_t)3) + 4 * lane;
+      kb[u] = (k0[u] & ~3) + 4 * lane;
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       if (kb[u] < k1[u]) {
-        v[u].load(val + kb[u]);
-        lc[u] = stream_load(reinterpret_cast<const rt_u16x4*>(lcol + kb[u]));
+        v[u].load(vt + kb[u]);
+        lc[u] = stream_load(reinterpret_cast<const rt_u16x4*>(lt + kb[u]));
       }
     }
     T sum[UNR];
@@ -217,10 +222,10 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
     // rows longer than one pass of the group
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      for (int64_t kk = kb[u] + 4 * G; kk < k1[u]; kk += 4 * G) {
+      for (int kk = kb[u] + 4 * G; kk < k1[u]; kk += 4 * G) {
         Chunk4<T> w;
-        w.load(val + kk);
-        const rt_u16x4 l2 = stream_load(reinterpret_cast<const rt_u16x4*>(lcol + kk));
+        w.load(vt + kk);
+        const rt_u16x4 l2 = stream_load(reinterpret_cast<const rt_u16x4*>(lt + kk));
         sum[u] += chunk_dot<T>(w, l2, kk, k0[u], k1[u], xs);
       }
     }
@@ -255,7 +260,8 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
 }
 
 // Product shapes: plain ones (G lanes per row, E entries per lane, global x
-// gathers) and tiled ones (G lanes per row, four-entry chunks, x from LDS).
+// gathers) and tiled ones (G lanes per row, four-entry chunks, x from LDS,
+// E rows per lane group in flight).
 struct SpmvShape {
   int g, ent;
   bool tiled;
@@ -263,7 +269,8 @@ struct SpmvShape {
 constexpr SpmvShape kSpmvShapes[] = {{4, 4, false},  {4, 8, false},  {8, 8, false},
                                      {8, 12, false}, {16, 6, false}, {32, 6, false},
                                      {64, 4, false}, {4, 4, true},   {8, 4, true},
-                                     {16, 4, true},  {32, 4, true},  {64, 4, true}};
+                                     {16, 4, true},  {32, 4, true},  {64, 4, true},
+                                     {8, 2, true},   {16, 2, true},  {32, 2, true}};
 constexpr int kNumSpmvShapes = sizeof(kSpmvShapes) / sizeof(kSpmvShapes[0]);
 constexpr int kFirstTiledShape = 7;
 
@@ -273,11 +280,12 @@ inline int spmv_plain_shape_for(int64_t max_row) {
     if ((int64_t)kSpmvShapes[s].g * kSpmvShapes[s].ent >= max_row) return s;
   return kFirstTiledShape - 1;
 }
-// the smallest tiled shape whose one pass covers the longest row at any chunk alignment
+// the smallest tiled shape (four rows in flight) whose one pass covers the
+// longest row at any chunk alignment
 inline int spmv_tiled_shape_for(int64_t max_row) {
-  for (int s = kFirstTiledShape; s < kNumSpmvShapes; ++s)
+  for (int s = kFirstTiledShape; s < kFirstTiledShape + 5; ++s)
     if (4 * (int64_t)kSpmvShapes[s].g - 3 >= max_row) return s;
-  return kNumSpmvShapes - 1;
+  return kFirstTiledShape + 4;
 }
 // the shape a product over L runs with, given the requested one (-1: default)
 inline int spmv_effective_shape(const Level& L, int shape) {
@@ -309,16 +317,19 @@ int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* dia
   if (n == 0) return RT_OK;
   if (sh.tiled) {
     const size_t lds = sizeof(T) * (size_t)(L.max_tile_cols > 0 ? L.max_tile_cols : 1);
-#define RT_SPMV_T(G_)                                                                         \
-  hipLaunchKernelGGL((k_spmv_tiled<T, G_, MODE>), dim3(grid), dim3(kBlock), lds, st, n, per,  \
-                     L.rp.p, L.lcol.p, val, diag, L.tile_off.p, L.tile_cols.p, x, b, s, y, y32, \
+#define RT_SPMV_T(G_, U_)                                                                     \
+  hipLaunchKernelGGL((k_spmv_tiled<T, G_, U_, MODE>), dim3(grid), dim3(kBlock), lds, st, n, per, \
+                     L.rp.p, L.lcol.p, val, diag, L.tile_off.p, L.tile_cols.p, x, b, s, y, y32,  \
                      part)
-    switch (sh.g) {
-      case 4: RT_SPMV_T(4); break;
-      case 8: RT_SPMV_T(8); break;
-      case 16: RT_SPMV_T(16); break;
-      case 32: RT_SPMV_T(32); break;
-      default: RT_SPMV_T(64); break;
+    switch (shape) {
+      case 7: RT_SPMV_T(4, 4); break;
+      case 8: RT_SPMV_T(8, 4); break;
+      case 9: RT_SPMV_T(16, 4); break;
+      case 10: RT_SPMV_T(32, 4); break;
+      case 11: RT_SPMV_T(64, 4); break;
+      case 12: RT_SPMV_T(8, 2); break;
+      case 13: RT_SPMV_T(16, 2); break;
+      default: RT_SPMV_T(32, 2); break;
     }
 #undef RT_SPMV_T
   } else {

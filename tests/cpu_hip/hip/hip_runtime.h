@@ -197,6 +197,21 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
   return r;
 }
 
+// wave-wide vote: bit l of the result is lane l's predicate (64-lane waves)
+inline unsigned long long __ballot(int pred) {
+  const int t = (int)threadIdx.x;
+  const int base = t - t % 64;
+  auto& bar = *cpuhip::g_block.group_bar[6][t / 64];
+  cpuhip::g_block.slot[t] = pred ? 1 : 0;
+  bar.arrive_and_wait();
+  unsigned long long m = 0;
+  for (int l = 0; l < 64 && base + l < (int)(blockDim.x * blockDim.y * blockDim.z); ++l)
+    if (cpuhip::g_block.slot[base + l]) m |= 1ull << l;
+  bar.arrive_and_wait();
+  return m;
+}
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+
 template <typename... KArgs, typename... Args>
 inline void hipLaunchKernelGGL(void (*k)(KArgs...), dim3 grid, dim3 block, size_t shmem,
                                hipStream_t, Args... args) {

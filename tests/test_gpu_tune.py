@@ -50,11 +50,11 @@ def _solve(ctx, A, b, precision, tol):
 
 
 @pytest.mark.parametrize("name", ["marshak3d_16", "mms2d_64"])
-@pytest.mark.parametrize("shape", range(12))
+@pytest.mark.parametrize("shape", range(15))
 def test_every_shape_solves(ctx, built, name, shape):
     from paper_2001_11606_amd import rt
     shapes = rt.rt_spmv_shapes()
-    assert len(shapes) == 12
+    assert len(shapes) == 15
     prob, b, x_ref, (dp, nb, A) = built[name]
     info = ctx.matrix_info(A)
     assert info.level_tile_cols[0] > 0, "the fine level of these cases is tiled"
@@ -97,7 +97,7 @@ def test_tune_reports_and_keeps_choice(ctx, built):
 def test_shape_arguments_rejected(ctx, built):
     from paper_2001_11606_amd import rt
     A = built["mms2d_64"][3][2]
-    for args in ((99, rt.RT_PREC_FP64, 0), (0, 7, 0), (0, rt.RT_PREC_FP64, 12),
+    for args in ((99, rt.RT_PREC_FP64, 0), (0, 7, 0), (0, rt.RT_PREC_FP64, 15),
                  (0, rt.RT_PREC_FP64, -2)):
         with pytest.raises(rt.RtError):
             rt.rt_matrix_set_spmv_shape(A, *args)
