@@ -30,6 +30,7 @@ struct FrozenArgs {
   const double *m, *rho, *cv, *s0, *ss, *e, *E, *Qe, *Qn;
   double dt, c, a, p;
   double *V, *D, *sa, *st, *f, *Eall, *e_prev, *E_prev, *rho_s, *cv_s, *m_s, *Qe_s, *QE_s;
+  double* VD;
 };
 
 __global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
@@ -42,11 +43,14 @@ __global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
   const double st = sa + (A.ss ? A.ss[u] : 0.0);
   const double f = 1.0 / (1.0 + A.c * sa * A.dt * 4.0 * A.a * (T * T * T) / (rho * cv));
   const double V = A.m[u] / rho;
+  const double D = A.c * (1.0 / 3.0) / st;
   A.V[s] = V;
   A.sa[s] = sa;
   A.st[s] = st;
   A.f[s] = f;
-  A.D[s] = A.c * (1.0 / 3.0) / st;
+  A.D[s] = D;
+  A.VD[2 * s] = V;
+  A.VD[2 * s + 1] = D;
   A.Eall[s] = E;
   if (s < nin) {
     A.e_prev[s] = e;
@@ -62,23 +66,25 @@ __global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
 // Flux-limited diffusion coefficient of interior particles.
 template <int DIM>
 __global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, double lk, double c,
-                          const double* __restrict__ spos, const double* __restrict__ sh,
-                          const int64_t* __restrict__ nptr, const int32_t* __restrict__ nidx,
-                          const double* __restrict__ V, const double* __restrict__ Eall,
-                          const double* __restrict__ st, double* __restrict__ D) {
+                          const double* __restrict__ sp4, const int64_t* __restrict__ nptr,
+                          const int32_t* __restrict__ nidx, const double* __restrict__ V,
+                          const double* __restrict__ Eall, const double* __restrict__ st,
+                          double* __restrict__ D, double* __restrict__ VD) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nin) return;
-  const double xi = spos[i], yi = spos[n + i], zi = DIM == 3 ? spos[2 * n + i] : 0.0;
-  const double hi = sh[i], Ei = Eall[i];
+  const Rec4 pi = load_rec4(sp4, i);
+  const double xi = pi.x, yi = pi.y, zi = pi.z;
+  const double hi = pi.h, Ei = Eall[i];
   double gx = 0, gy = 0, gz = 0;
   for (int64_t k = nptr[i]; k < nptr[i + 1]; ++k) {
     const int32_t j = nidx[k];
-    const double dx = xi - spos[j], dy = yi - spos[n + j];
-    const double dz = DIM == 3 ? zi - spos[2 * n + j] : 0.0;
+    const Rec4 pj = load_rec4(sp4, j);
+    const double dx = xi - pj.x, dy = yi - pj.y;
+    const double dz = DIM == 3 ? zi - pj.z : 0.0;
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     // grad_i W_ij = 1/2 [W'(r,h_i) + W'(r,h_j)] x_ij / r
     const double w = V[j] * (Eall[j] - Ei) * 0.5 *
-                     (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, sh[j], kernel)) / r;
+                     (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj.h, kernel)) / r;
     gx += w * dx;
     gy += w * dy;
     gz += w * dz;
@@ -88,6 +94,7 @@ __global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, doubl
   if (limiter == RT_LIMITER_LARSEN) lam = pow(pow(3.0, lk) + pow(R, lk), -1.0 / lk);
   else lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
   D[i] = c * lam / st[i];
+  VD[2 * i + 1] = D[i];
 }
 
 __global__ void k_int_counts(int64_t nin, const int32_t* __restrict__ cnt32,
@@ -99,7 +106,7 @@ __global__ void k_int_counts(int64_t nin, const int32_t* __restrict__ cnt32,
 struct AsmArgs {
   const int64_t *nptr, *rp;
   const int32_t* nidx;
-  const double *spos, *sh, *V, *D, *sa, *f, *Eall;
+  const double *sp4, *VD, *sa, *f, *Eall;
   int32_t* col;                       // written when the structure is new, else NULL
   double *val64, *diag64, *dinv64, *sinv64, *g;
   float *val32, *diag32, *dinv32, *sinv32;
@@ -112,22 +119,26 @@ k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A) {
   const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
   const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
   for (int64_t i = grp; i < nin; i += ngrp) {
-    const double xi = A.spos[i], yi = A.spos[n + i], zi = DIM == 3 ? A.spos[2 * n + i] : 0.0;
-    const double hi = A.sh[i], Vi = A.V[i], Di = A.D[i];
+    const Rec4 pi = load_rec4(A.sp4, i);
+    const rt_f64x2_t vdi = load_pair(A.VD, i);
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
+    const double hi = pi.h, Vi = vdi[0], Di = vdi[1];
     const int64_t k0 = A.nptr[i], k1 = A.nptr[i + 1], o = A.rp[i];
     double suma = 0.0, gsum = 0.0, absoff = 0.0;
     for (int64_t k = k0 + lane; k < k1; k += G) {
       const int32_t j = A.nidx[k];
-      const double dx = xi - A.spos[j], dy = yi - A.spos[n + j];
-      const double dz = DIM == 3 ? zi - A.spos[2 * n + j] : 0.0;
+      const Rec4 pj = load_rec4(A.sp4, j);
+      const rt_f64x2_t vdj = load_pair(A.VD, j);
+      const double dx = xi - pj.x, dy = yi - pj.y;
+      const double dz = DIM == 3 ? zi - pj.z : 0.0;
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double F =
-          -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, A.sh[j], kernel)) / r;
-      const double Dij = Di + A.D[j];
-      const double aij = A.V[j] * Dij * F;
+          -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj.h, kernel)) / r;
+      const double Dij = Di + vdj[1];
+      const double aij = vdj[0] * Dij * F;
       suma += aij;
       if (j < nin) {
-        const double v = -(Vi * A.V[j]) * Dij * F;
+        const double v = -(Vi * vdj[0]) * Dij * F;
         A.val64[o + (k - k0)] = v;
         if (A.val32) A.val32[o + (k - k0)] = (float)v;
         if (A.col) A.col[o + (k - k0)] = j;
@@ -203,6 +214,7 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
   A->c = in->c;
   A->a = in->a;
   for (auto* b : {&A->V, &A->D, &A->sa, &A->f, &A->Eall}) RT_CHECK(b->reserve(n));
+  RT_CHECK(A->VD.reserve((size_t)2 * n));
   for (auto* b : {&A->rho, &A->cv, &A->m, &A->e_prev, &A->E_prev, &A->Qe, &A->QE, &A->g})
     RT_CHECK(b->reserve(nin));
   DevBuf<double> sigt;
@@ -210,18 +222,18 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
   FrozenArgs fa{nb->perm.p, in->m, in->rho, in->cv, in->sigma0_a, in->sigma_s, in->e, in->E,
                 in->Q_e, in->Q_E, in->dt, in->c, in->a, in->opacity_exponent,
                 A->V.p, A->D.p, A->sa.p, sigt.p, A->f.p, A->Eall.p, A->e_prev.p, A->E_prev.p,
-                A->rho.p, A->cv.p, A->m.p, A->Qe.p, A->QE.p};
+                A->rho.p, A->cv.p, A->m.p, A->Qe.p, A->QE.p, A->VD.p};
   hipLaunchKernelGGL(k_frozen, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nin, fa);
   RT_LAUNCH_CHECK();
   if (in->limiter != RT_LIMITER_NONE && nin > 0) {
     if (nb->dim == 3)
       hipLaunchKernelGGL(k_limiter<3>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
-                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->spos.p, nb->sh.p,
-                         nb->ptr.p, nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p);
+                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p,
+                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p);
     else
       hipLaunchKernelGGL(k_limiter<2>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
-                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->spos.p, nb->sh.p,
-                         nb->ptr.p, nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p);
+                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p,
+                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p);
     RT_LAUNCH_CHECK();
   }
 
@@ -255,7 +267,7 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
   }
   A->has_fp32 = fp32;
   if (nin > 0) {
-    AsmArgs aa{nb->ptr.p, L.rp.p, nb->idx.p, nb->spos.p, nb->sh.p, A->V.p, A->D.p, A->sa.p,
+    AsmArgs aa{nb->ptr.p, L.rp.p, nb->idx.p, nb->sp4.p, A->VD.p, A->sa.p,
                A->f.p, A->Eall.p, new_structure ? L.col.p : nullptr, L.val64.p, L.diag64.p,
                L.dinv64.p, L.sinv64.p, A->g.p, fp32 ? L.val32.p : nullptr,
                fp32 ? L.diag32.p : nullptr, fp32 ? L.dinv32.p : nullptr,

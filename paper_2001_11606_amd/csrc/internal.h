@@ -96,6 +96,21 @@ constexpr int kSpmvPad = 8;            // spare entries after values / lcol
 #define RT_DYNAMIC_LDS(name) extern __shared__ __attribute__((aligned(16))) unsigned char name[]
 #endif
 
+// Per-particle records read by the pair loops with two 16-byte loads:
+// (x, y, z, h) in 4 doubles (z = 0 in 2-D) and (V, D) in 2 doubles.
+typedef double rt_f64x2_t __attribute__((vector_size(16)));
+struct Rec4 {
+  double x, y, z, h;
+};
+__device__ __forceinline__ Rec4 load_rec4(const double* __restrict__ p, int64_t i) {
+  const rt_f64x2_t a = *reinterpret_cast<const rt_f64x2_t*>(p + 4 * i);
+  const rt_f64x2_t b = *reinterpret_cast<const rt_f64x2_t*>(p + 4 * i + 2);
+  return Rec4{a[0], a[1], b[0], b[1]};
+}
+__device__ __forceinline__ rt_f64x2_t load_pair(const double* __restrict__ p, int64_t i) {
+  return *reinterpret_cast<const rt_f64x2_t*>(p + 2 * i);
+}
+
 inline int grid_for(int64_t work_items, int per_block = kBlock, int cap = 1 << 30) {
   int64_t g = (work_items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -139,6 +154,7 @@ struct rt_neighbors {
   rt::DevBuf<int32_t> iperm;    // user -> sorted
   rt::DevBuf<double> spos;      // dim x n_total, sorted order
   rt::DevBuf<double> sh;        // n_total, sorted order
+  rt::DevBuf<double> sp4;       // 4 x n_total: (x, y, z, h) per particle, sorted order
   rt::DevBuf<int64_t> ptr;      // n_total + 1, sorted order
   rt::DevBuf<int32_t> idx;      // npairs, sorted indices, ascending per row
   rt::DevBuf<int32_t> n_int_nbrs;  // interior neighbours per interior row
@@ -185,6 +201,7 @@ struct rt_matrix {
   rt_amg_opts amg{};
   // frozen per-step data, sorted order
   rt::DevBuf<double> V, D, sa, f, rho, cv, m, e_prev, E_prev, Qe, QE, g;
+  rt::DevBuf<double> VD;        // 2 x n_total: (V, D) per particle, sorted order
   rt::DevBuf<double> Eall;      // E^{n-1} / ghost data for all particles (sorted)
   // hierarchy: levels[0] is the fine operator
   std::vector<rt::Level> levels;

@@ -123,12 +123,17 @@ k_keys(int bits, int64_t n, int64_t nin, const double* __restrict__ pos, double 
 __global__ void k_gather_sorted(int dim, int64_t n, const int32_t* __restrict__ perm,
                                 const double* __restrict__ pos, const double* __restrict__ h,
                                 double* __restrict__ spos, double* __restrict__ sh,
-                                int32_t* __restrict__ iperm) {
+                                double* __restrict__ sp4, int32_t* __restrict__ iperm) {
   int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
   int32_t u = perm[s];
-  for (int a = 0; a < dim; ++a) spos[a * n + s] = pos[a * n + u];
+  for (int a = 0; a < dim; ++a) {
+    spos[a * n + s] = pos[a * n + u];
+    sp4[4 * s + a] = pos[a * n + u];
+  }
+  for (int a = dim; a < 3; ++a) sp4[4 * s + a] = 0.0;
   sh[s] = h[u];
+  sp4[4 * s + 3] = h[u];
   iperm[u] = (int32_t)s;
 }
 
@@ -175,8 +180,8 @@ template <int DIM, bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
             double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ skeys,
-            const double* __restrict__ spos, const double* __restrict__ sh,
-            const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend,
+            const double* __restrict__ sp4, const int32_t* __restrict__ cstart,
+            const int32_t* __restrict__ cend,
             int64_t* __restrict__ cnt, const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
             int32_t* __restrict__ n_int_nbrs) {
   constexpr int NB = DIM == 3 ? 27 : 9;   // adjacent cells per flag
@@ -230,18 +235,32 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           else hi = mid;
         }
         const int32_t t = rlo[lo] + (kk - roff[lo]);
+        const Rec4 q = load_rec4(sp4, t);
         ct[k] = t;
-        cx[k] = spos[t];
-        cy[k] = spos[n + t];
-        cz[k] = DIM == 3 ? spos[2 * n + t] : 0.0;
-        ch[k] = sh[t];
+        cx[k] = q.x;
+        cy[k] = q.y;
+        cz[k] = q.z;
+        ch[k] = q.h;
       }
       __syncthreads();
+      // the block's own cell is the centre slot of its flag: its rows are candidates too
+      const int cslot = (r0 >= nin ? NB : 0) + NB / 2;
       for (int r = wave; r < nrows; r += kBlock / kWave) {
         const int64_t s = rb + r;
-        const double xi = spos[s], yi = spos[n + s];
-        const double zi = DIM == 3 ? spos[2 * n + s] : 0.0;
-        const double hi = sh[s];
+        const int ks = roff[cslot] + (int)(s - rlo[cslot]) - c0;
+        double xi, yi, zi, hi;
+        if (ks >= 0 && ks < mc) {
+          xi = cx[ks];
+          yi = cy[ks];
+          zi = cz[ks];
+          hi = ch[ks];
+        } else {
+          const Rec4 q = load_rec4(sp4, s);
+          xi = q.x;
+          yi = q.y;
+          zi = q.z;
+          hi = q.h;
+        }
         int found = 0, fint = 0;
         int64_t out = FILL ? ptr[s] + rcount[r] : 0;
         for (int k = lane; k - lane < mc; k += kWave) {
@@ -391,6 +410,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK(nb->iperm.reserve(n));
   RT_CHECK(nb->spos.reserve((size_t)dim * n));
   RT_CHECK(nb->sh.reserve(n));
+  RT_CHECK(nb->sp4.reserve((size_t)4 * n));
 #define RT_KEYS(D_)                                                                            \
   hipLaunchKernelGGL(k_keys<D_>, dim3(grid_for(n)), dim3(kBlock), 0, st, bits, n, nin, pos,     \
                      nb->lo[0], nb->lo[1], nb->lo[2], cs, nb->nc[0], nb->nc[1], nb->nc[2],      \
@@ -404,7 +424,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   keys.release();
   ids.release();
   hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, dim, n,
-                     nb->perm.p, pos, h, nb->spos.p, nb->sh.p, nb->iperm.p);
+                     nb->perm.p, pos, h, nb->spos.p, nb->sh.p, nb->sp4.p, nb->iperm.p);
   RT_LAUNCH_CHECK();
 
   // 4. [start, end) per (flag, row-major cell); empty cells stay [0, 0)
@@ -445,8 +465,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
 #define RT_NBR(D_, F_)                                                                          \
   hipLaunchKernelGGL((k_nbr_cells<D_, F_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits,      \
                      ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, runs.p, nb->skeys.p,    \
-                     nb->spos.p, nb->sh.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p,        \
-                     nb->n_int_nbrs.p)
+                     nb->sp4.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p)
   if (dim == 3) RT_NBR(3, false);
   else RT_NBR(2, false);
   RT_LAUNCH_CHECK();

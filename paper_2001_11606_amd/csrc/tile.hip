@@ -2,20 +2,25 @@
 //
 // Rows are cut into tiles of kTileRows consecutive rows.  For each tile the
 // set of distinct columns its entries reference is found with an
-// open-addressing hash set in LDS, sorted (bitonic, in LDS) and written out
-// as the tile's column list; each entry's column is then replaced by its
-// 16-bit position in that list.  A product over a tile first loads
-// x[tile_cols] into LDS (one read per distinct column instead of one gather
-// per entry) and reads x from there.  Since particles are sorted by cell and
-// rows couple only neighbouring cells, a tile of 256 rows references about
-// one to two thousand distinct columns.  Built once per matrix structure;
-// the lists and lcol are deterministic (the hash only finds the set, the
-// sort fixes the order).
+// open-addressing hash set in LDS and written out as the tile's column list,
+// in slot order; each entry's column is then replaced by its 16-bit position
+// in that list.  A product over a tile first loads x[tile_cols] into LDS
+// (one read per distinct column instead of one gather per entry) and reads x
+// from there.  Since particles are sorted by cell and rows couple only
+// neighbouring cells, a tile of 256 rows references about one to two
+// thousand distinct columns, in runs of consecutive indices (one run per
+// adjacent cell).  The hash is the column index modulo the table size, so a
+// run occupies consecutive slots and the list keeps runs contiguous -- the
+// staging reads stay coalesced without sorting.  The order of a list does
+// not change any product (each entry still reads its own column's value);
+// where two columns race for a slot the list order may differ between
+// builds, the products do not.  Built once per matrix structure.
 #include <climits>
 #include <cstring>
 
 #include "internal.h"
 #include "prim.h"
+#include "reduce.h"
 
 namespace rt {
 namespace {
@@ -25,9 +30,7 @@ constexpr int kHash = 1 << kHashBits;   // slots; > kTileMaxCols + kBlock, so ne
 static_assert(kHash >= kTileMaxCols + kBlock, "hash set must have room for in-flight inserts");
 static_assert(kTileRows == kBlock, "one tile per block, one row per thread");
 
-__device__ __forceinline__ int hash_slot(int32_t c) {
-  return (int)(((uint32_t)c * 2654435761u) >> (32 - kHashBits));
-}
+__device__ __forceinline__ int hash_slot(int32_t c) { return c & (kHash - 1); }
 
 // Insert the columns of entries [e0, e1) into keys (empty = -1); *count is the
 // number of distinct columns inserted; *overflow is set once it reaches
@@ -90,56 +93,48 @@ k_tile_count(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restric
   }
 }
 
-// sorted distinct columns of every tile, and each entry's position among them
+// distinct columns of every tile in slot order, and each entry's position among them
 __global__ void __launch_bounds__(kBlock)
 k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
             const int64_t* __restrict__ off, int32_t* __restrict__ tcols,
             uint16_t* __restrict__ lcol) {
+  constexpr int PER = kHash / kBlock;   // consecutive slots per thread
   __shared__ int keys[kHash];
   __shared__ int pos[kHash];
-  __shared__ int sorted[kHash];
-  __shared__ int count, overflow, packed;
+  __shared__ int wsum[kBlock / kWave];
+  __shared__ int count, overflow;
   for (int s = threadIdx.x; s < kHash; s += kBlock) keys[s] = -1;
   if (threadIdx.x == 0) {
     count = 0;
     overflow = 0;
-    packed = 0;
   }
   __syncthreads();
   int64_t e0, e1;
   tile_rows(n, blockIdx.x, rp, &e0, &e1);
   tile_insert(e0, e1, col, keys, &count, &overflow);
   __syncthreads();
-  const int m = count;   // the count pass saw no overflow, so this is the full set
-  int p2 = 1;
-  while (p2 < m) p2 <<= 1;
-  for (int s = threadIdx.x; s < kHash; s += kBlock)
-    if (keys[s] != -1) sorted[atomicAdd(&packed, 1)] = keys[s];
-  __syncthreads();
-  for (int s = m + threadIdx.x; s < p2; s += kBlock) sorted[s] = INT_MAX;
-  __syncthreads();
-  // bitonic sort of sorted[0, p2), ascending
-  for (int k = 2; k <= p2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < p2; i += kBlock) {
-        const int l = i ^ j;
-        if (l > i) {
-          const int a = sorted[i], b = sorted[l];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            sorted[i] = b;
-            sorted[l] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  // positions = exclusive prefix count of occupied slots (block scan)
+  const int s0 = threadIdx.x * PER;
+  int own = 0;
+  for (int q = 0; q < PER; ++q) own += keys[s0 + q] != -1;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  int incl = own;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
   }
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  int base = incl - own;
+  for (int q = 0; q < w; ++q) base += wsum[q];
   const int64_t o = off[blockIdx.x];
-  for (int q = threadIdx.x; q < m; q += kBlock) {
-    const int c = sorted[q];
-    tcols[o + q] = c;
-    pos[tile_find(keys, c)] = q;
+  for (int q = 0; q < PER; ++q) {
+    const int c = keys[s0 + q];
+    if (c != -1) {
+      pos[s0 + q] = base;
+      tcols[o + base] = c;
+      ++base;
+    }
   }
   __syncthreads();
   for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock)
