@@ -9,12 +9,16 @@
 // from there.  Since particles are sorted by cell and rows couple only
 // neighbouring cells, a tile of 256 rows references about one to two
 // thousand distinct columns, in runs of consecutive indices (one run per
-// adjacent cell).  The hash is the column index modulo the table size, so a
-// run occupies consecutive slots and the list keeps runs contiguous -- the
-// staging reads stay coalesced without sorting.  The order of a list does
-// not change any product (each entry still reads its own column's value);
-// where two columns race for a slot the list order may differ between
-// builds, the products do not.  Built once per matrix structure.
+// adjacent cell).  The table is 256 buckets of 16 slots: column c probes the
+// buckets h(c / 16), h(c / 16) + 1, ... at the in-bucket offset c mod 16, so
+// the columns of one aligned block of 16 land in one bucket in ascending
+// order, and compaction in slot order keeps every such block contiguous in
+// the list -- the staging reads stay coalesced without sorting.  The order
+// of a list does not change any product (each entry still reads its own
+// column's value); where two columns race for a slot the list order may
+// differ between builds, the products do not.  A probe that visits every
+// bucket marks the tile as overflowing (the level then stays untiled), so
+// insertion ends for any input.  Built once per matrix structure.
 #include <climits>
 #include <cstring>
 
@@ -30,37 +34,50 @@ constexpr int kHash = 1 << kHashBits;   // slots; > kTileMaxCols + kBlock, so ne
 static_assert(kHash >= kTileMaxCols + kBlock, "hash set must have room for in-flight inserts");
 static_assert(kTileRows == kBlock, "one tile per block, one row per thread");
 
-__device__ __forceinline__ int hash_slot(int32_t c) { return c & (kHash - 1); }
+constexpr int kBucket = 16;                   // slots per bucket = columns per block
+constexpr int kBuckets = kHash / kBucket;
+
+// first bucket probed by column c
+__device__ __forceinline__ int first_bucket(int32_t c) {
+  return (int)((((uint32_t)c >> 4) * 2654435761u) >> 24) & (kBuckets - 1);
+}
 
 // Insert the columns of entries [e0, e1) into keys (empty = -1); *count is the
 // number of distinct columns inserted; *overflow is set once it reaches
-// kTileMaxCols (then insertion stops: at most kBlock more can land).
+// kTileMaxCols or a probe finds no free slot (then insertion stops).
 __device__ void tile_insert(int64_t e0, int64_t e1, const int32_t* __restrict__ col, int* keys,
                             int* count, int* overflow) {
   for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock) {
     if (*(volatile int*)overflow) break;
     const int c = col[k];
-    int s = hash_slot(c);
-    for (;;) {
+    const int off = c & (kBucket - 1);
+    int b = first_bucket(c);
+    bool placed = false;
+    for (int step = 0; step < kBuckets && !placed; ++step, b = (b + 1) & (kBuckets - 1)) {
+      const int s = b * kBucket + off;
       const int cur = ((volatile int*)keys)[s];
-      if (cur == c) break;
-      if (cur == -1) {
+      if (cur == c) {
+        placed = true;
+      } else if (cur == -1) {
         const int prev = atomicCAS(&keys[s], -1, c);
         if (prev == -1) {
           if (atomicAdd(count, 1) + 1 >= kTileMaxCols) *(volatile int*)overflow = 1;
-          break;
+          placed = true;
+        } else if (prev == c) {
+          placed = true;
         }
-        if (prev == c) break;
       }
-      s = (s + 1) & (kHash - 1);
     }
+    if (!placed) *(volatile int*)overflow = 1;
   }
 }
 
+// slot of a column that was inserted
 __device__ __forceinline__ int tile_find(const int* keys, int c) {
-  int s = hash_slot(c);
-  while (keys[s] != c) s = (s + 1) & (kHash - 1);
-  return s;
+  const int off = c & (kBucket - 1);
+  int b = first_bucket(c);
+  while (keys[b * kBucket + off] != c) b = (b + 1) & (kBuckets - 1);
+  return b * kBucket + off;
 }
 
 __device__ __forceinline__ void tile_rows(int64_t n, int64_t t, const int64_t* rp, int64_t* e0,
