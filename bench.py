@@ -133,6 +133,109 @@ def cpu_baseline(workload: str, n_sample: int, outer: int):
                       f"one time step with {outer} outer iterations, {dt:.1f} s"}
 
 
+def run_ensemble(args):
+    """The ensemble workload: 96 independent problems (2-D / 3-D, log-uniform
+    sizes 8k-500k, about 1.1e7 particles), one step = per-problem neighbour
+    lists and assembly, the block-diagonal batch, and one batched outer
+    iteration of Algorithm 1 (initial material solve, right-hand side, mixed
+    solve to the tolerance, material update) for every problem at once."""
+    import torch
+    import synth
+    from paper_2001_11606_amd import driver, rt
+    t0 = time.perf_counter()
+    probs = synth.config5(args.nprob, args.scale)
+    nin = [pr.n_interior for pr in probs]
+    ntot = int(sum(nin))
+    log(f"[bench] ensemble of {len(probs)} problems, {ntot} particles, generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    ctx = rt.Context(0)
+    dps = [driver.upload(pr, ctx.device) for pr in probs]
+    amg = rt.amg_opts(max_levels=1, build_fp32=1)
+    e0 = torch.cat([dp.arrays["e"][:dp.n_interior] for dp in dps])
+    E0 = torch.cat([dp.arrays["E"][:dp.n_interior] for dp in dps])
+    torch.cuda.synchronize()
+    tuned = None
+
+    def step(precision, keep=False):
+        nonlocal tuned
+        nbs, mats = [], []
+        for dp in dps:
+            nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+            A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                             dp.limiter_k, amg=amg)
+            nbs.append(nb)
+            mats.append(A)
+        B = rt.rt_batch_create(ctx.handle, mats)
+        if tuned is None:   # tuned on the first batch (warm-up), outside the timed steps
+            tuned = rt.rt_batch_tune(ctx.handle, B, 5)
+        rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_FP64, tuned.chosen[0][0])
+        rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_MIXED, tuned.chosen[0][1])
+        e, E = e0.clone(), E0.clone()
+        nopts = rt.newton_opts(rt.solve_opts(precision, 0, args.tol, 5000, args.inner_tol, 30))
+        s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), 0,
+                                        nopts, args.graph_iters)
+        torch.cuda.synchronize()
+        for A, nb in zip(mats, nbs):
+            rt.rt_matrix_free(A)
+            rt.rt_neighbors_free(nb.handle)
+        ctx._owned.clear()
+        if keep:
+            return e, E, st, B
+        rt.rt_batch_free(B)
+        return e, E, st, None
+
+    for w in range(max(1, args.warmup)):
+        log(f"[bench] warmup step {w}")
+        step(rt.RT_PREC_MIXED)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        e, E, st, _ = step(rt.RT_PREC_MIXED)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    value = ntot / (ms * 1e-3)
+    # batched solve alone, mixed vs FP64, on one kept batch
+    e, E, st, B = step(rt.RT_PREC_MIXED, keep=True)
+    rows, nnz, tcols = rt.rt_batch_get_info(B)
+    solve_t = {}
+    for prec in (rt.RT_PREC_MIXED, rt.RT_PREC_FP64):
+        bt = torch.ones(ntot, dtype=torch.float64, device=ctx.device)
+        xt = torch.zeros_like(bt)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        s, sst = rt.rt_batch_solve(ctx.handle, B, len(probs), bt.data_ptr(), xt.data_ptr(),
+                                   rt.solve_opts(prec, 0, args.tol, 5000, args.inner_tol, 30),
+                                   args.graph_iters)
+        torch.cuda.synchronize()
+        solve_t[prec] = time.perf_counter() - ta
+    rt.rt_batch_free(B)
+    sh = tuned.chosen[0][1]
+    shapes = rt.rt_spmv_shapes()
+    us32 = tuned.us[0][1][sh]
+    bytes32 = spmv_bytes(4, nnz, rows, tcols if shapes[sh][2] else 0)
+    achieved = bytes32 / (us32 * 1e-6) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"ensemble of {len(probs)} problems ({ntot} particles), one outer "
+                               f"iteration each, batched mixed FP32/FP64 to {args.tol:g}",
+                   "particles": ntot, "rows_padded": rows, "nnz": nnz},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"batched SpMV shape {shapes[sh]} (tuner timing)",
+                     "bytes_per_launch": bytes32, "avg_launch_us": round(us32, 2)},
+        "cpu_baseline": None,
+        "mixed_vs_fp64": {"solve_s_mixed": round(solve_t[rt.RT_PREC_MIXED], 5),
+                          "solve_s_fp64": round(solve_t[rt.RT_PREC_FP64], 5),
+                          "ratio_fp64_over_mixed": round(solve_t[rt.RT_PREC_FP64] /
+                                                         solve_t[rt.RT_PREC_MIXED], 3)},
+        "krylov_max": max(s.solve.iterations for s in st),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +251,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--nprob", type=int, default=96, help="ensemble: number of problems")
+    ap.add_argument("--scale", type=float, default=1.0, help="ensemble: size factor")
+    ap.add_argument("--graph-iters", type=int, default=8,
+                    help="ensemble: PCG iterations per replayed HIP graph (0: none)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default SpMV shapes instead of tuning them during warm-up")
     args = ap.parse_args()
@@ -161,6 +268,9 @@ def main():
     from paper_2001_11606_amd import driver, rt
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.workload == "ensemble":
+        run_ensemble(args)
+        return
     log(f"[bench] generating {args.workload} n={args.n}")
     t0 = time.perf_counter()
     prob = make_problem(args.workload, args.n)

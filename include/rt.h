@@ -283,6 +283,40 @@ typedef struct {
 int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
                    const rt_newton_opts* opts, rt_newton_stats* stats);
 
+/* ---- ensembles of independent problems (Sec. 3.2 per problem, batched) ----
+ * Not in the paper: many independent problems advanced together, one launch
+ * per kernel for the whole ensemble.  rt_batch_create concatenates the
+ * fine-level systems of nprob matrices (each from rt_assemble; FP32 copies
+ * in all of them for RT_PREC_MIXED) into one block-diagonal system, each
+ * problem padded with identity rows to a multiple of 256 rows, plus the
+ * per-particle data of the Newton step; each problem keeps its own dt, c, a.
+ * The batch copies what it needs: the matrices may be freed afterwards; after
+ * re-assembling them, create a new batch.  Solves use Jacobi-preconditioned
+ * CG (precond must be 0) with per-problem Krylov scalars and per-problem
+ * convergence: a problem that meets its tolerance stops while the others go
+ * on.  graph_iters > 0 replays HIP graphs of that many PCG iterations between
+ * host reads of the convergence flags (extra iterations of finished problems
+ * are no-ops); 0 checks after every iteration.
+ * Vectors (b, x, e, E) are the problems' interior vectors concatenated in
+ * problem order, each in its own user order (problem p at the offset
+ * sum_{q<p} n_interior(q)), device memory.  stats arrays hold nprob entries
+ * (or are NULL).  Returns the worst status over the problems.               */
+typedef struct rt_batch rt_batch;
+int rt_batch_create(rt_ctx* ctx, int nprob, rt_matrix* const* mats, rt_batch** out);
+void rt_batch_free(rt_batch* B);
+/* rows (padded), stored off-diagonal entries, tile columns (0 = untiled) */
+int rt_batch_get_info(const rt_batch* B, int64_t* rows, int64_t* nnz, int64_t* tile_cols);
+/* rt_matrix_tune / rt_matrix_set_spmv_shape on the concatenated operator
+ * (one level: the report's level 0)                                        */
+int rt_batch_tune(rt_ctx* ctx, rt_batch* B, int reps, rt_tune_report* rep);
+int rt_batch_set_spmv_shape(rt_batch* B, int precision, int shape);
+int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x,
+                   const rt_solve_opts* opts, int graph_iters, rt_solve_stats* stats);
+/* One outer iteration of Algorithm 1 for every problem (ell == 0 first does
+ * the initial material solve), as rt_newton_step per problem.              */
+int rt_batch_newton_step(rt_ctx* ctx, rt_batch* B, double* e, double* E, int ell,
+                         const rt_newton_opts* opts, int graph_iters, rt_newton_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,12 +3,8 @@
 // Right-hand side of the diffusion solve (Sec. 2.2, inexact Newton equation;
 // operators S and N of Sec. 3.2), multiplied by V_i:
 //   b_i = V_i [E_i^{n-1}/dt + c sigma_a,i a T_i^4 - (1 - f_i) c sigma_a,i E_i^l + Q_E,i] + g_i
-// Material update, the operator M^-1 of Sec. 3.2: per particle solve
-//   u(e) = rho/dt (e - e^{n-1}) + c sigma_a a (e/c_v)^4 - P = 0,  P = Q_e + c sigma_a E^{l+1},
-// by Newton with J = rho/dt + 4 c sigma_a a T^3/c_v.  u is increasing and
-// convex on e >= 0 with u(0) <= 0 <= u(e^{n-1} + dt P/rho), so a Newton step
-// leaving the current bracket is replaced by bisection; a negative upper end
-// means the root is negative (reported as non-physical, e clamped to 0).
+// Material update, the operator M^-1 of Sec. 3.2: the per-particle bracketed
+// Newton solve of material.h.
 // Convergence measures (Sec. 2.2): max_i |e^{l+1} - e^l|/|e^{l+1}| and the
 // same for E; energy (Sec. 2.5): sum_i (m_i e_i + V_i E_i).
 #include <algorithm>
@@ -16,6 +12,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "material.h"
 #include "reduce.h"
 #include "spmv.h"
 
@@ -52,44 +49,14 @@ __global__ void __launch_bounds__(kBlock) k_material(int64_t n, MatArgs A, doubl
   double de = 0.0, dE = 0.0, its_max = 0.0, bad = 0.0, nonphys = 0.0, en = 0.0, en0 = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double rho = A.rho[i], cv = A.cv[i], sa = A.sa[i], ep = A.e_prev[i];
+    const double ep = A.e_prev[i];
     const double Enew = A.E_new[i];
-    const double ca = A.c * sa;
-    const double P = A.Qe[i] + ca * Enew;
-    const double rdt = rho / A.dt;
-    double lo = 0.0, hi = ep + A.dt * P / rho;
-    double e;
-    int it = 0;
-    bool conv = true;
-    if (hi < 0.0) {
-      e = 0.0;
-      nonphys += 1.0;
-    } else {
-      e = fmin(fmax(A.e_start[i], lo), hi);
-      conv = false;
-      while (it < A.max_iter) {
-        const double T = e / cv;
-        const double T2 = T * T;
-        const double u = rdt * (e - ep) + ca * A.a * (T2 * T2) - P;
-        const double J = rdt + 4.0 * ca * A.a * (T2 * T) / cv;
-        ++it;
-        if (u == 0.0) {
-          conv = true;
-          break;
-        }
-        if (u > 0.0) hi = e;
-        else lo = e;
-        const double en = e - u / J;
-        const bool small = fabs(en - e) <= A.tol * fabs(en);
-        const bool inside = en > lo && en < hi;
-        e = (small || inside) ? en : 0.5 * (lo + hi);
-        if (small) {
-          conv = true;
-          break;
-        }
-      }
-    }
-    if (!conv) bad += 1.0;
+    const MaterialResult mr = material_solve(A.rho[i], A.cv[i], A.sa[i], ep, A.Qe[i], Enew,
+                                             A.e_start[i], A.dt, A.c, A.a, A.tol, A.max_iter);
+    const double e = mr.e;
+    const int it = mr.iterations;
+    if (mr.nonphysical) nonphys += 1.0;
+    if (!mr.converged) bad += 1.0;
     A.e_out[i] = e;
     de = fmax(de, fabs(e - A.e_start[i]) / fabs(e));
     dE = fmax(dE, fabs(Enew - A.E_old[i]) / fabs(Enew));

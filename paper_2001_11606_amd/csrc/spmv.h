@@ -52,10 +52,15 @@ __global__ void __launch_bounds__(kBlock)
 k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
        const T* __restrict__ val, const T* __restrict__ diag, const T* __restrict__ x,
        const T* __restrict__ b, const T* __restrict__ s, T* __restrict__ y,
-       float* __restrict__ y32, double* __restrict__ part) {
+       float* __restrict__ y32, double* __restrict__ part, const int32_t* __restrict__ tprob,
+       const int32_t* __restrict__ skip) {
   __shared__ double red[kBlock / kWave];
   constexpr int RPB = kBlock / G;
   const int lb = xcd_block(per);
+  if (skip) {   // batched systems: rows of a finished problem are left as they are
+    const int64_t rb = (int64_t)lb * RPB;
+    if (rb < n && skip[tprob[rb / kTileRows]]) return;
+  }
   const int lane = threadIdx.x & (G - 1);
   const int64_t i = (int64_t)lb * RPB + threadIdx.x / G;
   double acc = 0.0;
@@ -160,7 +165,8 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
              const T* __restrict__ val, const T* __restrict__ diag,
              const int64_t* __restrict__ toff, const int32_t* __restrict__ tcols,
              const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ s,
-             T* __restrict__ y, float* __restrict__ y32, double* __restrict__ part) {
+             T* __restrict__ y, float* __restrict__ y32, double* __restrict__ part,
+             const int32_t* __restrict__ tprob, const int32_t* __restrict__ skip) {
   RT_DYNAMIC_LDS(dyn_lds);
   T* xs = reinterpret_cast<T*>(dyn_lds);
   __shared__ int srp[kTileRows + 1];      // row bounds relative to the tile's aligned base
@@ -173,6 +179,7 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)t * kTileRows;
   const int64_t i = r0 + tid;
+  if (skip && r0 < n && skip[tprob[t]]) return;   // batched: a finished problem's tile
   const bool live = i < n;   // grids are padded to a multiple of the XCD count
   T di = 0, xi = 0, bi = 0, si = 0;
   if (tid == 0) sbase = r0 < n ? rp[r0] & ~(int64_t)3 : 0;
@@ -304,10 +311,19 @@ inline int spmv_blocks(int64_t n, int G) { return spmv_blocks_rows(n, kBlock / G
 
 // Product over level L in the precision of T; *nparts receives the number of
 // partials written.  shape: index into kSpmvShapes, -1 = the level's default.
+// Rows per block (= per partial) of a product over L with the given shape.
+inline int spmv_rows_per_block(const Level& L, int shape) {
+  const SpmvShape sh = kSpmvShapes[spmv_effective_shape(L, shape)];
+  return sh.tiled ? kTileRows : kBlock / sh.g;
+}
+
+// tprob / skip (batched systems, else NULL): the problem of every 256-row
+// tile and a per-problem flag; blocks whose problem is flagged do nothing.
 template <typename T, int MODE>
 int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* diag, const T* x,
                       const T* b, const T* s, T* y, float* y32, double* part, int* nparts,
-                      int shape = -1) {
+                      int shape = -1, const int32_t* tprob = nullptr,
+                      const int32_t* skip = nullptr) {
   const int64_t n = L.n;
   shape = spmv_effective_shape(L, shape);
   const SpmvShape sh = kSpmvShapes[shape];
@@ -320,7 +336,7 @@ int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* dia
 #define RT_SPMV_T(G_, U_)                                                                     \
   hipLaunchKernelGGL((k_spmv_tiled<T, G_, U_, MODE>), dim3(grid), dim3(kBlock), lds, st, n, per, \
                      L.rp.p, L.lcol.p, val, diag, L.tile_off.p, L.tile_cols.p, x, b, s, y, y32,  \
-                     part)
+                     part, tprob, skip)
     switch (shape) {
       case 7: RT_SPMV_T(4, 4); break;
       case 8: RT_SPMV_T(8, 4); break;
@@ -335,7 +351,7 @@ int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* dia
   } else {
 #define RT_SPMV_S(G_, E_)                                                                       \
   hipLaunchKernelGGL((k_spmv<T, G_, E_, MODE>), dim3(grid), dim3(kBlock), 0, st, n, per, L.rp.p, \
-                     L.col.p, val, diag, x, b, s, y, y32, part)
+                     L.col.p, val, diag, x, b, s, y, y32, part, tprob, skip)
     switch (shape) {
       case 0: RT_SPMV_S(4, 4); break;
       case 1: RT_SPMV_S(4, 8); break;

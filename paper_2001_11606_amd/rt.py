@@ -118,6 +118,16 @@ _SIGS = {
                                ctypes.POINTER(c_int), c_int]),
     "rt_matrix_tune": (c_int, [c_vp, c_vp, c_int, ctypes.POINTER(rt_tune_report)]),
     "rt_matrix_set_spmv_shape": (c_int, [c_vp, c_int, c_int, c_int]),
+    "rt_batch_create": (c_int, [c_vp, c_int, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp)]),
+    "rt_batch_free": (None, [c_vp]),
+    "rt_batch_get_info": (c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
+                                  ctypes.POINTER(c_i64)]),
+    "rt_batch_tune": (c_int, [c_vp, c_vp, c_int, ctypes.POINTER(rt_tune_report)]),
+    "rt_batch_set_spmv_shape": (c_int, [c_vp, c_int, c_int]),
+    "rt_batch_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts), c_int,
+                               ctypes.POINTER(rt_solve_stats)]),
+    "rt_batch_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
+                                     c_int, ctypes.POINTER(rt_newton_stats)]),
     "rt_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
                          ctypes.POINTER(rt_solve_stats)]),
     "rt_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
@@ -249,6 +259,51 @@ def rt_matrix_tune(ctx: int, A: int, reps: int) -> rt_tune_report:
 
 def rt_matrix_set_spmv_shape(A: int, level: int, precision: int, shape: int) -> None:
     _check("rt_matrix_set_spmv_shape", load().rt_matrix_set_spmv_shape(A, level, precision, shape))
+
+
+def rt_batch_create(ctx: int, mats: list) -> int:
+    arr = (c_vp * len(mats))(*mats)
+    out = c_vp()
+    _check("rt_batch_create", load().rt_batch_create(ctx, len(mats), arr, ctypes.byref(out)))
+    return out.value
+
+
+def rt_batch_free(B: int) -> None:
+    load().rt_batch_free(B)
+
+
+def rt_batch_get_info(B: int) -> tuple:
+    rows, nnz, tc = c_i64(), c_i64(), c_i64()
+    _check("rt_batch_get_info", load().rt_batch_get_info(B, ctypes.byref(rows), ctypes.byref(nnz),
+                                                         ctypes.byref(tc)))
+    return rows.value, nnz.value, tc.value
+
+
+def rt_batch_tune(ctx: int, B: int, reps: int) -> rt_tune_report:
+    rep = rt_tune_report()
+    _check("rt_batch_tune", load().rt_batch_tune(ctx, B, reps, ctypes.byref(rep)))
+    return rep
+
+
+def rt_batch_set_spmv_shape(B: int, precision: int, shape: int) -> None:
+    _check("rt_batch_set_spmv_shape", load().rt_batch_set_spmv_shape(B, precision, shape))
+
+
+def rt_batch_solve(ctx: int, B: int, nprob: int, b: int, x: int, opts: rt_solve_opts,
+                   graph_iters: int = 0) -> tuple:
+    st = (rt_solve_stats * nprob)()
+    s = _check("rt_batch_solve", load().rt_batch_solve(ctx, B, b, x, ctypes.byref(opts),
+                                                       graph_iters, st))
+    return s, list(st)
+
+
+def rt_batch_newton_step(ctx: int, B: int, nprob: int, e: int, E: int, ell: int,
+                         opts: rt_newton_opts, graph_iters: int = 0) -> tuple:
+    st = (rt_newton_stats * nprob)()
+    s = _check("rt_batch_newton_step", load().rt_batch_newton_step(ctx, B, e, E, ell,
+                                                                   ctypes.byref(opts),
+                                                                   graph_iters, st))
+    return s, list(st)
 
 
 def rt_solve(ctx: int, A: int, b: int, x: int, opts: rt_solve_opts) -> tuple:

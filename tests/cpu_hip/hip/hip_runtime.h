@@ -48,6 +48,14 @@ struct dim3 {
 typedef enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 } hipError_t;
 typedef struct ihipStream_t* hipStream_t;
 typedef struct ihipEvent_t* hipEvent_t;
+typedef struct ihipGraph_t* hipGraph_t;
+typedef struct ihipGraphExec_t* hipGraphExec_t;
+typedef struct ihipGraphNode_t* hipGraphNode_t;
+enum hipStreamCaptureMode {
+  hipStreamCaptureModeGlobal = 0,
+  hipStreamCaptureModeThreadLocal,
+  hipStreamCaptureModeRelaxed
+};
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost,
                      hipMemcpyDeviceToDevice, hipMemcpyDefault };
 #define hipHostMallocDefault 0
@@ -59,6 +67,8 @@ struct ThreadCtx {
 };
 inline thread_local ThreadCtx tctx;
 inline unsigned char* g_dyn_lds = nullptr;
+// stream capture: launches are recorded while this is set (graphs replay them)
+inline std::vector<std::function<void()>>* g_capture = nullptr;
 
 struct BlockState {
   int nthreads = 0;
@@ -234,6 +244,11 @@ template <typename... KArgs, typename... Args>
 inline void hipLaunchKernelGGL(void (*k)(KArgs...), dim3 grid, dim3 block, size_t shmem,
                                hipStream_t, Args... args) {
   // a fresh dynamic-LDS buffer per block, sized exactly as requested
+  if (cpuhip::g_capture) {
+    cpuhip::g_capture->push_back(
+        [=] { cpuhip::launch(grid, block, [&] { k(args...); }, shmem); });
+    return;
+  }
   cpuhip::launch(grid, block, [&] { k(args...); }, shmem);
 }
 
@@ -261,6 +276,42 @@ inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {
   return hipSuccess;
 }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipStreamCreate(hipStream_t* s) {
+  *s = (hipStream_t) new int(0);
+  return hipSuccess;
+}
+inline hipError_t hipStreamDestroy(hipStream_t s) {
+  delete (int*)s;
+  return hipSuccess;
+}
+using cpuhip_graph = std::vector<std::function<void()>>;
+inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) {
+  if (cpuhip::g_capture) return hipErrorInvalidValue;
+  cpuhip::g_capture = new cpuhip_graph();
+  return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
+  *g = (hipGraph_t)cpuhip::g_capture;
+  cpuhip::g_capture = nullptr;
+  return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*,
+                                      size_t) {
+  *e = (hipGraphExec_t) new cpuhip_graph(*(cpuhip_graph*)g);
+  return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete (cpuhip_graph*)g;
+  return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+  delete (cpuhip_graph*)e;
+  return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  for (auto& f : *(cpuhip_graph*)e) f();
+  return hipSuccess;
+}
 inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
 inline hipError_t hipGetDeviceCount(int* n) {
   *n = 1;

@@ -130,6 +130,57 @@ def check_case(ctx, name, prob):
     c.free()
 
 
+def check_batch(ctx):
+    """An ensemble through the batched entry points against per-problem oracle results."""
+    probs = [synth.config5_member(q, s) for q, s in enumerate((150.0, 300.0, 90.0, 700.0))]
+    cases = [Case(ctx, pr, amg=rt.amg_opts(max_levels=1)) for pr in probs]
+    B = rt.rt_batch_create(ctx, [c.A for c in cases])
+    rows, nnz, tcols = rt.rt_batch_get_info(B)
+    offs = np.cumsum([0] + [pr.n_interior for pr in probs])
+    rng = np.random.default_rng(11)
+    bs, xref = [], []
+    for c, pr in zip(cases, probs):
+        sysm = oracle_system(pr)[3]
+        b = rng.standard_normal(pr.n_interior) * sysm.A.diagonal()
+        bs.append(b)
+        xref.append(linsolve.dense(sysm.A, b))
+    bcat = np.concatenate(bs)
+    for prec, tol, bar, graph in ((0, 1e-14, 1e-12, 0), (1, 1e-12, 1e-10, 0), (1, 1e-12, 1e-10, 3),
+                                  (0, 1e-14, 1e-12, 2)):
+        x = np.zeros(offs[-1])
+        s, st = rt.rt_batch_solve(ctx, B, len(probs), p(bcat), p(x),
+                                  rt.solve_opts(prec, 0, tol, 3000, 1e-4, 50), graph)
+        assert s == 0, f"batch solve status {s}"
+        for q in range(len(probs)):
+            xq = x[offs[q]:offs[q + 1]]
+            err = np.max(np.abs(xq - xref[q])) / np.max(np.abs(xref[q]))
+            assert err <= bar, f"batch solve prec={prec} graph={graph} problem {q}: {err}"
+    # three outer iterations of Algorithm 1 for every problem
+    e = np.concatenate([pr.e[:pr.n_interior] for pr in probs]).copy()
+    E = np.concatenate([pr.E[:pr.n_interior] for pr in probs]).copy()
+    nopts = rt.newton_opts(rt.solve_opts(0, 0, 1e-14, 3000))
+    for ell in range(3):
+        s, st = rt.rt_batch_newton_step(ctx, B, len(probs), p(e), p(E), ell, nopts, 2)
+        assert s == 0, f"batch newton status {s}"
+    for q, pr in enumerate(probs):
+        ref = ostep.time_step(pr.copy(), fixed_outer=3, solve_tol=1e-15)
+        ee = np.max(np.abs(e[offs[q]:offs[q + 1]] - ref.e) / ref.e)
+        eE = np.max(np.abs(E[offs[q]:offs[q + 1]] - ref.E) / ref.E)
+        assert ee <= 1e-12 and eE <= 1e-12, f"batch newton problem {q}: {ee} {eE}"
+        assert st[q].energy == pytest_approx(ref.energy_after), "batch energy"
+    rt.rt_batch_free(B)
+    for c in cases:
+        c.free()
+    say(f"ok batch: {len(probs)} problems, rows={rows} nnz={nnz} tile_cols={tcols}")
+
+
+def pytest_approx(v, rel=1e-12):
+    class _A:
+        def __eq__(self, o):
+            return abs(o - v) <= rel * abs(v)
+    return _A()
+
+
 def main():
     rt.load(os.environ["RT_CPU_LIB"])
     ctx = rt.rt_create(0, 0)
@@ -146,6 +197,8 @@ def main():
         if only and name not in only.split(","):
             continue
         check_case(ctx, name, prob)
+    if not only or "batch" in only.split(","):
+        check_batch(ctx)
     # error contract on the host
     pos = np.random.default_rng(0).uniform(0, 1, (3, 40))
     h = np.full(40, 0.2)

@@ -1,0 +1,148 @@
+"""Batched ensembles through the C ABI against the oracle, problem by problem.
+
+An ensemble of independent problems (the 2-D / 3-D mix of the ensemble
+workload, shrunk) is concatenated into one block-diagonal system.  Every
+problem's solution must match its own oracle solve (FP64 to 1e-12, mixed to
+1e-10, max-norm relative) whatever the graph replay length, and a batched
+Newton step must match the oracle's time step per problem.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_system, oracle_system, say
+from oracle import linsolve, step as ostep
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (150.0, 2200.0, 90.0, 5000.0, 700.0, 12000.0, 64.0, 3000.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2001_11606_amd import rt
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ensemble(ctx):
+    from paper_2001_11606_amd import rt
+    probs = [synth.config5_member(q, s) for q, s in enumerate(SIZES)]
+    systems = [gpu_system(ctx, pr, amg=rt.amg_opts(max_levels=1)) for pr in probs]
+    B = rt.rt_batch_create(ctx.handle, [A for (_, _, A) in systems])
+    yield probs, systems, B
+    rt.rt_batch_free(B)
+
+
+def _offsets(probs):
+    return np.cumsum([0] + [pr.n_interior for pr in probs])
+
+
+def _rhs(probs):
+    rng = np.random.default_rng(31)
+    bs, refs = [], []
+    for pr in probs:
+        A = oracle_system(pr)[3].A
+        b = rng.standard_normal(pr.n_interior) * A.diagonal()
+        bs.append(b)
+        refs.append(linsolve.dense(A, b) if pr.n_interior <= 4000
+                    else linsolve.pcg_jacobi(A, b, tol=1e-15)[0])
+    return bs, refs
+
+
+@pytest.mark.parametrize("precision,tol,bar", [(0, 1e-14, 1e-12), (1, 1e-12, 1e-10)])
+@pytest.mark.parametrize("graph", [0, 4])
+def test_batch_solve_matches_oracle(ctx, ensemble, precision, tol, bar, graph):
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B = ensemble
+    say(f"[batch solve] precision={precision} graph={graph} problems={len(probs)}")
+    bs, refs = _rhs(probs)
+    offs = _offsets(probs)
+    b = torch.tensor(np.concatenate(bs), device=ctx.device)
+    x = torch.zeros(offs[-1], dtype=torch.float64, device=ctx.device)
+    s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                              rt.solve_opts(precision, 0, tol, 4000, 1e-4, 50), graph)
+    assert s == rt.RT_OK, rt.rt_last_error()
+    xh = x.cpu().numpy()
+    for q, pr in enumerate(probs):
+        err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
+        assert err <= bar, (q, err, st[q].iterations)
+        assert st[q].rel_residual <= tol
+        if precision == 1:
+            assert st[q].refinements >= 1
+
+
+def test_batch_solve_equals_single_solves(ctx, ensemble):
+    """Each problem's batched FP64 solve reaches the same tolerance as its own
+    rt_solve, and the problems converge independently (different counts)."""
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B = ensemble
+    bs, refs = _rhs(probs)
+    offs = _offsets(probs)
+    b = torch.tensor(np.concatenate(bs), device=ctx.device)
+    x = torch.zeros(offs[-1], dtype=torch.float64, device=ctx.device)
+    s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                              rt.solve_opts(0, 0, 1e-12, 4000), 0)
+    assert s == rt.RT_OK
+    its_batch = [st[q].iterations for q in range(len(probs))]
+    its_single = []
+    for q, (dp, nb, A) in enumerate(systems):
+        xq = torch.zeros(probs[q].n_interior, dtype=torch.float64, device=ctx.device)
+        s1, st1 = ctx.solve(A, b[offs[q]:offs[q + 1]].clone(), xq, rt.solve_opts(0, 0, 1e-12, 4000))
+        assert s1 == rt.RT_OK
+        its_single.append(st1.iterations)
+    say(f"[batch] iterations batched {its_batch} single {its_single}")
+    # same algorithm; the reductions round differently, so allow one iteration either way
+    assert all(abs(a - b) <= 1 for a, b in zip(its_batch, its_single))
+    assert len(set(its_batch)) > 1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_newton_matches_oracle(ctx, ensemble, precision):
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B = ensemble
+    say(f"[batch newton] precision={precision}")
+    offs = _offsets(probs)
+    e = torch.tensor(np.concatenate([pr.e[:pr.n_interior] for pr in probs]), device=ctx.device)
+    E = torch.tensor(np.concatenate([pr.E[:pr.n_interior] for pr in probs]), device=ctx.device)
+    tol = 1e-14 if precision == 0 else 1e-12
+    nopts = rt.newton_opts(rt.solve_opts(precision, 0, tol, 4000, 1e-4, 50))
+    for ell in range(3):
+        s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), ell,
+                                        nopts, 4)
+        assert s == rt.RT_OK, rt.rt_last_error()
+    eh, Eh = e.cpu().numpy(), E.cpu().numpy()
+    bar = 1e-12 if precision == 0 else 1e-10
+    for q, pr in enumerate(probs):
+        ref = ostep.time_step(pr.copy(), fixed_outer=3, inner_tol_e=1e-14, solve_tol=1e-15)
+        err_e = np.max(np.abs(eh[offs[q]:offs[q + 1]] - ref.e) / np.abs(ref.e))
+        err_E = np.max(np.abs(Eh[offs[q]:offs[q + 1]] - ref.E) / np.abs(ref.E))
+        assert err_e <= bar and err_E <= bar, (q, err_e, err_E)
+        if precision == 0:
+            assert st[q].energy == pytest.approx(ref.energy_after, rel=1e-12)
+
+
+def test_batch_tune_and_errors(ctx, ensemble):
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B = ensemble
+    rep = rt.rt_batch_tune(ctx.handle, B, 2)
+    assert rep.levels == 1 and 0 <= rep.chosen[0][0] < rep.shapes
+    offs = _offsets(probs)
+    b = torch.ones(offs[-1], dtype=torch.float64, device=ctx.device)
+    x = torch.zeros_like(b)
+    with pytest.raises(rt.RtError):   # AMG is not offered for batches
+        rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                          rt.solve_opts(0, 1, 1e-10, 100), 0)
+    with pytest.raises(rt.RtError):
+        rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                          rt.solve_opts(0, 0, 1e-10, 100), -1)
+    with pytest.raises(rt.RtError):
+        rt.rt_batch_create(ctx.handle, [])
