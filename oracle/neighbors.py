@@ -116,3 +116,26 @@ def pairs(ptr: np.ndarray, idx: np.ndarray):
     """Expand CSR to (i, j) arrays."""
     n = ptr.shape[0] - 1
     return np.repeat(np.arange(n), np.diff(ptr)), idx.astype(np.int64)
+
+
+class Sampled:
+    """Ascending neighbour lists of chosen particles in a large set, without
+    building every pair: candidates within kappa * max(h) (slightly enlarged)
+    come from a k-d tree range query (a library primitive), and each candidate
+    is then decided by the pair predicate above."""
+
+    def __init__(self, pos: np.ndarray, h: np.ndarray, kappa: float):
+        from scipy.spatial import cKDTree
+        self.pos, self.h, self.kappa = pos, h, kappa
+        self.tree = cKDTree(np.ascontiguousarray(pos.T))
+        self.radius = kappa * float(np.max(h)) * (1.0 + 1e-9)
+        self.cache = {}
+
+    def of(self, i: int) -> np.ndarray:
+        i = int(i)
+        if i not in self.cache:
+            cand = np.asarray(self.tree.query_ball_point(self.pos[:, i], self.radius),
+                              dtype=np.int64)
+            m = pair_mask(self.pos, self.h, np.full(cand.shape, i), cand, self.kappa)
+            self.cache[i] = np.sort(cand[m]).astype(np.int32)
+        return self.cache[i]

@@ -160,3 +160,62 @@ def brookshaw(prob, ptr, idx, k: np.ndarray, g: np.ndarray) -> np.ndarray:
     # x_ij . dW_ij / |x_ij|^2 = 1/2 [W'(r,h_i)+W'(r,h_j)] / r = -F_ij
     w = V[J] * (k[I] + k[J]) * (g[I] - g[J]) * (-F)
     return np.bincount(I, weights=w, minlength=prob.n_total)
+
+
+def frozen_at(prob, ids, nbrs_of) -> dict:
+    """The frozen data of ``frozen`` for the particles ``ids`` only (same
+    formulas); ``nbrs_of(i)`` gives the ascending neighbour list of i, needed
+    for the flux limiter's gradient.  Returns {i: (sigma_a, f, V, D)}."""
+    out = {}
+    for i in ids:
+        i = int(i)
+        T = prob.e[i] / prob.cv[i]
+        sigma_a = prob.sigma0_a[i] * T ** prob.opacity_exponent
+        sigma_t = sigma_a + prob.sigma_s[i]
+        f = 1.0 / (1.0 + prob.c * sigma_a * prob.dt * 4.0 * prob.a * T ** 3 /
+                   (prob.rho[i] * prob.cv[i]))
+        V = prob.m[i] / prob.rho[i]
+        lam = 1.0 / 3.0
+        if prob.limiter != LIMITER_NONE and i < prob.n_interior:
+            J = nbrs_of(i).astype(np.int64)
+            I = np.full(J.shape, i)
+            r = np.sqrt(pair_r2(prob.pos, I, J))
+            F = -0.5 * (kernels.dWdr(r, prob.h[I], prob.dim, prob.kernel) +
+                        kernels.dWdr(r, prob.h[J], prob.dim, prob.kernel)) / r
+            Vj = prob.m[J] / prob.rho[J]
+            w = Vj * (prob.E[J] - prob.E[i]) * (-F)
+            g = np.array([np.sum(w * (prob.pos[ax][i] - prob.pos[ax][J]))
+                          for ax in range(prob.dim)])
+            R = np.sqrt(np.sum(g * g)) / (sigma_t * prob.E[i])
+            lam = float(flux_limiter(np.array([R]), prob.limiter, prob.limiter_k)[0])
+        out[i] = (sigma_a, f, V, prob.c * lam / sigma_t)
+    return out
+
+
+def rows_at(prob, rows, nbrs_of) -> dict:
+    """Rows of the V-scaled system of ``assemble`` for the interior particles
+    ``rows`` only (same formulas).  Returns {i: (diag, cols, vals, g_i)} with
+    the interior columns ascending."""
+    nin = prob.n_interior
+    need = set(int(i) for i in rows)
+    for i in rows:
+        need.update(int(j) for j in nbrs_of(i))
+    fz = frozen_at(prob, sorted(need), nbrs_of)
+    out = {}
+    for i in rows:
+        i = int(i)
+        J = nbrs_of(i).astype(np.int64)
+        I = np.full(J.shape, i)
+        r = np.sqrt(pair_r2(prob.pos, I, J))
+        F = -0.5 * (kernels.dWdr(r, prob.h[I], prob.dim, prob.kernel) +
+                    kernels.dWdr(r, prob.h[J], prob.dim, prob.kernel)) / r
+        sa_i, f_i, V_i, D_i = fz[i]
+        Vj = np.array([fz[int(j)][2] for j in J])
+        Dj = np.array([fz[int(j)][3] for j in J])
+        a = Vj * (D_i + Dj) * F
+        diag = V_i * (1.0 / prob.dt + prob.c * sa_i * f_i) + V_i * np.sum(a)
+        inner = J < nin
+        vals = -(V_i * Vj[inner]) * (D_i + Dj[inner]) * F[inner]
+        g = V_i * np.sum(a[~inner] * prob.E[J[~inner]])
+        out[i] = (diag, J[inner].astype(np.int32), vals, g)
+    return out

@@ -173,3 +173,32 @@ def test_fleck_factor_is_schur_complement_of_jacobian():
     J_me = p.rho / p.dt + p.c / p.cv * fz.sigma_a * dBdT
     J_re = -p.c / p.cv * fz.sigma_a * dBdT
     assert np.allclose(J_re / J_me, fz.f - 1.0, rtol=1e-13, atol=1e-15)
+
+
+def test_sampled_rows_match_full_assembly():
+    """The per-row oracle (used at full sizes) equals the full assembly on a
+    problem with ghosts and one with the flux limiter; its neighbour lists
+    equal the brute-force ones."""
+    import synth
+    from oracle import neighbors, operator
+    for prob in (synth.config4(n=10), synth.config3(n=10)):
+        kappa = 2.0
+        ptr, idx = neighbors.brute_force(prob.pos, prob.h, kappa)
+        sam = neighbors.Sampled(prob.pos, prob.h, kappa)
+        for i in range(0, prob.n_total, 37):
+            assert np.array_equal(sam.of(i), idx[ptr[i]:ptr[i + 1]])
+        fz = operator.frozen(prob, ptr, idx)
+        sysm = operator.assemble(prob, ptr, idx, fz)
+        rows = list(range(0, prob.n_interior, 17))
+        got = operator.rows_at(prob, rows, sam.of)
+        A = sysm.A
+        for i in rows:
+            diag, cols, vals, g = got[i]
+            lo, hi = A.indptr[i], A.indptr[i + 1]
+            c_ref, v_ref = A.indices[lo:hi], A.data[lo:hi]
+            off = c_ref != i
+            scale = np.max(np.abs(v_ref))
+            assert np.array_equal(cols, c_ref[off])
+            assert np.max(np.abs(vals - v_ref[off]), initial=0.0) <= 1e-14 * scale
+            assert abs(diag - v_ref[~off][0]) <= 1e-14 * scale
+            assert abs(g - sysm.g[i]) <= 1e-14 * max(abs(sysm.g[i]), scale)
