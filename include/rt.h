@@ -283,6 +283,18 @@ typedef struct {
 int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
                    const rt_newton_opts* opts, rt_newton_stats* stats);
 
+/* ---- time-step control (Sec. 3.3) -----------------------------------------
+ * The fractional changes of the material and radiation energies over a step,
+ *   eta_e = max_i |e_i^n - e_i^{n-1}| / (e_i^n + eta_target ebar^n + tiny),
+ * ebar^n = sum_i e_i^n V_i / sum_i V_i over interior particles (V from A), and
+ * eta_E likewise for E; eta[0] = eta_e, eta[1] = eta_E.  The next step is
+ * dt (eta_target / eta)^(1/2), the smaller of the two, within the user's
+ * bounds (the host driver applies that rule).  e_*, E_*: n_interior doubles,
+ * user order, device; tiny (>= 0) guards an energy that is zero everywhere. */
+int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
+                         const double* e_old, const double* E_new, const double* E_old,
+                         double eta_target, double tiny, double* eta);
+
 /* ---- ensembles of independent problems (Sec. 3.2 per problem, batched) ----
  * Not in the paper: many independent problems advanced together, one launch
  * per kernel for the whole ensemble.  rt_batch_create concatenates the

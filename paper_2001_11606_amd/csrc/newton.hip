@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 #include "material.h"
@@ -118,8 +119,97 @@ int material(rt_ctx* ctx, rt_matrix* A, const double* E_new, const double* E_old
   return RT_OK;
 }
 
+// pass 1: sums of e V, E V and V; pass 2: the largest fractional changes
+__global__ void __launch_bounds__(kBlock)
+k_frac_sums(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ V,
+            const double* __restrict__ e, const double* __restrict__ E, double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double se = 0.0, sE = 0.0, sv = 0.0;
+  for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * kBlock) {
+    const int32_t u = perm[s];
+    se += e[u] * V[s];
+    sE += E[u] * V[s];
+    sv += V[s];
+  }
+  se = block_sum(se, red);
+  sE = block_sum(sE, red);
+  sv = block_sum(sv, red);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = se;
+    part[3 * blockIdx.x + 1] = sE;
+    part[3 * blockIdx.x + 2] = sv;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_frac_max(int64_t n, const double* __restrict__ e_new, const double* __restrict__ e_old,
+           const double* __restrict__ E_new, const double* __restrict__ E_old, double pe,
+           double pE, double tiny, double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double me = 0.0, mE = 0.0;
+  for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * kBlock) {
+    me = fmax(me, fabs(e_new[u] - e_old[u]) / (e_new[u] + pe + tiny));
+    mE = fmax(mE, fabs(E_new[u] - E_old[u]) / (E_new[u] + pE + tiny));
+  }
+  me = block_max(me, red);
+  mE = block_max(mE, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = me;
+    part[2 * blockIdx.x + 1] = mE;
+  }
+}
+
 }  // namespace
 }  // namespace rt
+
+extern "C" int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
+                                    const double* e_old, const double* E_new,
+                                    const double* E_old, double eta_target, double tiny,
+                                    double* eta) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !A || !eta || (A->n > 0 && (!e_new || !e_old || !E_new || !E_old))) {
+    set_error("rt_fractional_change: NULL argument");
+    return RT_E_ARG;
+  }
+  if (!(eta_target > 0.0) || !(tiny >= 0.0)) {
+    set_error("rt_fractional_change: eta_target must be > 0 and tiny >= 0");
+    return RT_E_ARG;
+  }
+  eta[0] = eta[1] = 0.0;
+  const int64_t n = A->n;
+  if (n == 0) return RT_OK;
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int g = grid_for(n, kBlock, kMaxPartials);
+  DevBuf<double> part;
+  RT_CHECK(part.reserve((size_t)3 * g));
+  std::vector<double> hp((size_t)3 * g);
+  hipLaunchKernelGGL(k_frac_sums, dim3(g), dim3(kBlock), 0, st, n, A->nb->perm.p, A->V.p, e_new,
+                     E_new, part.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 3 * g, hipMemcpyDeviceToHost, st));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  double se = 0.0, sE = 0.0, sv = 0.0;
+  for (int b = 0; b < g; ++b) {
+    se += hp[3 * b];
+    sE += hp[3 * b + 1];
+    sv += hp[3 * b + 2];
+  }
+  const double ebar = se / sv, Ebar = sE / sv;
+  hipLaunchKernelGGL(k_frac_max, dim3(g), dim3(kBlock), 0, st, n, e_new, e_old, E_new, E_old,
+                     eta_target * ebar, eta_target * Ebar, tiny, part.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 2 * g, hipMemcpyDeviceToHost, st));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < g; ++b) {
+    eta[0] = std::max(eta[0], hp[2 * b]);
+    eta[1] = std::max(eta[1], hp[2 * b + 1]);
+  }
+  return RT_OK;
+}
 
 extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
                               const rt_newton_opts* opts, rt_newton_stats* stats) {

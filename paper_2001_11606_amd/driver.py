@@ -110,3 +110,44 @@ def advance(dp: DeviceProblem, e, E) -> None:
     nin = dp.n_interior
     dp.arrays["e"][:nin] = e
     dp.arrays["E"][:nin] = E
+
+
+def run_adaptive(ctx: rt.Context, dp: DeviceProblem, t_end: float, dt0: float,
+                 eta_target: float = 0.05, dt_min: float = 0.0, dt_max: float = float("inf"),
+                 max_growth: float = 10.0, amg: Optional[rt.rt_amg_opts] = None,
+                 solve: Optional[rt.rt_solve_opts] = None, eps_e: float = 1e-8,
+                 eps_E: float = 1e-8, material_tol: float = 1e-14, tiny: float = 1e-15,
+                 callback=None):
+    """Time steps from t = 0 to t_end with the step control of Sec. 3.3.
+
+    The particles are stationary, so the neighbour lists and the matrix
+    structure are built once; every step re-assembles the values on that
+    structure and runs Algorithm 1 to the outer tolerances.  After a step the
+    library returns the fractional changes (eta_e, eta_E) and the next step is
+    dt (eta_target/eta)^(1/2) for the more restrictive of the two, at most
+    max_growth times the last step, within [dt_min, dt_max]; the last step is
+    shortened to land on t_end.  Returns (steps, [(t, dt, StepReport)]).
+    callback(t, e, E) is called after every step."""
+    nin = dp.n_interior
+    nb = ctx.build_neighbors(dp.pos, dp.h, nin, dp.kernel)
+    A = 0
+    t, dt = 0.0, dt0
+    history = []
+    while t < t_end * (1.0 - 1e-14):
+        dt = min(dt, t_end - t)
+        dp.dt = dt
+        e_old = dp.arrays["e"][:nin].clone()
+        E_old = dp.arrays["E"][:nin].clone()
+        e, E, A, rep = time_step(ctx, dp, nb, A=A, amg=amg, solve=solve, eps_e=eps_e, eps_E=eps_E,
+                                 material_tol=material_tol)
+        eta_e, eta_E = rt.rt_fractional_change(ctx.handle, A, e.data_ptr(), e_old.data_ptr(),
+                                               E.data_ptr(), E_old.data_ptr(), eta_target, tiny)
+        advance(dp, e, E)
+        t += dt
+        history.append((t, dt, rep))
+        if callback:
+            callback(t, e, E)
+        props = [dt * (eta_target / eta) ** 0.5 if eta > 0.0 else float("inf")
+                 for eta in (eta_e, eta_E)]
+        dt = max(dt_min, min(min(props), max_growth * dt, dt_max))
+    return len(history), history

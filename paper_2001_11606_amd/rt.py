@@ -118,6 +118,8 @@ _SIGS = {
                                ctypes.POINTER(c_int), c_int]),
     "rt_matrix_tune": (c_int, [c_vp, c_vp, c_int, ctypes.POINTER(rt_tune_report)]),
     "rt_matrix_set_spmv_shape": (c_int, [c_vp, c_int, c_int, c_int]),
+    "rt_fractional_change": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl,
+                                     ctypes.POINTER(c_dbl)]),
     "rt_batch_create": (c_int, [c_vp, c_int, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp)]),
     "rt_batch_free": (None, [c_vp]),
     "rt_batch_get_info": (c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
@@ -259,6 +261,14 @@ def rt_matrix_tune(ctx: int, A: int, reps: int) -> rt_tune_report:
 
 def rt_matrix_set_spmv_shape(A: int, level: int, precision: int, shape: int) -> None:
     _check("rt_matrix_set_spmv_shape", load().rt_matrix_set_spmv_shape(A, level, precision, shape))
+
+
+def rt_fractional_change(ctx: int, A: int, e_new: int, e_old: int, E_new: int, E_old: int,
+                         eta_target: float, tiny: float = 1e-15) -> tuple:
+    eta = (c_dbl * 2)()
+    _check("rt_fractional_change", load().rt_fractional_change(ctx, A, e_new, e_old, E_new, E_old,
+                                                               eta_target, tiny, eta))
+    return eta[0], eta[1]
 
 
 def rt_batch_create(ctx: int, mats: list) -> int:
