@@ -382,10 +382,12 @@ def main():
         rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_MIXED, s32)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    eb = dp.arrays["e"][:nin].clone()
-    Eb = dp.arrays["E"][:nin].clone()
+    eb = torch.empty(nin, dtype=torch.float64, device=ctx.device)
+    Eb = torch.empty_like(eb)
+    rt.rt_to_sorted(ctx.handle, nbb.handle, dp.arrays["e"].data_ptr(), eb.data_ptr())
+    rt.rt_to_sorted(ctx.handle, nbb.handle, dp.arrays["E"].data_ptr(), Eb.data_ptr())
     nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, args.precond, args.tol, 5000,
-                                         args.inner_tol, 30))
+                                         args.inner_tol, 30), state_order=1)
     solve_b = 0.0
     for ell in range(args.outer):
         _, stb = ctx.newton_step(Ab, eb, Eb, ell, nopts)

@@ -262,11 +262,16 @@ int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
  * stats: delta_e = max_i |e^{l+1} - e^l|/|e^{l+1}|, delta_E likewise
  * (Sec. 2.2 convergence test), energy = sum_i (m_i e_i + V_i E_i) (Sec. 2.5).
  * Returns RT_NONPHYSICAL if a material root was negative, RT_NOT_CONVERGED
- * if the linear or a material solve did not converge.                        */
+ * if the linear or a material solve did not converge.
+ * state_order 0: e and E are in user order; 1: in the library's cell-sorted
+ * order of the neighbour object (rt_to_sorted / rt_to_user convert), which
+ * saves two gathers and two scatters per call for callers that keep their
+ * state in that order between steps (particles are stationary).             */
 typedef struct {
   rt_solve_opts solve;
   double material_tol;
   int material_max_iter;
+  int state_order;
 } rt_newton_opts;
 
 typedef struct {
@@ -282,6 +287,11 @@ typedef struct {
 
 int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
                    const rt_newton_opts* opts, rt_newton_stats* stats);
+
+/* Interior per-particle vectors between user order and the library's sorted
+ * order (n = n_interior doubles, device; in and out must not overlap).      */
+int rt_to_sorted(rt_ctx* ctx, const rt_neighbors* nb, const double* user, double* sorted);
+int rt_to_user(rt_ctx* ctx, const rt_neighbors* nb, const double* sorted, double* user);
 
 /* ---- time-step control (Sec. 3.3) -----------------------------------------
  * The fractional changes of the material and radiation energies over a step,

@@ -841,8 +841,10 @@ int rt_batch_newton_step(rt_ctx* ctx, rt_batch* B, double* e, double* E, int ell
     set_error("rt_batch_newton_step: mixed precision needs FP32 copies in every matrix");
     return RT_E_STATE;
   }
-  if (!(opts->material_tol > 0.0) || opts->material_max_iter < 1 || graph_iters < 0) {
-    set_error("rt_batch_newton_step: invalid material options or graph_iters");
+  if (!(opts->material_tol > 0.0) || opts->material_max_iter < 1 || graph_iters < 0 ||
+      opts->state_order != 0) {
+    set_error("rt_batch_newton_step: invalid material options, graph_iters or state_order "
+              "(batches take user order)");
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));

@@ -220,8 +220,9 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
     return RT_E_ARG;
   }
   RT_CHECK(check_solve_opts(&opts->solve));
-  if (!(opts->material_tol > 0.0) || opts->material_max_iter < 1) {
-    set_error("rt_newton_step: material_tol must be > 0 and material_max_iter >= 1");
+  if (!(opts->material_tol > 0.0) || opts->material_max_iter < 1 ||
+      (opts->state_order != 0 && opts->state_order != 1)) {
+    set_error("rt_newton_step: material_tol must be > 0, material_max_iter >= 1, state_order 0 or 1");
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
@@ -233,28 +234,34 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   if (n == 0) return RT_OK;
   hipStream_t st = ctx->stream;
   for (auto* b : {&A->ecur, &A->Ecur, &A->enew, &A->xs, &A->bs}) RT_CHECK(b->reserve(n));
-  RT_CHECK(gather_sorted(ctx, A->nb, n, e, A->ecur.p));
-  RT_CHECK(gather_sorted(ctx, A->nb, n, E, A->Ecur.p));
+  const bool in_sorted = opts->state_order == 1;
+  // the state in sorted order: the caller's arrays themselves, or gathered copies
+  double* ecur = in_sorted ? e : A->ecur.p;
+  double* Ecur = in_sorted ? E : A->Ecur.p;
+  if (!in_sorted) {
+    RT_CHECK(gather_sorted(ctx, A->nb, n, e, ecur));
+    RT_CHECK(gather_sorted(ctx, A->nb, n, E, Ecur));
+  }
   double res[8];
   int status = RT_OK;
   if (ell == 0) {
     // initial material solve with E^{n,0} from e^{n-1} (Algorithm 1, before the loop)
-    RT_CHECK(material(ctx, A, A->Ecur.p, A->Ecur.p, A->e_prev.p, A->ecur.p, opts->material_tol,
+    RT_CHECK(material(ctx, A, Ecur, Ecur, A->e_prev.p, ecur, opts->material_tol,
                       opts->material_max_iter, res));
     if (res[3] > 0) status = RT_NOT_CONVERGED;
     if (res[4] > 0) status = RT_NONPHYSICAL;
   }
   hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->dt, A->c, A->a, A->V.p,
-                     A->sa.p, A->f.p, A->cv.p, A->E_prev.p, A->QE.p, A->g.p, A->ecur.p,
-                     A->Ecur.p, A->bs.p);
+                     A->sa.p, A->f.p, A->cv.p, A->E_prev.p, A->QE.p, A->g.p, ecur, Ecur,
+                     A->bs.p);
   RT_LAUNCH_CHECK();
-  RT_CHECK_HIP(hipMemcpyAsync(A->xs.p, A->Ecur.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  RT_CHECK_HIP(hipMemcpyAsync(A->xs.p, Ecur, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   RT_CHECK_HIP(hipEventRecord(ctx->ev0, st));
   int s = solve_sorted(ctx, A, A->bs.p, A->xs.p, &opts->solve, &stt->solve);
   if (s < 0) return s;
   RT_CHECK_HIP(hipEventRecord(ctx->ev1, st));
   if (s == RT_NOT_CONVERGED) status = RT_NOT_CONVERGED;
-  RT_CHECK(material(ctx, A, A->xs.p, A->Ecur.p, A->ecur.p, A->enew.p, opts->material_tol,
+  RT_CHECK(material(ctx, A, A->xs.p, Ecur, ecur, A->enew.p, opts->material_tol,
                     opts->material_max_iter, res));
   stt->delta_e = res[0];
   stt->delta_E = res[1];
@@ -264,8 +271,13 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   stt->energy_prev = res[6];
   if (res[3] > 0 && status == RT_OK) status = RT_NOT_CONVERGED;
   if (res[4] > 0) status = RT_NONPHYSICAL;
-  RT_CHECK(scatter_user(ctx, A->nb, n, A->enew.p, e));
-  RT_CHECK(scatter_user(ctx, A->nb, n, A->xs.p, E));
+  if (in_sorted) {
+    RT_CHECK_HIP(hipMemcpyAsync(e, A->enew.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    RT_CHECK_HIP(hipMemcpyAsync(E, A->xs.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  } else {
+    RT_CHECK(scatter_user(ctx, A->nb, n, A->enew.p, e));
+    RT_CHECK(scatter_user(ctx, A->nb, n, A->xs.p, E));
+  }
   RT_CHECK_HIP(hipStreamSynchronize(st));
   float solve_ms = 0.f;
   RT_CHECK_HIP(hipEventElapsedTime(&solve_ms, ctx->ev0, ctx->ev1));
@@ -276,4 +288,30 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   else if (status == RT_NOT_CONVERGED && rt_last_error()[0] == 0)
     set_error("rt_newton_step: a material solve did not converge");
   return status;
+}
+
+extern "C" int rt_to_sorted(rt_ctx* ctx, const rt_neighbors* nb, const double* user,
+                            double* sorted) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !nb || (nb->n_interior > 0 && (!user || !sorted))) {
+    set_error("rt_to_sorted: NULL argument");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  if (nb->n_interior > 0) RT_CHECK(gather_sorted(ctx, nb, nb->n_interior, user, sorted));
+  return RT_OK;
+}
+
+extern "C" int rt_to_user(rt_ctx* ctx, const rt_neighbors* nb, const double* sorted,
+                          double* user) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !nb || (nb->n_interior > 0 && (!user || !sorted))) {
+    set_error("rt_to_user: NULL argument");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  if (nb->n_interior > 0) RT_CHECK(scatter_user(ctx, nb, nb->n_interior, sorted, user));
+  return RT_OK;
 }

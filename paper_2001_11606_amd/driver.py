@@ -65,11 +65,13 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
               amg: Optional[rt.rt_amg_opts] = None, solve: Optional[rt.rt_solve_opts] = None,
               eps_e: float = 1e-8, eps_E: float = 1e-8, material_tol: float = 1e-14,
               max_outer: int = 50, fixed_outer: Optional[int] = None,
-              shapes: Optional[list] = None):
+              shapes: Optional[list] = None, sorted_state: bool = True):
     """One backward-Euler step.  Returns (e, E, A, report) with e, E the new
     interior energies (device tensors, user order).  shapes: per-level
     (FP64, FP32) SpMV shape indices, e.g. the "chosen" list of Context.tune on
-    an earlier matrix of the same problem, applied after assembly."""
+    an earlier matrix of the same problem, applied after assembly.
+    sorted_state: keep e, E in the library's sorted order during the outer
+    iterations (one conversion each way per step instead of per iteration)."""
     A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                      dp.limiter_k, amg=amg, A=A)
     if shapes:
@@ -78,10 +80,17 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
             rt.rt_matrix_set_spmv_shape(A, lvl, rt.RT_PREC_FP64, s64)
             rt.rt_matrix_set_spmv_shape(A, lvl, rt.RT_PREC_MIXED, s32)
     nin = dp.n_interior
-    e = dp.arrays["e"][:nin].clone()
-    E = dp.arrays["E"][:nin].clone()
+    import torch
+    e_user = dp.arrays["e"][:nin].clone()
+    E_user = dp.arrays["E"][:nin].clone()
+    if sorted_state:
+        e, E = torch.empty_like(e_user), torch.empty_like(E_user)
+        rt.rt_to_sorted(ctx.handle, nb.handle, e_user.data_ptr(), e.data_ptr())
+        rt.rt_to_sorted(ctx.handle, nb.handle, E_user.data_ptr(), E.data_ptr())
+    else:
+        e, E = e_user, E_user
     solve = solve or rt.solve_opts()
-    nopts = rt.newton_opts(solve, material_tol)
+    nopts = rt.newton_opts(solve, material_tol, state_order=1 if sorted_state else 0)
     rep = StepReport()
     n_outer = fixed_outer if fixed_outer is not None else max_outer
     for ell in range(n_outer):
@@ -102,6 +111,10 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
         rep.spmv32_seconds += st.solve.spmv32_seconds
         if fixed_outer is None and st.delta_e < eps_e and st.delta_E < eps_E:
             break
+    if sorted_state:
+        rt.rt_to_user(ctx.handle, nb.handle, e.data_ptr(), e_user.data_ptr())
+        rt.rt_to_user(ctx.handle, nb.handle, E.data_ptr(), E_user.data_ptr())
+        e, E = e_user, E_user
     return e, E, A, rep
 
 

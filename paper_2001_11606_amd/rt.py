@@ -76,7 +76,8 @@ class rt_solve_stats(ctypes.Structure):
 
 
 class rt_newton_opts(ctypes.Structure):
-    _fields_ = [("solve", rt_solve_opts), ("material_tol", c_dbl), ("material_max_iter", c_int)]
+    _fields_ = [("solve", rt_solve_opts), ("material_tol", c_dbl), ("material_max_iter", c_int),
+                ("state_order", c_int)]
 
 
 class rt_newton_stats(ctypes.Structure):
@@ -118,6 +119,8 @@ _SIGS = {
                                ctypes.POINTER(c_int), c_int]),
     "rt_matrix_tune": (c_int, [c_vp, c_vp, c_int, ctypes.POINTER(rt_tune_report)]),
     "rt_matrix_set_spmv_shape": (c_int, [c_vp, c_int, c_int, c_int]),
+    "rt_to_sorted": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "rt_to_user": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "rt_fractional_change": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl,
                                      ctypes.POINTER(c_dbl)]),
     "rt_batch_create": (c_int, [c_vp, c_int, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp)]),
@@ -263,6 +266,14 @@ def rt_matrix_set_spmv_shape(A: int, level: int, precision: int, shape: int) -> 
     _check("rt_matrix_set_spmv_shape", load().rt_matrix_set_spmv_shape(A, level, precision, shape))
 
 
+def rt_to_sorted(ctx: int, nb: int, user: int, sorted_: int) -> None:
+    _check("rt_to_sorted", load().rt_to_sorted(ctx, nb, user, sorted_))
+
+
+def rt_to_user(ctx: int, nb: int, sorted_: int, user: int) -> None:
+    _check("rt_to_user", load().rt_to_user(ctx, nb, sorted_, user))
+
+
 def rt_fractional_change(ctx: int, A: int, e_new: int, e_old: int, E_new: int, E_old: int,
                          eta_target: float, tiny: float = 1e-15) -> tuple:
     eta = (c_dbl * 2)()
@@ -356,8 +367,9 @@ def amg_opts(max_levels=8, coarse_size=256, strength=0.08, build_fp32=1,
     return rt_amg_opts(max_levels, coarse_size, strength, build_fp32, tiled_spmv)
 
 
-def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100) -> rt_newton_opts:
-    return rt_newton_opts(solve, material_tol, material_max_iter)
+def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100,
+                state_order=0) -> rt_newton_opts:
+    return rt_newton_opts(solve, material_tol, material_max_iter, state_order)
 
 
 @dataclass

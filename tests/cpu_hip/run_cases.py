@@ -125,6 +125,23 @@ def check_case(ctx, name, prob):
     ee = np.max(np.abs(e_ - ref.e) / ref.e)
     eE = np.max(np.abs(E_ - ref.E) / ref.E)
     assert ee <= 1e-12 and eE <= 1e-12, f"{name}: newton {ee} {eE}"
+    # the same steps with the state kept in the library's sorted order
+    es = np.zeros(nin)
+    Es = np.zeros(nin)
+    e_in = c.arr["e"][:nin].copy()
+    E_in = c.arr["E"][:nin].copy()
+    rt.rt_to_sorted(ctx, c.nb, p(e_in), p(es))
+    rt.rt_to_sorted(ctx, c.nb, p(E_in), p(Es))
+    nso = rt.newton_opts(rt.solve_opts(0, 1, 1e-14, 3000), state_order=1)
+    for ell in range(n_outer):
+        s, st = rt.rt_newton_step(ctx, c.A, p(es), p(Es), ell, nso)
+        assert s == 0, f"{name}: sorted newton status {s}"
+    eu = np.zeros(nin)
+    Eu = np.zeros(nin)
+    rt.rt_to_user(ctx, c.nb, p(es), p(eu))
+    rt.rt_to_user(ctx, c.nb, p(Es), p(Eu))
+    assert np.max(np.abs(eu - e_) / e_) <= 1e-13 and np.max(np.abs(Eu - E_) / E_) <= 1e-13, \
+        f"{name}: sorted-order state"
     say(f"ok {name}: n={prob.n_total} pairs={info.nnz} levels={info.levels} "
         f"err(values)={err:.1e} newton=({ee:.1e},{eE:.1e})")
     c.free()
