@@ -420,7 +420,9 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
 #undef RT_KEYS
   RT_LAUNCH_CHECK();
   const int end_bit = dim * bits + 1;
-  RT_CHECK(radix_sort_pairs(ctx, keys.p, nb->skeys.p, ids.p, nb->perm.p, n, end_bit));
+  bool sorted = false;
+  RT_CHECK(bucket_sort_pairs(ctx, keys.p, nb->skeys.p, ids.p, nb->perm.p, n, end_bit, &sorted));
+  if (!sorted) RT_CHECK(radix_sort_pairs(ctx, keys.p, nb->skeys.p, ids.p, nb->perm.p, n, end_bit));
   keys.release();
   ids.release();
   hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, dim, n,

@@ -129,6 +129,31 @@ __global__ void k_row_sort(int64_t nseg, const int64_t* __restrict__ off, K* __r
   }
 }
 
+// counting sort: bucket sizes, then every item to its bucket's next free slot
+__global__ void k_bucket_count(int64_t n, const uint64_t* __restrict__ keys,
+                               int32_t* __restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[keys[i]], 1);
+}
+
+__global__ void k_bucket_scatter(int64_t n, const uint64_t* __restrict__ kin,
+                                 const int32_t* __restrict__ vin, int32_t* __restrict__ cur,
+                                 uint64_t* __restrict__ kout, int32_t* __restrict__ vout) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = kin[i];
+  const int32_t d = atomicAdd(&cur[k], 1);
+  kout[d] = k;
+  vout[d] = vin[i];
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t* __restrict__ p, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_set_last(int64_t* p, int64_t v) { *p = v; }
+
 // per-block maximum of non-negative values (grid-stride)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -161,6 +186,39 @@ int max_nonneg(rt_ctx* ctx, const T* in, int64_t n, T* out) {
 }
 
 template int max_nonneg<int64_t>(rt_ctx*, const int64_t*, int64_t, int64_t*);
+template int max_nonneg<int32_t>(rt_ctx*, const int32_t*, int64_t, int32_t*);
+
+int bucket_sort_pairs(rt_ctx* ctx, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                      int32_t* vout, int64_t n, int key_bits, bool* done) {
+  *done = false;
+  if (key_bits > kBucketSortMaxBits || n <= 0 || n >= ((int64_t)1 << 31)) return RT_OK;
+  hipStream_t st = ctx->stream;
+  const int64_t nb = (int64_t)1 << key_bits;
+  DevBuf<int32_t> cnt, cur;
+  DevBuf<int64_t> off;
+  RT_CHECK(cnt.reserve(nb));
+  RT_CHECK(cur.reserve(nb));
+  RT_CHECK(off.reserve(nb + 1));
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb)), dim3(kBlock), 0, st, nb, cnt.p, 0);
+  RT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(n)), dim3(kBlock), 0, st, n, kin, cnt.p);
+  RT_LAUNCH_CHECK();
+  int32_t maxb = 0;
+  RT_CHECK(max_nonneg<int32_t>(ctx, cnt.p, nb, &maxb));
+  if (maxb > kBucketSortMaxBucket) return RT_OK;   // long buckets: the split sort does better
+  RT_CHECK((scan<int32_t, int32_t>(ctx, cnt.p, cur.p, nb, false)));
+  RT_CHECK((scan<int32_t, int64_t>(ctx, cnt.p, off.p, nb, false)));
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, n, kin, vin, cur.p,
+                     kout, vout);
+  RT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, off.p + nb, n);
+  RT_LAUNCH_CHECK();
+  // the scatter order within a bucket is arbitrary: restore the input order
+  RT_CHECK((row_sort<int32_t, int32_t>(ctx, off.p, vout, nullptr, nb)));
+  RT_CHECK_HIP(hipStreamSynchronize(st));   // the temporaries are freed on return
+  *done = true;
+  return RT_OK;
+}
 
 template <typename In, typename Out>
 int scan(rt_ctx* ctx, const In* in, Out* out, int64_t n, bool inclusive) {
