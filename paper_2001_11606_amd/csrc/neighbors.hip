@@ -175,15 +175,45 @@ __global__ void k_run_starts(int64_t n, const int32_t* __restrict__ flags,
 
 constexpr int kNbrCand = 512;   // candidates staged in LDS per pass
 constexpr int kNbrRows = 512;   // rows of one cell handled per pass
+constexpr double kNbrMaskBytes = 4.0e9;   // largest hit-mask buffer kept between the passes
 
-template <int DIM, bool FILL>
+// Candidates of a cell: the particle count of its 2 * 3^DIM adjacent-cell slots.
+template <int DIM>
+__global__ void k_cell_candidates(int64_t nruns, int bits, int64_t ncells, int nc0, int nc1,
+                                  int nc2, const int32_t* __restrict__ runs,
+                                  const uint64_t* __restrict__ skeys,
+                                  const int32_t* __restrict__ cstart,
+                                  const int32_t* __restrict__ cend, int32_t* __restrict__ m) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nruns) return;
+  const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
+  int c[3];
+  demorton<DIM>(bits, skeys[runs[q]] & mask, c);
+  int32_t total = 0;
+  for (int flag = 0; flag < 2; ++flag)
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
+          if (x < 0 || x >= nc0 || y < 0 || y >= nc1 || z < 0 || z >= nc2) continue;
+          const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
+          total += cend[cell] - cstart[cell];
+        }
+  m[q] = total;
+}
+
+// FILL = false: count neighbours per row and, when masks is not NULL, store
+// every 64-candidate hit mask (row s, candidate chunk q at masks[s*mstride+q]).
+// FILL = true, FROM_MASK = true: write the lists from those masks (no distance
+// tests, no staged positions); FROM_MASK = false: test the pairs again.
+template <int DIM, bool FILL, bool FROM_MASK>
 __global__ void __launch_bounds__(kBlock)
 k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
             double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ skeys,
             const double* __restrict__ sp4, const int32_t* __restrict__ cstart,
             const int32_t* __restrict__ cend,
             int64_t* __restrict__ cnt, const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
-            int32_t* __restrict__ n_int_nbrs) {
+            int32_t* __restrict__ n_int_nbrs, uint64_t* __restrict__ masks, int mstride) {
   constexpr int NB = DIM == 3 ? 27 : 9;   // adjacent cells per flag
   __shared__ double cx[kNbrCand], cy[kNbrCand], cz[kNbrCand], ch[kNbrCand];
   __shared__ int32_t ct[kNbrCand];
@@ -235,12 +265,14 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           else hi = mid;
         }
         const int32_t t = rlo[lo] + (kk - roff[lo]);
-        const Rec4 q = load_rec4(sp4, t);
         ct[k] = t;
-        cx[k] = q.x;
-        cy[k] = q.y;
-        cz[k] = q.z;
-        ch[k] = q.h;
+        if (!FROM_MASK) {
+          const Rec4 q = load_rec4(sp4, t);
+          cx[k] = q.x;
+          cy[k] = q.y;
+          cz[k] = q.z;
+          ch[k] = q.h;
+        }
       }
       __syncthreads();
       // the block's own cell is the centre slot of its flag: its rows are candidates too
@@ -248,8 +280,10 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
       for (int r = wave; r < nrows; r += kBlock / kWave) {
         const int64_t s = rb + r;
         const int ks = roff[cslot] + (int)(s - rlo[cslot]) - c0;
-        double xi, yi, zi, hi;
-        if (ks >= 0 && ks < mc) {
+        double xi = 0.0, yi = 0.0, zi = 0.0, hi = 0.0;
+        if (FROM_MASK) {
+          // positions are not needed
+        } else if (ks >= 0 && ks < mc) {
           xi = cx[ks];
           yi = cy[ks];
           zi = cz[ks];
@@ -266,7 +300,13 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
         for (int k = lane; k - lane < mc; k += kWave) {
           bool hit = false;
           int32_t t = -1;
-          if (k < mc) {
+          if (FROM_MASK) {
+            const uint64_t mk = masks[s * mstride + (c0 + k - lane) / kWave];
+            if (k < mc) {
+              t = ct[k];
+              hit = (mk >> lane) & 1ull;
+            }
+          } else if (k < mc) {
             t = ct[k];
             if (t != s) {
               double d = xi - cx[k];
@@ -283,6 +323,7 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           }
           const unsigned long long bm = __ballot(hit);
           const unsigned long long bi = __ballot(hit && t < nin);
+          if (!FILL && masks && lane == 0) masks[s * mstride + (c0 + k) / kWave] = bm;
           if (FILL && hit) {
             const unsigned long long below = lane ? (bm & (~0ull >> (kWave - lane))) : 0ull;
             idx[out + __popcll(below)] = t;
@@ -458,18 +499,42 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
                      runs.p);
   RT_LAUNCH_CHECK();
 
-  // 6. count, scan, fill
+  // 6. hit masks of the count pass are kept for the fill pass when they fit
+  DevBuf<int32_t> mcell;
+  RT_CHECK(mcell.reserve((size_t)nruns));
+  if (dim == 3)
+    hipLaunchKernelGGL(k_cell_candidates<3>, dim3(grid_for(nruns)), dim3(kBlock), 0, st, nruns,
+                       bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], runs.p, nb->skeys.p, cstart.p,
+                       cend.p, mcell.p);
+  else
+    hipLaunchKernelGGL(k_cell_candidates<2>, dim3(grid_for(nruns)), dim3(kBlock), 0, st, nruns,
+                       bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], runs.p, nb->skeys.p, cstart.p,
+                       cend.p, mcell.p);
+  RT_LAUNCH_CHECK();
+  int32_t mmax = 0;
+  RT_CHECK(max_nonneg<int32_t>(ctx, mcell.p, nruns, &mmax));
+  const int mstride = (mmax + kWave - 1) / kWave;
+  DevBuf<uint64_t> masks;
+  const bool use_masks = mstride > 0 && (double)n * mstride * 8.0 <= kNbrMaskBytes &&
+                         masks.reserve((size_t)n * mstride) == RT_OK;
+  if (!use_masks) {
+    (void)hipGetLastError();
+    clear_error();
+  }
+
+  // 7. count, scan, fill
   DevBuf<int64_t> cnt;
   RT_CHECK(cnt.reserve(n + 1));
   RT_CHECK(nb->ptr.reserve(n + 1));
   RT_CHECK(nb->n_int_nbrs.reserve(n));
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int64_t), st));
-#define RT_NBR(D_, F_)                                                                          \
-  hipLaunchKernelGGL((k_nbr_cells<D_, F_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits,      \
+#define RT_NBR(D_, F_, M_)                                                                      \
+  hipLaunchKernelGGL((k_nbr_cells<D_, F_, M_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits,  \
                      ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, runs.p, nb->skeys.p,    \
-                     nb->sp4.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p)
-  if (dim == 3) RT_NBR(3, false);
-  else RT_NBR(2, false);
+                     nb->sp4.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p, \
+                     use_masks ? masks.p : nullptr, mstride)
+  if (dim == 3) RT_NBR(3, false, false);
+  else RT_NBR(2, false, false);
   RT_LAUNCH_CHECK();
   RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, nb->ptr.p, n + 1, false)));
   RT_CHECK(ctx->sync_read(nb->ptr.p + n, sizeof(int64_t)));
@@ -481,8 +546,13 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   }
   nb->npairs = npairs;
   RT_CHECK(nb->idx.reserve((size_t)npairs));
-  if (dim == 3) RT_NBR(3, true);
-  else RT_NBR(2, true);
+  if (use_masks) {
+    if (dim == 3) RT_NBR(3, true, true);
+    else RT_NBR(2, true, true);
+  } else {
+    if (dim == 3) RT_NBR(3, true, false);
+    else RT_NBR(2, true, false);
+  }
 #undef RT_NBR
   RT_LAUNCH_CHECK();
   RT_CHECK_HIP(hipStreamSynchronize(st));
