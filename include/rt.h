@@ -200,8 +200,9 @@ void rt_matrix_free(rt_matrix* A);
  * timed) and choices (-1 = none) to *rep when rep is not NULL.  It
  * synchronises the stream and allocates one temporary vector.
  * rt_matrix_set_spmv_shape forces a shape (index into the table; -1 restores
- * the default: the smallest shape whose one pass covers the level's longest
- * row).  Results of a product do not depend on the shape beyond the order
+ * the default, picked from the level's longest row: tiled shapes with two
+ * rows in flight on tiled levels, else the smallest plain shape whose one
+ * pass covers the row).  Results of a product do not depend on the shape beyond the order
  * of floating-point additions within a row.                                  */
 #define RT_MAX_LEVELS 16
 #define RT_MAX_SHAPES 16

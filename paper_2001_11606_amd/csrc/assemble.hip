@@ -112,56 +112,73 @@ struct AsmArgs {
   float *val32, *diag32, *dinv32, *sinv32;
 };
 
-template <int DIM, int G>
+// One group of G lanes per row, ENT neighbour entries per lane: the entry
+// indices, the neighbours' (x, y, z, h) and (V, D) records of a lane are all
+// requested before any arithmetic, so a row waits on memory about three
+// times whatever its length (rows longer than G*ENT take further passes).
+template <int DIM, int G, int ENT>
 __global__ void __launch_bounds__(kBlock)
 k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A) {
   const int lane = threadIdx.x & (G - 1);
-  const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
-  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
-  for (int64_t i = grp; i < nin; i += ngrp) {
-    const Rec4 pi = load_rec4(A.sp4, i);
-    const rt_f64x2_t vdi = load_pair(A.VD, i);
-    const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const double hi = pi.h, Vi = vdi[0], Di = vdi[1];
-    const int64_t k0 = A.nptr[i], k1 = A.nptr[i + 1], o = A.rp[i];
-    double suma = 0.0, gsum = 0.0, absoff = 0.0;
-    for (int64_t k = k0 + lane; k < k1; k += G) {
-      const int32_t j = A.nidx[k];
-      const Rec4 pj = load_rec4(A.sp4, j);
-      const rt_f64x2_t vdj = load_pair(A.VD, j);
-      const double dx = xi - pj.x, dy = yi - pj.y;
-      const double dz = DIM == 3 ? zi - pj.z : 0.0;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  if (i >= nin) return;   // whole groups leave together
+  const Rec4 pi = load_rec4(A.sp4, i);
+  const rt_f64x2_t vdi = load_pair(A.VD, i);
+  const double xi = pi.x, yi = pi.y, zi = pi.z;
+  const double hi = pi.h, Vi = vdi[0], Di = vdi[1];
+  const int64_t k0 = A.nptr[i], k1 = A.nptr[i + 1], o = A.rp[i];
+  double suma = 0.0, gsum = 0.0, absoff = 0.0;
+  for (int64_t kb = k0 + lane; kb < k1; kb += G * ENT) {
+    int32_t j[ENT];
+#pragma unroll
+    for (int e = 0; e < ENT; ++e) {
+      const int64_t k = kb + e * G;
+      j[e] = A.nidx[k < k1 ? k : k1 - 1];
+    }
+    Rec4 pj[ENT];
+    rt_f64x2_t vdj[ENT];
+#pragma unroll
+    for (int e = 0; e < ENT; ++e) {
+      pj[e] = load_rec4(A.sp4, j[e]);
+      vdj[e] = load_pair(A.VD, j[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < ENT; ++e) {
+      const int64_t k = kb + e * G;
+      if (k >= k1) break;
+      const double dx = xi - pj[e].x, dy = yi - pj[e].y;
+      const double dz = DIM == 3 ? zi - pj[e].z : 0.0;
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double F =
-          -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj.h, kernel)) / r;
-      const double Dij = Di + vdj[1];
-      const double aij = vdj[0] * Dij * F;
+          -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj[e].h, kernel)) / r;
+      const double Dij = Di + vdj[e][1];
+      const double aij = vdj[e][0] * Dij * F;
       suma += aij;
-      if (j < nin) {
-        const double v = -(Vi * vdj[0]) * Dij * F;
+      if (j[e] < nin) {
+        const double v = -(Vi * vdj[e][0]) * Dij * F;
         A.val64[o + (k - k0)] = v;
         if (A.val32) A.val32[o + (k - k0)] = (float)v;
-        if (A.col) A.col[o + (k - k0)] = j;
+        if (A.col) A.col[o + (k - k0)] = j[e];
         absoff += fabs(v);
       } else {
-        gsum += aij * A.Eall[j];
+        gsum += aij * A.Eall[j[e]];
       }
     }
-    suma = group_sum<G>(suma);
-    gsum = group_sum<G>(gsum);
-    absoff = group_sum<G>(absoff);
-    if (lane == 0) {
-      const double d = Vi * (1.0 / dt + c * A.sa[i] * A.f[i]) + Vi * suma;
-      A.diag64[i] = d;
-      A.dinv64[i] = 1.0 / d;                 // Jacobi preconditioner
-      A.sinv64[i] = 1.0 / (d + absoff);      // l1-Jacobi smoother of the V-cycle
-      if (A.diag32) {
-        A.diag32[i] = (float)d;
-        A.dinv32[i] = (float)(1.0 / d);
-        A.sinv32[i] = (float)(1.0 / (d + absoff));
-      }
-      A.g[i] = Vi * gsum;
+  }
+  suma = group_sum<G>(suma);
+  gsum = group_sum<G>(gsum);
+  absoff = group_sum<G>(absoff);
+  if (lane == 0) {
+    const double d = Vi * (1.0 / dt + c * A.sa[i] * A.f[i]) + Vi * suma;
+    A.diag64[i] = d;
+    A.dinv64[i] = 1.0 / d;                 // Jacobi preconditioner
+    A.sinv64[i] = 1.0 / (d + absoff);      // l1-Jacobi smoother of the V-cycle
+    if (A.diag32) {
+      A.diag32[i] = (float)d;
+      A.dinv32[i] = (float)(1.0 / d);
+      A.sinv32[i] = (float)(1.0 / (d + absoff));
     }
+    A.g[i] = Vi * gsum;
   }
 }
 
@@ -194,11 +211,12 @@ __global__ void k_export_scatter(int64_t nin, const int32_t* __restrict__ perm,
   if (ug) ug[u] = g[s];
 }
 
+// lanes per row (four entries per lane)
 int pick_group(double avg_row) {
-  if (avg_row > 40) return 64;
-  if (avg_row > 20) return 32;
-  if (avg_row > 10) return 16;
-  return 8;
+  if (avg_row > 100) return 64;
+  if (avg_row > 40) return 16;
+  if (avg_row > 20) return 8;
+  return 4;
 }
 
 }  // namespace
@@ -274,16 +292,16 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
                fp32 ? L.sinv32.p : nullptr};
     const double avg = nin ? (double)nb->npairs / (double)n : 0.0;
     const int G = pick_group(avg);
-    const int grid = grid_for(nin * (int64_t)G, kBlock, 1 << 20);
-#define RT_ASM(D_, G_)                                                                        \
-  hipLaunchKernelGGL((k_assemble<D_, G_>), dim3(grid), dim3(kBlock), 0, st, nin, n, nb->kernel, \
+    const int grid = grid_for(nin * (int64_t)G, kBlock);
+#define RT_ASM(D_, G_)                                                                           \
+  hipLaunchKernelGGL((k_assemble<D_, G_, 4>), dim3(grid), dim3(kBlock), 0, st, nin, n, nb->kernel, \
                      in->dt, in->c, aa)
     if (nb->dim == 3) {
-      if (G == 64) RT_ASM(3, 64); else if (G == 32) RT_ASM(3, 32);
-      else if (G == 16) RT_ASM(3, 16); else RT_ASM(3, 8);
+      if (G == 64) RT_ASM(3, 64); else if (G == 16) RT_ASM(3, 16);
+      else if (G == 8) RT_ASM(3, 8); else RT_ASM(3, 4);
     } else {
-      if (G == 64) RT_ASM(2, 64); else if (G == 32) RT_ASM(2, 32);
-      else if (G == 16) RT_ASM(2, 16); else RT_ASM(2, 8);
+      if (G == 64) RT_ASM(2, 64); else if (G == 16) RT_ASM(2, 16);
+      else if (G == 8) RT_ASM(2, 8); else RT_ASM(2, 4);
     }
 #undef RT_ASM
     RT_LAUNCH_CHECK();

@@ -287,12 +287,15 @@ inline int spmv_plain_shape_for(int64_t max_row) {
     if ((int64_t)kSpmvShapes[s].g * kSpmvShapes[s].ent >= max_row) return s;
   return kFirstTiledShape - 1;
 }
-// the smallest tiled shape (four rows in flight) whose one pass covers the
-// longest row at any chunk alignment
+// default tiled shape: two rows in flight per lane group (fewer registers
+// than four, which measured faster on the 3-D workloads), lanes per row so
+// that a row takes at most two passes; very short rows: four lanes, four rows
 inline int spmv_tiled_shape_for(int64_t max_row) {
-  for (int s = kFirstTiledShape; s < kFirstTiledShape + 5; ++s)
-    if (4 * (int64_t)kSpmvShapes[s].g - 3 >= max_row) return s;
-  return kFirstTiledShape + 4;
+  if (max_row <= 13) return kFirstTiledShape;        // (4, 4)
+  if (max_row <= 2 * (4 * 8 - 3)) return 12;        // (8, 2)
+  if (max_row <= 2 * (4 * 16 - 3)) return 13;        // (16, 2)
+  if (max_row <= 2 * (4 * 32 - 3)) return 14;        // (32, 2)
+  return kFirstTiledShape + 4;                        // (64, 4)
 }
 // the shape a product over L runs with, given the requested one (-1: default)
 inline int spmv_effective_shape(const Level& L, int shape) {
