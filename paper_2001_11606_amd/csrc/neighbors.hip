@@ -166,10 +166,14 @@ __global__ void k_run_flags(int64_t n, const uint64_t* __restrict__ skeys,
 }
 
 __global__ void k_run_starts(int64_t n, const int32_t* __restrict__ flags,
-                             const int32_t* __restrict__ rid, int32_t* __restrict__ runs) {
+                             const int32_t* __restrict__ rid, const uint64_t* __restrict__ skeys,
+                             int32_t* __restrict__ runs, uint64_t* __restrict__ runkey) {
   int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
-  if (flags[s]) runs[rid[s] - 1] = (int32_t)s;
+  if (flags[s]) {
+    runs[rid[s] - 1] = (int32_t)s;
+    runkey[rid[s] - 1] = skeys[s];
+  }
   if (s == n - 1) runs[rid[s]] = (int32_t)n;
 }
 
@@ -209,7 +213,7 @@ __global__ void k_cell_candidates(int64_t nruns, int bits, int64_t ncells, int n
 template <int DIM, bool FILL, bool FROM_MASK>
 __global__ void __launch_bounds__(kBlock)
 k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
-            double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ skeys,
+            double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
             const double* __restrict__ sp4, const int32_t* __restrict__ cstart,
             const int32_t* __restrict__ cend,
             int64_t* __restrict__ cnt, const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
@@ -223,8 +227,9 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
   const int wave = tid / kWave, lane = tid & (kWave - 1);
   const int64_t r0 = runs[blockIdx.x], r1 = runs[blockIdx.x + 1];
   // candidate ranges: slot = flag * NB + (z, y, x offset), empty when outside the grid
-  if (tid < 2 * NB) {
-    const uint64_t key = skeys[r0];
+  static_assert(2 * NB <= kWave, "the slot scan runs in one wave");
+  if (tid < kWave) {   // wave 0: slot ranges and their prefix sum
+    const uint64_t key = runkey[blockIdx.x];
     const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
     int c[3];
     demorton<DIM>(bits, key & mask, c);
@@ -232,18 +237,21 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
     const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
     int32_t lo = 0, len = 0;
-    if (x >= 0 && x < nc0 && y >= 0 && y < nc1 && z >= 0 && z < nc2) {
+    if (tid < 2 * NB && x >= 0 && x < nc0 && y >= 0 && y < nc1 && z >= 0 && z < nc2) {
       const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
       lo = cstart[cell];
       len = cend[cell] - lo;
     }
-    rlo[tid] = lo;
-    roff[tid + 1] = len;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    roff[0] = 0;
-    for (int q = 1; q <= 2 * NB; ++q) roff[q] += roff[q - 1];
+    int32_t incl = len;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int32_t v = __shfl_up(incl, d);
+      if (tid >= d) incl += v;
+    }
+    if (tid < 2 * NB) {
+      rlo[tid] = lo;
+      roff[tid + 1] = incl;
+    }
+    if (tid == 0) roff[0] = 0;
   }
   __syncthreads();
   const int m = roff[2 * NB];
@@ -486,6 +494,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
 
   // 5. occupied cells
   DevBuf<int32_t> rflag, rid, runs;
+  DevBuf<uint64_t> runkey;
   RT_CHECK(rflag.reserve(n));
   RT_CHECK(rid.reserve(n));
   hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nb->skeys.p, rflag.p);
@@ -495,8 +504,9 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   int32_t nruns = 0;
   std::memcpy(&nruns, ctx->host, sizeof(int32_t));
   RT_CHECK(runs.reserve((size_t)nruns + 1));
+  RT_CHECK(runkey.reserve((size_t)nruns));
   hipLaunchKernelGGL(k_run_starts, dim3(grid_for(n)), dim3(kBlock), 0, st, n, rflag.p, rid.p,
-                     runs.p);
+                     nb->skeys.p, runs.p, runkey.p);
   RT_LAUNCH_CHECK();
 
   // 6. hit masks of the count pass are kept for the fill pass when they fit
@@ -530,7 +540,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int64_t), st));
 #define RT_NBR(D_, F_, M_)                                                                      \
   hipLaunchKernelGGL((k_nbr_cells<D_, F_, M_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits,  \
-                     ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, runs.p, nb->skeys.p,    \
+                     ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, runs.p, runkey.p,       \
                      nb->sp4.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p, \
                      use_masks ? masks.p : nullptr, mstride)
   if (dim == 3) RT_NBR(3, false, false);
