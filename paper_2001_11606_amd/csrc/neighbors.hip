@@ -355,6 +355,117 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
   }
 }
 
+// Fill pass from the count pass's hit masks, for cells whose candidates span
+// at most kMaskWords mask words per staged chunk: each lane expands one mask
+// word of one row (kMaskWords lanes per row, 64 / kMaskWords rows per wave at a
+// time), so the work follows the hits, not the candidates.
+constexpr int kMaskWords = kNbrCand / kWave;   // mask words per staged chunk (8)
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
+                 const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
+                 const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend,
+                 const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
+                 int32_t* __restrict__ n_int_nbrs, const uint64_t* __restrict__ masks,
+                 int mstride) {
+  constexpr int NB = DIM == 3 ? 27 : 9;
+  constexpr int RPW = kWave / kMaskWords;   // rows per wave per step
+  __shared__ int32_t ct[kNbrCand];
+  __shared__ int32_t rlo[2 * NB], roff[2 * NB + 1];
+  __shared__ int32_t rcount[kNbrRows], rint[kNbrRows];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave, lane = tid & (kWave - 1);
+  const int64_t r0 = runs[blockIdx.x], r1 = runs[blockIdx.x + 1];
+  static_assert(2 * NB <= kWave, "the slot scan runs in one wave");
+  if (tid < kWave) {
+    const uint64_t key = runkey[blockIdx.x];
+    const uint64_t mask = ((uint64_t)1 << (DIM * bits)) - 1;
+    int c[3];
+    demorton<DIM>(bits, key & mask, c);
+    const int flag = tid / NB, o = tid % NB;
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
+    const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
+    int32_t lo = 0, len = 0;
+    if (tid < 2 * NB && x >= 0 && x < nc0 && y >= 0 && y < nc1 && z >= 0 && z < nc2) {
+      const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
+      lo = cstart[cell];
+      len = cend[cell] - lo;
+    }
+    int32_t incl = len;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int32_t v = __shfl_up(incl, d);
+      if (tid >= d) incl += v;
+    }
+    if (tid < 2 * NB) {
+      rlo[tid] = lo;
+      roff[tid + 1] = incl;
+    }
+    if (tid == 0) roff[0] = 0;
+  }
+  __syncthreads();
+  const int m = roff[2 * NB];
+  const int rr = lane / kMaskWords, q = lane % kMaskWords;
+  for (int64_t rb = r0; rb < r1; rb += kNbrRows) {
+    const int nrows = (int)(r1 - rb < kNbrRows ? r1 - rb : kNbrRows);
+    for (int r = tid; r < nrows; r += kBlock) {
+      rcount[r] = 0;
+      rint[r] = 0;
+    }
+    for (int c0 = 0; c0 < m; c0 += kNbrCand) {
+      const int mc = m - c0 < kNbrCand ? m - c0 : kNbrCand;
+      __syncthreads();
+      for (int k = tid; k < mc; k += kBlock) {
+        const int kk = c0 + k;
+        int lo = 0, hi = 2 * NB;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (roff[mid] <= kk) lo = mid;
+          else hi = mid;
+        }
+        ct[k] = rlo[lo] + (kk - roff[lo]);
+      }
+      __syncthreads();
+      const int words = (mc + kWave - 1) / kWave;
+      for (int base = wave * RPW; base < nrows; base += (kBlock / kWave) * RPW) {
+        const int r = base + rr;
+        const bool live = r < nrows && q < words;
+        const int64_t s = rb + r;
+        const uint64_t mk = live ? masks[s * mstride + c0 / kWave + q] : 0ull;
+        const int cntw = __popcll(mk);
+        int incl = cntw;   // prefix over the words of this row
+        for (int d = 1; d < kMaskWords; d <<= 1) {
+          const int v = __shfl_up(incl, d, kMaskWords);
+          if (q >= d) incl += v;
+        }
+        int interior = 0;
+        if (live && mk) {
+          int64_t out = ptr[s] + rcount[r] + (incl - cntw);
+          uint64_t bitsleft = mk;
+          while (bitsleft) {
+            const int b = __builtin_ctzll(bitsleft);
+            bitsleft &= bitsleft - 1;
+            const int32_t t = ct[q * kWave + b];
+            idx[out++] = t;
+            interior += t < nin;
+          }
+        }
+        for (int d = kMaskWords / 2; d > 0; d >>= 1) interior += __shfl_xor(interior, d, kMaskWords);
+        const int total = __shfl(incl, kMaskWords - 1, kMaskWords);
+        // rows belong to one wave per chunk, and the reads above precede this
+        // write in the wave's instruction stream
+        if (q == 0 && r < nrows) {
+          rcount[r] += total;
+          rint[r] += interior;
+        }
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < nrows; r += kBlock) n_int_nbrs[rb + r] = rint[r];
+    __syncthreads();
+  }
+}
+
 // user-order export: scatter mapped rows, then sort each row
 __global__ void k_user_counts(int64_t n, const int32_t* __restrict__ iperm,
                               const int64_t* __restrict__ ptr, int64_t* __restrict__ ucnt) {
@@ -557,8 +668,13 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   nb->npairs = npairs;
   RT_CHECK(nb->idx.reserve((size_t)npairs));
   if (use_masks) {
-    if (dim == 3) RT_NBR(3, true, true);
-    else RT_NBR(2, true, true);
+#define RT_FILLM(D_)                                                                             \
+  hipLaunchKernelGGL((k_nbr_fill_masks<D_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits, ncells, \
+                     nb->nc[0], nb->nc[1], nb->nc[2], runs.p, runkey.p, cstart.p, cend.p,         \
+                     nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p, masks.p, mstride)
+    if (dim == 3) RT_FILLM(3);
+    else RT_FILLM(2);
+#undef RT_FILLM
   } else {
     if (dim == 3) RT_NBR(3, true, false);
     else RT_NBR(2, true, false);

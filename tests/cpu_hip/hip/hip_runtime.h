@@ -207,6 +207,24 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
   return r;
 }
 
+// value of lane src of the group of width lanes
+template <typename T>
+inline T __shfl(T v, int src, int width = 64) {
+  static_assert(sizeof(T) <= 8, "shuffle of more than 8 bytes");
+  const int t = (int)threadIdx.x;
+  const int lane = t % width;
+  auto& bar = *cpuhip::g_block.group_bar[cpuhip::log2i(width)][t / width];
+  uint64_t bits = 0;
+  memcpy(&bits, &v, sizeof(T));
+  cpuhip::g_block.slot[t] = bits;
+  bar.arrive_and_wait();
+  const uint64_t got = cpuhip::g_block.slot[t - lane + (src % width)];
+  bar.arrive_and_wait();
+  T r;
+  memcpy(&r, &got, sizeof(T));
+  return r;
+}
+
 // value of the lane delta below (own value for the lowest delta lanes)
 template <typename T>
 inline T __shfl_up(T v, unsigned delta, int width = 64) {
