@@ -68,11 +68,22 @@ typedef struct rt_matrix rt_matrix;
  * `hip_stream` (a hipStream_t; NULL = the null stream).  *ctx receives a new
  * context.  Errors: RT_E_ARG (ctx NULL), RT_E_DEVICE.                        */
 int rt_create(rt_ctx** ctx, int device, void* hip_stream);
+/* rt_destroy: waits for the context's stream, then frees the context and the
+ * device memory the library keeps cached for its device.                    */
 void rt_destroy(rt_ctx* ctx);
 int rt_set_stream(rt_ctx* ctx, void* hip_stream);
 /* Record HIP events around every sparse matrix-vector product launch so that
  * rt_solve_stats.spmv_* report per-launch device time (on = 1).             */
 int rt_set_profiling(rt_ctx* ctx, int on);
+/* Device memory (a property of this library, not of the paper): buffers of
+ * freed handles and of finished calls are kept by the library for reuse, per
+ * device, instead of being returned to HIP (up to 96 GiB; an allocation that
+ * fails frees them and is retried), so repeated builds of same-sized problems
+ * allocate nothing.  rt_cached_bytes reports the bytes kept for ctx's device;
+ * rt_release_cached synchronises the device and frees them (*freed_bytes, if
+ * not NULL, receives the amount).  rt_destroy frees them too.               */
+int rt_cached_bytes(const rt_ctx* ctx, int64_t* bytes);
+int rt_release_cached(rt_ctx* ctx, int64_t* freed_bytes);
 const char* rt_last_error(void);
 const char* rt_version(void);
 

@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict
 // x = M b with the dense FP64 inverse; one wavefront per row.
 template <typename T>
 __global__ void k_coarse_solve(int64_t n, const double* __restrict__ M, const T* __restrict__ b,
-                               T* __restrict__ x) {
+                               T* __restrict__ x, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   if (i >= n) return;
@@ -200,14 +201,16 @@ __global__ void k_coarse_solve(int64_t n, const double* __restrict__ M, const T*
 
 template <typename T>
 __global__ void k_scale(int64_t n, const T* __restrict__ s, const T* __restrict__ b,
-                        T* __restrict__ x) {
+                        T* __restrict__ x, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[i] = s[i] * b[i];
 }
 
 template <typename T>
 __global__ void k_restrict(int64_t nc, const int32_t* __restrict__ crange, const T* __restrict__ r,
-                           T* __restrict__ bc) {
+                           T* __restrict__ bc, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (I >= nc) return;
   T s = 0;
@@ -217,7 +220,8 @@ __global__ void k_restrict(int64_t nc, const int32_t* __restrict__ crange, const
 
 template <typename T>
 __global__ void k_prolong(int64_t n, const int32_t* __restrict__ pmap, const T* __restrict__ xc,
-                          T* __restrict__ x) {
+                          T* __restrict__ x, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[i] += xc[pmap[i]];
 }
@@ -373,7 +377,8 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
 }
 
 template <typename T>
-static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out) {
+static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
+                        const int32_t* stop) {
   using B = LevelBufs<T>;
   hipStream_t st = ctx->stream;
   Level& L = A->levels[l];
@@ -381,20 +386,21 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out)
   if (l + 1 == A->levels.size()) {
     if (A->coarse_direct) {
       hipLaunchKernelGGL(k_coarse_solve<T>, dim3(grid_for(n * kWave)), dim3(kBlock), 0, st, n,
-                         A->coarse_inv.p, b, out);
+                         A->coarse_inv.p, b, out, stop);
       RT_LAUNCH_CHECK();
       return RT_OK;
     }
     // four l1-Jacobi sweeps from zero (a symmetric positive-definite operator)
     T* t = B::t(L);
-    hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t);
+    hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t,
+                       stop);
     RT_LAUNCH_CHECK();
     T* src = t;
     T* dst = out;
     for (int sweep = 0; sweep < 3; ++sweep) {
       RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), src, b, B::sinv(L),
                                                 dst, nullptr, nullptr, nullptr,
-                                                level_shape<T>(L))));
+                                                level_shape<T>(L), nullptr, stop)));
       T* tmp = src;
       src = dst;
       dst = tmp;
@@ -406,28 +412,31 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out)
   Level& C = A->levels[l + 1];
   T* t = B::t(L);
   T* r = B::r(L);
-  hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t);
+  hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t,
+                     stop);
   RT_LAUNCH_CHECK();
   RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
-                                           nullptr, A->partB.p, nullptr, level_shape<T>(L))));
+                                           nullptr, A->partB.p, nullptr, level_shape<T>(L),
+                                           nullptr, stop)));
   hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
-                     r, B::b(C));
+                     r, B::b(C), stop);
   RT_LAUNCH_CHECK();
-  RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::b(C), B::x(C)));
+  RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::b(C), B::x(C), stop));
   hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p, B::x(C),
-                     t);
+                     t, stop);
   RT_LAUNCH_CHECK();
   RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), t, b, B::sinv(L), out,
-                                            nullptr, nullptr, nullptr, level_shape<T>(L))));
+                                            nullptr, nullptr, nullptr, level_shape<T>(L),
+                                            nullptr, stop)));
   return RT_OK;
 }
 
 template <typename T>
-int vcycle(rt_ctx* ctx, rt_matrix* A, const T* b, T* z) {
-  return vcycle_level<T>(ctx, A, 0, b, z);
+int vcycle(rt_ctx* ctx, rt_matrix* A, const T* b, T* z, const int32_t* stop) {
+  return vcycle_level<T>(ctx, A, 0, b, z, stop);
 }
 
-template int vcycle<double>(rt_ctx*, rt_matrix*, const double*, double*);
-template int vcycle<float>(rt_ctx*, rt_matrix*, const float*, float*);
+template int vcycle<double>(rt_ctx*, rt_matrix*, const double*, double*, const int32_t*);
+template int vcycle<float>(rt_ctx*, rt_matrix*, const float*, float*, const int32_t*);
 
 }  // namespace rt

@@ -1,7 +1,10 @@
 // Context, error reporting and version of the C ABI.
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 
 #include "internal.h"
 
@@ -19,6 +22,91 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { g_last_error.clear(); }
+
+namespace {
+std::mutex g_pool_mu;
+// (device, bytes) -> cached block
+std::multimap<std::pair<int, size_t>, void*> g_pool;
+size_t g_pool_total = 0;
+
+// sizes are rounded so that blocks of nearly equal requests are shared
+size_t pool_round(size_t b) {
+  const size_t g = b >= ((size_t)1 << 20) ? ((size_t)2 << 20) : 256;
+  return (b + g - 1) / g * g;
+}
+}  // namespace
+
+void* pool_get(size_t* bytes, int* device) {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  *device = d;
+  const size_t want = pool_round(*bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.lower_bound({d, want});
+    if (it != g_pool.end() && it->first.first == d && it->first.second <= want + want / 8) {
+      void* p = it->second;
+      *bytes = it->first.second;
+      g_pool_total -= it->first.second;
+      g_pool.erase(it);
+#ifdef RT_POOL_POISON
+      std::memset(p, 0xBE, *bytes);   // a reused block reads as garbage, like a fresh one
+#endif
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) == hipSuccess) {
+    *bytes = want;
+    return p;
+  }
+  (void)hipGetLastError();
+  pool_trim(d);
+  if (hipMalloc(&p, want) == hipSuccess) {
+    *bytes = want;
+    return p;
+  }
+  (void)hipGetLastError();
+  return nullptr;
+}
+
+void pool_put(void* p, size_t bytes, int device) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_total + bytes <= kPoolCapBytes) {
+      g_pool.insert({{device, bytes}, p});
+      g_pool_total += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+void pool_trim(int device) {
+  std::vector<void*> out;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto it = g_pool.begin(); it != g_pool.end();) {
+      if (device < 0 || it->first.first == device) {
+        out.push_back(it->second);
+        g_pool_total -= it->first.second;
+        it = g_pool.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (void* p : out) (void)hipFree(p);
+}
+
+size_t pool_cached_bytes(int device) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  size_t t = 0;
+  for (const auto& kv : g_pool)
+    if (device < 0 || kv.first.first == device) t += kv.first.second;
+  return t;
+}
 
 }  // namespace rt
 
@@ -106,7 +194,31 @@ void rt_destroy(rt_ctx* ctx) {
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  const int dev = ctx->device;
   delete ctx;
+  rt::pool_trim(dev);
+}
+
+int rt_release_cached(rt_ctx* ctx, int64_t* freed_bytes) {
+  if (!ctx) {
+    rt::set_error("rt_release_cached: ctx is NULL");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  RT_CHECK_HIP(hipDeviceSynchronize());
+  const size_t b = rt::pool_cached_bytes(ctx->device);
+  rt::pool_trim(ctx->device);
+  if (freed_bytes) *freed_bytes = (int64_t)b;
+  return RT_OK;
+}
+
+int rt_cached_bytes(const rt_ctx* ctx, int64_t* bytes) {
+  if (!ctx || !bytes) {
+    rt::set_error("rt_cached_bytes: NULL argument");
+    return RT_E_ARG;
+  }
+  *bytes = (int64_t)rt::pool_cached_bytes(ctx->device);
+  return RT_OK;
 }
 
 int rt_set_stream(rt_ctx* ctx, void* hip_stream) {

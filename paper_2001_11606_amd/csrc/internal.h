@@ -45,42 +45,74 @@ void clear_error();
 
 #define RT_LAUNCH_CHECK() RT_CHECK_HIP(hipGetLastError())
 
+// Device memory cache behind every buffer of the library.  A released block
+// is kept for reuse instead of being freed (the device is synchronised first,
+// so no queued work still uses it); a request takes a cached block of the
+// current device whose size is at least the request and at most about an
+// eighth above it, else allocates.  When an allocation fails, the device's
+// cached blocks are freed and the allocation is tried once more; blocks
+// beyond kPoolCapBytes of cache are freed at once.  Repeated set-up of
+// same-sized problems (a neighbour build and an assembly per time step) then
+// makes no hipMalloc / hipFree calls, which map and unmap pages and stall
+// the host for milliseconds at gigabyte sizes.
+constexpr size_t kPoolCapBytes = (size_t)96 << 30;
+// *bytes: requested size in, size of the returned block out; *device: the
+// device it belongs to.  NULL when the device is out of memory.
+void* pool_get(size_t* bytes, int* device);
+void pool_put(void* p, size_t bytes, int device);
+void pool_trim(int device);   // free the cached blocks of a device (-1: all)
+size_t pool_cached_bytes(int device);
+
 // Owning device buffer.  Not copyable; grows on demand.
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  size_t cap = 0;   // bytes of the block
+  int dev = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap), dev(o.dev) {
+    o.p = nullptr;
+    o.n = o.cap = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      cap = o.cap;
+      dev = o.dev;
+      o.p = nullptr;
+      o.n = o.cap = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   // Frees happen only in set-up paths; wait for queued work that may still
-  // read the buffer before returning it to the allocator.
+  // read the buffer before returning it to the cache.
   void release() {
     if (p) {
       (void)hipDeviceSynchronize();
-      (void)hipFree(p);
+      pool_put(p, cap, dev);
     }
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
   // Ensure capacity for `count` elements (contents are not preserved).
   int reserve(size_t count) {
     if (count <= n && p) return RT_OK;
     release();
     size_t bytes = (count ? count : 1) * sizeof(T);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
+    void* q = pool_get(&bytes, &dev);
+    if (!q) {
       set_error("device allocation of %zu bytes failed", bytes);
       return RT_E_OOM;
     }
+    p = static_cast<T*>(q);
     n = count;
+    cap = bytes;
     return RT_OK;
   }
 };
@@ -213,6 +245,7 @@ struct rt_matrix {
   rt::DevBuf<double> partA, partB;   // block partials of the reductions
   rt::DevBuf<double> partC;          // second level of the partial reductions
   rt::DevBuf<double> scal;           // device scalars (see solve.hip)
+  rt::DevBuf<int32_t> stop;          // PCG stop flag: set on the device when the loop ends
 };
 
 namespace rt {
@@ -233,8 +266,10 @@ int gather_sorted(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* 
                   double* sorted);
 int scatter_user(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* sorted,
                  double* user);
+// One V-cycle z = M^-1 b; every kernel does nothing once *stop is set (stop
+// may be NULL).
 template <typename T>
-int vcycle(rt_ctx* ctx, rt_matrix* A, const T* b, T* z);
+int vcycle(rt_ctx* ctx, rt_matrix* A, const T* b, T* z, const int32_t* stop = nullptr);
 int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_matrix* A,
              bool new_structure);
 }  // namespace rt

@@ -13,7 +13,13 @@
 //
 // Scalars (alpha, beta, r.z, ...) stay on the device; block partials of the
 // dot products are combined in FP64 by a one-block kernel in a fixed order.
-// The host reads ||r||^2 once per iteration for the stopping test.
+// The stopping test runs on the device too: the kernel that forms ||r||^2
+// sets a stop flag once it meets the threshold (or on breakdown), and every
+// kernel of the iteration does nothing once the flag is set.  The host queues
+// several iterations between reads of the state -- as many as the observed
+// convergence rate says are still needed, scaled down so that it rarely
+// queues past the end -- so an iteration costs no host round trip, and the
+// arithmetic is the same as stopping after each iteration.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -26,14 +32,19 @@
 namespace rt {
 namespace {
 
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_COUNT };
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_ITS, S_STOP, S_COUNT };
 enum { FIN_ALPHA = 0, FIN_BETA, FIN_RZ, FIN_RR, FIN_BB };
 enum { PROF_SPMV64 = 0, PROF_SPMV32 = 1, PROF_RESID64 = 2, PROF_KINDS = 3 };
 
+// One block: combine the partials and update the scalars.  In the loop
+// (FIN_ALPHA, FIN_BETA) nothing happens once *stop is set; FIN_BETA counts the
+// iteration and sets *stop when ||r||^2 <= thr2 (or is not a number);
+// FIN_ALPHA sets it on breakdown (p.Ap not positive).  FIN_RZ starts a loop.
 __global__ void __launch_bounds__(kBlock)
 k_finalize(int op, int np, const double* __restrict__ pa, const double* __restrict__ pb,
-           double* __restrict__ s) {
+           double* __restrict__ s, int32_t* __restrict__ stop, double thr2) {
   __shared__ double red[kBlock / kWave];
+  if ((op == FIN_ALPHA || op == FIN_BETA) && *stop) return;
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     a += pa[i];
@@ -50,16 +61,26 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
       } else {
         s[S_ALPHA] = 0.0;
         s[S_BAD] = 1.0;
+        s[S_STOP] = 1.0;
+        *stop = 1;
       }
       break;
     case FIN_BETA:   // a = ||r||^2, b = r.z (new)
       s[S_RR] = a;
       s[S_BETA] = b / s[S_RZ];
       s[S_RZ] = b;
+      s[S_ITS] += 1.0;
+      if (!(a > thr2)) {
+        s[S_STOP] = 1.0;
+        *stop = 1;
+      }
       break;
     case FIN_RZ:     // a = r.z at the start
       s[S_RZ] = a;
       s[S_BAD] = 0.0;
+      s[S_ITS] = 0.0;
+      s[S_STOP] = 0.0;
+      *stop = 0;
       break;
     case FIN_RR:
       s[S_RR] = a;
@@ -85,8 +106,9 @@ inline int vec_blocks(int64_t n) {
 // second reduction level: nb2 blocks each sum a contiguous chunk of pa (and pb)
 __global__ void __launch_bounds__(kBlock)
 k_partial_reduce(int np, int chunk, const double* __restrict__ pa, const double* __restrict__ pb,
-                 double* __restrict__ out) {
+                 double* __restrict__ out, const int32_t* __restrict__ stop) {
   __shared__ double red[kBlock / kWave];
+  if (stop && *stop) return;
   const int lo = blockIdx.x * chunk;
   const int hi = lo + chunk < np ? lo + chunk : np;
   double a = 0.0, b = 0.0;
@@ -135,8 +157,10 @@ k_copy_dot(int64_t n, const T* __restrict__ r, const T* __restrict__ z, T* __res
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_dot(int64_t n, const T* __restrict__ a, const T* __restrict__ b, double* __restrict__ part) {
+k_dot(int64_t n, const T* __restrict__ a, const T* __restrict__ b, double* __restrict__ part,
+      const int32_t* __restrict__ stop) {
   __shared__ double red[kBlock / kWave];
+  if (stop && *stop) return;
   double acc = 0.0;
   RT_VEC_LOOP(i) acc += (double)a[i] * (double)b[i];
   acc = block_sum(acc, red);
@@ -148,8 +172,9 @@ template <typename T, bool JAC>
 __global__ void __launch_bounds__(kBlock)
 k_update(int64_t n, const double* __restrict__ s, T* __restrict__ x, T* __restrict__ r,
          const T* __restrict__ p, const T* __restrict__ q, const T* __restrict__ dinv,
-         double* __restrict__ partA, double* __restrict__ partB) {
+         double* __restrict__ partA, double* __restrict__ partB, const int32_t* __restrict__ stop) {
   __shared__ double red[kBlock / kWave];
+  if (*stop) return;
   const T alpha = (T)s[S_ALPHA];
   double rr = 0.0, rz = 0.0;
   RT_VEC_LOOP(i) {
@@ -171,7 +196,9 @@ k_update(int64_t n, const double* __restrict__ s, T* __restrict__ x, T* __restri
 template <typename T, bool JAC>
 __global__ void __launch_bounds__(kBlock)
 k_pupdate(int64_t n, const double* __restrict__ s, const T* __restrict__ r,
-          const T* __restrict__ dinv, const T* __restrict__ z, T* __restrict__ p) {
+          const T* __restrict__ dinv, const T* __restrict__ z, T* __restrict__ p,
+          const int32_t* __restrict__ stop) {
+  if (*stop) return;
   const T beta = (T)s[S_BETA];
   RT_VEC_LOOP(i) {
     const T zi = JAC ? dinv[i] * r[i] : z[i];
@@ -248,22 +275,77 @@ int read_scalar(rt_ctx* ctx, rt_matrix* A, int idx, double* out) {
 #define RT_PARTIAL_FOLD_MIN (4 * kMaxPartials)
 #endif
 
-int finalize(rt_ctx* ctx, rt_matrix* A, int op, int np, const double* pa, const double* pb) {
+int finalize(rt_ctx* ctx, rt_matrix* A, int op, int np, const double* pa, const double* pb,
+             double thr2 = 0.0) {
+  const bool in_loop = op == FIN_ALPHA || op == FIN_BETA;
   if (np > RT_PARTIAL_FOLD_MIN) {
     // first fold the partials into at most kMaxPartials values per array
     const int nb2 = std::min(kMaxPartials, std::max(1, np / 8));
     const int chunk = (np + nb2 - 1) / nb2;
     hipLaunchKernelGGL(k_partial_reduce, dim3(nb2), dim3(kBlock), 0, ctx->stream, np, chunk, pa,
-                       pb, A->partC.p);
+                       pb, A->partC.p, in_loop ? A->stop.p : nullptr);
     RT_LAUNCH_CHECK();
     pa = A->partC.p;
     pb = pb ? A->partC.p + nb2 : nullptr;
     np = nb2;
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, ctx->stream, op, np, pa, pb,
-                     A->scal.p);
+                     A->scal.p, A->stop.p, thr2);
   RT_LAUNCH_CHECK();
   return RT_OK;
+}
+
+// One PCG iteration, queued; a no-op on the device once the stop flag is set.
+template <typename T>
+int pcg_iteration(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double thr2) {
+  using S = Sel<T>;
+  hipStream_t st = ctx->stream;
+  const Level& L = A->levels[0];
+  const int64_t n = L.n;
+  T* p = S::p(A);
+  T* q = S::q(A);
+  T* z = S::z(A);
+  const int32_t* stop = A->stop.p;
+  const int gv = vec_blocks(n);
+  int nbk = 0;
+  Prof pf(ctx, S::kind);
+  RT_CHECK(pf.begin());
+  RT_CHECK((launch_spmv_level<T, SP_DOT>(st, L, S::val(L), S::diag(L), p, nullptr, nullptr, q,
+                                         nullptr, A->partA.p, &nbk, level_shape<T>(L), nullptr,
+                                         stop)));
+  RT_CHECK(pf.end());
+  RT_CHECK(finalize(ctx, A, FIN_ALPHA, nbk, A->partA.p, nullptr));
+  if (amg) {
+    hipLaunchKernelGGL((k_update<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r, p,
+                       q, nullptr, A->partA.p, nullptr, stop);
+    RT_LAUNCH_CHECK();
+    RT_CHECK(vcycle<T>(ctx, A, r, z, stop));
+    hipLaunchKernelGGL(k_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, A->partB.p, stop);
+  } else {
+    hipLaunchKernelGGL((k_update<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r, p,
+                       q, S::dinv(L), A->partA.p, A->partB.p, stop);
+  }
+  RT_LAUNCH_CHECK();
+  RT_CHECK(finalize(ctx, A, FIN_BETA, gv, A->partA.p, A->partB.p, thr2));
+  if (amg)
+    hipLaunchKernelGGL((k_pupdate<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
+                       nullptr, z, p, stop);
+  else
+    hipLaunchKernelGGL((k_pupdate<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
+                       S::dinv(L), nullptr, p, stop);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
+// Iterations to queue before the next read of the state, from the decrease
+// of ||r||^2 since the last read: three quarters of the estimated remaining
+// count (at least one, at most 64); one while there is no decrease to go by.
+int next_chunk(double rr_prev, int its_prev, double rr, int its, double thr2) {
+  if (!(its > its_prev) || !(rr > 0.0) || !(rr < rr_prev) || !(thr2 > 0.0)) return 1;
+  const double per_it = std::log(rr / rr_prev) / (its - its_prev);   // < 0
+  const double need = std::log(thr2 / rr) / per_it;                  // > 0
+  if (!std::isfinite(need)) return 1;
+  return (int)std::min(64.0, std::max(1.0, std::floor(0.75 * need)));
 }
 
 // PCG iterations on A x = b given r = b - A x and s[S_RR] = ||r||^2 on entry.
@@ -276,12 +358,11 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double
   const Level& L = A->levels[0];
   const int64_t n = L.n;
   T* p = S::p(A);
-  T* q = S::q(A);
   T* z = S::z(A);
   const int gv = vec_blocks(n);
   *its_out = 0;
   *rr_out = rr0;
-  if (rr0 <= thr2) return RT_OK;
+  if (rr0 <= thr2 || max_it <= 0) return RT_OK;
   if (amg) {
     RT_CHECK(vcycle<T>(ctx, A, r, z));
     hipLaunchKernelGGL(k_copy_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, p, A->partB.p);
@@ -290,47 +371,38 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double
                        A->partB.p);
   }
   RT_LAUNCH_CHECK();
-  RT_CHECK(finalize(ctx, A, FIN_RZ, gv, A->partB.p, nullptr));
-  double rr = rr0;
-  int it = 0;
-  while (it < max_it) {
-    int nbk = 0;
-    Prof pf(ctx, S::kind);
-    RT_CHECK(pf.begin());
-    RT_CHECK((launch_spmv_level<T, SP_DOT>(st, L, S::val(L), S::diag(L), p, nullptr, nullptr, q,
-                                           nullptr, A->partA.p, &nbk, level_shape<T>(L))));
-    RT_CHECK(pf.end());
-    RT_CHECK(finalize(ctx, A, FIN_ALPHA, nbk, A->partA.p, nullptr));
-    if (amg) {
-      hipLaunchKernelGGL((k_update<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r,
-                         p, q, nullptr, A->partA.p, nullptr);
-      RT_LAUNCH_CHECK();
-      RT_CHECK(vcycle<T>(ctx, A, r, z));
-      hipLaunchKernelGGL(k_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, A->partB.p);
-    } else {
-      hipLaunchKernelGGL((k_update<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r,
-                         p, q, S::dinv(L), A->partA.p, A->partB.p);
-    }
-    RT_LAUNCH_CHECK();
-    RT_CHECK(finalize(ctx, A, FIN_BETA, gv, A->partA.p, A->partB.p));
-    ++it;
-    RT_CHECK(read_scalar(ctx, A, S_RR, &rr));
-    if (!std::isfinite(rr)) {
+  RT_CHECK(finalize(ctx, A, FIN_RZ, gv, A->partB.p, nullptr));   // clears the stop flag
+  const size_t spans0 = ctx->prof_spans.size();
+  double rr = rr0, rr_prev = rr0;
+  int its = 0, its_prev = 0, queued = 0, chunk = 1;
+  bool stopped = false, bad = false;
+  while (queued < max_it) {
+    const int k = std::min(chunk, max_it - queued);
+    for (int j = 0; j < k; ++j) RT_CHECK(pcg_iteration<T>(ctx, A, amg, x, r, thr2));
+    queued += k;
+    RT_CHECK(ctx->sync_read(A->scal.p, sizeof(double) * S_COUNT));
+    const double* hs = ctx->host;
+    rr = hs[S_RR];
+    its = (int)hs[S_ITS];
+    stopped = hs[S_STOP] != 0.0;
+    bad = hs[S_BAD] != 0.0;
+    if (its > 0 && !std::isfinite(rr)) {
       set_error("PCG breakdown: non-finite residual");
-      *its_out = it;
+      *its_out = its;
       *rr_out = rr;
       return RT_E_DEVICE;
     }
-    if (rr <= thr2) break;
-    if (amg)
-      hipLaunchKernelGGL((k_pupdate<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
-                         nullptr, z, p);
-    else
-      hipLaunchKernelGGL((k_pupdate<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
-                         S::dinv(L), nullptr, p);
-    RT_LAUNCH_CHECK();
+    if (stopped) break;
+    chunk = next_chunk(rr_prev, its_prev, rr, its, thr2);
+    rr_prev = rr;
+    its_prev = its;
   }
-  *its_out = it;
+  if (its == 0) rr = rr0;
+  if (bad && rr > thr2) set_error("PCG breakdown: p.Ap not positive after %d iterations", its);
+  // product timings of queued iterations that did not run are dropped
+  if (ctx->profiling && ctx->prof_spans.size() > spans0 + (size_t)its)
+    ctx->prof_spans.resize(spans0 + (size_t)its);
+  *its_out = its;
   *rr_out = rr;
   return RT_OK;
 }
@@ -342,6 +414,7 @@ int ensure_work(rt_matrix* A, bool mixed) {
   RT_CHECK(A->partB.reserve(max_partials(n)));
   RT_CHECK(A->partC.reserve(2 * kMaxPartials));
   RT_CHECK(A->scal.reserve(S_COUNT));
+  RT_CHECK(A->stop.reserve(1));
   if (mixed)
     for (auto* b : {&A->r32, &A->p32, &A->q32, &A->z32, &A->d32}) RT_CHECK(b->reserve(n));
   return RT_OK;
@@ -378,7 +451,8 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
   *stt = rt_solve_stats{};
   if (n == 0) return RT_OK;
   const int gv = vec_blocks(n);
-  hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p);
+  hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p,
+                     nullptr);
   RT_LAUNCH_CHECK();
   RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
   double bb = 0.0;

@@ -57,9 +57,9 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
   __shared__ double red[kBlock / kWave];
   constexpr int RPB = kBlock / G;
   const int lb = xcd_block(per);
-  if (skip) {   // batched systems: rows of a finished problem are left as they are
+  if (skip) {   // rows of a finished problem are left as they are
     const int64_t rb = (int64_t)lb * RPB;
-    if (rb < n && skip[tprob[rb / kTileRows]]) return;
+    if (rb < n && skip[tprob ? tprob[rb / kTileRows] : 0]) return;
   }
   const int lane = threadIdx.x & (G - 1);
   const int64_t i = (int64_t)lb * RPB + threadIdx.x / G;
@@ -179,7 +179,7 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)t * kTileRows;
   const int64_t i = r0 + tid;
-  if (skip && r0 < n && skip[tprob[t]]) return;   // batched: a finished problem's tile
+  if (skip && r0 < n && skip[tprob ? tprob[t] : 0]) return;   // a finished problem's tile
   const bool live = i < n;   // grids are padded to a multiple of the XCD count
   T di = 0, xi = 0, bi = 0, si = 0;
   if (tid == 0) sbase = r0 < n ? rp[r0] & ~(int64_t)3 : 0;
@@ -320,8 +320,9 @@ inline int spmv_rows_per_block(const Level& L, int shape) {
   return sh.tiled ? kTileRows : kBlock / sh.g;
 }
 
-// tprob / skip (batched systems, else NULL): the problem of every 256-row
-// tile and a per-problem flag; blocks whose problem is flagged do nothing.
+// skip (else NULL): per-problem stop flags; blocks whose problem is flagged
+// do nothing.  tprob: the problem of every 256-row tile (batched systems), or
+// NULL for one problem (flag skip[0]).
 template <typename T, int MODE>
 int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* diag, const T* x,
                       const T* b, const T* s, T* y, float* y32, double* part, int* nparts,

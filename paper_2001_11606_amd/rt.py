@@ -102,6 +102,8 @@ _SIGS = {
     "rt_destroy": (None, [c_vp]),
     "rt_set_stream": (c_int, [c_vp, c_vp]),
     "rt_set_profiling": (c_int, [c_vp, c_int]),
+    "rt_cached_bytes": (c_int, [c_vp, ctypes.POINTER(c_i64)]),
+    "rt_release_cached": (c_int, [c_vp, ctypes.POINTER(c_i64)]),
     "rt_last_error": (ctypes.c_char_p, []),
     "rt_version": (ctypes.c_char_p, []),
     "rt_build_neighbors": (c_int, [c_vp, c_int, c_i64, c_i64, c_vp, c_vp, c_int,
@@ -196,6 +198,18 @@ def rt_set_stream(ctx: int, stream: int) -> None:
 
 def rt_set_profiling(ctx: int, on: bool) -> None:
     _check("rt_set_profiling", load().rt_set_profiling(ctx, int(bool(on))))
+
+
+def rt_cached_bytes(ctx: int) -> int:
+    out = c_i64(0)
+    _check("rt_cached_bytes", load().rt_cached_bytes(ctx, ctypes.byref(out)))
+    return out.value
+
+
+def rt_release_cached(ctx: int) -> int:
+    out = c_i64(0)
+    _check("rt_release_cached", load().rt_release_cached(ctx, ctypes.byref(out)))
+    return out.value
 
 
 def rt_build_neighbors(ctx: int, dim: int, n_total: int, n_interior: int, pos: int, h: int,

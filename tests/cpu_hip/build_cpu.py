@@ -19,7 +19,7 @@ from paper_2001_11606_amd.build import SOURCES  # noqa: E402  (the same source l
 FLAGS = ["-x", "c++", "-std=c++20", "-O1", "-g", "-fPIC", "-fno-omit-frame-pointer",
          "-fsanitize=address", "-ffp-contract=off", "-pthread", "-w",
          # always take the two-level reduction path, which large GPU runs use
-         "-DRT_PARTIAL_FOLD_MIN=4",
+         "-DRT_PARTIAL_FOLD_MIN=4", "-DRT_POOL_POISON",
          "-I" + HERE, "-I" + os.path.join(ROOT, "include")]
 
 

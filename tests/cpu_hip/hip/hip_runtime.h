@@ -336,6 +336,10 @@ inline hipError_t hipGetDeviceCount(int* n) {
   return hipSuccess;
 }
 inline hipError_t hipSetDevice(int) { return hipSuccess; }
+inline hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "cpuhip error"; }
 inline hipError_t hipEventCreate(hipEvent_t* e) {

@@ -147,6 +147,27 @@ def check_case(ctx, name, prob):
     c.free()
 
 
+def check_cache(ctx):
+    """Freed buffers go to the library's cache (filled with garbage bytes when
+    reused in this build); a rebuild from cached blocks must still match the
+    oracle, and releasing the cache empties it."""
+    prob = synth.config4(n=6)
+    ptr, idx, fz, sysm = oracle_system(prob)
+    for rep in range(2):
+        c = Case(ctx, prob, amg=rt.amg_opts(max_levels=1))
+        gptr, gidx = c.neighbors()
+        rp, col, val, g, info = c.matrix()
+        assert np.array_equal(gptr, ptr) and np.array_equal(gidx, idx), f"cache rebuild {rep}: neighbours"
+        assert np.array_equal(rp, sysm.A.indptr) and np.array_equal(col, sysm.A.indices), \
+            f"cache rebuild {rep}: CSR"
+        assert rowwise_rel_err(rp, val, sysm.A.data) <= 1e-13, f"cache rebuild {rep}: values"
+        c.free()
+        assert rt.rt_cached_bytes(ctx) > 0
+    freed = rt.rt_release_cached(ctx)
+    assert freed > 0 and rt.rt_cached_bytes(ctx) == 0
+    say(f"ok cache: rebuilt from cached blocks, released {freed} bytes")
+
+
 def check_batch(ctx):
     """An ensemble through the batched entry points against per-problem oracle results."""
     probs = [synth.config5_member(q, s) for q, s in enumerate((150.0, 300.0, 90.0, 700.0))]
@@ -216,6 +237,7 @@ def main():
         check_case(ctx, name, prob)
     if not only or "batch" in only.split(","):
         check_batch(ctx)
+    check_cache(ctx)
     # error contract on the host
     pos = np.random.default_rng(0).uniform(0, 1, (3, 40))
     h = np.full(40, 0.2)

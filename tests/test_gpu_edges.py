@@ -118,3 +118,29 @@ def test_reassemble_reuses_matrix(ctx):
     ptr, idx, fz, sysm = oracle_system(prob)
     assert np.array_equal(col, sysm.A.indices)
     assert np.max(np.abs(val - sysm.A.data)) <= 1e-13 * np.max(np.abs(sysm.A.data))
+
+
+def test_rebuild_from_cached_memory(ctx):
+    """Freed handles leave their device blocks in the library's cache; a
+    rebuild of the same problem takes them and must give the oracle's lists
+    and matrix again; releasing the cache empties it."""
+    from paper_2001_11606_amd import driver, rt
+    say("[edges] rebuild from cached device memory")
+    prob = synth.config4(n=12)
+    ptr, idx, fz, sysm = oracle_system(prob)
+    dp = driver.upload(prob, ctx.device)
+    for rep in range(2):
+        nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+        A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=rt.amg_opts(max_levels=1))
+        gptr, gidx = [t.cpu().numpy() for t in ctx.export_neighbors(nb)]
+        assert np.array_equal(gptr, ptr) and np.array_equal(gidx, idx), rep
+        rp, col, val, g = [t.cpu().numpy() for t in ctx.export_matrix(A)]
+        assert np.array_equal(rp, sysm.A.indptr) and np.array_equal(col, sysm.A.indices), rep
+        assert np.max(np.abs(val - sysm.A.data)) <= 1e-13 * np.max(np.abs(sysm.A.data)), rep
+        rt.rt_matrix_free(A)
+        rt.rt_neighbors_free(nb.handle)
+        ctx._owned = [o for o in ctx._owned if o[1] not in (A, nb.handle)]
+        assert rt.rt_cached_bytes(ctx.handle) > 0
+    freed = rt.rt_release_cached(ctx.handle)
+    assert freed > 0 and rt.rt_cached_bytes(ctx.handle) == 0
