@@ -1,8 +1,9 @@
 """Multi-step runs with the Sec. 3.3 step control through the C ABI, against
-the oracle's run of the same controller: the paper's hot-material infinite
-medium (Sec. 4.1, from dt = 1e-20 to t = 10), where the oracle takes 780
-steps (the paper prints 779, tests/golden/infinite_medium_sec4_1.json).  The
-GPU run must take the same steps and end in the same state."""
+the oracle's run of the same controller: the paper's two infinite-medium
+cases (Sec. 4.1: hot material from dt = 1e-20, hot radiation from dt = 1e-7,
+both to t = 10), where the oracle takes 780 and 156 steps (the paper prints
+779 and 155, tests/golden/infinite_medium_sec4_1.json).  The GPU run must
+take the same steps and end in the same state."""
 import numpy as np
 import pytest
 
@@ -13,8 +14,12 @@ from oracle import step as ostep, timestep
 pytestmark = pytest.mark.gpu
 
 
-def _problem():
-    prob = synth.config2_infinite(1.0, 1e-16, n=2, sigma0=1.0, dt=1e-20)
+CASES = {"hot_material": (1.0, 1e-16, 1e-20), "hot_radiation": (1e-4, 1.0, 1e-7)}
+
+
+def _problem(case):
+    e0, E0, dt0 = CASES[case]
+    prob = synth.config2_infinite(e0, E0, n=2, sigma0=1.0, dt=dt0)
     prob.opacity_exponent = 0.0
     return prob
 
@@ -36,18 +41,19 @@ def _oracle_run(prob, t_end):
     return np.array(ts), prob.e[:nin].copy(), prob.E[:nin].copy()
 
 
-def test_adaptive_infinite_medium_matches_oracle():
-    import torch
+@pytest.mark.parametrize("case", list(CASES))
+def test_adaptive_infinite_medium_matches_oracle(case):
     from paper_2001_11606_amd import driver, rt
+    e0, E0, dt0 = CASES[case]
     ctx = rt.Context(0)
     try:
         t_end = 10.0
-        ts_ref, e_ref, E_ref = _oracle_run(_problem(), t_end)
-        prob = _problem()
+        ts_ref, e_ref, E_ref = _oracle_run(_problem(case), t_end)
+        prob = _problem(case)
         dp = driver.upload(prob, ctx.device)
-        say(f"[adaptive] oracle steps {len(ts_ref)}")
+        say(f"[adaptive] {case}: oracle steps {len(ts_ref)}")
         steps, hist = driver.run_adaptive(
-            ctx, dp, t_end, 1e-20, eta_target=0.05, dt_max=0.1, max_growth=10.0,
+            ctx, dp, t_end, dt0, eta_target=0.05, dt_max=0.1, max_growth=10.0,
             amg=rt.amg_opts(max_levels=1), solve=rt.solve_opts(0, 0, 1e-14, 100),
             eps_e=1e-12, eps_E=1e-12, material_tol=1e-14)
         ts = np.array([h[0] for h in hist])
@@ -58,6 +64,6 @@ def test_adaptive_infinite_medium_matches_oracle():
         E = dp.arrays["E"][:prob.n_interior].cpu().numpy()
         assert np.max(np.abs(e - e_ref) / e_ref) <= 1e-10
         assert np.max(np.abs(E - E_ref) / E_ref) <= 1e-10
-        assert abs(float(e[0] + E[0]) - (1.0 + 1e-16)) <= 1e-12   # energy conserved
+        assert abs(float(e[0] + E[0]) - (e0 + E0)) <= 1e-12   # energy conserved
     finally:
         ctx.close()
