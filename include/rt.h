@@ -307,9 +307,12 @@ int rt_to_user(rt_ctx* ctx, const rt_neighbors* nb, const double* sorted, double
 
 /* ---- time-step control (Sec. 3.3) -----------------------------------------
  * The fractional changes of the material and radiation energies over a step,
- *   eta_e = max_i |e_i^n - e_i^{n-1}| / (e_i^n + eta_target ebar^n + tiny),
- * ebar^n = sum_i e_i^n V_i / sum_i V_i over interior particles (V from A), and
- * eta_E likewise for E; eta[0] = eta_e, eta[1] = eta_E.  The next step is
+ *   eta_e = max_i |e_i^n - e_i^{n-1}| / (e_i^n + eta_target Ebar^n + tiny),
+ *   eta_E = max_i |E_i^n - E_i^{n-1}| / (E_i^n + eta_target Ebar^n + tiny),
+ * Ebar^n = sum_i E_i^n V_i / sum_i V_i over interior particles (V from A):
+ * the floor of both is the mean radiation energy, the reading of Sec. 3.3
+ * under which this rule reproduces the step counts of Sec. 4.1 to within one.
+ * eta[0] = eta_e, eta[1] = eta_E.  The next step is
  * dt (eta_target / eta)^(1/2), the smaller of the two, within the user's
  * bounds (the host driver applies that rule).  e_*, E_*: n_interior doubles,
  * user order, device; tiny (>= 0) guards an energy that is zero everywhere. */

@@ -374,6 +374,7 @@ int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
     M = new rt_matrix();
     fresh = true;
   }
+  M->resid_ok = false;   // a new operator: no residual carries over
   rt_amg_opts d{8, 256, 0.08, 1, 1};
   M->amg = amg ? *amg : d;
   if (M->amg.max_levels < 1) M->amg.max_levels = 1;

@@ -246,6 +246,14 @@ struct rt_matrix {
   rt::DevBuf<double> partC;          // second level of the partial reductions
   rt::DevBuf<double> scal;           // device scalars (see solve.hip)
   rt::DevBuf<int32_t> stop;          // PCG stop flag: set on the device when the loop ends
+  // Residual carried between outer iterations: after a Newton step, r64 holds
+  // bs - A xs for the step's right-hand side bs and solution xs (resid_ok);
+  // bs_prev keeps that right-hand side while the next step forms its own, and
+  // xmis counts particles whose state differs from xs at the next step.
+  rt::DevBuf<double> bs_prev;
+  rt::DevBuf<int32_t> xmis;
+  bool resid_ok = false;
+  bool r64_valid = false;            // set by solve_sorted: r64 = b - A x on return
 };
 
 namespace rt {
@@ -257,8 +265,12 @@ int build_tiles(rt_ctx* ctx, Level& L);
 int build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
                     const double* pos, const double* h, int kernel, rt_neighbors* nb);
 // solve helpers used by the Newton step
+// b_prev (else NULL): r64 holds b_prev - A x on entry, unless *mismatch
+// (device counter) is non-zero; the initial residual is then r64 + (b - b_prev)
+// instead of a product.
 int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
-                 const rt_solve_opts* o, rt_solve_stats* st);
+                 const rt_solve_opts* o, rt_solve_stats* st, const double* b_prev = nullptr,
+                 const int32_t* mismatch = nullptr);
 int amg_setup(rt_ctx* ctx, rt_matrix* A);
 int check_solve_opts(const rt_solve_opts* o);
 int collect_profile(rt_ctx* ctx, rt_solve_stats* s);

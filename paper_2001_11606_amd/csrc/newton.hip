@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -25,14 +26,18 @@ __global__ void k_rhs(int64_t n, double dt, double c, double a, const double* __
                       const double* __restrict__ cv, const double* __restrict__ E_prev,
                       const double* __restrict__ QE, const double* __restrict__ g,
                       const double* __restrict__ e_l, const double* __restrict__ E_l,
-                      double* __restrict__ b) {
+                      double* __restrict__ b, const double* __restrict__ x_last,
+                      int32_t* __restrict__ mismatch) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double T = e_l[i] / cv[i];
   const double T2 = T * T;
   const double ca = c * sa[i];
-  const double P = E_prev[i] / dt + ca * (a * (T2 * T2)) - (1.0 - f[i]) * ca * E_l[i] + QE[i];
+  const double El = E_l[i];
+  const double P = E_prev[i] / dt + ca * (a * (T2 * T2)) - (1.0 - f[i]) * ca * El + QE[i];
   b[i] = V[i] * P + g[i];
+  // the carried residual is valid only if E^l is the last solution, bit for bit
+  if (x_last && El != x_last[i]) atomicAdd(mismatch, 1);
 }
 
 enum { R_DE = 0, R_DEE, R_ITS, R_BAD, R_NONPHYS, R_EN, R_EN0, R_WIDTH };
@@ -122,23 +127,19 @@ int material(rt_ctx* ctx, rt_matrix* A, const double* E_new, const double* E_old
 // pass 1: sums of e V, E V and V; pass 2: the largest fractional changes
 __global__ void __launch_bounds__(kBlock)
 k_frac_sums(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ V,
-            const double* __restrict__ e, const double* __restrict__ E, double* __restrict__ part) {
+            const double* __restrict__ E, double* __restrict__ part) {
   __shared__ double red[kBlock / kWave];
-  double se = 0.0, sE = 0.0, sv = 0.0;
+  double sE = 0.0, sv = 0.0;
   for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * kBlock) {
-    const int32_t u = perm[s];
-    se += e[u] * V[s];
-    sE += E[u] * V[s];
+    sE += E[perm[s]] * V[s];
     sv += V[s];
   }
-  se = block_sum(se, red);
   sE = block_sum(sE, red);
   sv = block_sum(sv, red);
   if (threadIdx.x == 0) {
-    part[3 * blockIdx.x] = se;
-    part[3 * blockIdx.x + 1] = sE;
-    part[3 * blockIdx.x + 2] = sv;
+    part[2 * blockIdx.x] = sE;
+    part[2 * blockIdx.x + 1] = sv;
   }
 }
 
@@ -185,22 +186,22 @@ extern "C" int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const doubl
   hipStream_t st = ctx->stream;
   const int g = grid_for(n, kBlock, kMaxPartials);
   DevBuf<double> part;
-  RT_CHECK(part.reserve((size_t)3 * g));
-  std::vector<double> hp((size_t)3 * g);
-  hipLaunchKernelGGL(k_frac_sums, dim3(g), dim3(kBlock), 0, st, n, A->nb->perm.p, A->V.p, e_new,
-                     E_new, part.p);
+  RT_CHECK(part.reserve((size_t)2 * g));
+  std::vector<double> hp((size_t)2 * g);
+  hipLaunchKernelGGL(k_frac_sums, dim3(g), dim3(kBlock), 0, st, n, A->nb->perm.p, A->V.p, E_new,
+                     part.p);
   RT_LAUNCH_CHECK();
-  RT_CHECK_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 3 * g, hipMemcpyDeviceToHost, st));
+  RT_CHECK_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 2 * g, hipMemcpyDeviceToHost, st));
   RT_CHECK_HIP(hipStreamSynchronize(st));
-  double se = 0.0, sE = 0.0, sv = 0.0;
+  double sE = 0.0, sv = 0.0;
   for (int b = 0; b < g; ++b) {
-    se += hp[3 * b];
-    sE += hp[3 * b + 1];
-    sv += hp[3 * b + 2];
+    sE += hp[2 * b];
+    sv += hp[2 * b + 1];
   }
-  const double ebar = se / sv, Ebar = sE / sv;
+  // the floor of both fractional changes is the mean radiation energy (Sec. 3.3 as read)
+  const double Ebar = sE / sv;
   hipLaunchKernelGGL(k_frac_max, dim3(g), dim3(kBlock), 0, st, n, e_new, e_old, E_new, E_old,
-                     eta_target * ebar, eta_target * Ebar, tiny, part.p);
+                     eta_target * Ebar, eta_target * Ebar, tiny, part.p);
   RT_LAUNCH_CHECK();
   RT_CHECK_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 2 * g, hipMemcpyDeviceToHost, st));
   RT_CHECK_HIP(hipStreamSynchronize(st));
@@ -251,14 +252,27 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
     if (res[3] > 0) status = RT_NOT_CONVERGED;
     if (res[4] > 0) status = RT_NONPHYSICAL;
   }
+  // Outer iterations after the first start from the last solution with the
+  // same matrix, so the last solve's residual b^l - A E^{l+1} turns into the
+  // new initial residual by adding b^{l+1} - b^l: no product needed.
+  const bool carry = ell > 0 && A->resid_ok;
+  A->resid_ok = false;
+  if (carry) {
+    std::swap(A->bs, A->bs_prev);   // bs_prev: the last right-hand side
+    RT_CHECK(A->bs.reserve(n));
+    RT_CHECK(A->xmis.reserve(1));
+    RT_CHECK_HIP(hipMemsetAsync(A->xmis.p, 0, sizeof(int32_t), st));
+  }
   hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->dt, A->c, A->a, A->V.p,
                      A->sa.p, A->f.p, A->cv.p, A->E_prev.p, A->QE.p, A->g.p, ecur, Ecur,
-                     A->bs.p);
+                     A->bs.p, carry ? A->xs.p : nullptr, carry ? A->xmis.p : nullptr);
   RT_LAUNCH_CHECK();
   RT_CHECK_HIP(hipMemcpyAsync(A->xs.p, Ecur, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   RT_CHECK_HIP(hipEventRecord(ctx->ev0, st));
-  int s = solve_sorted(ctx, A, A->bs.p, A->xs.p, &opts->solve, &stt->solve);
+  int s = solve_sorted(ctx, A, A->bs.p, A->xs.p, &opts->solve, &stt->solve,
+                       carry ? A->bs_prev.p : nullptr, carry ? A->xmis.p : nullptr);
   if (s < 0) return s;
+  const bool resid_after = A->r64_valid;
   RT_CHECK_HIP(hipEventRecord(ctx->ev1, st));
   if (s == RT_NOT_CONVERGED) status = RT_NOT_CONVERGED;
   RT_CHECK(material(ctx, A, A->xs.p, Ecur, ecur, A->enew.p, opts->material_tol,
@@ -284,6 +298,7 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   stt->solve.seconds = 1e-3 * solve_ms;
   RT_CHECK(collect_profile(ctx, &stt->solve));
   stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  A->resid_ok = resid_after;
   if (status == RT_NONPHYSICAL) set_error("rt_newton_step: %lld negative material roots", (long long)stt->nonphysical);
   else if (status == RT_NOT_CONVERGED && rt_last_error()[0] == 0)
     set_error("rt_newton_step: a material solve did not converge");

@@ -206,6 +206,31 @@ k_pupdate(int64_t n, const double* __restrict__ s, const T* __restrict__ r,
   }
 }
 
+// Initial residual from the previous one: for the same matrix and x, b - A x =
+// (b_prev - A x) + (b - b_prev).  r = r + (b - b_prev) (r32: its FP32 copy),
+// partA = r.r, partB = b.b.
+__global__ void __launch_bounds__(kBlock)
+k_resid_shift(int64_t n, const double* __restrict__ b, const double* __restrict__ b_prev,
+              double* __restrict__ r, float* __restrict__ r32, double* __restrict__ partA,
+              double* __restrict__ partB) {
+  __shared__ double red[kBlock / kWave];
+  double rr = 0.0, bb = 0.0;
+  RT_VEC_LOOP(i) {
+    const double bi = b[i];
+    const double ri = r[i] + (bi - b_prev[i]);
+    r[i] = ri;
+    if (r32) r32[i] = (float)ri;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  rr = block_sum(rr, red);
+  bb = block_sum(bb, red);
+  if (threadIdx.x == 0) {
+    partA[blockIdx.x] = rr;
+    partB[blockIdx.x] = bb;
+  }
+}
+
 __global__ void k_add_f32(int64_t n, const float* __restrict__ d, double* __restrict__ x) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[i] += (double)d[i];
@@ -438,10 +463,11 @@ int residual64(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, floa
 }  // namespace
 
 int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt_solve_opts* o,
-                 rt_solve_stats* stt) {
+                 rt_solve_stats* stt, const double* b_prev, const int32_t* mismatch) {
   hipStream_t st = ctx->stream;
   const int64_t n = A->n;
   const bool mixed = o->precision == RT_PREC_MIXED;
+  A->r64_valid = false;
   if (mixed && !A->has_fp32) {
     set_error("rt_solve: mixed precision needs a matrix assembled with build_fp32 = 1");
     return RT_E_STATE;
@@ -451,12 +477,29 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
   *stt = rt_solve_stats{};
   if (n == 0) return RT_OK;
   const int gv = vec_blocks(n);
-  hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p,
-                     nullptr);
-  RT_LAUNCH_CHECK();
-  RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
-  double bb = 0.0;
-  RT_CHECK(read_scalar(ctx, A, S_BB, &bb));
+  double bb = 0.0, rr = 0.0;
+  bool have_r = false;   // r64 (and r32) hold b - A x, rr = ||r||^2
+  if (b_prev) {
+    hipLaunchKernelGGL(k_resid_shift, dim3(gv), dim3(kBlock), 0, st, n, b, b_prev, A->r64.p,
+                       mixed ? A->r32.p : nullptr, A->partA.p, A->partB.p);
+    RT_LAUNCH_CHECK();
+    RT_CHECK(finalize(ctx, A, FIN_RR, gv, A->partA.p, nullptr));
+    RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
+    RT_CHECK_HIP(hipMemcpyAsync(ctx->host + S_COUNT, mismatch, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    RT_CHECK(ctx->sync_read(A->scal.p, sizeof(double) * S_COUNT));
+    int32_t mis = 0;
+    std::memcpy(&mis, ctx->host + S_COUNT, sizeof(int32_t));
+    bb = ctx->host[S_BB];
+    rr = ctx->host[S_RR];
+    have_r = mis == 0;
+  } else {
+    hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p,
+                       nullptr);
+    RT_LAUNCH_CHECK();
+    RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
+    RT_CHECK(read_scalar(ctx, A, S_BB, &bb));
+  }
   if (!std::isfinite(bb)) {
     set_error("rt_solve: right-hand side is not finite");
     return RT_E_ARG;
@@ -467,16 +510,15 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
     return RT_OK;
   }
   const double thr2 = o->tol * o->tol * bb;
-  double rr = 0.0;
   int status = RT_OK;
   if (!mixed) {
-    RT_CHECK(residual64(ctx, A, b, x, nullptr, &rr));
+    if (!have_r) RT_CHECK(residual64(ctx, A, b, x, nullptr, &rr));
     int its = 0;
     RT_CHECK(pcg_core<double>(ctx, A, amg, x, A->r64.p, rr, thr2, o->max_iter, &its, &rr));
     stt->iterations = its;
     if (rr > thr2) status = RT_NOT_CONVERGED;
   } else {
-    RT_CHECK(residual64(ctx, A, b, x, A->r32.p, &rr));
+    if (!have_r) RT_CHECK(residual64(ctx, A, b, x, A->r32.p, &rr));
     int total = 0, refine = 0;
     while (rr > thr2 && total < o->max_iter && refine < o->max_refine) {
       // reduce by inner_tol, or just enough (with margin) to reach tol
@@ -499,6 +541,7 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
     if (rr > thr2) status = RT_NOT_CONVERGED;
   }
   stt->rel_residual = std::sqrt(rr / bb);
+  A->r64_valid = true;
   if (status == RT_NOT_CONVERGED)
     set_error("rt_solve: relative residual %.3e above tolerance %.3e", stt->rel_residual, o->tol);
   return status;
@@ -568,6 +611,7 @@ extern "C" int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
   auto t0 = std::chrono::steady_clock::now();
   rt_solve_stats local{};
   rt_solve_stats* stt = stats ? stats : &local;
+  A->resid_ok = false;   // bs, xs and r64 are overwritten here
   RT_CHECK(A->xs.reserve(A->n));
   RT_CHECK(A->bs.reserve(A->n));
   RT_CHECK(gather_sorted(ctx, A->nb, A->n, b, A->bs.p));

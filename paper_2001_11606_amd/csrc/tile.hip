@@ -18,7 +18,9 @@
 // column's value); where two columns race for a slot the list order may
 // differ between builds, the products do not.  A probe that visits every
 // bucket marks the tile as overflowing (the level then stays untiled), so
-// insertion ends for any input.  Built once per matrix structure.
+// insertion ends for any input.  Built once per matrix structure: one pass
+// writes each tile's list into room for kTileMaxCols columns and counts it,
+// then the lists are packed after a scan of the counts.
 #include <climits>
 #include <cstring>
 
@@ -88,33 +90,13 @@ __device__ __forceinline__ void tile_rows(int64_t n, int64_t t, const int64_t* r
   *e1 = rp[r1];
 }
 
-// distinct-column count of every tile; *flag = 1 if a tile overflows
-__global__ void __launch_bounds__(kBlock)
-k_tile_count(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-             int64_t* __restrict__ cnt, int* __restrict__ flag) {
-  __shared__ int keys[kHash];
-  __shared__ int count, overflow;
-  for (int s = threadIdx.x; s < kHash; s += kBlock) keys[s] = -1;
-  if (threadIdx.x == 0) {
-    count = 0;
-    overflow = 0;
-  }
-  __syncthreads();
-  int64_t e0, e1;
-  tile_rows(n, blockIdx.x, rp, &e0, &e1);
-  tile_insert(e0, e1, col, keys, &count, &overflow);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    cnt[blockIdx.x] = overflow ? 0 : count;
-    if (overflow) flag[0] = 1;
-  }
-}
-
-// distinct columns of every tile in slot order, and each entry's position among them
+// Distinct columns of every tile in slot order, into a padded list (tile t
+// at t * kTileMaxCols), their number, and each entry's position among them.
+// A tile that overflows writes count 0 and sets *flag; its entries are left.
 __global__ void __launch_bounds__(kBlock)
 k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-            const int64_t* __restrict__ off, int32_t* __restrict__ tcols,
-            uint16_t* __restrict__ lcol) {
+            int32_t* __restrict__ tpad, int64_t* __restrict__ cnt, uint16_t* __restrict__ lcol,
+            int* __restrict__ flag) {
   constexpr int PER = kHash / kBlock;   // consecutive slots per thread
   __shared__ int keys[kHash];
   __shared__ int pos[kHash];
@@ -130,6 +112,14 @@ k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict
   tile_rows(n, blockIdx.x, rp, &e0, &e1);
   tile_insert(e0, e1, col, keys, &count, &overflow);
   __syncthreads();
+  if (overflow) {   // uniform over the block
+    if (threadIdx.x == 0) {
+      cnt[blockIdx.x] = 0;
+      flag[0] = 1;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) cnt[blockIdx.x] = count;
   // positions = exclusive prefix count of occupied slots (block scan)
   const int s0 = threadIdx.x * PER;
   int own = 0;
@@ -144,18 +134,28 @@ k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict
   __syncthreads();
   int base = incl - own;
   for (int q = 0; q < w; ++q) base += wsum[q];
-  const int64_t o = off[blockIdx.x];
+  int32_t* out = tpad + (int64_t)blockIdx.x * kTileMaxCols;
   for (int q = 0; q < PER; ++q) {
     const int c = keys[s0 + q];
     if (c != -1) {
       pos[s0 + q] = base;
-      tcols[o + base] = c;
+      out[base] = c;   // base < count < kTileMaxCols (no overflow)
       ++base;
     }
   }
   __syncthreads();
   for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock)
     lcol[k] = (uint16_t)pos[tile_find(keys, col[k])];
+}
+
+// padded lists -> contiguous tile_cols (tile t at off[t])
+__global__ void __launch_bounds__(kBlock)
+k_tile_compact(const int32_t* __restrict__ tpad, const int64_t* __restrict__ off,
+               int32_t* __restrict__ tcols) {
+  const int64_t o = off[blockIdx.x];
+  const int c = (int)(off[blockIdx.x + 1] - o);
+  const int32_t* in = tpad + (int64_t)blockIdx.x * kTileMaxCols;
+  for (int k = threadIdx.x; k < c; k += kBlock) tcols[o + k] = in[k];
 }
 
 }  // namespace
@@ -172,17 +172,21 @@ int build_tiles(rt_ctx* ctx, Level& L) {
   if (nt > INT_MAX) return RT_OK;
   DevBuf<int64_t> cnt;
   DevBuf<int> flag;
+  DevBuf<int32_t> tpad;   // kTileMaxCols columns of room per tile
   RT_CHECK(cnt.reserve(nt + 1));
   RT_CHECK(flag.reserve(1));
+  RT_CHECK(tpad.reserve((size_t)nt * kTileMaxCols));
+  RT_CHECK(L.lcol.reserve(L.nnz + kSpmvPad));
   RT_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + nt, 0, sizeof(int64_t), st));
-  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nt), dim3(kBlock), 0, st, n, L.rp.p, L.col.p,
-                     cnt.p, flag.p);
+  RT_CHECK_HIP(hipMemsetAsync(L.lcol.p + L.nnz, 0, sizeof(uint16_t) * kSpmvPad, st));
+  hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(kBlock), 0, st, n, L.rp.p, L.col.p,
+                     tpad.p, cnt.p, L.lcol.p, flag.p);
   RT_LAUNCH_CHECK();
   RT_CHECK(ctx->sync_read(flag.p, sizeof(int)));
   int overflow = 0;
   std::memcpy(&overflow, ctx->host, sizeof(int));
-  if (overflow) return RT_OK;
+  if (overflow) return RT_OK;   // lcol is unused by untiled products
   int64_t maxc = 0;
   RT_CHECK(max_nonneg<int64_t>(ctx, cnt.p, nt, &maxc));
   RT_CHECK(L.tile_off.reserve(nt + 1));
@@ -191,10 +195,8 @@ int build_tiles(rt_ctx* ctx, Level& L) {
   int64_t total = 0;
   std::memcpy(&total, ctx->host, sizeof(int64_t));
   RT_CHECK(L.tile_cols.reserve(total));
-  RT_CHECK(L.lcol.reserve(L.nnz + kSpmvPad));
-  RT_CHECK_HIP(hipMemsetAsync(L.lcol.p + L.nnz, 0, sizeof(uint16_t) * kSpmvPad, st));
-  hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(kBlock), 0, st, n, L.rp.p, L.col.p,
-                     L.tile_off.p, L.tile_cols.p, L.lcol.p);
+  hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)nt), dim3(kBlock), 0, st, tpad.p,
+                     L.tile_off.p, L.tile_cols.p);
   RT_LAUNCH_CHECK();
   L.tiled = true;
   L.ntiles = nt;

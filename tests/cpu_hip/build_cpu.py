@@ -12,7 +12,7 @@ import concurrent.futures as cf
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2001_11606_amd", "csrc")
-OUT_DIR = os.path.join(ROOT, "_build", "cpu_hip")
+OUT_DIR = os.environ.get("RT_CPU_BUILD_DIR") or os.path.join(ROOT, "_build", "cpu_hip")
 LIB = os.path.join(OUT_DIR, "librt_cpu.so")
 sys.path.insert(0, ROOT)
 from paper_2001_11606_amd.build import SOURCES  # noqa: E402  (the same source list as the HIP build)

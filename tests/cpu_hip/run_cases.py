@@ -114,7 +114,7 @@ def check_case(ctx, name, prob):
     e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
     assert s == 0 and e <= 1e-10, f"{name}: tuned solve err={e}"
     # Algorithm 1, three outer iterations, FP64 + AMG
-    n_outer = 1 if QUICK else 3
+    n_outer = 2 if QUICK else 3   # the second outer iteration carries the residual over
     ref = ostep.time_step(prob.copy(), fixed_outer=n_outer, solve_tol=1e-15)
     e_ = c.arr["e"][:nin].copy()
     E_ = c.arr["E"][:nin].copy()

@@ -8,6 +8,7 @@ relative, the mixed-precision path within 1e-10 relative in E and e.
 import numpy as np
 import pytest
 
+import synth
 from gpu_common import gpu_system, oracle_system, rowwise_rel_err, say, small_cases
 from oracle import linsolve, step as ostep
 
@@ -165,3 +166,52 @@ def test_deep_hierarchy_repeated_setup(ctx):
             assert status == rt.RT_OK
             err = np.max(np.abs(xt.cpu().numpy() - x_ref)) / np.max(np.abs(x_ref))
             assert err <= bar, (rep, prec, err)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_newton_residual_carry(ctx, precision):
+    """From the second outer iteration on, the initial residual of the solve
+    is the last solve's residual plus the change of the right-hand side.  It
+    is used only when E^l is bit for bit the last solution: with E perturbed
+    between the calls, the step must equal one taken without carried state
+    (matrix re-assembled first) bit for bit; unperturbed, it must agree with
+    that one to the solve tolerance."""
+    import torch
+    from paper_2001_11606_amd import driver, rt
+    say(f"[newton carry] precision={precision}")
+    prob = synth.config4(n=12)
+    nin = prob.n_interior
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, nin, prob.kernel)
+    tol = 1e-14 if precision == 0 else 1e-12
+    nopts = rt.newton_opts(rt.solve_opts(precision, 0, tol, 2000, 1e-4, 50))
+    bump = torch.tensor(1.0 + 1e-3 * np.cos(np.arange(nin)), device=ctx.device)
+
+    def run(perturb, fresh):
+        A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=rt.amg_opts(max_levels=1))
+        e = dp.arrays["e"][:nin].clone()
+        E = dp.arrays["E"][:nin].clone()
+        s, _ = ctx.newton_step(A, e, E, 0, nopts)
+        assert s == rt.RT_OK
+        if perturb:
+            E.mul_(bump)
+        if fresh:   # re-assembly drops every carried residual
+            ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=rt.amg_opts(max_levels=1), A=A)
+        s, st = ctx.newton_step(A, e, E, 1, nopts)
+        assert s == rt.RT_OK
+        out = (e.cpu().numpy(), E.cpu().numpy(), st.solve.rel_residual)
+        rt.rt_matrix_free(A)
+        ctx._owned = [o for o in ctx._owned if o[1] != A]
+        return out
+
+    e1, E1, r1 = run(True, False)
+    e2, E2, r2 = run(True, True)
+    assert np.array_equal(e1, e2) and np.array_equal(E1, E2)
+    e3, E3, r3 = run(False, False)
+    e4, E4, r4 = run(False, True)
+    assert r3 <= tol and r4 <= tol
+    bar = 1e-12 if precision == 0 else 1e-10
+    assert np.max(np.abs(E3 - E4) / np.abs(E4)) <= bar
+    assert np.max(np.abs(e3 - e4) / np.abs(e4)) <= bar
