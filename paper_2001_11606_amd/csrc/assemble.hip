@@ -21,6 +21,7 @@
 #include "kernels_sph.h"
 #include "prim.h"
 #include "reduce.h"
+#include "spmv.h"
 
 namespace rt {
 namespace {
@@ -118,9 +119,11 @@ struct AsmArgs {
 // times whatever its length (rows longer than G*ENT take further passes).
 template <int DIM, int G, int ENT>
 __global__ void __launch_bounds__(kBlock)
-k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A) {
+k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A, int per) {
   const int lane = threadIdx.x & (G - 1);
-  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  // each XCD takes one contiguous range of rows, so that the neighbour records
+  // its rows gather stay in its own L2
+  const int64_t i = ((int64_t)xcd_block(per) * kBlock + threadIdx.x) / G;
   if (i >= nin) return;   // whole groups leave together
   const Rec4 pi = load_rec4(A.sp4, i);
   const rt_f64x2_t vdi = load_pair(A.VD, i);
@@ -292,10 +295,11 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
                fp32 ? L.sinv32.p : nullptr};
     const double avg = nin ? (double)nb->npairs / (double)n : 0.0;
     const int G = pick_group(avg);
-    const int grid = grid_for(nin * (int64_t)G, kBlock);
+    const int per = (grid_for(nin * (int64_t)G, kBlock) + kXcd - 1) / kXcd;
+    const int grid = per * kXcd;
 #define RT_ASM(D_, G_)                                                                           \
   hipLaunchKernelGGL((k_assemble<D_, G_, 4>), dim3(grid), dim3(kBlock), 0, st, nin, n, nb->kernel, \
-                     in->dt, in->c, aa)
+                     in->dt, in->c, aa, per)
     if (nb->dim == 3) {
       if (G == 64) RT_ASM(3, 64); else if (G == 16) RT_ASM(3, 16);
       else if (G == 8) RT_ASM(3, 8); else RT_ASM(3, 4);

@@ -127,6 +127,11 @@ constexpr int kSpmvPad = 8;            // spare entries after values / lcol
 #ifndef RT_DYNAMIC_LDS
 #define RT_DYNAMIC_LDS(name) extern __shared__ __attribute__((aligned(16))) unsigned char name[]
 #endif
+// A value the code knows to be equal in all lanes of the wave, moved to a
+// scalar register so that loops and branches on it stay scalar.
+#ifndef RT_UNIFORM
+#define RT_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
+#endif
 
 // Per-particle records read by the pair loops with two 16-byte loads:
 // (x, y, z, h) in 4 doubles (z = 0 in 2-D) and (V, D) in 2 doubles.

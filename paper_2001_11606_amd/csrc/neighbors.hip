@@ -179,6 +179,7 @@ __global__ void k_run_starts(int64_t n, const int32_t* __restrict__ flags,
 
 constexpr int kNbrCand = 512;   // candidates staged in LDS per pass
 constexpr int kNbrRows = 512;   // rows of one cell handled per pass
+constexpr int kCountRows = 8;   // count pass: rows tested against a wave's candidates in turn
 constexpr double kNbrMaskBytes = 4.0e9;   // largest hit-mask buffer kept between the passes
 
 // Candidates of a cell: the particle count of its 2 * 3^DIM adjacent-cell slots.
@@ -285,6 +286,81 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
       __syncthreads();
       // the block's own cell is the centre slot of its flag: its rows are candidates too
       const int cslot = (r0 >= nin ? NB : 0) + NB / 2;
+      if (!FILL && !FROM_MASK) {
+        // Count pass: a wave holds one word of 64 candidates in registers and
+        // tests up to kCountRows rows against it, the row read by all lanes
+        // at once; work items are (candidate word, row group) pairs.
+        const int nwords = RT_UNIFORM((mc + kWave - 1) / kWave);
+        const int ngroups = RT_UNIFORM((nrows + kCountRows - 1) / kCountRows);
+        // item = g * nwords + w, stepped by the wave count without dividing
+        // (mc >= 1 inside the chunk loop, so nwords >= 1)
+        int w = wave, g = nwords > 0 ? 0 : ngroups;
+        while (g < ngroups && w >= nwords) {
+          w -= nwords;
+          ++g;
+        }
+        for (; g < ngroups; w += kBlock / kWave) {
+          while (w >= nwords) {
+            w -= nwords;
+            ++g;
+          }
+          if (g >= ngroups) break;
+          const int k = w * kWave + lane;
+          // The pair test r^2 < (kappa max(h_i, h_j))^2 as max((kappa h_i)^2,
+          // (kappa h_j)^2): rounding is monotone, so both give the same bits.
+          // An empty lane has NaN coordinates: its r^2 never tests true.
+          int32_t t = -1;
+          double qx = __builtin_nan(""), qy = qx, qz = qx, tq = 0.0;
+          if (k < mc) {
+            t = ct[k];
+            qx = cx[k];
+            qy = cy[k];
+            qz = cz[k];
+            const double kq = kappa * ch[k];
+            tq = kq * kq;
+          }
+          const int ra = g * kCountRows;
+          const int nr = RT_UNIFORM(nrows - ra < kCountRows ? nrows - ra : kCountRows);
+          const int32_t s0 = (int32_t)(rb + ra);   // particle indices fit in int32
+          const int ks0 = RT_UNIFORM(roff[cslot] + (s0 - rlo[cslot]) - c0);
+          const bool staged = ks0 >= 0 && ks0 + nr <= mc;   // the rows are candidates here
+          unsigned long long mine = 0ull;   // lane r keeps the mask word of row ra + r
+          for (int r = 0; r < nr; ++r) {
+            const int32_t s = s0 + r;
+            double xi, yi, zi, hi;
+            if (staged) {
+              xi = cx[ks0 + r];
+              yi = cy[ks0 + r];
+              zi = cz[ks0 + r];
+              hi = ch[ks0 + r];
+            } else {
+              const Rec4 q = load_rec4(sp4, s);
+              xi = q.x;
+              yi = q.y;
+              zi = q.z;
+              hi = q.h;
+            }
+            const double ki = kappa * hi;
+            double d = xi - qx;
+            double r2 = d * d;
+            d = yi - qy;
+            r2 = r2 + d * d;
+            if (DIM == 3) {
+              d = zi - qz;
+              r2 = r2 + d * d;
+            }
+            const double th2 = fmax(ki * ki, tq);
+            const bool hit = (t != s) & (r2 < th2);
+            const unsigned long long bm = __ballot(hit);
+            if (lane == r) mine = bm;
+          }
+          if (lane < nr) {
+            if (masks) masks[(int64_t)(s0 + lane) * mstride + c0 / kWave + w] = mine;
+            atomicAdd(&rcount[ra + lane], (int)__popcll(mine));
+          }
+        }
+        continue;   // next chunk of candidates
+      }
       for (int r = wave; r < nrows; r += kBlock / kWave) {
         const int64_t s = rb + r;
         const int ks = roff[cslot] + (int)(s - rlo[cslot]) - c0;

@@ -39,6 +39,7 @@
 #define __builtin_nontemporal_load(p) (*(p))
 // dynamic LDS: a heap buffer of the launch's byte count (bounds seen by ASan)
 #define RT_DYNAMIC_LDS(name) unsigned char* name = cpuhip::g_dyn_lds
+#define RT_UNIFORM(x) (x)
 
 struct dim3 {
   unsigned x, y, z;
