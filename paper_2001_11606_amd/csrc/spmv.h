@@ -146,8 +146,9 @@ __device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int kb, 
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const bool in = kb + j >= k0 && kb + j < k1;
-    const T w = in ? v[j] : T(0);
-    s += w * xs[in ? (int)lc[j] : 0];
+    // an entry outside the row adds an exact zero, whatever xs[0] holds
+    const T xj = xs[in ? (int)lc[j] : 0];
+    s += in ? v[j] * xj : T(0);
   }
   return s;
 }
