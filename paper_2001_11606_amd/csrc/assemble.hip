@@ -28,22 +28,44 @@ namespace {
 
 struct FrozenArgs {
   const int32_t* perm;
-  const double *m, *rho, *cv, *s0, *ss, *e, *E, *Qe, *Qn;
+  const double* rec;   // per-particle input records in user order (k_pack_inputs)
+  const double* ss;
   double dt, c, a, p;
   double *V, *D, *sa, *st, *f, *Eall, *e_prev, *E_prev, *rho_s, *cv_s, *m_s, *Qe_s, *QE_s;
   double* VD;
 };
 
+// The caller's per-particle inputs, read in user order (coalesced) and
+// packed into one 64-byte record per particle, (c_v, rho, e, E, sigma_0, m,
+// Q_e, Q_E); the sorted-order pass then gathers one record instead of eight
+// scattered values.
+__global__ void k_pack_inputs(int64_t n, const double* __restrict__ cv,
+                              const double* __restrict__ rho, const double* __restrict__ e,
+                              const double* __restrict__ E, const double* __restrict__ s0,
+                              const double* __restrict__ m, const double* __restrict__ Qe,
+                              const double* __restrict__ Qn, double* __restrict__ rec) {
+  int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  rt_f64x2_t* out = reinterpret_cast<rt_f64x2_t*>(rec + 8 * u);
+  out[0] = rt_f64x2_t{cv[u], rho[u]};
+  out[1] = rt_f64x2_t{e[u], E[u]};
+  out[2] = rt_f64x2_t{s0[u], m[u]};
+  out[3] = rt_f64x2_t{Qe ? Qe[u] : 0.0, Qn ? Qn[u] : 0.0};
+}
+
 __global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
   int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int32_t u = A.perm[s];
-  const double cv = A.cv[u], rho = A.rho[u], e = A.e[u], E = A.E[u];
+  const rt_f64x2_t* in = reinterpret_cast<const rt_f64x2_t*>(A.rec + 8 * (int64_t)u);
+  const rt_f64x2_t r0 = in[0], r1 = in[1], r2 = in[2], r3 = in[3];
+  const double cv = r0[0], rho = r0[1], e = r1[0], E = r1[1];
+  const double s0 = r2[0], m = r2[1];
   const double T = e / cv;
-  const double sa = A.p == 0.0 ? A.s0[u] : A.s0[u] * pow(T, A.p);
+  const double sa = A.p == 0.0 ? s0 : s0 * pow(T, A.p);
   const double st = sa + (A.ss ? A.ss[u] : 0.0);
   const double f = 1.0 / (1.0 + A.c * sa * A.dt * 4.0 * A.a * (T * T * T) / (rho * cv));
-  const double V = A.m[u] / rho;
+  const double V = m / rho;
   const double D = A.c * (1.0 / 3.0) / st;
   A.V[s] = V;
   A.sa[s] = sa;
@@ -58,9 +80,9 @@ __global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
     A.E_prev[s] = E;
     A.rho_s[s] = rho;
     A.cv_s[s] = cv;
-    A.m_s[s] = A.m[u];
-    A.Qe_s[s] = A.Qe ? A.Qe[u] : 0.0;
-    A.QE_s[s] = A.Qn ? A.Qn[u] : 0.0;
+    A.m_s[s] = m;
+    A.Qe_s[s] = r3[0];
+    A.QE_s[s] = r3[1];
   }
 }
 
@@ -238,10 +260,13 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
   RT_CHECK(A->VD.reserve((size_t)2 * n));
   for (auto* b : {&A->rho, &A->cv, &A->m, &A->e_prev, &A->E_prev, &A->Qe, &A->QE, &A->g})
     RT_CHECK(b->reserve(nin));
-  DevBuf<double> sigt;
+  DevBuf<double> sigt, rec;
   RT_CHECK(sigt.reserve(n));
-  FrozenArgs fa{nb->perm.p, in->m, in->rho, in->cv, in->sigma0_a, in->sigma_s, in->e, in->E,
-                in->Q_e, in->Q_E, in->dt, in->c, in->a, in->opacity_exponent,
+  RT_CHECK(rec.reserve((size_t)8 * n));
+  hipLaunchKernelGGL(k_pack_inputs, dim3(grid_for(n)), dim3(kBlock), 0, st, n, in->cv, in->rho,
+                     in->e, in->E, in->sigma0_a, in->m, in->Q_e, in->Q_E, rec.p);
+  RT_LAUNCH_CHECK();
+  FrozenArgs fa{nb->perm.p, rec.p, in->sigma_s, in->dt, in->c, in->a, in->opacity_exponent,
                 A->V.p, A->D.p, A->sa.p, sigt.p, A->f.p, A->Eall.p, A->e_prev.p, A->E_prev.p,
                 A->rho.p, A->cv.p, A->m.p, A->Qe.p, A->QE.p, A->VD.p};
   hipLaunchKernelGGL(k_frozen, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nin, fa);

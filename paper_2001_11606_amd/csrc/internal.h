@@ -189,8 +189,6 @@ struct rt_neighbors {
   rt::DevBuf<uint64_t> skeys;   // sorted keys: ghost flag << (dim*bits) | Morton(cell)
   rt::DevBuf<int32_t> perm;     // sorted -> user
   rt::DevBuf<int32_t> iperm;    // user -> sorted
-  rt::DevBuf<double> spos;      // dim x n_total, sorted order
-  rt::DevBuf<double> sh;        // n_total, sorted order
   rt::DevBuf<double> sp4;       // 4 x n_total: (x, y, z, h) per particle, sorted order
   rt::DevBuf<int64_t> ptr;      // n_total + 1, sorted order
   rt::DevBuf<int32_t> idx;      // npairs, sorted indices, ascending per row

@@ -120,20 +120,28 @@ k_keys(int bits, int64_t n, int64_t nin, const double* __restrict__ pos, double 
   ids[i] = (int32_t)i;
 }
 
-__global__ void k_gather_sorted(int dim, int64_t n, const int32_t* __restrict__ perm,
-                                const double* __restrict__ pos, const double* __restrict__ h,
-                                double* __restrict__ spos, double* __restrict__ sh,
-                                double* __restrict__ sp4, int32_t* __restrict__ iperm) {
+// (x, y, z, h) of every particle in user order, read coalesced from the
+// caller's arrays into one 32-byte record each (z = 0 in 2-D).
+__global__ void k_pack_pos(int dim, int64_t n, const double* __restrict__ pos,
+                           const double* __restrict__ h, double* __restrict__ rec) {
+  int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  rt_f64x2_t* out = reinterpret_cast<rt_f64x2_t*>(rec + 4 * u);
+  out[0] = rt_f64x2_t{pos[u], pos[n + u]};
+  out[1] = rt_f64x2_t{dim == 3 ? pos[2 * n + u] : 0.0, h[u]};
+}
+
+// Sorted records: one gathered per particle; iperm = inverse of perm.
+__global__ void k_gather_sorted(int64_t n, const int32_t* __restrict__ perm,
+                                const double* __restrict__ rec, double* __restrict__ sp4,
+                                int32_t* __restrict__ iperm) {
   int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
-  int32_t u = perm[s];
-  for (int a = 0; a < dim; ++a) {
-    spos[a * n + s] = pos[a * n + u];
-    sp4[4 * s + a] = pos[a * n + u];
-  }
-  for (int a = dim; a < 3; ++a) sp4[4 * s + a] = 0.0;
-  sh[s] = h[u];
-  sp4[4 * s + 3] = h[u];
+  const int32_t u = perm[s];
+  const Rec4 q = load_rec4(rec, u);
+  rt_f64x2_t* o = reinterpret_cast<rt_f64x2_t*>(sp4 + 4 * s);
+  o[0] = rt_f64x2_t{q.x, q.y};
+  o[1] = rt_f64x2_t{q.z, q.h};
   iperm[u] = (int32_t)s;
 }
 
@@ -644,8 +652,6 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK(ids.reserve(n));
   RT_CHECK(nb->perm.reserve(n));
   RT_CHECK(nb->iperm.reserve(n));
-  RT_CHECK(nb->spos.reserve((size_t)dim * n));
-  RT_CHECK(nb->sh.reserve(n));
   RT_CHECK(nb->sp4.reserve((size_t)4 * n));
 #define RT_KEYS(D_)                                                                            \
   hipLaunchKernelGGL(k_keys<D_>, dim3(grid_for(n)), dim3(kBlock), 0, st, bits, n, nin, pos,     \
@@ -661,9 +667,14 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   if (!sorted) RT_CHECK(radix_sort_pairs(ctx, keys.p, nb->skeys.p, ids.p, nb->perm.p, n, end_bit));
   keys.release();
   ids.release();
-  hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, dim, n,
-                     nb->perm.p, pos, h, nb->spos.p, nb->sh.p, nb->sp4.p, nb->iperm.p);
-  RT_LAUNCH_CHECK();
+  {
+    DevBuf<double> rec;
+    RT_CHECK(rec.reserve((size_t)4 * n));
+    hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(n)), dim3(kBlock), 0, st, dim, n, pos, h, rec.p);
+    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nb->perm.p,
+                       rec.p, nb->sp4.p, nb->iperm.p);
+    RT_LAUNCH_CHECK();
+  }
 
   // 4. [start, end) per (flag, row-major cell); empty cells stay [0, 0)
   DevBuf<int32_t> cstart, cend;

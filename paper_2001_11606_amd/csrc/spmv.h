@@ -146,9 +146,10 @@ __device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int kb, 
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const bool in = kb + j >= k0 && kb + j < k1;
-    // an entry outside the row adds an exact zero, whatever xs[0] holds
-    const T xj = xs[in ? (int)lc[j] : 0];
-    s += in ? v[j] * xj : T(0);
+    // an entry outside the row adds 0 * 0, whatever xs[0] holds
+    const T w = in ? v[j] : T(0);
+    const T xj = in ? xs[(int)lc[j]] : T(0);
+    s += w * xj;
   }
   return s;
 }
