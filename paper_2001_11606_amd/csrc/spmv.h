@@ -146,10 +146,8 @@ __device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int kb, 
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const bool in = kb + j >= k0 && kb + j < k1;
-    // an entry outside the row adds 0 * 0, whatever xs[0] holds
     const T w = in ? v[j] : T(0);
-    const T xj = in ? xs[(int)lc[j]] : T(0);
-    s += w * xj;
+    s += w * xs[in ? (int)lc[j] : 0];
   }
   return s;
 }
@@ -227,7 +225,10 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
     T sum[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
-      sum[u] = kb[u] < k1[u] ? chunk_dot<T>(v[u], lc[u], kb[u], k0[u], k1[u], xs) : T(0);
+      // (an empty row reads nothing: xs[0] is staged only in a tile with columns)
+      sum[u] = kb[u] < k1[u] && k0[u] < k1[u]
+                   ? chunk_dot<T>(v[u], lc[u], kb[u], k0[u], k1[u], xs)
+                   : T(0);
     // rows longer than one pass of the group
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
