@@ -393,6 +393,7 @@ int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   rt_matrix* M = *A;
   bool fresh = false;
   if (M && M->nb != nb) {
@@ -445,6 +446,10 @@ int rt_matrix_export(rt_ctx* ctx, const rt_matrix* A, int64_t* row_ptr, int32_t*
   return rt::matrix_export(ctx, A, row_ptr, col, val, ghost_rhs);
 }
 
-void rt_matrix_free(rt_matrix* A) { delete A; }
+void rt_matrix_free(rt_matrix* A) {
+  if (!A) return;
+  rt::IdleScope idle;   // one wait for the device, then every buffer goes back to the cache
+  delete A;
+}
 
 }  // extern "C"

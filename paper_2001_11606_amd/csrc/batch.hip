@@ -607,6 +607,7 @@ int rt_batch_create(rt_ctx* ctx, int nprob, rt_matrix* const* mats, rt_batch** o
     fp32 = fp32 && mats[p]->has_fp32;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   hipStream_t st = ctx->stream;
   rt_batch* B = new rt_batch();
   B->nprob = nprob;
@@ -735,7 +736,11 @@ int rt_batch_create(rt_ctx* ctx, int nprob, rt_matrix* const* mats, rt_batch** o
   return RT_OK;
 }
 
-void rt_batch_free(rt_batch* B) { delete B; }
+void rt_batch_free(rt_batch* B) {
+  if (!B) return;
+  rt::IdleScope idle;   // one wait for the device, then every buffer goes back to the cache
+  delete B;
+}
 
 int rt_batch_get_info(const rt_batch* B, int64_t* rows, int64_t* nnz, int64_t* tile_cols) {
   rt::clear_error();
@@ -809,6 +814,7 @@ int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x, const r
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   hipStream_t st = ctx->stream;
   const int64_t n = B->n;
   hipLaunchKernelGGL(k_b_gather, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B->perm.p, b, B->bs.p);
@@ -848,6 +854,7 @@ int rt_batch_newton_step(rt_ctx* ctx, rt_batch* B, double* e, double* E, int ell
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   hipStream_t st = ctx->stream;
   const int64_t n = B->n;
   const int np = B->nprob;

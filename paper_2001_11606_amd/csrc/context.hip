@@ -23,10 +23,20 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_last_error.clear(); }
 
+ReleaseState& release_state() {
+  static thread_local ReleaseState st;
+  return st;
+}
+
 namespace {
+struct Cached {
+  void* p;
+  bool idle;           // no queued work uses it
+  hipStream_t stream;  // else: the stream whose queued work may use it
+};
 std::mutex g_pool_mu;
 // (device, bytes) -> cached block
-std::multimap<std::pair<int, size_t>, void*> g_pool;
+std::multimap<std::pair<int, size_t>, Cached> g_pool;
 size_t g_pool_total = 0;
 
 // sizes are rounded so that blocks of nearly equal requests are shared
@@ -41,21 +51,38 @@ void* pool_get(size_t* bytes, int* device) {
   (void)hipGetDevice(&d);
   *device = d;
   const size_t want = pool_round(*bytes);
+  const ReleaseState& rs = release_state();
+  bool wait = false;
+  void* p = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    auto it = g_pool.lower_bound({d, want});
-    if (it != g_pool.end() && it->first.first == d && it->first.second <= want + want / 8) {
-      void* p = it->second;
-      *bytes = it->first.second;
-      g_pool_total -= it->first.second;
-      g_pool.erase(it);
-#ifdef RT_POOL_POISON
-      std::memset(p, 0xBE, *bytes);   // a reused block reads as garbage, like a fresh one
-#endif
-      return p;
+    auto best = g_pool.end();
+    for (auto it = g_pool.lower_bound({d, want});
+         it != g_pool.end() && it->first.first == d && it->first.second <= want + want / 8; ++it) {
+      const Cached& c = it->second;
+      const bool ready = c.idle || (rs.stream_scopes > 0 && c.stream == rs.stream);
+      if (ready) {
+        best = it;
+        break;
+      }
+      if (best == g_pool.end()) best = it;   // usable after waiting for the device
+    }
+    if (best != g_pool.end()) {
+      const Cached& c = best->second;
+      wait = !(c.idle || (rs.stream_scopes > 0 && c.stream == rs.stream));
+      p = c.p;
+      *bytes = best->first.second;
+      g_pool_total -= best->first.second;
+      g_pool.erase(best);
     }
   }
-  void* p = nullptr;
+  if (p) {
+    if (wait) (void)hipDeviceSynchronize();   // another stream may still use it
+#ifdef RT_POOL_POISON
+    std::memset(p, 0xBE, *bytes);   // a reused block reads as garbage, like a fresh one
+#endif
+    return p;
+  }
   if (hipMalloc(&p, want) == hipSuccess) {
     *bytes = want;
     return p;
@@ -70,17 +97,17 @@ void* pool_get(size_t* bytes, int* device) {
   return nullptr;
 }
 
-void pool_put(void* p, size_t bytes, int device) {
+void pool_put(void* p, size_t bytes, int device, bool idle, hipStream_t stream) {
   if (!p) return;
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     if (g_pool_total + bytes <= kPoolCapBytes) {
-      g_pool.insert({{device, bytes}, p});
+      g_pool.insert({{device, bytes}, Cached{p, idle, stream}});
       g_pool_total += bytes;
       return;
     }
   }
-  (void)hipFree(p);
+  (void)hipFree(p);   // synchronises with the device before freeing
 }
 
 void pool_trim(int device) {
@@ -89,7 +116,7 @@ void pool_trim(int device) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto it = g_pool.begin(); it != g_pool.end();) {
       if (device < 0 || it->first.first == device) {
-        out.push_back(it->second);
+        out.push_back(it->second.p);
         g_pool_total -= it->first.second;
         it = g_pool.erase(it);
       } else {

@@ -46,22 +46,61 @@ void clear_error();
 #define RT_LAUNCH_CHECK() RT_CHECK_HIP(hipGetLastError())
 
 // Device memory cache behind every buffer of the library.  A released block
-// is kept for reuse instead of being freed (the device is synchronised first,
-// so no queued work still uses it); a request takes a cached block of the
-// current device whose size is at least the request and at most about an
+// is kept for reuse instead of being freed; a request takes a cached block of
+// the current device whose size is at least the request and at most about an
 // eighth above it, else allocates.  When an allocation fails, the device's
 // cached blocks are freed and the allocation is tried once more; blocks
 // beyond kPoolCapBytes of cache are freed at once.  Repeated set-up of
 // same-sized problems (a neighbour build and an assembly per time step) then
 // makes no hipMalloc / hipFree calls, which map and unmap pages and stall
 // the host for milliseconds at gigabyte sizes.
+//
+// Reuse is stream-ordered.  Inside a library call (a StreamScope for the
+// context's stream) a released block is tagged with that stream and handed
+// back without waiting: work queued later on the same stream runs after the
+// work that used it.  A block taken by another stream first waits for the
+// device.  Outside any scope, release waits for the device; an IdleScope
+// waits once for a whole group of releases (freeing a handle).
 constexpr size_t kPoolCapBytes = (size_t)96 << 30;
 // *bytes: requested size in, size of the returned block out; *device: the
 // device it belongs to.  NULL when the device is out of memory.
 void* pool_get(size_t* bytes, int* device);
-void pool_put(void* p, size_t bytes, int device);
+// idle: no queued work uses the block; else it was used on `stream` only
+void pool_put(void* p, size_t bytes, int device, bool idle, hipStream_t stream);
 void pool_trim(int device);   // free the cached blocks of a device (-1: all)
 size_t pool_cached_bytes(int device);
+
+// Release context of the calling thread (see above).
+struct ReleaseState {
+  int stream_scopes = 0;      // > 0 inside a library call
+  hipStream_t stream = nullptr;
+  int idle_scopes = 0;        // > 0 while the device is known to be idle
+};
+ReleaseState& release_state();
+struct StreamScope {
+  ReleaseState& st;
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : st(release_state()), prev(st.stream) {
+    ++st.stream_scopes;
+    st.stream = s;
+  }
+  ~StreamScope() {
+    st.stream = prev;
+    --st.stream_scopes;
+  }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+struct IdleScope {
+  ReleaseState& st;
+  IdleScope() : st(release_state()) {
+    (void)hipDeviceSynchronize();
+    ++st.idle_scopes;
+  }
+  ~IdleScope() { --st.idle_scopes; }
+  IdleScope(const IdleScope&) = delete;
+  IdleScope& operator=(const IdleScope&) = delete;
+};
 
 // Owning device buffer.  Not copyable; grows on demand.
 template <typename T>
@@ -90,12 +129,19 @@ struct DevBuf {
     return *this;
   }
   ~DevBuf() { release(); }
-  // Frees happen only in set-up paths; wait for queued work that may still
-  // read the buffer before returning it to the cache.
+  // Frees happen only in set-up paths.  The block goes back to the cache,
+  // stream-ordered inside a library call, else once queued work is done.
   void release() {
     if (p) {
-      (void)hipDeviceSynchronize();
-      pool_put(p, cap, dev);
+      ReleaseState& rs = release_state();
+      if (rs.idle_scopes > 0) {
+        pool_put(p, cap, dev, true, nullptr);
+      } else if (rs.stream_scopes > 0) {
+        pool_put(p, cap, dev, false, rs.stream);
+      } else {
+        (void)hipDeviceSynchronize();
+        pool_put(p, cap, dev, true, nullptr);
+      }
     }
     p = nullptr;
     n = cap = 0;

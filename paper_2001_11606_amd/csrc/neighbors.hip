@@ -798,6 +798,7 @@ int rt_build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   rt_neighbors* nb = new rt_neighbors();
   int s = rt::build_neighbors(ctx, dim, n_total, n_interior, pos, h, kernel, nb);
   if (s < 0) {
@@ -859,6 +860,10 @@ int rt_neighbors_export(rt_ctx* ctx, const rt_neighbors* nb, int64_t* nbr_ptr, i
   return RT_OK;
 }
 
-void rt_neighbors_free(rt_neighbors* nb) { delete nb; }
+void rt_neighbors_free(rt_neighbors* nb) {
+  if (!nb) return;
+  rt::IdleScope idle;   // one wait for the device, then every buffer goes back to the cache
+  delete nb;
+}
 
 }  // extern "C"

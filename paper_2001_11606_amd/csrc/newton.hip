@@ -183,6 +183,7 @@ extern "C" int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const doubl
   const int64_t n = A->n;
   if (n == 0) return RT_OK;
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   hipStream_t st = ctx->stream;
   const int g = grid_for(n, kBlock, kMaxPartials);
   DevBuf<double> part;
@@ -227,6 +228,7 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   auto t0 = std::chrono::steady_clock::now();
   rt_newton_stats local{};
   rt_newton_stats* stt = stats ? stats : &local;
@@ -314,6 +316,7 @@ extern "C" int rt_to_sorted(rt_ctx* ctx, const rt_neighbors* nb, const double* u
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   if (nb->n_interior > 0) RT_CHECK(gather_sorted(ctx, nb, nb->n_interior, user, sorted));
   return RT_OK;
 }
@@ -327,6 +330,7 @@ extern "C" int rt_to_user(rt_ctx* ctx, const rt_neighbors* nb, const double* sor
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   if (nb->n_interior > 0) RT_CHECK(scatter_user(ctx, nb, nb->n_interior, sorted, user));
   return RT_OK;
 }

@@ -608,6 +608,7 @@ extern "C" int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
   }
   RT_CHECK(check_solve_opts(opts));
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   auto t0 = std::chrono::steady_clock::now();
   rt_solve_stats local{};
   rt_solve_stats* stt = stats ? stats : &local;

@@ -68,6 +68,7 @@ int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep) {
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   rt_tune_report local{};
   rt_tune_report* r = rep ? rep : &local;
   std::memset(r, 0, sizeof(*r));
