@@ -219,6 +219,11 @@ def pytest_approx(v, rel=1e-12):
     return _A()
 
 
+def _levermore(prob):
+    prob.limiter = synth.LIMITER_LEVERMORE
+    return prob
+
+
 def main():
     rt.load(os.environ["RT_CPU_LIB"])
     ctx = rt.rt_create(0, 0)
@@ -226,6 +231,7 @@ def main():
         "mms2d_16": synth.config1(n=16),
         "mms3d_6": synth.config2_mms(n=6),
         "densitystep3d_8": synth.config3(n=8),
+        "levermore3d_8": _levermore(synth.config3(n=8)),
         "marshak3d_8": synth.config4(n=8),
         "ensemble2d": synth.config5_member(0, 400.0),
         "infinite3d_5": synth.config2_infinite(1.0, 0.01, n=5),

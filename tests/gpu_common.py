@@ -13,6 +13,13 @@ def say(*a):
     sys.stdout.flush()
 
 
+def _levermore(prob):
+    """The density-step problem with the Levermore limiter of Sec. 2.1 in
+    place of Larsen's."""
+    prob.limiter = synth.LIMITER_LEVERMORE
+    return prob
+
+
 def small_cases():
     """Seeded problems of every workload family, sized so the oracle finishes in
     seconds while still spanning many rows per block and ragged tails."""
@@ -20,6 +27,7 @@ def small_cases():
         "mms2d_64": lambda: synth.config1(n=64),
         "mms3d_12": lambda: synth.config2_mms(n=12),
         "densitystep3d_16": lambda: synth.config3(n=16),
+        "densitystep3d_16_levermore": lambda: _levermore(synth.config3(n=16)),
         "marshak3d_16": lambda: synth.config4(n=16),
         "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
         "ensemble2d": lambda: synth.config5_member(0, 2500.0),
