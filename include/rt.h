@@ -305,6 +305,29 @@ int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
 int rt_to_sorted(rt_ctx* ctx, const rt_neighbors* nb, const double* user, double* sorted);
 int rt_to_user(rt_ctx* ctx, const rt_neighbors* nb, const double* sorted, double* user);
 
+/* ---- GMRES on the unscaled operator (Sec. 3.2, the paper's solver) ---------
+ * rt_solve_gmres solves the same system as rt_solve in the paper's own,
+ * unscaled form U x = c, U = diag(V)^-1 A, c = diag(V)^-1 b (A, b the
+ * V-scaled operator and right-hand side of rt_solve; same solution x), with
+ * restarted right-preconditioned GMRES(restart) in FP64.  precond: 0 Jacobi
+ * (diag(U)^-1), 1 the matrix's AMG V-cycle applied to V v (Jacobi when the
+ * matrix has one level).  Stops when ||c - U x||_2 <= tol ||c||_2 (the final
+ * value recomputed from a product, in stats->rel_residual) or after max_iter
+ * inner iterations (RT_NOT_CONVERGED, x then holds the last iterate).
+ * b, x: n_interior doubles, user order, device; x is the initial guess on
+ * entry.  The method keeps restart + 1 basis vectors of n doubles.  Errors:
+ * RT_E_ARG (precond not 0/1, tol < 0, max_iter < 0, restart outside 1..64,
+ * non-finite b), RT_E_DEVICE (non-finite residual).                         */
+typedef struct {
+  int precond;
+  double tol;
+  int max_iter;
+  int restart;
+} rt_gmres_opts;
+
+int rt_solve_gmres(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
+                   const rt_gmres_opts* opts, rt_solve_stats* stats);
+
 /* ---- time-step control (Sec. 3.3) -----------------------------------------
  * The fractional changes of the material and radiation energies over a step,
  *   eta_e = max_i |e_i^n - e_i^{n-1}| / (e_i^n + eta_target Ebar^n + tiny),

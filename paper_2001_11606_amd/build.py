@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librt.so")
 
-SOURCES = ["context.hip", "prim.hip", "neighbors.hip", "assemble.hip", "amg.hip", "solve.hip", "newton.hip", "tune.hip", "tile.hip", "batch.hip"]
+SOURCES = ["context.hip", "prim.hip", "neighbors.hip", "assemble.hip", "amg.hip", "solve.hip", "newton.hip", "tune.hip", "tile.hip", "batch.hip", "gmres.hip"]
 
 ARCH = os.environ.get("RT_OFFLOAD_ARCH", "gfx950")
 

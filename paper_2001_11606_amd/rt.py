@@ -69,6 +69,10 @@ class rt_solve_opts(ctypes.Structure):
                 ("inner_tol", c_dbl), ("max_refine", c_int)]
 
 
+class rt_gmres_opts(ctypes.Structure):
+    _fields_ = [("precond", c_int), ("tol", c_dbl), ("max_iter", c_int), ("restart", c_int)]
+
+
 class rt_solve_stats(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("refinements", c_int), ("rel_residual", c_dbl),
                 ("seconds", c_dbl), ("spmv_calls", c_int), ("spmv_seconds", c_dbl),
@@ -137,6 +141,8 @@ _SIGS = {
                                      c_int, ctypes.POINTER(rt_newton_stats)]),
     "rt_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
                          ctypes.POINTER(rt_solve_stats)]),
+    "rt_solve_gmres": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_gmres_opts),
+                               ctypes.POINTER(rt_solve_stats)]),
     "rt_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
                                ctypes.POINTER(rt_newton_stats)]),
 }
@@ -347,6 +353,17 @@ def rt_solve(ctx: int, A: int, b: int, x: int, opts: rt_solve_opts) -> tuple:
     return s, st
 
 
+def rt_solve_gmres(ctx: int, A: int, b: int, x: int, opts: rt_gmres_opts) -> tuple:
+    st = rt_solve_stats()
+    s = _check("rt_solve_gmres", load().rt_solve_gmres(ctx, A, b, x, ctypes.byref(opts),
+                                                       ctypes.byref(st)))
+    return s, st
+
+
+def gmres_opts(precond=PRECOND_JACOBI, tol=1e-10, max_iter=1000, restart=30) -> rt_gmres_opts:
+    return rt_gmres_opts(precond, tol, max_iter, restart)
+
+
 def rt_newton_step(ctx: int, A: int, e: int, E: int, ell: int, opts: rt_newton_opts) -> tuple:
     st = rt_newton_stats()
     s = _check("rt_newton_step", load().rt_newton_step(ctx, A, e, E, ell, ctypes.byref(opts),
@@ -481,6 +498,11 @@ class Context:
     def solve(self, A: int, b, x, opts: rt_solve_opts):
         torch = self.torch
         return rt_solve(self.handle, A, _ptr(b, torch.float64), _ptr(x, torch.float64), opts)
+
+    def solve_gmres(self, A: int, b, x, opts: rt_gmres_opts):
+        torch = self.torch
+        return rt_solve_gmres(self.handle, A, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                              opts)
 
     def newton_step(self, A: int, e, E, ell: int, opts: rt_newton_opts):
         torch = self.torch

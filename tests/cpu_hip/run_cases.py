@@ -93,6 +93,13 @@ def check_case(ctx, name, prob):
         s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50))
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: solve prec={prec} precond={precond} err={e} its={st.iterations}"
+    # GMRES on the unscaled operator, Jacobi and AMG, with and without restarts
+    for precond, restart in (((1, 4),) if QUICK else ((0, 30), (1, 30), (1, 4))):
+        x = np.zeros(nin)
+        s, st = rt.rt_solve_gmres(ctx, c.A, p(b), p(x), rt.gmres_opts(precond, 1e-13, 3000, restart))
+        e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+        assert s == 0 and e <= 1e-10 and st.rel_residual <= 1e-13, \
+            f"{name}: gmres precond={precond} restart={restart} err={e} its={st.iterations}"
     # every SpMV shape (forced on all levels), then the autotuner's choice
     nshapes = len(rt.rt_spmv_shapes())
     sweep = range(nshapes) if name in ("marshak3d_8", "mms2d_16") else (0, 7, nshapes - 1)

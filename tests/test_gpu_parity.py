@@ -215,3 +215,45 @@ def test_newton_residual_carry(ctx, precision):
     bar = 1e-12 if precision == 0 else 1e-10
     assert np.max(np.abs(E3 - E4) / np.abs(E4)) <= bar
     assert np.max(np.abs(e3 - e4) / np.abs(e4)) <= bar
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "densitystep3d_16", "marshak3d_16"])
+@pytest.mark.parametrize("precond,restart", [(0, 30), (1, 30), (1, 5)])
+def test_gmres_unscaled_matches_oracle(ctx, systems, name, precond, restart):
+    """GMRES on the paper's unscaled operator reaches the oracle's solution of
+    the same system (the V-scaling does not change x), restarts included."""
+    import torch
+    from paper_2001_11606_amd import rt
+    prob, (ptr, idx, fz, sysm) = _get(systems, name)
+    say(f"[gmres] {name} precond={precond} restart={restart}")
+    nin = prob.n_interior
+    b = np.random.default_rng(29).standard_normal(nin) * sysm.A.diagonal()
+    x_ref = linsolve.dense(sysm.A, b) if nin <= 5000 else linsolve.pcg_jacobi(sysm.A, b, tol=1e-15)[0]
+    dp, nb, A = gpu_system(ctx, prob)
+    bt = torch.tensor(b, device=ctx.device)
+    xt = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
+    s, st = ctx.solve_gmres(A, bt, xt, rt.gmres_opts(precond, 1e-13, 5000, restart))
+    assert s == rt.RT_OK, rt.rt_last_error()
+    x = xt.cpu().numpy()
+    assert np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref)) <= 1e-10
+    # the reported residual is that of the unscaled system, recomputed here
+    V = fz.V[:nin]
+    ru = (b - sysm.A @ x) / V
+    assert np.linalg.norm(ru) / np.linalg.norm(b / V) <= 1.05e-13
+    assert st.rel_residual <= 1e-13 and st.iterations > 0
+
+
+def test_gmres_not_converged_and_errors(ctx, systems):
+    import torch
+    from paper_2001_11606_amd import rt
+    prob, (ptr, idx, fz, sysm) = _get(systems, "mms2d_64")
+    nin = prob.n_interior
+    dp, nb, A = gpu_system(ctx, prob)
+    bt = torch.ones(nin, dtype=torch.float64, device=ctx.device)
+    xt = torch.zeros_like(bt)
+    s, st = ctx.solve_gmres(A, bt, xt, rt.gmres_opts(0, 1e-14, 3, 30))
+    assert s == rt.RT_NOT_CONVERGED and st.iterations == 3 and st.rel_residual > 1e-14
+    for bad in (rt.gmres_opts(2, 1e-10, 10, 30), rt.gmres_opts(0, -1.0, 10, 30),
+                rt.gmres_opts(0, 1e-10, 10, 0), rt.gmres_opts(0, 1e-10, 10, 65)):
+        with pytest.raises(rt.RtError):
+            ctx.solve_gmres(A, bt, xt, bad)
