@@ -144,3 +144,58 @@ def test_rebuild_from_cached_memory(ctx):
         assert rt.rt_cached_bytes(ctx.handle) > 0
     freed = rt.rt_release_cached(ctx.handle)
     assert freed > 0 and rt.rt_cached_bytes(ctx.handle) == 0
+
+
+def test_concurrent_contexts_on_their_own_streams():
+    """Problems built from several host threads, each with its own context on
+    its own stream, share the library's cache of device blocks (reuse across
+    streams waits for the device): every matrix must equal the one built
+    alone, bit for bit, over several rounds of builds and frees."""
+    import threading
+    import torch
+    from paper_2001_11606_amd import driver, rt
+    say("[edges] concurrent contexts")
+    probs = [synth.config5_member(q, s) for q, s in enumerate((900.0, 3000.0, 400.0, 2000.0,
+                                                                1500.0, 700.0))]
+    main = rt.Context(0)
+    dps = [driver.upload(pr, main.device) for pr in probs]
+    torch.cuda.synchronize()
+    ref = []
+    for dp in dps:
+        nb = main.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+        A = main.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                          dp.limiter_k, amg=rt.amg_opts(max_levels=1))
+        ref.append([t.cpu().numpy() for t in main.export_matrix(A)])
+    main.close()
+    ctxs = []
+    for _ in range(3):
+        with torch.cuda.stream(torch.cuda.Stream()):
+            ctxs.append(rt.Context(0))
+    errors = []
+
+    def work(w):
+        try:
+            c = ctxs[w]
+            for rnd in range(3):
+                for q in range(w, len(dps), len(ctxs)):
+                    dp = dps[q]
+                    nb = c.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+                    A = c.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent,
+                                   dp.limiter, dp.limiter_k, amg=rt.amg_opts(max_levels=1))
+                    got = [t.cpu().numpy() for t in c.export_matrix(A)]
+                    if not all(np.array_equal(a, b) for a, b in zip(got, ref[q])):
+                        errors.append((w, rnd, q))
+                    rt.rt_matrix_free(A)
+                    rt.rt_neighbors_free(nb.handle)
+                    c._owned.clear()
+        except Exception as exc:   # reported below, on the test's thread
+            errors.append(repr(exc))
+
+    threads = [threading.Thread(target=work, args=(w,)) for w in range(len(ctxs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for c in ctxs:
+        c.close()
+    assert not errors, errors
