@@ -16,7 +16,7 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import synth  # noqa: E402
 from oracle import linsolve, neighbors, step as ostep  # noqa: E402
-from gpu_common import oracle_system, rowwise_rel_err  # noqa: E402
+from gpu_common import _wendland, oracle_system, rowwise_rel_err  # noqa: E402
 from paper_2001_11606_amd import rt  # noqa: E402
 
 FIELDS = ("m", "rho", "cv", "sigma0_a", "sigma_s", "e", "E", "Q_e", "Q_E")
@@ -239,6 +239,8 @@ def main():
         "mms3d_6": synth.config2_mms(n=6),
         "densitystep3d_8": synth.config3(n=8),
         "levermore3d_8": _levermore(synth.config3(n=8)),
+        "wendland2d_12": _wendland(2, 12),
+        "wendland3d_6": _wendland(3, 6),
         "marshak3d_8": synth.config4(n=8),
         "ensemble2d": synth.config5_member(0, 400.0),
         "infinite3d_5": synth.config2_infinite(1.0, 0.01, n=5),

@@ -20,6 +20,22 @@ def _levermore(prob):
     return prob
 
 
+def _wendland(dim, n):
+    """A jittered lattice with the paper's Wendland kernel at h = 4 spacings
+    (Sec. 2.3 and Sec. 3.1: about 50 neighbours in 2-D, 250 in 3-D), a
+    Dirichlet ghost layer, a smooth temperature field and sigma ~ T^-3."""
+    rng = np.random.default_rng(11606700 + dim)
+    pos, nin = synth.jittered_lattice(dim, n, 0.1, 2, rng)
+    N = pos.shape[1]
+    dx = 1.0 / n
+    T = 1.0 + 0.2 * np.prod(np.sin(np.pi * np.clip(pos, 0.0, 1.0)), axis=0)
+    return synth.Problem(name=f"wendland{dim}d_{n}", dim=dim, pos=pos, h=np.full(N, 4.0 * dx),
+                         n_interior=nin, m=np.full(N, dx ** dim), rho=np.ones(N), cv=np.ones(N),
+                         sigma0_a=np.full(N, 10.0), sigma_s=np.zeros(N), opacity_exponent=-3.0,
+                         e=T.copy(), E=(0.9 * T) ** 4, Q_e=np.zeros(N), Q_E=np.zeros(N), dt=1e-3,
+                         kernel=synth.KERNEL_WENDLAND_C4)
+
+
 def small_cases():
     """Seeded problems of every workload family, sized so the oracle finishes in
     seconds while still spanning many rows per block and ragged tails."""
@@ -28,6 +44,8 @@ def small_cases():
         "mms3d_12": lambda: synth.config2_mms(n=12),
         "densitystep3d_16": lambda: synth.config3(n=16),
         "densitystep3d_16_levermore": lambda: _levermore(synth.config3(n=16)),
+        "wendland2d_24": lambda: _wendland(2, 24),
+        "wendland3d_9": lambda: _wendland(3, 9),
         "marshak3d_16": lambda: synth.config4(n=16),
         "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
         "ensemble2d": lambda: synth.config5_member(0, 2500.0),
