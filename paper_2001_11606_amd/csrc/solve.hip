@@ -45,13 +45,26 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
            double* __restrict__ s, int32_t* __restrict__ stop, double thr2) {
   __shared__ double red[kBlock / kWave];
   if ((op == FIN_ALPHA || op == FIN_BETA) && *stop) return;
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
-    a += pa[i];
-    if (pb) b += pb[i];
+  // four independent running sums per thread keep four loads in flight; they
+  // are combined in a fixed order, so the result is the same on every run
+  double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 3 * kBlock < np; i += 4 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a4[u] += pa[i + u * kBlock];
+    if (pb) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) b4[u] += pb[i + u * kBlock];
+    }
   }
+  for (int u = 0; i < np; i += kBlock, ++u) {
+    a4[u] += pa[i];
+    if (pb) b4[u] += pb[i];
+  }
+  double a = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  double b = (b4[0] + b4[1]) + (b4[2] + b4[3]);
   a = block_sum(a, red);
-  b = block_sum(b, red);
+  if (pb) b = block_sum(b, red);
   if (threadIdx.x != 0) return;
   switch (op) {
     case FIN_ALPHA:
