@@ -41,6 +41,8 @@ def make_problem(workload: str, n: int):
         return synth.config4(n=n)
     if workload == "densitystep3d":
         return synth.config3(n=n)
+    if workload == "wendland3d":
+        return synth.wendland_lattice(3, n)
     raise SystemExit(f"unknown workload {workload}")
 
 

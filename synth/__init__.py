@@ -377,6 +377,24 @@ def config3(n: int = 128, seed: Optional[int] = None) -> Problem:
                    meta=dict(config=3, n=n, spacing=dx))
 
 
+def wendland_lattice(dim: int, n: int, seed: Optional[int] = None) -> Problem:
+    """The paper's own kernel regime (Sec. 2.3, Sec. 3.1): a jittered n^dim
+    lattice (+-0.1 spacing) with two ghost layers, the Wendland kernel at
+    h = 4 spacings (support h: about 50 neighbours in 2-D, 250 in 3-D),
+    m = spacing^dim, rho = c_v = 1, T = 1 + 0.2 prod sin(pi x_a), E = (0.9 T)^4,
+    sigma_a = 10 T^-3, dt = 1e-3."""
+    rng = np.random.default_rng(SEED_BASE + 700 + dim if seed is None else seed)
+    pos, nin = jittered_lattice(dim, n, 0.1, 2, rng)
+    N = pos.shape[1]
+    dx = 1.0 / n
+    T = 1.0 + 0.2 * np.prod(np.sin(np.pi * np.clip(pos, 0.0, 1.0)), axis=0)
+    return Problem(name=f"wendland{dim}d", dim=dim, pos=pos, h=_filled(N, 4.0 * dx),
+                   n_interior=nin, m=_filled(N, dx ** dim), rho=_filled(N, 1.0),
+                   cv=_filled(N, 1.0), sigma0_a=_filled(N, 10.0), sigma_s=np.zeros(N),
+                   opacity_exponent=-3.0, e=T.copy(), E=(0.9 * T) ** 4, Q_e=np.zeros(N),
+                   Q_E=np.zeros(N), dt=1e-3, kernel=KERNEL_WENDLAND_C4)
+
+
 def config4(n: int = 256, seed: Optional[int] = None) -> Problem:
     """3D Marshak-like front on a non-lattice point set: n^3 points by greedy
     dart throwing on a jittered ceil(1.1 n)^3 candidate grid, V = 1/n^3,

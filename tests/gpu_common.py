@@ -21,19 +21,8 @@ def _levermore(prob):
 
 
 def _wendland(dim, n):
-    """A jittered lattice with the paper's Wendland kernel at h = 4 spacings
-    (Sec. 2.3 and Sec. 3.1: about 50 neighbours in 2-D, 250 in 3-D), a
-    Dirichlet ghost layer, a smooth temperature field and sigma ~ T^-3."""
-    rng = np.random.default_rng(11606700 + dim)
-    pos, nin = synth.jittered_lattice(dim, n, 0.1, 2, rng)
-    N = pos.shape[1]
-    dx = 1.0 / n
-    T = 1.0 + 0.2 * np.prod(np.sin(np.pi * np.clip(pos, 0.0, 1.0)), axis=0)
-    return synth.Problem(name=f"wendland{dim}d_{n}", dim=dim, pos=pos, h=np.full(N, 4.0 * dx),
-                         n_interior=nin, m=np.full(N, dx ** dim), rho=np.ones(N), cv=np.ones(N),
-                         sigma0_a=np.full(N, 10.0), sigma_s=np.zeros(N), opacity_exponent=-3.0,
-                         e=T.copy(), E=(0.9 * T) ** 4, Q_e=np.zeros(N), Q_E=np.zeros(N), dt=1e-3,
-                         kernel=synth.KERNEL_WENDLAND_C4)
+    """The paper's Wendland kernel at h = 4 spacings (synth.wendland_lattice)."""
+    return synth.wendland_lattice(dim, n)
 
 
 def small_cases():
