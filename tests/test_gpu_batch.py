@@ -146,3 +146,49 @@ def test_batch_tune_and_errors(ctx, ensemble):
                           rt.solve_opts(0, 0, 1e-10, 100), -1)
     with pytest.raises(rt.RtError):
         rt.rt_batch_create(ctx.handle, [])
+
+
+def test_full_ensemble_sampled_against_oracle(ctx):
+    """The full 96-problem ensemble of the bench (11.8M particles, one batch,
+    graph-replayed PCG): the batched Newton step's e and E of the smallest
+    problems match the oracle's step to the mixed bar, and every problem's
+    reported FP64 residual meets the tolerance."""
+    import torch
+    from paper_2001_11606_amd import driver, rt
+    probs = synth.config5(96)
+    say(f"[full ensemble] {sum(p.n_interior for p in probs)} particles")
+    amg = rt.amg_opts(max_levels=1, build_fp32=1)
+    handles = []
+    for pr in probs:
+        dp = driver.upload(pr, ctx.device)
+        nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+        A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=amg)
+        handles.append((nb, A))
+    B = rt.rt_batch_create(ctx.handle, [A for _, A in handles])
+    try:
+        offs = _offsets(probs)
+        e = torch.tensor(np.concatenate([pr.e[:pr.n_interior] for pr in probs]), device=ctx.device)
+        E = torch.tensor(np.concatenate([pr.E[:pr.n_interior] for pr in probs]), device=ctx.device)
+        tol = 1e-12
+        nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, 0, tol, 5000, 1e-4, 50))
+        s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), 0,
+                                        nopts, 8)
+        assert s == rt.RT_OK, rt.rt_last_error()
+        assert all(st[q].solve.rel_residual <= tol for q in range(len(probs)))
+        eh, Eh = e.cpu().numpy(), E.cpu().numpy()
+        smallest = sorted(range(len(probs)), key=lambda q: probs[q].n_interior)[:3]
+        for q in smallest:
+            ref = ostep.time_step(probs[q].copy(), fixed_outer=1, inner_tol_e=1e-14,
+                                  solve_tol=1e-15)
+            err_e = np.max(np.abs(eh[offs[q]:offs[q + 1]] - ref.e) / np.abs(ref.e))
+            err_E = np.max(np.abs(Eh[offs[q]:offs[q + 1]] - ref.E) / np.abs(ref.E))
+            say(f"[full ensemble] problem {q} ({probs[q].n_interior} particles): "
+                f"e {err_e:.1e} E {err_E:.1e}")
+            assert err_e <= 1e-10 and err_E <= 1e-10, (q, err_e, err_E)
+    finally:
+        rt.rt_batch_free(B)
+        for nb, A in handles:
+            rt.rt_matrix_free(A)
+            rt.rt_neighbors_free(nb.handle)
+        ctx._owned.clear()
