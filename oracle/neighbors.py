@@ -21,18 +21,30 @@ import itertools
 import numpy as np
 
 
-def pair_r2(pos: np.ndarray, i, j):
+def disp(pos: np.ndarray, ax: int, i, j, period=None):
+    """x_i - x_j along axis ax; on a periodic axis of length L (period[ax] > 0)
+    the nearest image: one period is subtracted above L/2 and added below
+    -L/2 (positions lie in [0, L), so one correction suffices)."""
+    d = pos[ax][i] - pos[ax][j]
+    if period is not None and period[ax] > 0.0:
+        L = float(period[ax])
+        half = 0.5 * L
+        d = np.where(d > half, d - L, np.where(d < -half, d + L, d))
+    return d
+
+
+def pair_r2(pos: np.ndarray, i, j, period=None):
     """Squared distance accumulated in axis order, no fused operations."""
     d2 = np.zeros(np.broadcast(np.asarray(i), np.asarray(j)).shape)
     for ax in range(pos.shape[0]):
-        d = pos[ax][i] - pos[ax][j]
+        d = disp(pos, ax, i, j, period)
         d2 = d2 + d * d
     return d2
 
 
-def pair_mask(pos, h, i, j, kappa: float):
+def pair_mask(pos, h, i, j, kappa: float, period=None):
     t = kappa * np.maximum(h[i], h[j])
-    return (np.asarray(i) != np.asarray(j)) & (pair_r2(pos, i, j) < t * t)
+    return (np.asarray(i) != np.asarray(j)) & (pair_r2(pos, i, j, period) < t * t)
 
 
 def _to_csr(n: int, pi: np.ndarray, pj: np.ndarray):
@@ -45,8 +57,9 @@ def _to_csr(n: int, pi: np.ndarray, pj: np.ndarray):
     return ptr, pj.astype(np.int32)
 
 
-def brute_force(pos: np.ndarray, h: np.ndarray, kappa: float, chunk: int = 512):
-    """All pairs by testing every (i, j): O(N^2), for small inputs."""
+def brute_force(pos: np.ndarray, h: np.ndarray, kappa: float, chunk: int = 512, period=None):
+    """All pairs by testing every (i, j): O(N^2), for small inputs (nearest
+    images on the periodic axes of ``period``)."""
     n = h.shape[0]
     PI, PJ = [], []
     allj = np.arange(n)
@@ -55,17 +68,18 @@ def brute_force(pos: np.ndarray, h: np.ndarray, kappa: float, chunk: int = 512):
         I, J = np.meshgrid(ii, allj, indexing="ij")
         I = I.reshape(-1)
         J = J.reshape(-1)
-        m = pair_mask(pos, h, I, J, kappa)
+        m = pair_mask(pos, h, I, J, kappa, period)
         PI.append(I[m])
         PJ.append(J[m])
     return _to_csr(n, np.concatenate(PI), np.concatenate(PJ))
 
 
-def neighbors_of(pos: np.ndarray, h: np.ndarray, i: int, kappa: float) -> np.ndarray:
+def neighbors_of(pos: np.ndarray, h: np.ndarray, i: int, kappa: float,
+                 period=None) -> np.ndarray:
     """Ascending neighbour list of one particle by testing it against all others."""
     n = h.shape[0]
     J = np.arange(n)
-    return J[pair_mask(pos, h, np.full(n, i), J, kappa)].astype(np.int32)
+    return J[pair_mask(pos, h, np.full(n, i), J, kappa, period)].astype(np.int32)
 
 
 def cell_list(pos: np.ndarray, h: np.ndarray, kappa: float, chunk: int = 1 << 18):
@@ -105,10 +119,11 @@ def cell_list(pos: np.ndarray, h: np.ndarray, kappa: float, chunk: int = 1 << 18
     return _to_csr(n, np.concatenate(PI), np.concatenate(PJ))
 
 
-def build(pos: np.ndarray, h: np.ndarray, kappa: float):
-    """Neighbour CSR: brute force for small inputs, cell list otherwise."""
-    if h.shape[0] <= 6000:
-        return brute_force(pos, h, kappa)
+def build(pos: np.ndarray, h: np.ndarray, kappa: float, period=None):
+    """Neighbour CSR: brute force for small inputs, cell list otherwise;
+    periodic inputs (test-sized) always by brute force."""
+    if h.shape[0] <= 6000 or (period is not None and np.any(np.asarray(period) > 0.0)):
+        return brute_force(pos, h, kappa, period=period)
     return cell_list(pos, h, kappa)
 
 

@@ -40,7 +40,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import kernels
-from .neighbors import pairs, pair_r2
+from .neighbors import disp, pairs, pair_r2
 
 LIMITER_NONE = 0
 LIMITER_LARSEN = 1
@@ -61,7 +61,7 @@ class Frozen:
 def pair_geometry(prob, ptr, idx):
     """(i, j, r, F_ij) for every neighbour pair."""
     I, J = pairs(ptr, idx)
-    r = np.sqrt(pair_r2(prob.pos, I, J))
+    r = np.sqrt(pair_r2(prob.pos, I, J, prob.period))
     dwi = kernels.dWdr(r, prob.h[I], prob.dim, prob.kernel)
     dwj = kernels.dWdr(r, prob.h[J], prob.dim, prob.kernel)
     F = -0.5 * (dwi + dwj) / r
@@ -76,7 +76,7 @@ def grad_E(prob, ptr, idx, E):
     g = np.zeros((prob.dim, prob.n_total))
     w = V[J] * (E[J] - E[I]) * (-F)
     for ax in range(prob.dim):
-        xij = prob.pos[ax][I] - prob.pos[ax][J]
+        xij = disp(prob.pos, ax, I, J, prob.period)
         g[ax] = np.bincount(I, weights=w * xij, minlength=prob.n_total)
     return g
 
@@ -179,12 +179,12 @@ def frozen_at(prob, ids, nbrs_of) -> dict:
         if prob.limiter != LIMITER_NONE and i < prob.n_interior:
             J = nbrs_of(i).astype(np.int64)
             I = np.full(J.shape, i)
-            r = np.sqrt(pair_r2(prob.pos, I, J))
+            r = np.sqrt(pair_r2(prob.pos, I, J, prob.period))
             F = -0.5 * (kernels.dWdr(r, prob.h[I], prob.dim, prob.kernel) +
                         kernels.dWdr(r, prob.h[J], prob.dim, prob.kernel)) / r
             Vj = prob.m[J] / prob.rho[J]
             w = Vj * (prob.E[J] - prob.E[i]) * (-F)
-            g = np.array([np.sum(w * (prob.pos[ax][i] - prob.pos[ax][J]))
+            g = np.array([np.sum(w * disp(prob.pos, ax, I, J, prob.period))
                           for ax in range(prob.dim)])
             R = np.sqrt(np.sum(g * g)) / (sigma_t * prob.E[i])
             lam = float(flux_limiter(np.array([R]), prob.limiter, prob.limiter_k)[0])
@@ -206,7 +206,7 @@ def rows_at(prob, rows, nbrs_of) -> dict:
         i = int(i)
         J = nbrs_of(i).astype(np.int64)
         I = np.full(J.shape, i)
-        r = np.sqrt(pair_r2(prob.pos, I, J))
+        r = np.sqrt(pair_r2(prob.pos, I, J, prob.period))
         F = -0.5 * (kernels.dWdr(r, prob.h[I], prob.dim, prob.kernel) +
                     kernels.dWdr(r, prob.h[J], prob.dim, prob.kernel)) / r
         sa_i, f_i, V_i, D_i = fz[i]

@@ -68,6 +68,9 @@ class Problem:
     # Optional manufactured solution: mms(t) -> (e_exact, E_exact, Q_e, Q_E)
     # evaluated at every particle position (sources are zeroed on ghosts).
     mms: Optional[Callable[[float], tuple]] = None
+    # Optional periodic box: period[a] > 0 makes axis a periodic with that
+    # length (positions in [0, period[a])); 0 leaves it open.
+    period: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -393,6 +396,26 @@ def wendland_lattice(dim: int, n: int, seed: Optional[int] = None) -> Problem:
                    cv=_filled(N, 1.0), sigma0_a=_filled(N, 10.0), sigma_s=np.zeros(N),
                    opacity_exponent=-3.0, e=T.copy(), E=(0.9 * T) ** 4, Q_e=np.zeros(N),
                    Q_E=np.zeros(N), dt=1e-3, kernel=KERNEL_WENDLAND_C4)
+
+
+def periodic_wendland(dim: int, n: int, seed: Optional[int] = None) -> Problem:
+    """The geometry of the paper's periodic manufactured problem (Sec. 4.3):
+    a jittered n^dim lattice (+-0.1 spacing) on the unit box, periodic on
+    every axis (jittered points wrapped back into [0, 1)), the Wendland kernel
+    at h = 4 spacings; m = spacing^dim, rho = c_v = 1,
+    T = 1 + 0.2 prod cos(2 pi x_a), E = (0.9 T)^4, sigma_a = 10 T^-3, dt = 1e-3."""
+    rng = np.random.default_rng(SEED_BASE + 800 + dim if seed is None else seed)
+    pos, nin = jittered_lattice(dim, n, 0.1, 0, rng)
+    pos = np.mod(pos, 1.0)
+    N = pos.shape[1]
+    dx = 1.0 / n
+    T = 1.0 + 0.2 * np.prod(np.cos(2.0 * np.pi * pos), axis=0)
+    return Problem(name=f"periodic{dim}d", dim=dim, pos=pos, h=_filled(N, 4.0 * dx),
+                   n_interior=nin, m=_filled(N, dx ** dim), rho=_filled(N, 1.0),
+                   cv=_filled(N, 1.0), sigma0_a=_filled(N, 10.0), sigma_s=np.zeros(N),
+                   opacity_exponent=-3.0, e=T.copy(), E=(0.9 * T) ** 4, Q_e=np.zeros(N),
+                   Q_E=np.zeros(N), dt=1e-3, kernel=KERNEL_WENDLAND_C4,
+                   period=np.ones(dim))
 
 
 def config4(n: int = 256, seed: Optional[int] = None) -> Problem:

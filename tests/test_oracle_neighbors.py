@@ -8,12 +8,14 @@
   and 56 in 3D at h = 1.2 spacing (|i|^2+|j|^2+|k|^2 <= 5), self excluded.
 * The relation is symmetric.
 """
+import itertools
+
 import numpy as np
 import pytest
 from scipy.spatial import cKDTree
 
 import synth
-from oracle import neighbors
+from oracle import kernels, neighbors
 
 
 def _kdtree_csr(pos, radius):
@@ -81,3 +83,35 @@ def test_symmetric_relation():
     fwd = set(zip(I.tolist(), J.tolist()))
     assert all((j, i) in fwd for i, j in fwd)
     assert not np.any(I == J)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 12), (3, 10)])
+def test_periodic_neighbours_equal_explicit_images(dim, n):
+    """Nearest-image pairs on a periodic box equal the pairs found by testing
+    every particle against every shifted copy of the others (3^dim images,
+    plain distances): with a box wider than twice the support, at most one
+    image of a particle is in range.  (The two round differently only for a
+    pair within rounding of the support edge; the jittered lattice has none.)"""
+    prob = synth.periodic_wendland(dim, n)
+    pos, h, L = prob.pos, prob.h, prob.period
+    kappa = kernels.KAPPA[prob.kernel]
+    assert np.all(2.0 * kappa * h.max() < L)
+    ptr, idx = neighbors.brute_force(pos, h, kappa, period=L)
+    N = h.shape[0]
+    pairs = set()
+    for shift in itertools.product((-1.0, 0.0, 1.0), repeat=dim):
+        img = pos + (np.array(shift) * L)[:, None]
+        both = np.concatenate([pos, img], axis=1)
+        hh = np.concatenate([h, h])
+        for i in range(N):
+            J = np.arange(N)
+            d2 = np.zeros(N)
+            for ax in range(dim):
+                d = both[ax][i] - both[ax][N + J]
+                d2 = d2 + d * d
+            t = kappa * np.maximum(hh[i], hh[N + J])
+            for j in J[(d2 < t * t) & (J != i)]:
+                pairs.add((i, int(j)))
+    got = {(i, int(j)) for i in range(N) for j in idx[ptr[i]:ptr[i + 1]]}
+    assert got == pairs
+    assert all((j, i) in got for i, j in got)   # the relation stays symmetric
