@@ -101,6 +101,21 @@ int rt_build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior
                        const double* pos, const double* h, int kernel,
                        rt_neighbors** out);
 
+/* Neighbour lists in a box with periodic axes (the periodic box of the
+ * manufactured problem of Sec. 4.3).  period: host array of dim lengths, or
+ * NULL (then this is rt_build_neighbors); period[a] > 0 makes axis a periodic
+ * with that length, 0 leaves it open.  On a periodic axis every position must
+ * lie in [0, period[a]) and the period must span at least three supports
+ * (3 * kappa * max h); each displacement component x_i - x_j is replaced by
+ * its nearest image (one period subtracted above period/2, added below
+ * -period/2) before it is squared, and the assembly that uses these lists
+ * (rt_assemble) takes the same images.
+ * Errors: those of rt_build_neighbors; RT_E_ARG for a negative or non-finite
+ * period, positions outside [0, period), or a period under three supports. */
+int rt_build_neighbors_periodic(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
+                                const double* pos, const double* h, int kernel,
+                                const double* period, rt_neighbors** out);
+
 typedef struct {
   int dim;
   int kernel;

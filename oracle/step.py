@@ -63,7 +63,7 @@ def time_step(prob, ptr=None, idx=None, eps_e: float = 1e-12, eps_E: float = 1e-
     ``fixed_outer`` runs exactly that many outer iterations (deterministic work
     for parity runs); otherwise iterate until the outer tolerances are met."""
     if ptr is None:
-        ptr, idx = neighbors.build(prob.pos, prob.h, KAPPA[prob.kernel])
+        ptr, idx = neighbors.build(prob.pos, prob.h, KAPPA[prob.kernel], prob.period)
     nin = prob.n_interior
     fz = operator.frozen(prob, ptr, idx)
     sysm = operator.assemble(prob, ptr, idx, fz)

@@ -92,7 +92,7 @@ __global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, doubl
                           const double* __restrict__ sp4, const int64_t* __restrict__ nptr,
                           const int32_t* __restrict__ nidx, const double* __restrict__ V,
                           const double* __restrict__ Eall, const double* __restrict__ st,
-                          double* __restrict__ D, double* __restrict__ VD) {
+                          double* __restrict__ D, double* __restrict__ VD, PeriodicBox box) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nin) return;
   const Rec4 pi = load_rec4(sp4, i);
@@ -102,8 +102,9 @@ __global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, doubl
   for (int64_t k = nptr[i]; k < nptr[i + 1]; ++k) {
     const int32_t j = nidx[k];
     const Rec4 pj = load_rec4(sp4, j);
-    const double dx = xi - pj.x, dy = yi - pj.y;
-    const double dz = DIM == 3 ? zi - pj.z : 0.0;
+    // nearest images on periodic axes (the pair is within one support)
+    const double dx = periodic_disp(xi - pj.x, box, 0), dy = periodic_disp(yi - pj.y, box, 1);
+    const double dz = DIM == 3 ? periodic_disp(zi - pj.z, box, 2) : 0.0;
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     // grad_i W_ij = 1/2 [W'(r,h_i) + W'(r,h_j)] x_ij / r
     const double w = V[j] * (Eall[j] - Ei) * 0.5 *
@@ -133,6 +134,7 @@ struct AsmArgs {
   int32_t* col;                       // written when the structure is new, else NULL
   double *val64, *diag64, *dinv64, *sinv64, *g;
   float *val32, *diag32, *dinv32, *sinv32;
+  PeriodicBox box;                    // periodic axes of the neighbour lists
 };
 
 // One group of G lanes per row, ENT neighbour entries per lane: the entry
@@ -171,8 +173,9 @@ k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A, i
     for (int e = 0; e < ENT; ++e) {
       const int64_t k = kb + e * G;
       if (k >= k1) break;
-      const double dx = xi - pj[e].x, dy = yi - pj[e].y;
-      const double dz = DIM == 3 ? zi - pj[e].z : 0.0;
+      const double dx = periodic_disp(xi - pj[e].x, A.box, 0);
+      const double dy = periodic_disp(yi - pj[e].y, A.box, 1);
+      const double dz = DIM == 3 ? periodic_disp(zi - pj[e].z, A.box, 2) : 0.0;
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double F =
           -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj[e].h, kernel)) / r;
@@ -275,11 +278,11 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
     if (nb->dim == 3)
       hipLaunchKernelGGL(k_limiter<3>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
                          nb->kernel, in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p,
-                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p);
+                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p, nb->box);
     else
       hipLaunchKernelGGL(k_limiter<2>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
                          nb->kernel, in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p,
-                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p);
+                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p, nb->box);
     RT_LAUNCH_CHECK();
   }
 
@@ -317,7 +320,7 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
                A->f.p, A->Eall.p, new_structure ? L.col.p : nullptr, L.val64.p, L.diag64.p,
                L.dinv64.p, L.sinv64.p, A->g.p, fp32 ? L.val32.p : nullptr,
                fp32 ? L.diag32.p : nullptr, fp32 ? L.dinv32.p : nullptr,
-               fp32 ? L.sinv32.p : nullptr};
+               fp32 ? L.sinv32.p : nullptr, nb->box};
     const double avg = nin ? (double)nb->npairs / (double)n : 0.0;
     const int G = pick_group(avg);
     const int per = (grid_for(nin * (int64_t)G, kBlock) + kXcd - 1) / kXcd;

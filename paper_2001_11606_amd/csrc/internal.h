@@ -222,6 +222,25 @@ struct rt_ctx {
   ~rt_ctx();
 };
 
+namespace rt {
+// Periodic axes of a neighbour object: bit a of mask set means axis a has
+// period len[a] (positions in [0, len[a])).
+struct PeriodicBox {
+  double len[3];
+  int mask;
+};
+// x_i - x_j reduced to the nearest image on an axis of period L: one period
+// off above L/2, one on below -L/2.
+__device__ __forceinline__ double nearest_image(double d, double L) {
+  const double half = 0.5 * L;
+  return d > half ? d - L : (d < -half ? d + L : d);
+}
+// Component a of a displacement, reduced on the box's periodic axes.
+__device__ __forceinline__ double periodic_disp(double d, const PeriodicBox& box, int a) {
+  return ((box.mask >> a) & 1) ? nearest_image(d, box.len[a]) : d;
+}
+}  // namespace rt
+
 struct rt_neighbors {
   int dim = 3;
   int kernel = RT_KERNEL_CUBIC_SPLINE;
@@ -232,6 +251,7 @@ struct rt_neighbors {
   int64_t ncells = 0;
   double lo[3] = {0, 0, 0};
   double cell_size = 0;
+  rt::PeriodicBox box{{0.0, 0.0, 0.0}, 0};   // periodic axes (mask 0: none)
   rt::DevBuf<uint64_t> skeys;   // sorted keys: ghost flag << (dim*bits) | Morton(cell)
   rt::DevBuf<int32_t> perm;     // sorted -> user
   rt::DevBuf<int32_t> iperm;    // user -> sorted
@@ -312,7 +332,8 @@ int build_tiles(rt_ctx* ctx, Level& L);
 
 // neighbours
 int build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
-                    const double* pos, const double* h, int kernel, rt_neighbors* nb);
+                    const double* pos, const double* h, int kernel, const double* period,
+                    rt_neighbors* nb);
 // solve helpers used by the Newton step
 // b_prev (else NULL): r64 holds b_prev - A x on entry, unless *mismatch
 // (device counter) is non-zero; the initial residual is then r64 + (b - b_prev)

@@ -20,6 +20,11 @@
 // The predicate r^2 < (kappa * max(h_i, h_j))^2 is evaluated in FP64 with
 // r^2 accumulated in axis order and contraction to FMA disabled, so that it
 // decides exactly as a separately-rounded evaluation does.
+//
+// Periodic axes (the periodic box of the manufactured problem of Sec. 4.3):
+// the grid covers [0, L) with a whole number (at least 3) of cells no smaller
+// than the largest support, adjacent-cell offsets wrap around, and every
+// displacement is reduced to its nearest image before it is squared.
 #include <cmath>
 #include <cstring>
 #include <algorithm>
@@ -101,16 +106,17 @@ __device__ __forceinline__ void demorton(int bits, uint64_t code, int* c) {
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_keys(int bits, int64_t n, int64_t nin, const double* __restrict__ pos, double lo0, double lo1,
-       double lo2, double cs, int nc0, int nc1, int nc2, uint64_t* __restrict__ keys,
-       int32_t* __restrict__ ids) {
+       double lo2, double cs0, double cs1, double cs2, int nc0, int nc1, int nc2,
+       uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double lo[3] = {lo0, lo1, lo2};
+  const double cs[3] = {cs0, cs1, cs2};
   const int nc[3] = {nc0, nc1, nc2};
   int c[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    const double q = floor((pos[a * n + i] - lo[a]) / cs);
+    const double q = floor((pos[a * n + i] - lo[a]) / cs[a]);
     int ci = (int)q;
     ci = ci < 0 ? 0 : (ci >= nc[a] ? nc[a] - 1 : ci);
     c[a] = ci;
@@ -190,10 +196,30 @@ constexpr int kNbrRows = 512;   // rows of one cell handled per pass
 constexpr int kCountRows = 8;   // count pass: rows tested against a wave's candidates in turn
 constexpr double kNbrMaskBytes = 4.0e9;   // largest hit-mask buffer kept between the passes
 
+// Adjacent cell x + o on an axis of nc cells: wraps on a periodic axis
+// (nc >= 3, so the three offsets reach three distinct cells), else false
+// outside the grid.
+__device__ __forceinline__ bool adjacent(int& x, int nc, bool periodic) {
+  if (x < 0) {
+    if (!periodic) return false;
+    x += nc;
+  } else if (x >= nc) {
+    if (!periodic) return false;
+    x -= nc;
+  }
+  return true;
+}
+
+// Component a of a displacement; PER: nearest image on the box's periodic axes.
+template <bool PER>
+__device__ __forceinline__ double axis_disp(double d, const PeriodicBox& box, int a) {
+  return PER ? periodic_disp(d, box, a) : d;
+}
+
 // Candidates of a cell: the particle count of its 2 * 3^DIM adjacent-cell slots.
 template <int DIM>
 __global__ void k_cell_candidates(int64_t nruns, int bits, int64_t ncells, int nc0, int nc1,
-                                  int nc2, const int32_t* __restrict__ runs,
+                                  int nc2, int pmask, const int32_t* __restrict__ runs,
                                   const uint64_t* __restrict__ skeys,
                                   const int32_t* __restrict__ cstart,
                                   const int32_t* __restrict__ cend, int32_t* __restrict__ m) {
@@ -207,8 +233,10 @@ __global__ void k_cell_candidates(int64_t nruns, int bits, int64_t ncells, int n
     for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
       for (int oy = -1; oy <= 1; ++oy)
         for (int ox = -1; ox <= 1; ++ox) {
-          const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
-          if (x < 0 || x >= nc0 || y < 0 || y >= nc1 || z < 0 || z >= nc2) continue;
+          int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
+          if (!adjacent(x, nc0, pmask & 1) || !adjacent(y, nc1, pmask & 2) ||
+              !adjacent(z, nc2, pmask & 4))
+            continue;
           const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
           total += cend[cell] - cstart[cell];
         }
@@ -219,10 +247,10 @@ __global__ void k_cell_candidates(int64_t nruns, int bits, int64_t ncells, int n
 // every 64-candidate hit mask (row s, candidate chunk q at masks[s*mstride+q]).
 // FILL = true, FROM_MASK = true: write the lists from those masks (no distance
 // tests, no staged positions); FROM_MASK = false: test the pairs again.
-template <int DIM, bool FILL, bool FROM_MASK>
+template <int DIM, bool FILL, bool FROM_MASK, bool PER>
 __global__ void __launch_bounds__(kBlock)
 k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
-            double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
+            PeriodicBox box, double kappa, const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
             const double* __restrict__ sp4, const int32_t* __restrict__ cstart,
             const int32_t* __restrict__ cend,
             int64_t* __restrict__ cnt, const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
@@ -244,9 +272,10 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
     demorton<DIM>(bits, key & mask, c);
     const int flag = tid / NB, o = tid % NB;
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
-    const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
+    int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
     int32_t lo = 0, len = 0;
-    if (tid < 2 * NB && x >= 0 && x < nc0 && y >= 0 && y < nc1 && z >= 0 && z < nc2) {
+    if (tid < 2 * NB && adjacent(x, nc0, box.mask & 1) && adjacent(y, nc1, box.mask & 2) &&
+        adjacent(z, nc2, box.mask & 4)) {
       const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
       lo = cstart[cell];
       len = cend[cell] - lo;
@@ -349,12 +378,12 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
               hi = q.h;
             }
             const double ki = kappa * hi;
-            double d = xi - qx;
+            double d = axis_disp<PER>(xi - qx, box, 0);
             double r2 = d * d;
-            d = yi - qy;
+            d = axis_disp<PER>(yi - qy, box, 1);
             r2 = r2 + d * d;
             if (DIM == 3) {
-              d = zi - qz;
+              d = axis_disp<PER>(zi - qz, box, 2);
               r2 = r2 + d * d;
             }
             const double th2 = fmax(ki * ki, tq);
@@ -401,12 +430,12 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           } else if (k < mc) {
             t = ct[k];
             if (t != s) {
-              double d = xi - cx[k];
+              double d = axis_disp<PER>(xi - cx[k], box, 0);
               double r2 = d * d;
-              d = yi - cy[k];
+              d = axis_disp<PER>(yi - cy[k], box, 1);
               r2 = r2 + d * d;
               if (DIM == 3) {
-                d = zi - cz[k];
+                d = axis_disp<PER>(zi - cz[k], box, 2);
                 r2 = r2 + d * d;
               }
               const double th = kappa * fmax(hi, ch[k]);
@@ -448,7 +477,7 @@ constexpr int kMaskWords = kNbrCand / kWave;   // mask words per staged chunk (8
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
-                 const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
+                 PeriodicBox box, const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
                  const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend,
                  const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
                  int32_t* __restrict__ n_int_nbrs, const uint64_t* __restrict__ masks,
@@ -469,9 +498,10 @@ k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int 
     demorton<DIM>(bits, key & mask, c);
     const int flag = tid / NB, o = tid % NB;
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
-    const int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
+    int x = c[0] + ox, y = c[1] + oy, z = c[2] + oz;
     int32_t lo = 0, len = 0;
-    if (tid < 2 * NB && x >= 0 && x < nc0 && y >= 0 && y < nc1 && z >= 0 && z < nc2) {
+    if (tid < 2 * NB && adjacent(x, nc0, box.mask & 1) && adjacent(y, nc1, box.mask & 2) &&
+        adjacent(z, nc2, box.mask & 4)) {
       const int64_t cell = flag * ncells + ((int64_t)z * nc1 + y) * nc0 + x;
       lo = cstart[cell];
       len = cend[cell] - lo;
@@ -571,13 +601,25 @@ __global__ void k_user_scatter(int64_t n, const int32_t* __restrict__ perm,
 }  // namespace
 
 int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* pos,
-                    const double* h, int kernel, rt_neighbors* nb) {
+                    const double* h, int kernel, const double* period, rt_neighbors* nb) {
   hipStream_t st = ctx->stream;
   nb->dim = dim;
   nb->kernel = kernel;
   nb->kappa = kernel == RT_KERNEL_CUBIC_SPLINE ? 2.0 : 1.0;
   nb->n_total = n;
   nb->n_interior = nin;
+  PeriodicBox box{{0.0, 0.0, 0.0}, 0};
+  for (int a = 0; period && a < dim; ++a) {
+    if (period[a] == 0.0) continue;
+    if (!(period[a] > 0.0) || !std::isfinite(period[a])) {
+      set_error("rt_build_neighbors: period %g along axis %d is not a positive finite length",
+                period[a], a);
+      return RT_E_ARG;
+    }
+    box.len[a] = period[a];
+    box.mask |= 1 << a;
+  }
+  nb->box = box;
 
   // 1. bounding box
   int gb = grid_for(n, kBlock, 1024);
@@ -607,9 +649,32 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   // cells at least as large as the largest support, with a relative margin
   // far above the rounding of (x - lo)/cs, so adjacent cells hold every pair
   const double cs = nb->kappa * hmax * (1.0 + 1e-6);
+  double width[3] = {cs, cs, cs};
   int64_t ncells = 1;
   for (int a = 0; a < 3; ++a) {
-    if (a < dim) {
+    if (a < dim && ((box.mask >> a) & 1)) {
+      // a whole number of cells tiles the period; three or more keep the
+      // nearest image the only image inside any support
+      const double L = box.len[a];
+      if (!(lo[a] >= 0.0) || !(hi[a] < L)) {
+        set_error("rt_build_neighbors: positions along periodic axis %d span [%g, %g], "
+                  "outside [0, %g)", a, lo[a], hi[a], L);
+        return RT_E_ARG;
+      }
+      const double cnt = std::floor(L / cs);
+      if (cnt < 3.0) {
+        set_error("rt_build_neighbors: period %g along axis %d is shorter than three "
+                  "supports (%g)", L, a, cs);
+        return RT_E_ARG;
+      }
+      if (cnt > 2.0e9) {
+        set_error("rt_build_neighbors: grid too large along axis %d", a);
+        return RT_E_ARG;
+      }
+      nb->nc[a] = (int)cnt;
+      nb->lo[a] = 0.0;
+      width[a] = L / cnt;
+    } else if (a < dim) {
       double cnt = std::floor((hi[a] - lo[a]) / cs) + 1.0;
       if (cnt > 2.0e9) {
         set_error("rt_build_neighbors: grid too large along axis %d", a);
@@ -655,8 +720,8 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK(nb->sp4.reserve((size_t)4 * n));
 #define RT_KEYS(D_)                                                                            \
   hipLaunchKernelGGL(k_keys<D_>, dim3(grid_for(n)), dim3(kBlock), 0, st, bits, n, nin, pos,     \
-                     nb->lo[0], nb->lo[1], nb->lo[2], cs, nb->nc[0], nb->nc[1], nb->nc[2],      \
-                     keys.p, ids.p)
+                     nb->lo[0], nb->lo[1], nb->lo[2], width[0], width[1], width[2], nb->nc[0],  \
+                     nb->nc[1], nb->nc[2], keys.p, ids.p)
   if (dim == 3) RT_KEYS(3);
   else RT_KEYS(2);
 #undef RT_KEYS
@@ -712,11 +777,13 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK(mcell.reserve((size_t)nruns));
   if (dim == 3)
     hipLaunchKernelGGL(k_cell_candidates<3>, dim3(grid_for(nruns)), dim3(kBlock), 0, st, nruns,
-                       bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], runs.p, nb->skeys.p, cstart.p,
+                       bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], box.mask, runs.p, nb->skeys.p,
+                       cstart.p,
                        cend.p, mcell.p);
   else
     hipLaunchKernelGGL(k_cell_candidates<2>, dim3(grid_for(nruns)), dim3(kBlock), 0, st, nruns,
-                       bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], runs.p, nb->skeys.p, cstart.p,
+                       bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], box.mask, runs.p, nb->skeys.p,
+                       cstart.p,
                        cend.p, mcell.p);
   RT_LAUNCH_CHECK();
   int32_t mmax = 0;
@@ -736,11 +803,17 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK(nb->ptr.reserve(n + 1));
   RT_CHECK(nb->n_int_nbrs.reserve(n));
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int64_t), st));
-#define RT_NBR(D_, F_, M_)                                                                      \
-  hipLaunchKernelGGL((k_nbr_cells<D_, F_, M_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits,  \
-                     ncells, nb->nc[0], nb->nc[1], nb->nc[2], nb->kappa, runs.p, runkey.p,       \
+#define RT_NBR1(D_, F_, M_, P_)                                                                  \
+  hipLaunchKernelGGL((k_nbr_cells<D_, F_, M_, P_>), dim3(nruns), dim3(kBlock), 0, st, n, nin,    \
+                     bits, ncells, nb->nc[0], nb->nc[1], nb->nc[2], box, nb->kappa, runs.p,      \
+                     runkey.p,                                                                   \
                      nb->sp4.p, cstart.p, cend.p, cnt.p, nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p, \
                      use_masks ? masks.p : nullptr, mstride)
+#define RT_NBR(D_, F_, M_)                                                                      \
+  do {                                                                                          \
+    if (box.mask) RT_NBR1(D_, F_, M_, true);                                                    \
+    else RT_NBR1(D_, F_, M_, false);                                                            \
+  } while (0)
   if (dim == 3) RT_NBR(3, false, false);
   else RT_NBR(2, false, false);
   RT_LAUNCH_CHECK();
@@ -757,7 +830,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   if (use_masks) {
 #define RT_FILLM(D_)                                                                             \
   hipLaunchKernelGGL((k_nbr_fill_masks<D_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits, ncells, \
-                     nb->nc[0], nb->nc[1], nb->nc[2], runs.p, runkey.p, cstart.p, cend.p,         \
+                     nb->nc[0], nb->nc[1], nb->nc[2], box, runs.p, runkey.p, cstart.p, cend.p,    \
                      nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p, masks.p, mstride)
     if (dim == 3) RT_FILLM(3);
     else RT_FILLM(2);
@@ -767,6 +840,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
     else RT_NBR(2, true, false);
   }
 #undef RT_NBR
+#undef RT_NBR1
   RT_LAUNCH_CHECK();
   RT_CHECK_HIP(hipStreamSynchronize(st));
   return RT_OK;
@@ -778,6 +852,12 @@ extern "C" {
 
 int rt_build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
                        const double* pos, const double* h, int kernel, rt_neighbors** out) {
+  return rt_build_neighbors_periodic(ctx, dim, n_total, n_interior, pos, h, kernel, nullptr, out);
+}
+
+int rt_build_neighbors_periodic(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior,
+                                const double* pos, const double* h, int kernel,
+                                const double* period, rt_neighbors** out) {
   rt::clear_error();
   if (!ctx || !out || !pos || !h) {
     rt::set_error("rt_build_neighbors: NULL argument");
@@ -800,7 +880,7 @@ int rt_build_neighbors(rt_ctx* ctx, int dim, int64_t n_total, int64_t n_interior
   RT_CHECK_HIP(hipSetDevice(ctx->device));
   rt::StreamScope release_scope(ctx->stream);   // buffers released here are stream-ordered
   rt_neighbors* nb = new rt_neighbors();
-  int s = rt::build_neighbors(ctx, dim, n_total, n_interior, pos, h, kernel, nb);
+  int s = rt::build_neighbors(ctx, dim, n_total, n_interior, pos, h, kernel, period, nb);
   if (s < 0) {
     delete nb;
     return s;

@@ -31,6 +31,7 @@ class DeviceProblem:
     limiter: int
     limiter_k: float
     kernel: int
+    period: object = None   # per-axis periods (0 = open axis) or None
 
 
 def upload(prob, device) -> DeviceProblem:
@@ -40,7 +41,9 @@ def upload(prob, device) -> DeviceProblem:
     return DeviceProblem(dim=prob.dim, n_total=prob.n_total, n_interior=prob.n_interior,
                          pos=t(prob.pos), h=t(prob.h), arrays={k: t(getattr(prob, k)) for k in FIELDS},
                          dt=prob.dt, c=prob.c, a=prob.a, opacity_exponent=prob.opacity_exponent,
-                         limiter=prob.limiter, limiter_k=prob.limiter_k, kernel=prob.kernel)
+                         limiter=prob.limiter, limiter_k=prob.limiter_k, kernel=prob.kernel,
+                         period=(None if getattr(prob, "period", None) is None
+                                 else [float(v) for v in prob.period]))
 
 
 @dataclass
@@ -142,7 +145,7 @@ def run_adaptive(ctx: rt.Context, dp: DeviceProblem, t_end: float, dt0: float,
     shortened to land on t_end.  Returns (steps, [(t, dt, StepReport)]).
     callback(t, e, E) is called after every step."""
     nin = dp.n_interior
-    nb = ctx.build_neighbors(dp.pos, dp.h, nin, dp.kernel)
+    nb = ctx.build_neighbors(dp.pos, dp.h, nin, dp.kernel, period=dp.period)
     A = 0
     t, dt = 0.0, dt0
     history = []

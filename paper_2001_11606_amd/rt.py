@@ -112,6 +112,8 @@ _SIGS = {
     "rt_version": (ctypes.c_char_p, []),
     "rt_build_neighbors": (c_int, [c_vp, c_int, c_i64, c_i64, c_vp, c_vp, c_int,
                                    ctypes.POINTER(c_vp)]),
+    "rt_build_neighbors_periodic": (c_int, [c_vp, c_int, c_i64, c_i64, c_vp, c_vp, c_int,
+                                            ctypes.POINTER(c_dbl), ctypes.POINTER(c_vp)]),
     "rt_neighbors_get_info": (c_int, [c_vp, ctypes.POINTER(rt_neighbors_info)]),
     "rt_neighbors_export": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "rt_neighbors_order": (c_int, [c_vp, c_vp, c_vp]),
@@ -223,6 +225,21 @@ def rt_build_neighbors(ctx: int, dim: int, n_total: int, n_interior: int, pos: i
     out = c_vp()
     _check("rt_build_neighbors", load().rt_build_neighbors(ctx, dim, n_total, n_interior, pos, h,
                                                            kernel, ctypes.byref(out)))
+    return out.value
+
+
+def rt_build_neighbors_periodic(ctx: int, dim: int, n_total: int, n_interior: int, pos: int,
+                                h: int, kernel: int, period) -> int:
+    """period: dim lengths (0 leaves an axis open) or None (no periodic axis)."""
+    out = c_vp()
+    arr = None
+    if period is not None:
+        if len(period) != dim:
+            raise ValueError(f"period needs {dim} entries, got {len(period)}")
+        arr = (c_dbl * dim)(*[float(v) for v in period])
+    _check("rt_build_neighbors_periodic",
+           load().rt_build_neighbors_periodic(ctx, dim, n_total, n_interior, pos, h, kernel, arr,
+                                              ctypes.byref(out)))
     return out.value
 
 
@@ -438,11 +455,17 @@ class Context:
     def set_profiling(self, on: bool):
         rt_set_profiling(self.handle, on)
 
-    def build_neighbors(self, pos, h, n_interior: int, kernel: int = RT_KERNEL_CUBIC_SPLINE):
+    def build_neighbors(self, pos, h, n_interior: int, kernel: int = RT_KERNEL_CUBIC_SPLINE,
+                        period=None):
         torch = self.torch
         dim, n = pos.shape
-        nb = rt_build_neighbors(self.handle, dim, n, n_interior, _ptr(pos, torch.float64),
-                                _ptr(h, torch.float64), kernel)
+        if period is None:
+            nb = rt_build_neighbors(self.handle, dim, n, n_interior, _ptr(pos, torch.float64),
+                                    _ptr(h, torch.float64), kernel)
+        else:
+            nb = rt_build_neighbors_periodic(self.handle, dim, n, n_interior,
+                                             _ptr(pos, torch.float64), _ptr(h, torch.float64),
+                                             kernel, list(period))
         self._owned.append(("N", nb))
         return Neighbors(nb, rt_neighbors_get_info(nb))
 

@@ -38,8 +38,9 @@ class Case:
         self.h = np.ascontiguousarray(prob.h)
         self.arr = {k: np.ascontiguousarray(getattr(prob, k)).copy() for k in FIELDS}
         self.ctx = ctx
-        self.nb = rt.rt_build_neighbors(ctx, prob.dim, prob.n_total, prob.n_interior, p(self.pos),
-                                        p(self.h), prob.kernel)
+        self.nb = rt.rt_build_neighbors_periodic(ctx, prob.dim, prob.n_total, prob.n_interior,
+                                                 p(self.pos), p(self.h), prob.kernel,
+                                                 None if prob.period is None else list(prob.period))
         self.info = rt.rt_neighbors_get_info(self.nb)
         self.A = self.assemble(amg)
 
@@ -241,6 +242,7 @@ def main():
         "levermore3d_8": _levermore(synth.config3(n=8)),
         "wendland2d_12": _wendland(2, 12),
         "wendland3d_6": _wendland(3, 6),
+        "periodic2d_16": synth.periodic_wendland(2, 16),
         "marshak3d_8": synth.config4(n=8),
         "ensemble2d": synth.config5_member(0, 400.0),
         "infinite3d_5": synth.config2_infinite(1.0, 0.01, n=5),
@@ -261,6 +263,15 @@ def main():
         raise AssertionError("dim=4 accepted")
     except rt.RtError as e:
         assert e.code == rt.RT_E_ARG
+    # periodic axes: a period under three supports, positions outside [0, L)
+    for period, word in (([0.5, 0.0, 0.0], "three"), ([0.0, 0.9, 0.0], "outside")):
+        sq = pos.copy()
+        sq[0] *= 0.49
+        try:
+            rt.rt_build_neighbors_periodic(ctx, 3, 40, 40, p(sq), p(h), 0, period)
+            raise AssertionError(f"period {period} accepted")
+        except rt.RtError as e:
+            assert e.code == rt.RT_E_ARG and word in str(e), str(e)
     # empty interior, single particle
     nb = rt.rt_build_neighbors(ctx, 3, 40, 0, p(pos), p(h), 0)
     rt.rt_neighbors_free(nb)

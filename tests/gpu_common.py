@@ -35,6 +35,8 @@ def small_cases():
         "densitystep3d_16_levermore": lambda: _levermore(synth.config3(n=16)),
         "wendland2d_24": lambda: _wendland(2, 24),
         "wendland3d_9": lambda: _wendland(3, 9),
+        "periodic2d_16": lambda: synth.periodic_wendland(2, 16),
+        "periodic3d_13": lambda: synth.periodic_wendland(3, 13),
         "marshak3d_16": lambda: synth.config4(n=16),
         "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
         "ensemble2d": lambda: synth.config5_member(0, 2500.0),
@@ -43,7 +45,7 @@ def small_cases():
 
 
 def oracle_system(prob):
-    ptr, idx = neighbors.build(prob.pos, prob.h, kernels.KAPPA[prob.kernel])
+    ptr, idx = neighbors.build(prob.pos, prob.h, kernels.KAPPA[prob.kernel], prob.period)
     fz = operator.frozen(prob, ptr, idx)
     sysm = operator.assemble(prob, ptr, idx, fz)
     return ptr, idx, fz, sysm
@@ -52,7 +54,7 @@ def oracle_system(prob):
 def gpu_system(ctx, prob, amg=None):
     from paper_2001_11606_amd import driver
     dp = driver.upload(prob, ctx.device)
-    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel, period=dp.period)
     A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                      dp.limiter_k, amg=amg)
     return dp, nb, A

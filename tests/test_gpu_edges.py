@@ -42,6 +42,38 @@ def test_invalid_arguments(ctx):
         ctx.build_neighbors(pos, hz, 50)
 
 
+def test_periodic_axes_and_their_errors(ctx):
+    """One periodic axis beside two open ones, random positions and smoothing
+    lengths: lists equal the oracle's brute force with nearest images; a
+    period under three supports, positions outside [0, L) and a negative
+    period are rejected."""
+    from paper_2001_11606_amd import rt
+    from oracle import neighbors
+    say("[edges] periodic x, open y and z")
+    rng = np.random.default_rng(31)
+    n = 3000
+    pos_np = rng.uniform(0.0, 1.0, (3, n))
+    h_np = rng.uniform(0.03, 0.06, n)
+    ptr, idx = neighbors.brute_force(pos_np, h_np, 2.0, period=np.array([1.0, 0.0, 0.0]))
+    pos, h = _t(ctx, pos_np), _t(ctx, h_np)
+    nb = ctx.build_neighbors(pos, h, n, period=[1.0, 0.0, 0.0])
+    gptr, gidx = ctx.export_neighbors(nb)
+    assert np.array_equal(gptr.cpu().numpy(), ptr)
+    assert np.array_equal(gidx.cpu().numpy(), idx)
+    wraps = np.abs(pos_np[0, neighbors.pairs(ptr, idx)[0]] - pos_np[0, idx]) > 0.5
+    assert wraps.any()   # the case reaches across the periodic boundary
+    squeezed = pos.clone()
+    squeezed[0] *= 0.29
+    with pytest.raises(rt.RtError) as ei:
+        ctx.build_neighbors(squeezed, h, n, period=[0.3, 0.0, 0.0])
+    assert "three" in str(ei.value)
+    with pytest.raises(rt.RtError) as ei:
+        ctx.build_neighbors(pos, h, n, period=[0.0, 0.9, 0.0])
+    assert "outside" in str(ei.value)
+    with pytest.raises(rt.RtError):
+        ctx.build_neighbors(pos, h, n, period=[-1.0, 0.0, 0.0])
+
+
 def test_mixed_needs_fp32_copy(ctx):
     from paper_2001_11606_amd import driver, rt
     import torch

@@ -102,7 +102,7 @@ def _newton_case(ctx, name, precision, precond, outer):
     say(f"[newton] {name} precision={precision} precond={precond} outer={outer}")
     ref = ostep.time_step(prob.copy(), fixed_outer=outer, inner_tol_e=1e-14, solve_tol=1e-15)
     dp = driver.upload(prob, ctx.device)
-    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel, period=dp.period)
     tol = 1e-14 if precision == 0 else 1e-12
     e, E, A, rep = driver.time_step(ctx, dp, nb, solve=rt.solve_opts(precision, precond, tol, 2000),
                                     fixed_outer=outer)
@@ -115,7 +115,7 @@ def _newton_case(ctx, name, precision, precond, outer):
 
 @pytest.mark.parametrize("name", ["mms2d_64", "mms3d_12", "densitystep3d_16", "marshak3d_16",
                                   "infinite3d_10", "densitystep3d_16_levermore", "wendland2d_24",
-                                  "wendland3d_9"])
+                                  "wendland3d_9", "periodic2d_16", "periodic3d_13"])
 def test_newton_fp64(ctx, name):
     err_e, err_E, rep, ref = _newton_case(ctx, name, 0, 1, 3)
     assert err_e <= 1e-12 and err_E <= 1e-12, (err_e, err_E)
