@@ -167,3 +167,36 @@ def run_adaptive(ctx: rt.Context, dp: DeviceProblem, t_end: float, dt0: float,
                  for eta in (eta_e, eta_E)]
         dt = max(dt_min, min(min(props), max_growth * dt, dt_max))
     return len(history), history
+
+
+def run_fixed(ctx: rt.Context, dp: DeviceProblem, dt: float, steps: int, sources=None,
+              amg: Optional[rt.rt_amg_opts] = None, solve: Optional[rt.rt_solve_opts] = None,
+              eps_e: float = 1e-8, eps_E: float = 1e-8, material_tol: float = 1e-14,
+              fixed_outer: Optional[int] = None, callback=None):
+    """``steps`` backward-Euler steps of length dt from t = 0 (Algorithm 1 per
+    step).  sources(t) -> (Q_e, Q_E), device tensors over all particles, gives
+    the sources of the step ending at t (time-dependent problems such as the
+    manufactured solution of Sec. 4.3); None keeps dp's sources.  Neighbour
+    lists and the matrix structure are built once.  Returns (t, [StepReport]).
+    callback(t, e, E) is called after every step."""
+    nin = dp.n_interior
+    nb = ctx.build_neighbors(dp.pos, dp.h, nin, dp.kernel, period=dp.period)
+    A = 0
+    dp.dt = dt
+    t = 0.0
+    reports = []
+    for s in range(steps):
+        t = (s + 1) * dt
+        if sources is not None:
+            Qe, QE = sources(t)
+            dp.arrays["Q_e"].copy_(Qe)
+            dp.arrays["Q_E"].copy_(QE)
+        e, E, A, rep = time_step(ctx, dp, nb, A=A, amg=amg, solve=solve, eps_e=eps_e,
+                                 eps_E=eps_E, material_tol=material_tol, fixed_outer=fixed_outer)
+        if rep.status != rt.RT_OK:
+            raise rt.RtError("run_fixed", rep.status, f"step {s + 1} did not complete")
+        advance(dp, e, E)
+        reports.append(rep)
+        if callback:
+            callback(t, e, E)
+    return t, reports

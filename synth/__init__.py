@@ -418,6 +418,103 @@ def periodic_wendland(dim: int, n: int, seed: Optional[int] = None) -> Problem:
                    period=np.ones(dim))
 
 
+# cgs constants of the cos-wave manufactured problem (Sec. 4.3)
+CGS_C = 2.99792458e10            # speed of light, cm/s
+CGS_A = 7.565723e-15             # radiation constant a = 4 sigma_SB / c, erg cm^-3 K^-4
+CGS_KB = 1.380649e-16            # Boltzmann constant, erg/K
+CGS_MP = 1.67262192e-24          # proton mass, g
+
+
+def cos_wave_fields(pos, t: float, e0: float, E0: float, v: float, d: float, omega: float,
+                    xp=np):
+    """The manufactured solution of Sec. 4.3 and its derivatives at time t:
+    e_m = e0 [1.2 + prod_a cos th_a],  th_a = 2 pi (x_a - v t)/d,
+    E_m = E0 [1.2 + prod_a cos ph_a],  ph_a = 2 pi (x_a + v t)/d - omega.
+    Returns (e_m, E_m, de_m/dt, dE_m/dt, Laplacian of E_m).  ``xp`` is the
+    array module of ``pos`` (numpy, or torch for device arrays)."""
+    k = 2.0 * np.pi / d
+    dim = pos.shape[0]
+    th = [k * (pos[a] - v * t) for a in range(dim)]
+    ph = [k * (pos[a] + v * t) - omega for a in range(dim)]
+    ce, cE = [xp.cos(u) for u in th], [xp.cos(u) for u in ph]
+
+    def prod(fs, skip=-1):
+        out = None
+        for a, f in enumerate(fs):
+            if a != skip:
+                out = f if out is None else out * f
+        return 1.0 if out is None else out
+
+    # d/dt prod_a cos(u_a) = sum_a (-sin u_a) du_a/dt prod_{b != a} cos u_b
+    de = 0.0
+    dE = 0.0
+    for a in range(dim):
+        de = de + xp.sin(th[a]) * (k * v) * prod(ce, a)
+        dE = dE - xp.sin(ph[a]) * (k * v) * prod(cE, a)
+    Pe, PE = prod(ce), prod(cE)
+    return (e0 * (1.2 + Pe), E0 * (1.2 + PE), e0 * de, E0 * dE, -dim * k * k * E0 * PE)
+
+
+class CosWaveSources:
+    """Sources of the step ending at t for the cos-wave problem (see
+    ``cos_wave_mms``), evaluated with the array module of ``pos``."""
+
+    def __init__(self, pos, consts: dict, xp=np):
+        self.pos, self.c, self.xp = pos, consts, xp
+
+    def __call__(self, t: float):
+        c = self.c
+        e_m, E_m, de, dE, lapE = cos_wave_fields(self.pos, t, c["e0"], c["E0"], c["v"], c["d"],
+                                                 c["omega"], self.xp)
+        x = c["c"] * c["sigma_a"] * (c["a"] * (e_m / c["cv"]) ** 4 - E_m)   # emission - absorption
+        return e_m, E_m, c["rho"] * de + x, dE - c["D"] * lapE - x
+
+
+def cos_wave_mms(dim: int, n: int, steps: int = 1000) -> Problem:
+    """The paper's manufactured problem for material-radiation coupling
+    (Sec. 4.3): an unjittered n^dim lattice on the periodic box [0, d_m)^dim,
+    d_m = 5 cm (one wavelength per axis), the Wendland kernel at h = 4
+    spacings, e0 = 1e13 erg/g, E0 = 7 a (e0/c_v)^4, v_m = 5e9 cm/s,
+    omega_m = 1/16, sigma_a = 0.05 and sigma_s = 0.95 per cm (constant), the
+    ideal gas c_v = k_B/(mu (gamma - 1) m_p) with gamma = 5/3 and mu = 1, one
+    cycle t_end = d_m/v_m in ``steps`` steps of dt = t_end/steps.
+    Readings (the paper leaves them open): rho = E0/e0, so that the material
+    and radiation energy densities, and with them the terms of both
+    equations, are of one magnitude; no flux limiter (lambda = 1/3, so
+    D = c/(3 sigma_t) is constant); the sources of the step ending at t are
+    the manufactured residuals at t (backward Euler):
+    Q_e = rho de_m/dt + c sigma_a (a T_m^4 - E_m),
+    Q_E = dE_m/dt - D lap E_m - c sigma_a (a T_m^4 - E_m),  T_m = e_m/c_v.
+    Call ``set_time`` before each step."""
+    d, v, omega = 5.0, 5.0e9, 1.0 / 16.0
+    e0 = 1.0e13
+    gamma, mu = 5.0 / 3.0, 1.0
+    cv = CGS_KB / (mu * (gamma - 1.0) * CGS_MP)
+    E0 = 7.0 * CGS_A * (e0 / cv) ** 4
+    rho = E0 / e0
+    sa, ss = 0.05, 0.95
+    D = CGS_C / (3.0 * (sa + ss))
+    dx = d / n
+    pos, nin = jittered_lattice(dim, n, 0.0, 0, np.random.default_rng(0))
+    pos = pos * d
+    N = pos.shape[1]
+
+    consts = dict(e0=e0, E0=E0, v=v, d=d, omega=omega, c=CGS_C, a=CGS_A, cv=cv, rho=rho,
+                  sigma_a=sa, D=D)
+    mms = CosWaveSources(pos, consts)
+    t_end = d / v
+    e_i, E_i, _, _ = mms(0.0)
+    prob = Problem(name=f"coswave{dim}d", dim=dim, pos=pos, h=_filled(N, 4.0 * dx),
+                   n_interior=nin, m=_filled(N, rho * dx ** dim), rho=_filled(N, rho),
+                   cv=_filled(N, cv), sigma0_a=_filled(N, sa), sigma_s=_filled(N, ss),
+                   opacity_exponent=0.0, e=e_i.copy(), E=E_i.copy(), Q_e=np.zeros(N),
+                   Q_E=np.zeros(N), dt=t_end / steps, c=CGS_C, a=CGS_A,
+                   kernel=KERNEL_WENDLAND_C4, mms=mms, period=np.full(dim, d),
+                   meta=dict(n=n, spacing=dx, t_end=t_end, steps=steps, consts=consts))
+    prob.set_time(prob.dt)
+    return prob
+
+
 def config4(n: int = 256, seed: Optional[int] = None) -> Problem:
     """3D Marshak-like front on a non-lattice point set: n^3 points by greedy
     dart throwing on a jittered ceil(1.1 n)^3 candidate grid, V = 1/n^3,
