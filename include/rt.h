@@ -185,10 +185,25 @@ typedef struct {
   int build_fp32;        /* 1: also build the FP32 copies for RT_PREC_MIXED    */
   int tiled_spmv;        /* 1: also build the tiled product form of each level
                             (16-bit tile-local columns, x staged in LDS)      */
+  int smoother;          /* V-cycle smoother on every level above the coarsest:
+                            RT_SMOOTHER_L1_JACOBI (one sweep before and one
+                            after the coarse correction) or
+                            RT_SMOOTHER_CHEBYSHEV (a Chebyshev polynomial of
+                            degree smoother_degree in D1^-1 A before and after,
+                            D1 the l1 diagonal a_ii + sum_j |a_ij|, on the
+                            interval [1/4, 1] that contains the upper part of
+                            its spectrum, which lies in (0, 1])               */
+  int smoother_degree;   /* 1..8, Chebyshev only                              */
 } rt_amg_opts;
+
+#define RT_SMOOTHER_L1_JACOBI 0
+#define RT_SMOOTHER_CHEBYSHEV 1
 
 int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
                 const rt_amg_opts* amg /* NULL = defaults */, rt_matrix** A);
+/* AMG defaults: max_levels 8, coarse_size 256, strength 0.08, build_fp32 1,
+ * tiled_spmv 1, smoother RT_SMOOTHER_L1_JACOBI, smoother_degree 2.
+ * Errors: RT_E_ARG for an unknown smoother or a degree outside 1..8.       */
 
 typedef struct {
   int64_t n;             /* unknowns = interior particles                     */

@@ -12,11 +12,15 @@
 // piecewise-constant P (sums of fine entries by aggregate pair), computed
 // with a fixed summation order.
 //
-// V-cycle (symmetric, so it is a valid CG preconditioner): one l1-Jacobi
-// pre-smoothing sweep from zero, residual, restriction, coarse correction,
-// prolongation, one l1-Jacobi post-smoothing sweep.  The l1 diagonal
-// d_i = a_ii + sum_j |a_ij| bounds A from above, so the smoother converges
-// without an eigenvalue estimate.  The coarsest level is solved with a dense
+// V-cycle (symmetric, so it is a valid CG preconditioner): pre-smoothing
+// from zero, residual, restriction, coarse correction, prolongation,
+// post-smoothing with the same smoother.  The l1 diagonal
+// D1_ii = a_ii + sum_j |a_ij| bounds A from above (D1 - A is diagonally
+// dominant), so the spectrum of D1^-1 A lies in (0, 1] and neither smoother
+// needs an eigenvalue estimate: one l1-Jacobi sweep, or a Chebyshev
+// polynomial in D1^-1 A on [1/4, 1] (the three-term recurrence of Chebyshev
+// acceleration, Saad, Iterative Methods for Sparse Linear Systems, Sec. 12.3,
+// with the residual recomputed as b - A x at every step).  The coarsest level is solved with a dense
 // FP64 inverse (Gauss-Jordan at setup) when small enough, otherwise with four
 // l1-Jacobi sweeps.
 #include <climits>
@@ -226,6 +230,20 @@ __global__ void k_prolong(int64_t n, const int32_t* __restrict__ pmap, const T* 
   if (i < n) x[i] += xc[pmap[i]];
 }
 
+// Chebyshev step: d = c1 d + c2 D1^-1 r (c1 = 0 on the first step), then
+// xout = xin + d (xin NULL: from zero).  xin and xout may alias.
+template <typename T>
+__global__ void k_cheb(int64_t n, T c1, T c2, const T* __restrict__ s, const T* __restrict__ r,
+                       T* __restrict__ d, const T* xin, T* xout,
+                       const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T di = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * s[i] * r[i];
+  d[i] = di;
+  xout[i] = (xin ? xin[i] : T(0)) + di;
+}
+
 template <typename T> struct LevelBufs;
 template <> struct LevelBufs<double> {
   static const double* val(const Level& L) { return L.val64.p; }
@@ -235,6 +253,7 @@ template <> struct LevelBufs<double> {
   static double* x(Level& L) { return L.x64.p; }
   static double* t(Level& L) { return L.t64.p; }
   static double* r(Level& L) { return L.r64.p; }
+  static double* d(Level& L) { return L.d64.p; }
 };
 template <> struct LevelBufs<float> {
   static const float* val(const Level& L) { return L.val32.p; }
@@ -244,6 +263,7 @@ template <> struct LevelBufs<float> {
   static float* x(Level& L) { return L.x32.p; }
   static float* t(Level& L) { return L.t32.p; }
   static float* r(Level& L) { return L.r32.p; }
+  static float* d(Level& L) { return L.d32.p; }
 };
 
 // Values (and columns) of the coarse level C = P^T F P.
@@ -305,9 +325,10 @@ int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim) {
 }
 
 int level_vectors(Level& L, bool fp32) {
-  for (auto* b : {&L.b64, &L.x64, &L.t64, &L.r64, &L.sinv64, &L.dinv64}) RT_CHECK(b->reserve(L.n));
+  for (auto* b : {&L.b64, &L.x64, &L.t64, &L.r64, &L.d64, &L.sinv64, &L.dinv64})
+    RT_CHECK(b->reserve(L.n));
   if (fp32) {
-    for (auto* b : {&L.b32, &L.x32, &L.t32, &L.r32, &L.sinv32, &L.dinv32})
+    for (auto* b : {&L.b32, &L.x32, &L.t32, &L.r32, &L.d32, &L.sinv32, &L.dinv32})
       RT_CHECK(b->reserve(L.n));
     RT_CHECK(L.val32.reserve(L.nnz + kSpmvPad));
     RT_CHECK(L.diag32.reserve(L.n));
@@ -376,6 +397,42 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
   return RT_OK;
 }
 
+// Chebyshev smoothing of A x = b on level L, degree steps: from zero into x
+// (xin NULL), or from xin into x.  Each step after a start from zero costs
+// one residual product.
+template <typename T>
+static int cheb_smooth(hipStream_t st, rt_matrix* A, Level& L, int degree, const T* b,
+                       const T* xin, T* x, const int32_t* stop) {
+  using B = LevelBufs<T>;
+  const int64_t n = L.n;
+  const double hi = 1.0, lo = 0.25;   // interval of D1^-1 A to damp
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  T* r = B::r(L);
+  const T* r0 = b;   // residual of the zero start
+  if (xin) {
+    RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), xin, b, nullptr, r,
+                                             nullptr, A->partB.p, nullptr, level_shape<T>(L),
+                                             nullptr, stop)));
+    r0 = r;
+  }
+  hipLaunchKernelGGL(k_cheb<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, T(0),
+                     (T)(1.0 / theta), B::sinv(L), r0, B::d(L), xin, x, stop);
+  RT_LAUNCH_CHECK();
+  for (int k = 1; k < degree; ++k) {
+    RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), x, b, nullptr, r,
+                                             nullptr, A->partB.p, nullptr, level_shape<T>(L),
+                                             nullptr, stop)));
+    const double rho_next = 1.0 / (2.0 * sigma - rho);
+    hipLaunchKernelGGL(k_cheb<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n,
+                       (T)(rho_next * rho), (T)(2.0 * rho_next / delta), B::sinv(L), r, B::d(L),
+                       x, x, stop);
+    RT_LAUNCH_CHECK();
+    rho = rho_next;
+  }
+  return RT_OK;
+}
+
 template <typename T>
 static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
                         const int32_t* stop) {
@@ -412,9 +469,14 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   Level& C = A->levels[l + 1];
   T* t = B::t(L);
   T* r = B::r(L);
-  hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t,
-                     stop);
-  RT_LAUNCH_CHECK();
+  const bool cheb = A->amg.smoother == RT_SMOOTHER_CHEBYSHEV;
+  if (cheb) {
+    RT_CHECK(cheb_smooth<T>(st, A, L, A->amg.smoother_degree, b, nullptr, t, stop));
+  } else {
+    hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t,
+                       stop);
+    RT_LAUNCH_CHECK();
+  }
   RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
                                            nullptr, A->partB.p, nullptr, level_shape<T>(L),
                                            nullptr, stop)));
@@ -425,6 +487,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p, B::x(C),
                      t, stop);
   RT_LAUNCH_CHECK();
+  if (cheb) return cheb_smooth<T>(st, A, L, A->amg.smoother_degree, b, t, out, stop);
   RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), t, b, B::sinv(L), out,
                                             nullptr, nullptr, nullptr, level_shape<T>(L),
                                             nullptr, stop)));

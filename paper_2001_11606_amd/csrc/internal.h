@@ -284,8 +284,8 @@ struct Level {
   DevBuf<int32_t> pmap;         // node -> aggregate on the next level
   DevBuf<int32_t> crange;       // next-level aggregate -> first node (size n_next + 1)
   // work vectors of this level (b: right-hand side, x: result, t, r: temporaries)
-  DevBuf<double> b64, x64, t64, r64;
-  DevBuf<float> b32, x32, t32, r32;
+  DevBuf<double> b64, x64, t64, r64, d64;   // d: Chebyshev search direction
+  DevBuf<float> b32, x32, t32, r32, d32;
 };
 template <typename T>
 inline int level_shape(const Level& L) {

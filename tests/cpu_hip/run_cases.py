@@ -94,6 +94,15 @@ def check_case(ctx, name, prob):
         s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50))
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: solve prec={prec} precond={precond} err={e} its={st.iterations}"
+    # the V-cycle with the Chebyshev smoother (degrees 2 and 3), FP64 and mixed
+    cc = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8,
+                                         smoother=rt.RT_SMOOTHER_CHEBYSHEV, smoother_degree=3))
+    for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
+        x = np.zeros(nin)
+        s, st = rt.rt_solve(ctx, cc.A, p(b), p(x), rt.solve_opts(prec, 1, tol, 3000, 1e-4, 50))
+        e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+        assert s == 0 and e <= bar, f"{name}: chebyshev prec={prec} err={e} its={st.iterations}"
+    cc.free()
     # GMRES on the unscaled operator, Jacobi and AMG, with and without restarts
     for precond, restart in (((1, 4),) if QUICK else ((0, 30), (1, 30), (1, 4))):
         x = np.zeros(nin)

@@ -74,6 +74,19 @@ def test_periodic_axes_and_their_errors(ctx):
         ctx.build_neighbors(pos, h, n, period=[-1.0, 0.0, 0.0])
 
 
+def test_smoother_options_rejected(ctx):
+    from paper_2001_11606_amd import driver, rt
+    say("[edges] smoother options")
+    prob = synth.config3(n=6)
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+    for smoother, degree in ((2, 2), (rt.RT_SMOOTHER_CHEBYSHEV, 0), (rt.RT_SMOOTHER_CHEBYSHEV, 9)):
+        with pytest.raises(rt.RtError) as ei:
+            ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=rt.amg_opts(smoother=smoother, smoother_degree=degree))
+        assert ei.value.code == rt.RT_E_ARG and "smoother" in str(ei.value)
+
+
 def test_mixed_needs_fp32_copy(ctx):
     from paper_2001_11606_amd import driver, rt
     import torch
