@@ -286,7 +286,8 @@ def run_coswave(args):
     pos = torch.as_tensor(prob.pos, dtype=torch.float64, device=ctx.device)
     src = synth.CosWaveSources(pos, prob.meta["consts"], xp=torch)
     sources = lambda t: src(t)[2:]
-    solve = rt.solve_opts(rt.RT_PREC_FP64, args.precond, 1e-12, 2000)
+    prec = rt.RT_PREC_MIXED if args.mixed else rt.RT_PREC_FP64
+    solve = rt.solve_opts(prec, args.precond, 1e-12, 2000, args.inner_tol, 50)
     # Jacobi needs no coarse levels: the hierarchy is then not built per step
     amg = rt.amg_opts(max_levels=1) if args.precond == 0 else None
     kw = dict(sources=sources, solve=solve, amg=amg, eps_e=1e-8, eps_E=1e-8, material_tol=1e-12)
@@ -315,11 +316,11 @@ def run_coswave(args):
         "metric": "particle-updates/s", "value": nin * args.steps / wall,
         "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32+f64" if args.mixed else "f64", "data": "synthetic",
         "config": {"workload": f"coswave3d {args.n}^3 ({nin} particles, periodic), Sec. 4.3 "
                                f"manufactured problem, dt = t_end/{prob.meta['steps']}, outer "
-                               f"tolerance 1e-8, FP64 CG + {('Jacobi', 'AMG')[args.precond]} to "
-                               f"1e-12",
+                               f"tolerance 1e-8, {'mixed FP32/FP64' if args.mixed else 'FP64'} "
+                               f"CG + {('Jacobi', 'AMG')[args.precond]} to 1e-12",
                    "particles": nin, "precond": ("jacobi", "amg")[args.precond]},
         "outer_per_step": float(np.mean([r.outer for r in reps])),
         "krylov_per_outer": float(np.mean([k for r in reps for k in r.krylov])),
@@ -349,6 +350,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative reduction asked of each FP32 inner solve")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
+    ap.add_argument("--mixed", action="store_true",
+                    help="coswave3d: FP32 inner CG with FP64 refinement instead of FP64 CG")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--nprob", type=int, default=96, help="ensemble: number of problems")
