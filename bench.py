@@ -266,8 +266,9 @@ def run_ensemble(args):
 
 
 def run_coswave(args):
-    """The manufactured problem of Sec. 4.3 in 3-D (periodic box, Wendland
-    kernel at h = 4 spacings, a few hundred neighbours per row), time
+    """The manufactured problem of Sec. 4.3 in 3-D (coswave3d) or 2-D
+    (coswave2d): periodic box, Wendland kernel at h = 4 spacings (a few
+    hundred neighbours per row in 3-D, about 50 in 2-D), time
     stepped as the paper runs it: dt = t_end/1000, outer iterations to 1e-8,
     FP64 radiation solves to 1e-12 (CG, --precond 0 Jacobi or 1 the
     aggregation V-cycle), sources
@@ -281,8 +282,9 @@ def run_coswave(args):
     import synth
     from paper_2001_11606_amd import driver, rt
     ctx = rt.Context(0)
-    log(f"[bench] generating coswave3d n={args.n}")
-    prob = synth.cos_wave_mms(3, args.n)
+    dim = 3 if args.workload == "coswave3d" else 2
+    log(f"[bench] generating {args.workload} n={args.n}")
+    prob = synth.cos_wave_mms(dim, args.n)
     pos = torch.as_tensor(prob.pos, dtype=torch.float64, device=ctx.device)
     src = synth.CosWaveSources(pos, prob.meta["consts"], xp=torch)
     sources = lambda t: src(t)[2:]
@@ -317,7 +319,7 @@ def run_coswave(args):
         "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64" if args.mixed else "f64", "data": "synthetic",
-        "config": {"workload": f"coswave3d {args.n}^3 ({nin} particles, periodic), Sec. 4.3 "
+        "config": {"workload": f"{args.workload} {args.n}^{dim} ({nin} particles, periodic), Sec. 4.3 "
                                f"manufactured problem, dt = t_end/{prob.meta['steps']}, outer "
                                f"tolerance 1e-8, {'mixed FP32/FP64' if args.mixed else 'FP64'} "
                                f"CG + {('Jacobi', 'AMG')[args.precond]} to 1e-12",
@@ -376,7 +378,7 @@ def main():
     if args.workload == "ensemble":
         run_ensemble(args)
         return
-    if args.workload == "coswave3d":
+    if args.workload in ("coswave3d", "coswave2d"):
         run_coswave(args)
         return
     log(f"[bench] generating {args.workload} n={args.n}")
