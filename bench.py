@@ -290,8 +290,9 @@ def run_coswave(args):
     sources = lambda t: src(t)[2:]
     prec = rt.RT_PREC_MIXED if args.mixed else rt.RT_PREC_FP64
     solve = rt.solve_opts(prec, args.precond, 1e-12, 2000, args.inner_tol, 50)
-    # Jacobi needs no coarse levels: the hierarchy is then not built per step
-    amg = rt.amg_opts(max_levels=1) if args.precond == 0 else None
+    # Jacobi needs no coarse levels (the hierarchy is then not built per
+    # step), and FP64 solves need no FP32 copy of the matrix
+    amg = rt.amg_opts(max_levels=1 if args.precond == 0 else 8, build_fp32=int(args.mixed))
     kw = dict(sources=sources, solve=solve, amg=amg, eps_e=1e-8, eps_E=1e-8, material_tol=1e-12)
     if args.warmup > 0:
         dpw = driver.upload(prob, ctx.device)
