@@ -177,8 +177,10 @@ k_assemble(int64_t nin, int64_t n, int kernel, double dt, double c, AsmArgs A, i
       const double dy = periodic_disp(yi - pj[e].y, A.box, 1);
       const double dz = DIM == 3 ? periodic_disp(zi - pj[e].z, A.box, 2) : 0.0;
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const double F =
-          -0.5 * (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj[e].h, kernel)) / r;
+      // equal smoothing lengths give equal kernel derivatives: evaluate once
+      const double wi = sph_dwdr<DIM>(r, hi, kernel);
+      const double wj = pj[e].h == hi ? wi : sph_dwdr<DIM>(r, pj[e].h, kernel);
+      const double F = -0.5 * (wi + wj) / r;
       const double Dij = Di + vdj[e][1];
       const double aij = vdj[e][0] * Dij * F;
       suma += aij;

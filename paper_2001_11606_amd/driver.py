@@ -178,7 +178,9 @@ def run_fixed(ctx: rt.Context, dp: DeviceProblem, dt: float, steps: int, sources
     the sources of the step ending at t (time-dependent problems such as the
     manufactured solution of Sec. 4.3); None keeps dp's sources.  Neighbour
     lists and the matrix structure are built once.  Returns (t, [StepReport]).
-    callback(t, e, E) is called after every step."""
+    callback(t, e, E) is called after every step.  A step that ends with a
+    soft status (a solve not converged, a clamped material root) raises
+    RtError with that status; the state then holds the previous step."""
     nin = dp.n_interior
     nb = ctx.build_neighbors(dp.pos, dp.h, nin, dp.kernel, period=dp.period)
     A = 0

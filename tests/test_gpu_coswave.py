@@ -38,11 +38,14 @@ def _device_sources(prob, device):
     return lambda t: src(t)[2:]
 
 
-@pytest.mark.parametrize("dim,n,nsteps", [(2, 16, 12), (3, 13, 3)])
-def test_steps_match_oracle(ctx, dim, n, nsteps):
+@pytest.mark.parametrize("dim,n,nsteps,jacobi", [(2, 16, 12, False), (3, 13, 3, False),
+                                                  (3, 13, 3, True)])
+def test_steps_match_oracle(ctx, dim, n, nsteps, jacobi):
+    """jacobi: the benchmark's configuration, Jacobi-CG on a one-level
+    hierarchy without the FP32 copy of the matrix; else the V-cycle."""
     from paper_2001_11606_amd import driver, rt
     prob = synth.cos_wave_mms(dim, n)
-    say(f"[coswave parity] dim={dim} n={n} steps={nsteps}")
+    say(f"[coswave parity] dim={dim} n={n} steps={nsteps} jacobi={jacobi}")
     ref = prob.copy()
     ptr, idx = neighbors.build(ref.pos, ref.h, kernels.KAPPA[ref.kernel], ref.period)
     t = 0.0
@@ -52,8 +55,10 @@ def test_steps_match_oracle(ctx, dim, n, nsteps):
         r = ostep.time_step(ref, ptr, idx, fixed_outer=3, inner_tol_e=1e-14, solve_tol=1e-15)
         ostep.advance(ref, r)
     dp = driver.upload(prob, ctx.device)
+    amg = rt.amg_opts(max_levels=1, build_fp32=0) if jacobi else None
     tg, reps = driver.run_fixed(ctx, dp, prob.dt, nsteps, sources=_device_sources(prob, ctx.device),
-                                solve=rt.solve_opts(0, 1, 1e-14, 2000), fixed_outer=3)
+                                solve=rt.solve_opts(0, 0 if jacobi else 1, 1e-14, 2000), amg=amg,
+                                fixed_outer=3)
     assert tg == pytest.approx(t, rel=1e-14)
     nin = prob.n_interior
     e = dp.arrays["e"][:nin].cpu().numpy()
