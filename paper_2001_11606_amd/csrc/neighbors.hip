@@ -24,7 +24,10 @@
 // Periodic axes (the periodic box of the manufactured problem of Sec. 4.3):
 // the grid covers [0, L) with a whole number (at least 3) of cells no smaller
 // than the largest support, adjacent-cell offsets wrap around, and every
-// displacement is reduced to its nearest image before it is squared.
+// displacement is reduced to its nearest image before it is squared.  With
+// the period at least three supports long, this yields the pairs that copies
+// of the boundary points placed across the boundary would (Sec. 3.1), with
+// each pair coupled to the node itself.
 #include <cmath>
 #include <cstring>
 #include <algorithm>
