@@ -10,7 +10,8 @@ run of it (CPU).
   tolerance (the paper prints a relative change of 6.35e-14 at this size),
   every step needs at most the paper's two outer iterations plus one check,
   and the solution returns to the initial condition;
-* second-order convergence in space of the radiation energy (Sec. 4.3).
+* second-order convergence in space of the radiation energy (Sec. 4.3);
+* first-order convergence in time of both energies (Sec. 4.3).
 """
 import numpy as np
 import pytest
@@ -95,3 +96,20 @@ def test_radiation_energy_second_order_in_space():
         t, _, _ = _run(p, 100)
         errs.append(_l1(p.E, p.mms(t)[1]))
     assert 3.0 < errs[0] / errs[1] < 5.5, errs
+
+
+def test_first_order_in_time():
+    """At fixed particles, successive differences of the state at t = 1e-10 s
+    (a tenth of the cycle) for dt, dt/2, dt/4, dt/8 halve with the step
+    (backward Euler is first order in time, Sec. 4.3); the spatial error
+    cancels in the differences."""
+    states = []
+    for nsteps in (25, 50, 100, 200):
+        p = synth.cos_wave_mms(2, 16, steps=10 * nsteps)   # dt = t_end / (10 nsteps)
+        t, _, _ = _run(p, nsteps, tol_outer=1e-12, tol_inner=1e-14)
+        assert t == pytest.approx(1e-10, rel=1e-12)
+        states.append((p.e.copy(), p.E.copy()))
+    for k in (0, 1):
+        d = [np.max(np.abs(states[i + 1][k] - states[i][k])) for i in range(3)]
+        ratios = [d[i] / d[i + 1] for i in range(2)]
+        assert all(1.8 < r < 2.2 for r in ratios), (k, d, ratios)
