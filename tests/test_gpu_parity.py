@@ -237,18 +237,21 @@ def test_newton_residual_carry(ctx, precision):
 
 
 @pytest.mark.parametrize("name", ["mms2d_64", "densitystep3d_16", "marshak3d_16"])
-@pytest.mark.parametrize("precond,restart", [(0, 30), (1, 30), (1, 5)])
-def test_gmres_unscaled_matches_oracle(ctx, systems, name, precond, restart):
+@pytest.mark.parametrize("precond,restart,cheb", [(0, 30, False), (1, 30, False), (1, 5, False),
+                                                  (1, 30, True)])
+def test_gmres_unscaled_matches_oracle(ctx, systems, name, precond, restart, cheb):
     """GMRES on the paper's unscaled operator reaches the oracle's solution of
-    the same system (the V-scaling does not change x), restarts included."""
+    the same system (the V-scaling does not change x), restarts included;
+    cheb: the V-cycle with the Chebyshev smoother."""
     import torch
     from paper_2001_11606_amd import rt
     prob, (ptr, idx, fz, sysm) = _get(systems, name)
-    say(f"[gmres] {name} precond={precond} restart={restart}")
+    say(f"[gmres] {name} precond={precond} restart={restart} chebyshev={cheb}")
     nin = prob.n_interior
     b = np.random.default_rng(29).standard_normal(nin) * sysm.A.diagonal()
     x_ref = linsolve.dense(sysm.A, b) if nin <= 5000 else linsolve.pcg_jacobi(sysm.A, b, tol=1e-15)[0]
-    dp, nb, A = gpu_system(ctx, prob)
+    amg = rt.amg_opts(smoother=rt.RT_SMOOTHER_CHEBYSHEV, smoother_degree=2) if cheb else None
+    dp, nb, A = gpu_system(ctx, prob, amg=amg)
     bt = torch.tensor(b, device=ctx.device)
     xt = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
     s, st = ctx.solve_gmres(A, bt, xt, rt.gmres_opts(precond, 1e-13, 5000, restart))
