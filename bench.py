@@ -14,6 +14,11 @@ outer iterations / wall time per step.  The plain-FP64 solve of the same
 systems is timed afterwards for the mixed-vs-FP64 ratio; the SpMV roofline
 uses HIP events recorded around every SpMV launch on the library's stream.
 The CPU baseline times the oracle on a smaller instance of the same recipe.
+
+Other workloads (--workload): densitystep3d and wendland3d (one step of the
+same path on those recipes), ensemble (a batch of independent problems), and
+coswave3d / coswave2d (the manufactured problem of Sec. 4.3, time stepped
+with per-step sources; --steps 1000 runs one full cycle).
 """
 from __future__ import annotations
 
