@@ -25,6 +25,24 @@ def _wendland(dim, n):
     return synth.wendland_lattice(dim, n)
 
 
+def _periodic_x_ghosts_y(n):
+    """The 2-D manufactured recipe (fields periodic in x) with the ghost
+    layers beyond the y faces kept as Dirichlet boundaries and those beyond
+    the x faces removed; x is periodic with period 1."""
+    prob = synth.config1(n=n)
+    nin = prob.n_interior
+    x = prob.pos[0]
+    N = prob.n_total
+    keep = np.ones(N, bool)
+    keep[nin:] = (x[nin:] > 0.0) & (x[nin:] < 1.0)
+    for k, v in list(prob.__dict__.items()):
+        if isinstance(v, np.ndarray) and v.shape[-1] == N:
+            setattr(prob, k, np.ascontiguousarray(v[..., keep]))
+    prob.mms = None
+    prob.period = np.array([1.0, 0.0])
+    return prob
+
+
 def small_cases():
     """Seeded problems of every workload family, sized so the oracle finishes in
     seconds while still spanning many rows per block and ragged tails."""
@@ -37,6 +55,7 @@ def small_cases():
         "wendland3d_9": lambda: _wendland(3, 9),
         "periodic2d_16": lambda: synth.periodic_wendland(2, 16),
         "periodic3d_13": lambda: synth.periodic_wendland(3, 13),
+        "periodicx_ghostsy2d_32": lambda: _periodic_x_ghosts_y(32),
         "marshak3d_16": lambda: synth.config4(n=16),
         "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
         "ensemble2d": lambda: synth.config5_member(0, 2500.0),

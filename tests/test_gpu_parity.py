@@ -133,7 +133,8 @@ def _newton_case(ctx, name, precision, precond, outer):
 
 @pytest.mark.parametrize("name", ["mms2d_64", "mms3d_12", "densitystep3d_16", "marshak3d_16",
                                   "infinite3d_10", "densitystep3d_16_levermore", "wendland2d_24",
-                                  "wendland3d_9", "periodic2d_16", "periodic3d_13"])
+                                  "wendland3d_9", "periodic2d_16", "periodic3d_13",
+                                  "periodicx_ghostsy2d_32"])
 def test_newton_fp64(ctx, name):
     err_e, err_E, rep, ref = _newton_case(ctx, name, 0, 1, 3)
     assert err_e <= 1e-12 and err_E <= 1e-12, (err_e, err_E)
