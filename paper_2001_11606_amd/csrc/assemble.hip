@@ -86,33 +86,60 @@ __global__ void k_frozen(int64_t n, int64_t nin, FrozenArgs A) {
   }
 }
 
-// Flux-limited diffusion coefficient of interior particles.
-template <int DIM>
-__global__ void k_limiter(int64_t nin, int64_t n, int kernel, int limiter, double lk, double c,
-                          const double* __restrict__ sp4, const int64_t* __restrict__ nptr,
-                          const int32_t* __restrict__ nidx, const double* __restrict__ V,
-                          const double* __restrict__ Eall, const double* __restrict__ st,
-                          double* __restrict__ D, double* __restrict__ VD, PeriodicBox box) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nin) return;
+// Flux-limited diffusion coefficient of interior particles.  One group of G
+// lanes per row, ENT neighbour entries per lane requested before any
+// arithmetic, and each XCD on one contiguous range of rows, as in the
+// assembly; the gradient's three components are summed over the group.
+template <int DIM, int G, int ENT>
+__global__ void __launch_bounds__(kBlock)
+k_limiter(int64_t nin, int kernel, int limiter, double lk, double c,
+          const double* __restrict__ sp4, const int64_t* __restrict__ nptr,
+          const int32_t* __restrict__ nidx, const double* __restrict__ V,
+          const double* __restrict__ Eall, const double* __restrict__ st,
+          double* __restrict__ D, double* __restrict__ VD, PeriodicBox box, int per) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t i = ((int64_t)xcd_block(per) * kBlock + threadIdx.x) / G;
+  if (i >= nin) return;   // whole groups leave together
   const Rec4 pi = load_rec4(sp4, i);
   const double xi = pi.x, yi = pi.y, zi = pi.z;
   const double hi = pi.h, Ei = Eall[i];
+  const int64_t k0 = nptr[i], k1 = nptr[i + 1];
   double gx = 0, gy = 0, gz = 0;
-  for (int64_t k = nptr[i]; k < nptr[i + 1]; ++k) {
-    const int32_t j = nidx[k];
-    const Rec4 pj = load_rec4(sp4, j);
-    // nearest images on periodic axes (the pair is within one support)
-    const double dx = periodic_disp(xi - pj.x, box, 0), dy = periodic_disp(yi - pj.y, box, 1);
-    const double dz = DIM == 3 ? periodic_disp(zi - pj.z, box, 2) : 0.0;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    // grad_i W_ij = 1/2 [W'(r,h_i) + W'(r,h_j)] x_ij / r
-    const double w = V[j] * (Eall[j] - Ei) * 0.5 *
-                     (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj.h, kernel)) / r;
-    gx += w * dx;
-    gy += w * dy;
-    gz += w * dz;
+  for (int64_t kb = k0 + lane; kb < k1; kb += G * ENT) {
+    int32_t j[ENT];
+#pragma unroll
+    for (int e = 0; e < ENT; ++e) {
+      const int64_t k = kb + e * G;
+      j[e] = nidx[k < k1 ? k : k1 - 1];
+    }
+    Rec4 pj[ENT];
+    double vj[ENT], ej[ENT];
+#pragma unroll
+    for (int e = 0; e < ENT; ++e) {
+      pj[e] = load_rec4(sp4, j[e]);
+      vj[e] = V[j[e]];
+      ej[e] = Eall[j[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < ENT; ++e) {
+      if (kb + e * G >= k1) break;
+      // nearest images on periodic axes (the pair is within one support)
+      const double dx = periodic_disp(xi - pj[e].x, box, 0);
+      const double dy = periodic_disp(yi - pj[e].y, box, 1);
+      const double dz = DIM == 3 ? periodic_disp(zi - pj[e].z, box, 2) : 0.0;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      // grad_i W_ij = 1/2 [W'(r,h_i) + W'(r,h_j)] x_ij / r
+      const double w = vj[e] * (ej[e] - Ei) * 0.5 *
+                       (sph_dwdr<DIM>(r, hi, kernel) + sph_dwdr<DIM>(r, pj[e].h, kernel)) / r;
+      gx += w * dx;
+      gy += w * dy;
+      gz += w * dz;
+    }
   }
+  gx = group_sum<G>(gx);
+  gy = group_sum<G>(gy);
+  if (DIM == 3) gz = group_sum<G>(gz);
+  if (lane != 0) return;
   const double R = sqrt(gx * gx + gy * gy + gz * gz) / (st[i] * Ei);
   double lam;
   if (limiter == RT_LIMITER_LARSEN) lam = pow(pow(3.0, lk) + pow(R, lk), -1.0 / lk);
@@ -277,14 +304,21 @@ int assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in, rt_m
   hipLaunchKernelGGL(k_frozen, dim3(grid_for(n)), dim3(kBlock), 0, st, n, nin, fa);
   RT_LAUNCH_CHECK();
   if (in->limiter != RT_LIMITER_NONE && nin > 0) {
-    if (nb->dim == 3)
-      hipLaunchKernelGGL(k_limiter<3>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
-                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p,
-                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p, nb->box);
-    else
-      hipLaunchKernelGGL(k_limiter<2>, dim3(grid_for(nin)), dim3(kBlock), 0, st, nin, n,
-                         nb->kernel, in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p,
-                         nb->idx.p, A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p, nb->box);
+    const int G = pick_group(nin ? (double)nb->npairs / (double)n : 0.0);
+    const int per = (grid_for(nin * (int64_t)G, kBlock) + kXcd - 1) / kXcd;
+    const int grid = per * kXcd;
+#define RT_LIM(D_, G_)                                                                      \
+  hipLaunchKernelGGL((k_limiter<D_, G_, 4>), dim3(grid), dim3(kBlock), 0, st, nin, nb->kernel, \
+                     in->limiter, in->limiter_k, in->c, nb->sp4.p, nb->ptr.p, nb->idx.p,      \
+                     A->V.p, A->Eall.p, sigt.p, A->D.p, A->VD.p, nb->box, per)
+    if (nb->dim == 3) {
+      if (G == 64) RT_LIM(3, 64); else if (G == 16) RT_LIM(3, 16);
+      else if (G == 8) RT_LIM(3, 8); else RT_LIM(3, 4);
+    } else {
+      if (G == 64) RT_LIM(2, 64); else if (G == 16) RT_LIM(2, 16);
+      else if (G == 8) RT_LIM(2, 8); else RT_LIM(2, 4);
+    }
+#undef RT_LIM
     RT_LAUNCH_CHECK();
   }
 
