@@ -82,11 +82,33 @@ def grad_E(prob, ptr, idx, E):
 
 
 def flux_limiter(R, kind: int, k: float):
+    """lambda(R) of Sec. 2.1: Larsen (3^k + R^k)^(-1/k), Levermore
+    (2 + R)/(6 + 3R + R^2).  Above R = 1 the Levermore quotient is evaluated
+    with u = 1/R, as u(1 + 2u)/(1 + 3u + 6u^2), which is the same function and
+    stays finite as R grows without bound (lambda -> 0, lambda R -> 1)."""
+    R = np.asarray(R, dtype=float)
     if kind == LIMITER_LARSEN:
         return (3.0 ** k + R ** k) ** (-1.0 / k)
     if kind == LIMITER_LEVERMORE:
-        return (2.0 + R) / (6.0 + 3.0 * R + R * R)
+        out = np.empty_like(R)
+        lo = R <= 1.0
+        out[lo] = (2.0 + R[lo]) / (6.0 + 3.0 * R[lo] + R[lo] * R[lo])
+        with np.errstate(divide="ignore"):
+            u = 1.0 / R[~lo]
+        out[~lo] = u * (1.0 + 2.0 * u) / (1.0 + 3.0 * u + 6.0 * u * u)
+        return out
     return np.full_like(R, 1.0 / 3.0)
+
+
+def limiter_ratio(grad_norm, sigma_t, E):
+    """R = |grad E| / (sigma_t E) (Sec. 2.1), with its two degenerate cases
+    fixed: no gradient gives R = 0 (the diffusion limit, also where E = 0),
+    and a gradient where E <= 0 gives R = infinity (the free-streaming limit)."""
+    g = np.asarray(grad_norm, dtype=float)
+    den = np.asarray(sigma_t * E, dtype=float)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        R = np.where(den > 0.0, g / np.where(den > 0.0, den, 1.0), np.inf)
+    return np.where(g == 0.0, 0.0, R)
 
 
 def frozen(prob, ptr, idx) -> Frozen:
@@ -98,7 +120,7 @@ def frozen(prob, ptr, idx) -> Frozen:
     lam = np.full(prob.n_total, 1.0 / 3.0)
     if prob.limiter != LIMITER_NONE:
         g = grad_E(prob, ptr, idx, prob.E)
-        R = np.sqrt(np.sum(g * g, axis=0)) / (sigma_t * prob.E)
+        R = limiter_ratio(np.sqrt(np.sum(g * g, axis=0)), sigma_t, prob.E)
         nin = prob.n_interior
         lam[:nin] = flux_limiter(R[:nin], prob.limiter, prob.limiter_k)
     D = prob.c * lam / sigma_t
@@ -186,8 +208,8 @@ def frozen_at(prob, ids, nbrs_of) -> dict:
             w = Vj * (prob.E[J] - prob.E[i]) * (-F)
             g = np.array([np.sum(w * disp(prob.pos, ax, I, J, prob.period))
                           for ax in range(prob.dim)])
-            R = np.sqrt(np.sum(g * g)) / (sigma_t * prob.E[i])
-            lam = float(flux_limiter(np.array([R]), prob.limiter, prob.limiter_k)[0])
+            R = limiter_ratio(np.sqrt(np.sum(g * g)), sigma_t, prob.E[i])
+            lam = float(flux_limiter(np.array([float(R)]), prob.limiter, prob.limiter_k)[0])
         out[i] = (sigma_a, f, V, prob.c * lam / sigma_t)
     return out
 

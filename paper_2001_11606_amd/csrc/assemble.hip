@@ -140,10 +140,20 @@ k_limiter(int64_t nin, int kernel, int limiter, double lk, double c,
   gy = group_sum<G>(gy);
   if (DIM == 3) gz = group_sum<G>(gz);
   if (lane != 0) return;
-  const double R = sqrt(gx * gx + gy * gy + gz * gz) / (st[i] * Ei);
+  // R = |grad E|/(sigma_t E); no gradient is the diffusion limit (R = 0, also
+  // where E = 0), a gradient where E <= 0 the free-streaming limit (R = inf)
+  const double gn = sqrt(gx * gx + gy * gy + gz * gz);
+  const double den = st[i] * Ei;
+  const double R = gn == 0.0 ? 0.0 : (den > 0.0 ? gn / den : INFINITY);
   double lam;
-  if (limiter == RT_LIMITER_LARSEN) lam = pow(pow(3.0, lk) + pow(R, lk), -1.0 / lk);
-  else lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  if (limiter == RT_LIMITER_LARSEN) {
+    lam = pow(pow(3.0, lk) + pow(R, lk), -1.0 / lk);
+  } else if (R <= 1.0) {
+    lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  } else {   // the same quotient in u = 1/R, finite for any R
+    const double u = 1.0 / R;
+    lam = u * (1.0 + 2.0 * u) / (1.0 + 3.0 * u + 6.0 * u * u);
+  }
   D[i] = c * lam / st[i];
   VD[2 * i + 1] = D[i];
 }

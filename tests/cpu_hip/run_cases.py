@@ -16,7 +16,7 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import synth  # noqa: E402
 from oracle import linsolve, neighbors, step as ostep  # noqa: E402
-from gpu_common import _wendland, oracle_system, rowwise_rel_err  # noqa: E402
+from gpu_common import _cold_patch, _limited, _wendland, oracle_system, rowwise_rel_err  # noqa: E402
 from paper_2001_11606_amd import rt  # noqa: E402
 
 FIELDS = ("m", "rho", "cv", "sigma0_a", "sigma_s", "e", "E", "Q_e", "Q_E")
@@ -251,6 +251,10 @@ def main():
         "levermore3d_8": _levermore(synth.config3(n=8)),
         "wendland2d_12": _wendland(2, 12),
         "wendland3d_6": _wendland(3, 6),
+        "levermore2d_16": _limited(synth.config1(n=16), synth.LIMITER_LEVERMORE),
+        "larsen_wendland2d_12": _limited(_wendland(2, 12), synth.LIMITER_LARSEN),
+        "levermore_wendland3d_6": _limited(_wendland(3, 6), synth.LIMITER_LEVERMORE),
+        "coldpatch3d_8": _cold_patch(8),
         "periodic2d_16": synth.periodic_wendland(2, 16),
         "marshak3d_8": synth.config4(n=8),
         "ensemble2d": synth.config5_member(0, 400.0),

@@ -20,6 +20,25 @@ def _levermore(prob):
     return prob
 
 
+def _limited(prob, kind, k=2.0):
+    """A workload with the flux limiter of Sec. 2.1 switched on (kind: Larsen
+    or Levermore), so that the limiter's gradient runs on its row lengths and
+    dimension."""
+    prob.limiter = kind
+    prob.limiter_k = k
+    return prob
+
+
+def _cold_patch(n):
+    """The density-step recipe with the Levermore limiter and E = 0 on the
+    particles with x < 0.3: inside the patch the gradient vanishes (R = 0,
+    the diffusion limit), on its edge it does not while E = 0 (R infinite,
+    the free-streaming limit)."""
+    prob = _levermore(synth.config3(n=n))
+    prob.E = np.where(prob.pos[0] < 0.3, 0.0, prob.E)
+    return prob
+
+
 def _wendland(dim, n):
     """The paper's Wendland kernel at h = 4 spacings (synth.wendland_lattice)."""
     return synth.wendland_lattice(dim, n)
@@ -56,6 +75,10 @@ def small_cases():
         "periodic2d_16": lambda: synth.periodic_wendland(2, 16),
         "periodic3d_13": lambda: synth.periodic_wendland(3, 13),
         "periodicx_ghostsy2d_32": lambda: _periodic_x_ghosts_y(32),
+        "mms2d_32_levermore": lambda: _limited(synth.config1(n=32), synth.LIMITER_LEVERMORE),
+        "wendland2d_24_larsen": lambda: _limited(_wendland(2, 24), synth.LIMITER_LARSEN),
+        "wendland3d_9_levermore": lambda: _limited(_wendland(3, 9), synth.LIMITER_LEVERMORE),
+        "densitystep3d_12_coldpatch": lambda: _cold_patch(12),
         "marshak3d_16": lambda: synth.config4(n=16),
         "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
         "ensemble2d": lambda: synth.config5_member(0, 2500.0),

@@ -138,6 +138,57 @@ def test_matrix_with_ghosts_matches_pair_sum():
     assert np.allclose(lhs, direct, rtol=1e-12, atol=1e-12 * np.abs(direct).max())
 
 
+# Lattice-sum factor C(eta) = -(1/d) sum_{j != i} V_j W'(r_ij) r_ij of the
+# cubic spline on an unjittered lattice at the configurations' own smoothing
+# lengths (2-D h = 1.3 spacings, 3-D h = 1.2), evaluated to 30 digits by
+# summing the closed-form kernel derivative over the lattice offsets.
+LATTICE_C = {(2, 1.3): 1.0105429572533936, (3, 1.2): 0.98168856707997002}
+
+
+@pytest.mark.parametrize("dim,eta", sorted(LATTICE_C))
+def test_lattice_constant_at_config_eta(dim, eta):
+    """<d(k d|x|^2)> at an interior lattice point is 2 d k C(eta) exactly (up to
+    rounding): pins sigma_d, W' and the 1/2 of the symmetrised gradient at the
+    smoothing lengths the workloads use, to 1e-12."""
+    n = 12 if dim == 3 else 20
+    p = _lattice_problem(dim, n, eta)
+    ptr, idx = neighbors.build(p.pos, p.h, 2.0)
+    c = _center(p, n)
+    Lr2 = operator.brookshaw(p, ptr, idx, np.ones(p.n_total), np.sum(p.pos ** 2, axis=0))
+    C = Lr2[c] / (2.0 * dim)
+    assert abs(C - LATTICE_C[(dim, eta)]) < 1e-12 * LATTICE_C[(dim, eta)], C
+
+
+def test_levermore_between_limits():
+    """Levermore's lambda = (2 + R)/(6 + 3R + R^2) (Sec. 2.1) at hand-evaluated
+    points between its limits, and its large-R form without overflow."""
+    lev = lambda R: operator.flux_limiter(np.array([R], float), operator.LIMITER_LEVERMORE, 0.0)[0]
+    assert lev(1.0) == pytest.approx(3.0 / 10.0, rel=1e-15)
+    assert lev(2.0) == pytest.approx(1.0 / 4.0, rel=1e-15)
+    assert lev(3.0) == pytest.approx(5.0 / 24.0, rel=1e-15)
+    assert lev(0.5) == pytest.approx(2.5 / 7.75, rel=1e-15)
+    assert lev(10.0) == pytest.approx(12.0 / 136.0, rel=1e-15)
+    # far beyond where R^2 overflows: lambda R -> 1, lambda(inf) = 0
+    assert lev(1e200) * 1e200 == pytest.approx(1.0, rel=1e-12)
+    assert lev(np.inf) == 0.0
+    # continuous across the switch to the reciprocal form at R = 1
+    assert lev(np.nextafter(1.0, 2.0)) == pytest.approx(lev(1.0), rel=1e-15)
+    # Larsen k = 2 at R = 4: 1/5
+    assert operator.flux_limiter(np.array([4.0]), operator.LIMITER_LARSEN, 2.0)[0] == \
+        pytest.approx(0.2, rel=1e-15)
+
+
+def test_limiter_ratio_degenerate_cases():
+    """R = |grad E|/(sigma_t E): zero gradient is the diffusion limit (also at
+    E = 0), a gradient at E = 0 the free-streaming limit."""
+    R = operator.limiter_ratio(np.array([0.0, 0.0, 2.0, 3.0]), np.array([1.0, 1.0, 1.0, 2.0]),
+                               np.array([1.0, 0.0, 0.0, 0.5]))
+    assert R[0] == 0.0 and R[1] == 0.0 and np.isinf(R[2]) and R[3] == 3.0
+    for kind in (operator.LIMITER_LARSEN, operator.LIMITER_LEVERMORE):
+        lam = operator.flux_limiter(R, kind, 2.0)
+        assert lam[0] == pytest.approx(1.0 / 3.0) and lam[2] == 0.0 and np.all(np.isfinite(lam))
+
+
 def test_flux_limiter_limits():
     R = np.array([0.0, 1e-8, 1e6])
     for kind, k in ((operator.LIMITER_LARSEN, 2.0), (operator.LIMITER_LARSEN, 3.0),
