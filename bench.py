@@ -33,6 +33,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# The timed solve: Jacobi-preconditioned CG, stopped when ||b - A x|| <= 1e-10
+# ||b|| and max_i |b - A x|_i / (a_ii |x_i|) <= 1e-10 (every particle's E to
+# about 1e-10 relative, also far ahead of the front); mixed precision asks each
+# FP32 inner solve for a reduction of 1e-4.  Five outer iterations per step.
+BENCH_TOL = 1e-10
+BENCH_CW_TOL = 1e-10
+BENCH_INNER_TOL = 1e-4
+BENCH_OUTER = 5
+
+
+def bench_solve_opts(precision, precond=0, tol=BENCH_TOL, cw_tol=BENCH_CW_TOL,
+                     inner_tol=BENCH_INNER_TOL):
+    from paper_2001_11606_amd import rt
+    return rt.solve_opts(precision, precond, tol, 5000, inner_tol, 30, cw_tol)
+
+
 METRIC = "diffusion solve particle-updates/s + SpMV HBM GB/s; mixed vs FP64 @1e-10"
 
 
@@ -51,14 +68,12 @@ def make_problem(workload: str, n: int):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def run_step(ctx, dp, precision, precond, outer, tol, amg, shapes=None, inner_tol=1e-4):
+def run_step(ctx, dp, solve, outer, amg, shapes=None):
     """One pass of the whole hot path; returns (e, E, A, report, nb)."""
-    from paper_2001_11606_amd import driver, rt
+    from paper_2001_11606_amd import driver
     nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
-    e, E, A, rep = driver.time_step(ctx, dp, nb, amg=amg,
-                                    solve=rt.solve_opts(precision, precond, tol, 5000, inner_tol,
-                                                        30),
-                                    fixed_outer=outer, shapes=shapes)
+    e, E, A, rep = driver.time_step(ctx, dp, nb, amg=amg, solve=solve, fixed_outer=outer,
+                                    shapes=shapes)
     return e, E, A, rep, nb
 
 
@@ -79,6 +94,18 @@ def spmv_bytes(vbytes: int, nnz_off: int, n: int, tile_cols: int) -> float:
     else:
         idx = 4.0 * nnz_off
     return vbytes * nnz_off + idx + 8.0 * (n + 1) + 3.0 * vbytes * n
+
+
+def resid_bytes(nnz_off: int, n: int, tile_cols: int, with_w32: bool) -> float:
+    """Algorithmic bytes of one FP64 residual product r = b - A x of the
+    refinement loop: FP64 values and 16-bit tile-local columns (or 32-bit
+    columns untiled) per off-diagonal entry, the tiles' column lists, row
+    pointers, and per row the diagonal, x and b read, r written in FP64 and
+    in FP32 (the inner solve's right-hand side), and the FP32 weights of the
+    componentwise test when it is on."""
+    idx = (2.0 * nnz_off + 4.0 * tile_cols) if tile_cols else 4.0 * nnz_off
+    per_row = 8.0 * 4 + 4.0 + (4.0 if with_w32 else 0.0)
+    return 8.0 * nnz_off + idx + 8.0 * (n + 1) + per_row * n
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_spmv_tiled_marshak3d_16.8M_counters.md")
@@ -125,20 +152,53 @@ def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
     return 2.0 * nbytes / sec / 1e9
 
 
-def cpu_baseline(workload: str, n_sample: int, outer: int):
+def host_cpu():
+    """(logical CPUs this process may run on, CPU model name)."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return ncpu, model
+
+
+def cpu_baseline(workload: str, n_sample: int, outer: int, tol: float, cw_tol: float):
     """The oracle (plain FP64 numpy/scipy) on a smaller instance of the recipe,
-    with BLAS/OpenMP pools held to one thread."""
+    its linear solves to the bench's tolerances: once with BLAS/OpenMP pools
+    held to one thread, once with every pool free to use all host CPUs.  The
+    all-CPU leg's `cores` is what it used: process CPU time over wall time
+    (numpy's element-wise and scipy's sparse kernels run on one thread, so it
+    stays near one)."""
     from threadpoolctl import threadpool_limits
-    from oracle import step as ostep
-    prob = make_problem(workload, n_sample)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        ostep.time_step(prob, fixed_outer=outer, solve_tol=1e-10)
-        dt = time.perf_counter() - t0
-    return {"value": prob.n_interior * outer / dt, "unit": "particle-updates/s", "cores": 1,
+    from oracle import linsolve, step as ostep
+    solver = lambda A, b, x0: linsolve.solve(A, b, x0, max(tol, cw_tol))
+    legs = {}
+    for name, limit in (("one_core", 1), ("all_cores", None)):
+        prob = make_problem(workload, n_sample)
+        with threadpool_limits(limits=limit):
+            c0, t0 = time.process_time(), time.perf_counter()
+            ostep.time_step(prob, fixed_outer=outer, solver=solver)
+            wall = time.perf_counter() - t0
+            cpu = time.process_time() - c0
+        legs[name] = (prob.n_interior * outer / wall, wall, cpu / wall)
+    ncpu, model = host_cpu()
+    best = max(legs, key=lambda k: legs[k][0])
+    v, wall, used = legs[best]
+    return {"value": v, "unit": "particle-updates/s",
+            "cores": 1 if best == "one_core" else max(1, round(used, 1)),
             "kind": "oracle",
             "sample": f"{workload} recipe at n={n_sample} ({prob.n_interior} interior particles), "
-                      f"one time step with {outer} outer iterations, {dt:.1f} s"}
+                      f"one time step with {outer} outer iterations, {wall:.1f} s",
+            "legs": {k: {"value": round(lv[0], 1), "wall_s": round(lv[1], 2),
+                         "cpu_time_over_wall": round(lv[2], 2)} for k, lv in legs.items()},
+            "host_cpus": ncpu, "cpu_model": model}
 
 
 def run_ensemble(args):
@@ -345,6 +405,77 @@ def run_coswave(args):
     ctx.close()
 
 
+def run_config2(args):
+    """The 3-D manufactured problem of the 64^3 configuration: ten time steps
+    of inexact Newton with nonlinear elimination (outer iterations until both
+    relative changes are below 1e-8), every diffusion solve AMG-preconditioned
+    CG in FP64 to 1e-10 (normwise and componentwise), sources and ghost values
+    of the manufactured solution loaded before every step.  The neighbour
+    lists are built once (the particles do not move); every step re-assembles
+    the matrix and its hierarchy.  value = interior particles x outer
+    iterations / wall time of the ten steps."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2001_11606_amd import driver, rt
+    ctx = rt.Context(0)
+    prob = synth.config2_mms(n=args.n)
+    nin = prob.n_interior
+    precond = args.precond
+    amg = rt.amg_opts(max_levels=8 if precond == 1 else 1, build_fp32=0)
+    solve = rt.solve_opts(0, precond, args.tol, 5000, args.inner_tol, 30, args.cw_tol)
+
+    def run(steps):
+        dp = driver.upload(prob, ctx.device)
+        host = prob.copy()
+        nb = ctx.build_neighbors(dp.pos, dp.h, nin, prob.kernel)
+        A, reps = 0, []
+        for s in range(steps):
+            host.set_time((s + 1) * prob.dt)
+            for k in ("Q_e", "Q_E"):
+                dp.arrays[k].copy_(torch.as_tensor(getattr(host, k)))
+            for k in ("e", "E"):
+                dp.arrays[k][nin:] = torch.as_tensor(getattr(host, k)[nin:])
+            e, E, A, rep = driver.time_step(ctx, dp, nb, A=A, amg=amg, solve=solve, eps_e=1e-8,
+                                            eps_E=1e-8, material_tol=1e-14)
+            driver.advance(dp, e, E)
+            reps.append(rep)
+        torch.cuda.synchronize()
+        return reps, dp
+
+    for w in range(max(1, args.warmup)):
+        log(f"[bench] config2 warmup run {w}")
+        run(2)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps, dp = run(args.steps)
+    wall = time.perf_counter() - t0
+    outer = sum(r.outer for r in reps)
+    nm = prob.copy()
+    nm.set_time(args.steps * prob.dt)
+    em, Em = nm.mms(args.steps * prob.dt)[:2]
+    E = dp.arrays["E"][:nin].cpu().numpy()
+    e = dp.arrays["e"][:nin].cpu().numpy()
+    out = {
+        "metric": METRIC, "value": nin * outer / wall, "unit": "particle-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config2 manufactured {args.n}^3 ({nin} particles, "
+                               f"{prob.n_ghost} ghosts), {args.steps} steps dt={prob.dt}, outer "
+                               f"to 1e-8, FP64 CG + {('Jacobi', 'AMG')[precond]} to "
+                               f"{args.tol:g} (componentwise {args.cw_tol:g})",
+                   "particles": nin, "precond": ("jacobi", "amg")[precond]},
+        "outer_per_step": [r.outer for r in reps],
+        "krylov_per_solve": [k for r in reps for k in r.krylov],
+        "l1_rel_err_vs_exact": {"e": float(np.sum(np.abs(e - em[:nin])) / np.sum(em[:nin])),
+                                "E": float(np.sum(np.abs(E - Em[:nin])) / np.sum(Em[:nin]))},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,15 +483,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="marshak3d")
     ap.add_argument("--n", type=int, default=256, help="particles per axis")
-    ap.add_argument("--outer", type=int, default=5)
-    ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--precond", type=int, default=0, help="0 Jacobi, 1 AMG V-cycle")
-    ap.add_argument("--inner-tol", type=float, default=1e-4,
+    ap.add_argument("--outer", type=int, default=BENCH_OUTER)
+    ap.add_argument("--tol", type=float, default=BENCH_TOL, help="normwise solve tolerance")
+    ap.add_argument("--cw-tol", type=float, default=BENCH_CW_TOL,
+                    help="componentwise solve tolerance (0: normwise test only)")
+    ap.add_argument("--precond", type=int, default=None,
+                    help="0 Jacobi, 1 AMG V-cycle (default: 1 for config2, else 0)")
+    ap.add_argument("--inner-tol", type=float, default=BENCH_INNER_TOL,
                     help="relative reduction asked of each FP32 inner solve")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--mixed", action="store_true",
                     help="coswave3d: FP32 inner CG with FP64 refinement instead of FP64 CG")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-densitystep", action="store_true",
+                    help="marshak3d: skip the mixed-vs-FP64 leg on the density-step recipe")
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--nprob", type=int, default=96, help="ensemble: number of problems")
     ap.add_argument("--scale", type=float, default=1.0, help="ensemble: size factor")
@@ -371,6 +507,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default SpMV shapes instead of tuning them during warm-up")
     args = ap.parse_args()
+    if args.precond is None:
+        args.precond = 1 if args.workload == "config2" else 0
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); this build has no "
@@ -387,6 +525,77 @@ def main():
     if args.workload in ("coswave3d", "coswave2d"):
         run_coswave(args)
         return
+    if args.workload == "config2":
+        if args.n == 256:
+            args.n = 64
+        run_config2(args)
+        return
+    run_single(args)
+
+
+def _fp64_reference(ctx, dp, outer, amg):
+    """The same step solved to 1e-14 in both measures in FP64: the reference of
+    the accuracy figures."""
+    from paper_2001_11606_amd import rt
+    e, E, A, rep, nb = run_step(ctx, dp, rt.solve_opts(0, 0, 1e-14, 20000, 1e-4, 60, 1e-14),
+                                outer, amg)
+    release(ctx, nb, A)
+    return e, E
+
+
+def _max_rel(a, ref):
+    return float(((a - ref).abs() / ref.abs()).max())
+
+
+def _kernel_roof(name, nbytes, calls, seconds):
+    if not calls:
+        return None
+    us = 1e6 * seconds / calls
+    gbs = nbytes / (seconds / calls) / 1e9
+    return {"kernel": name, "bytes_per_launch": nbytes, "avg_launch_us": round(us, 2),
+            "launches": calls, "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "device_ms": round(1e3 * seconds, 3)}
+
+
+def densitystep_leg(ctx, args, steps=3):
+    """Mixed against FP64 on the density-step recipe at 128^3 (2,097,152
+    particles, tens of Krylov iterations per solve), same options as the main
+    workload: mean solve time per step of each, and both results' largest
+    relative difference from the 1e-14 FP64 step."""
+    import torch
+    from paper_2001_11606_amd import driver, rt
+    prob = make_problem("densitystep3d", 128)
+    dp = driver.upload(prob, ctx.device)
+    amg = rt.amg_opts(max_levels=1, build_fp32=1)
+    out = {"workload": f"densitystep3d 128^3 ({prob.n_interior} particles), {args.outer} outer "
+                       f"iterations, Jacobi, tol {args.tol:g}, componentwise {args.cw_tol:g}"}
+    eR, ER = _fp64_reference(ctx, dp, args.outer, amg)
+    res = {}
+    for prec, key in ((rt.RT_PREC_MIXED, "mixed"), (rt.RT_PREC_FP64, "fp64")):
+        solve = bench_solve_opts(prec, 0, args.tol, args.cw_tol, args.inner_tol)
+        e, E, A, rep, nb = run_step(ctx, dp, solve, args.outer, amg)   # warm-up
+        release(ctx, nb, A)
+        t = []
+        for _ in range(steps):
+            e, E, A, rep, nb = run_step(ctx, dp, solve, args.outer, amg)
+            t.append(rep.solve_seconds)
+            release(ctx, nb, A)
+        torch.cuda.synchronize()
+        res[key] = sum(t) / len(t)
+        out[f"solve_s_{key}"] = round(res[key], 5)
+        out[f"krylov_{key}"] = rep.krylov
+        out[f"max_rel_err_E_{key}"] = _max_rel(E, ER)
+        out[f"max_rel_err_e_{key}"] = _max_rel(e, eR)
+    out["ratio_fp64_over_mixed"] = round(res["fp64"] / res["mixed"], 3)
+    del dp
+    return out
+
+
+def run_single(args):
+    """One problem (marshak3d, densitystep3d or wendland3d), the whole path
+    per step; see the module docstring."""
+    import torch
+    from paper_2001_11606_amd import driver, rt
     log(f"[bench] generating {args.workload} n={args.n}")
     t0 = time.perf_counter()
     prob = make_problem(args.workload, args.n)
@@ -398,27 +607,28 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = copy_bandwidth()
     log(f"[bench] stream copy {copy_gbs:.0f} GB/s")
+    solve32 = bench_solve_opts(rt.RT_PREC_MIXED, args.precond, args.tol, args.cw_tol,
+                               args.inner_tol)
+    solve64 = bench_solve_opts(rt.RT_PREC_FP64, args.precond, args.tol, args.cw_tol,
+                               args.inner_tol)
 
     shapes = None
     tune = None
 
-    def one(precision, profile=False):
+    def one(solve, profile=False):
         ctx.set_profiling(profile)
-        out = run_step(ctx, dp, precision, args.precond, args.outer, args.tol, amg, shapes,
-                       args.inner_tol)
+        out = run_step(ctx, dp, solve, args.outer, amg, shapes)
         ctx.set_profiling(False)
         return out
 
     for w in range(args.warmup):
         log(f"[bench] warmup step {w}")
-        e, E, A, rep, nb = one(rt.RT_PREC_MIXED)
+        e, E, A, rep, nb = one(solve32)
         if w == 0 and not args.no_tune:
             # SpMV shapes are tuned once per problem, outside the timed region
             tune = ctx.tune(A, reps=5)
             shapes = tune["chosen"]
             log(f"[bench] tuned SpMV shapes {[(tune['shapes'][a], tune['shapes'][b]) for a, b in shapes]}")
-            log(f"[bench] level-0 us per shape fp64 {[round(t, 1) for t in tune['us'][0][0]]}")
-            log(f"[bench] level-0 us per shape fp32 {[round(t, 1) for t in tune['us'][0][1]]}")
         release(ctx, nb, A)
     torch.cuda.synchronize()
 
@@ -427,7 +637,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        e, E, A, rep, nb = one(rt.RT_PREC_MIXED, profile=True)
+        e, E, A, rep, nb = one(solve32, profile=True)
         reps.append(rep)
         info = ctx.matrix_info(A)
         if s + 1 < args.steps:
@@ -439,50 +649,62 @@ def main():
     value = nin * args.outer * args.steps / elapsed
     log(f"[bench] {ms_step:.1f} ms/step, krylov {reps[-1].krylov}, refinements "
         f"{reps[-1].refinements}, status {reps[-1].status}")
+    release(ctx, nb, A)
 
-    # SpMV roofline (FP32 inner SpMV, the operator of the mixed solve)
+    # per-kernel rooflines of the products, from the HIP events of the timed steps
     n_rows = info.n
     nnz_off = info.nnz - info.n
     tile_cols = info.level_tile_cols[0]
-    shape32 = tune["shapes"][shapes[0][1]] if shapes else None
-    tiled32 = bool(tile_cols) and (shape32 is None or shape32[2])
-    calls32 = sum(r.spmv32_calls for r in reps)
-    sec32 = sum(r.spmv32_seconds for r in reps)
-    bytes32 = spmv_bytes(4, nnz_off, n_rows, tile_cols if tiled32 else 0)
+    sh = tune["shapes"] if tune else None
+    s64, s32 = (shapes[0] if shapes else (None, None))
+    tiled32 = bool(tile_cols) and (sh is None or sh[s32][2])
+    tiled64 = bool(tile_cols) and (sh is None or sh[s64][2])
+    k32 = (("k_spmv_tiled<float, %d, %d, SP_DOT>" % tuple(sh[s32][:2])) if tiled32 and sh
+           else "k_spmv_tiled<float> (default shape)" if tiled32 else "k_spmv<float> (plain CSR)")
+    k64r = (("k_spmv_tiled<double, %d, %d, SP_RESID>" % tuple(sh[s64][:2])) if tiled64 and sh
+            else "k_spmv_tiled<double> SP_RESID" if tiled64 else "k_spmv<double> SP_RESID")
+    roof32 = _kernel_roof(k32, spmv_bytes(4, nnz_off, n_rows, tile_cols if tiled32 else 0),
+                          sum(r.spmv32_calls for r in reps), sum(r.spmv32_seconds for r in reps))
+    roof_res = _kernel_roof(k64r, resid_bytes(nnz_off, n_rows, tile_cols if tiled64 else 0,
+                                              args.cw_tol > 0),
+                            sum(r.resid_calls for r in reps), sum(r.resid_seconds for r in reps))
+    kernels = [k for k in (roof_res, roof32) if k]
     roof = None
-    if calls32:
-        achieved = bytes32 / (sec32 / calls32) / 1e9
-        kname = (("k_spmv_tiled<float, %d, %d, SP_DOT>" % (shape32[0], shape32[1]))
-                 if tiled32 and shape32 else "k_spmv<float> (plain CSR)")
-        traffic, traffic_req = profiled_traffic(args.workload, args.n, kname)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "traffic_rdreq128": traffic_req,
-                "stream_copy_gbs": round(copy_gbs, 1),
-                "kernel": kname,
-                "bytes_per_launch": bytes32, "avg_launch_us": round(1e6 * sec32 / calls32, 2),
-                "launches": calls32, "tile_cols": tile_cols}
+    if kernels:
+        dom = max(kernels, key=lambda k: k["device_ms"])   # most device time per step
+        traffic, traffic_req = profiled_traffic(args.workload, args.n, dom["kernel"])
+        roof = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["frac"], "traffic": traffic, "traffic_rdreq128": traffic_req,
+                "kernel": dom["kernel"], "bytes_per_launch": dom["bytes_per_launch"],
+                "avg_launch_us": dom["avg_launch_us"], "launches": dom["launches"],
+                "stream_copy_gbs": round(copy_gbs, 1), "tile_cols": tile_cols,
+                "kernels": kernels}
     solve_mixed = sum(r.solve_seconds for r in reps) / len(reps)
-    release(ctx, nb, A)
 
     cmp = None
     if not args.no_fp64:
-        log("[bench] FP64 comparison step")
-        e64, E64, A64, rep64, nb64 = one(rt.RT_PREC_FP64, profile=True)
+        log("[bench] FP64 comparison step and the 1e-14 reference")
+        e64, E64, A64, rep64, nb64 = one(solve64, profile=True)
+        release(ctx, nb64, A64)
+        eR, ER = _fp64_reference(ctx, dp, args.outer, amg)
         torch.cuda.synchronize()
-        err_E = float(((E64 - E).abs() / E64.abs()).max())
-        err_e = float(((e64 - e).abs() / e64.abs()).max())
-        shape64 = tune["shapes"][shapes[0][0]] if shapes else None
-        tiled64 = bool(tile_cols) and (shape64 is None or shape64[2])
-        bytes64 = spmv_bytes(8, nnz_off, n_rows, tile_cols if tiled64 else 0)
         cmp = {"solve_s_mixed": round(solve_mixed, 5), "solve_s_fp64": round(rep64.solve_seconds, 5),
                "ratio_fp64_over_mixed": round(rep64.solve_seconds / max(solve_mixed, 1e-12), 3),
                "krylov_mixed": reps[-1].krylov, "krylov_fp64": rep64.krylov,
-               "max_rel_diff_E": err_E, "max_rel_diff_e": err_e}
-        if rep64.spmv64_calls:
-            a64 = bytes64 / (rep64.spmv64_seconds / rep64.spmv64_calls) / 1e9
-            cmp["spmv64_gbs"] = round(a64, 1)
-        release(ctx, nb64, A64)
+               "refinements_mixed": reps[-1].refinements,
+               "max_rel_err_E_mixed": _max_rel(E, ER), "max_rel_err_e_mixed": _max_rel(e, eR),
+               "max_rel_err_E_fp64": _max_rel(E64, ER), "max_rel_err_e_fp64": _max_rel(e64, eR),
+               "reference": "the same step in FP64 to 1e-14, normwise and componentwise"}
+        k64 = (("k_spmv_tiled<double, %d, %d, SP_DOT>" % tuple(sh[s64][:2])) if tiled64 and sh
+               else "FP64 SP_DOT product")
+        r64 = _kernel_roof(k64, spmv_bytes(8, nnz_off, n_rows, tile_cols if tiled64 else 0),
+                           rep64.spmv64_calls, rep64.spmv64_seconds)
+        if r64:
+            cmp["fp64_cg_product"] = r64
+    c3 = None
+    if args.workload == "marshak3d" and not args.no_densitystep:
+        log("[bench] density-step leg (mixed vs FP64 at 128^3)")
+        c3 = densitystep_leg(ctx, args)
 
     # phase breakdown (one extra, synchronised step; not part of the timed region)
     log("[bench] phase breakdown step")
@@ -493,17 +715,16 @@ def main():
     t2 = time.perf_counter()
     Ab = ctx.assemble(nbb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                       dp.limiter_k, amg=amg)
-    for lvl, (s64, s32) in enumerate((shapes or [])[:ctx.matrix_info(Ab).levels]):
-        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_FP64, s64)
-        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_MIXED, s32)
+    for lvl, (a64, a32) in enumerate((shapes or [])[:ctx.matrix_info(Ab).levels]):
+        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_FP64, a64)
+        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_MIXED, a32)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     eb = torch.empty(nin, dtype=torch.float64, device=ctx.device)
     Eb = torch.empty_like(eb)
     rt.rt_to_sorted(ctx.handle, nbb.handle, dp.arrays["e"].data_ptr(), eb.data_ptr())
     rt.rt_to_sorted(ctx.handle, nbb.handle, dp.arrays["E"].data_ptr(), Eb.data_ptr())
-    nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, args.precond, args.tol, 5000,
-                                         args.inner_tol, 30), state_order=1)
+    nopts = rt.newton_opts(solve32, state_order=1)
     solve_b = 0.0
     for ell in range(args.outer):
         _, stb = ctx.newton_step(Ab, eb, Eb, ell, nopts)
@@ -515,23 +736,28 @@ def main():
               "of_which_solves_ms": round(1e3 * solve_b, 2)}
     release(ctx, nbb, Ab)
     log(f"[bench] phases {phases}")
+    solve_rate = nin * args.outer / (solve_mixed if solve_mixed > 0 else float("inf"))
 
     cpu = None
     if not args.no_cpu:
         log(f"[bench] CPU oracle baseline at n={args.cpu_n}")
-        cpu = cpu_baseline(args.workload, args.cpu_n, args.outer)
+        cpu = cpu_baseline(args.workload, args.cpu_n, args.outer, args.tol, args.cw_tol)
 
+    rule = (f"mixed FP32/FP64 to ||r|| <= {args.tol:g} ||b|| and max_i |r_i|/(a_ii |x_i|) <= "
+            f"{args.cw_tol:g} (inner {args.inner_tol:g})")
     out = {
         "metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {args.n}^3 ({nin} particles, {prob.n_ghost} ghosts), "
-                               f"1 step dt={prob.dt}, {args.outer} outer iterations, "
-                               f"mixed FP32/FP64 to {args.tol:g} (inner {args.inner_tol:g})",
+                               f"1 step dt={prob.dt}, {args.outer} outer iterations, {rule}",
                    "particles": nin, "nnz": info.nnz, "amg_levels": info.levels,
-                   "precond": "amg" if args.precond == 1 else "jacobi"},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp, "phases": phases,
+                   "precond": "amg" if args.precond == 1 else "jacobi",
+                   "tol": args.tol, "cw_tol": args.cw_tol, "inner_tol": args.inner_tol},
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp,
+        "mixed_vs_fp64_densitystep3d": c3, "phases": phases,
+        "solve_particle_updates_per_s": solve_rate,
         "spmv_tune": None if tune is None else {
             "shapes_g_e": tune["shapes"], "chosen": tune["chosen"],
             "level0_us_fp64": [round(t, 1) for t in tune["us"][0][0]],

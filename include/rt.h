@@ -261,14 +261,22 @@ int rt_matrix_set_spmv_shape(rt_matrix* A, int level, int precision, int shape);
 
 /* ---- linear solve (Sec. 3.2, the D^-1 operator) ---------------------------
  * Solves A x = b (the V-scaled system above) by preconditioned CG, stopping
- * when ||b - A x||_2 <= tol ||b||_2 evaluated in FP64.  b, x: n_interior
- * doubles, user order, device; x is the initial guess on entry (the paper
- * warm-starts with E^l) and the solution on return.
+ * when ||b - A x||_2 <= tol ||b||_2 evaluated in FP64 and, if cw_tol > 0,
+ * also max_i |b - A x|_i / (a_ii |x_i|) <= cw_tol (componentwise test: the
+ * largest relative change one Jacobi sweep would make to an unknown; a row
+ * with x_i = 0 passes only with a zero residual).  The normwise test alone
+ * does not bound the relative error of unknowns far below the largest one
+ * (E over several decades); the componentwise test does, up to the factor
+ * 1/(1 - rho) of the off-diagonal row sums rho relative to a_ii.
+ * b, x: n_interior doubles, user order, device; x is the initial guess on
+ * entry (the paper warm-starts with E^l) and the solution on return.
  * precond: 0 = Jacobi, 1 = AMG V-cycle (falls back to Jacobi when the
  * hierarchy has one level).  RT_PREC_MIXED runs FP32 PCG on the correction
  * equation A d = r to inner_tol, adds d in FP64 and recomputes r = b - A x in
- * FP64, until tol.  Returns RT_NOT_CONVERGED (stats valid) if max_iter
- * (total inner iterations) is exhausted.                                     */
+ * FP64, until tol (and cw_tol).  Returns RT_NOT_CONVERGED (stats valid) if
+ * max_iter (total inner iterations) or max_refine is exhausted.
+ * Errors: RT_E_ARG (unknown precision or precond, tol < 0, cw_tol < 0 or NaN,
+ * max_iter < 0, MIXED with inner_tol outside (0, 1)).                       */
 typedef struct {
   int precision;
   int precond;
@@ -276,6 +284,7 @@ typedef struct {
   int max_iter;
   double inner_tol;
   int max_refine;
+  double cw_tol;         /* componentwise tolerance; 0 = normwise test only   */
 } rt_solve_opts;
 
 typedef struct {
@@ -287,10 +296,15 @@ typedef struct {
   double spmv_seconds;     /* their summed device time                       */
   int spmv32_calls;
   double spmv32_seconds;
+  double cw_residual;      /* final max_i |b - A x|_i / (a_ii |x_i|): from an
+                              FP64 product (MIXED) or the CG recursion (FP64) */
+  int resid_calls;         /* FP64 residual products b - A x timed (profiling on) */
+  double resid_seconds;
 } rt_solve_stats;
 
 int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
              const rt_solve_opts* opts, rt_solve_stats* stats);
+
 
 /* ---- one outer iteration of Algorithm 1 ------------------------------------
  * e, E: n_interior doubles, user order, device, holding the iterate
@@ -382,7 +396,7 @@ int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
  * per-particle data of the Newton step; each problem keeps its own dt, c, a.
  * The batch copies what it needs: the matrices may be freed afterwards; after
  * re-assembling them, create a new batch.  Solves use Jacobi-preconditioned
- * CG (precond must be 0) with per-problem Krylov scalars and per-problem
+ * CG (precond must be 0; cw_tol must be 0) with per-problem Krylov scalars and per-problem
  * convergence: a problem that meets its tolerance stops while the others go
  * on.  graph_iters > 0 replays HIP graphs of that many PCG iterations between
  * host reads of the convergence flags (extra iterations of finished problems

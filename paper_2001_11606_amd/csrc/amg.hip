@@ -412,7 +412,7 @@ static int cheb_smooth(hipStream_t st, rt_matrix* A, Level& L, int degree, const
   const T* r0 = b;   // residual of the zero start
   if (xin) {
     RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), xin, b, nullptr, r,
-                                             nullptr, A->partB.p, nullptr, level_shape<T>(L),
+                                             nullptr, nullptr, nullptr, level_shape<T>(L),
                                              nullptr, stop)));
     r0 = r;
   }
@@ -421,7 +421,7 @@ static int cheb_smooth(hipStream_t st, rt_matrix* A, Level& L, int degree, const
   RT_LAUNCH_CHECK();
   for (int k = 1; k < degree; ++k) {
     RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), x, b, nullptr, r,
-                                             nullptr, A->partB.p, nullptr, level_shape<T>(L),
+                                             nullptr, nullptr, nullptr, level_shape<T>(L),
                                              nullptr, stop)));
     const double rho_next = 1.0 / (2.0 * sigma - rho);
     hipLaunchKernelGGL(k_cheb<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n,
@@ -478,7 +478,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
     RT_LAUNCH_CHECK();
   }
   RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
-                                           nullptr, A->partB.p, nullptr, level_shape<T>(L),
+                                           nullptr, nullptr, nullptr, level_shape<T>(L),
                                            nullptr, stop)));
   hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
                      r, B::b(C), stop);

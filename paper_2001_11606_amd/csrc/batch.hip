@@ -801,8 +801,9 @@ int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x, const r
     return RT_E_ARG;
   }
   RT_CHECK(check_solve_opts(opts));
-  if (opts->precond != 0) {
-    set_error("rt_batch_solve: batched solves use the Jacobi preconditioner (precond 0)");
+  if (opts->precond != 0 || opts->cw_tol != 0.0) {
+    set_error("rt_batch_solve: batched solves use the Jacobi preconditioner (precond 0) and "
+              "the normwise test only (cw_tol 0)");
     return RT_E_ARG;
   }
   if (opts->precision == RT_PREC_MIXED && !B->fp32) {
@@ -839,8 +840,9 @@ int rt_batch_newton_step(rt_ctx* ctx, rt_batch* B, double* e, double* E, int ell
     return RT_E_ARG;
   }
   RT_CHECK(check_solve_opts(&opts->solve));
-  if (opts->solve.precond != 0) {
-    set_error("rt_batch_newton_step: batched solves use the Jacobi preconditioner (precond 0)");
+  if (opts->solve.precond != 0 || opts->solve.cw_tol != 0.0) {
+    set_error("rt_batch_newton_step: batched solves use the Jacobi preconditioner (precond 0) "
+              "and the normwise test only (cw_tol 0)");
     return RT_E_ARG;
   }
   if (opts->solve.precision == RT_PREC_MIXED && !B->fp32) {

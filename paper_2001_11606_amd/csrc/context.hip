@@ -28,6 +28,7 @@ ReleaseState& release_state() {
   return st;
 }
 
+
 namespace {
 struct Cached {
   void* p;

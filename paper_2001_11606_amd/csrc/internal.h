@@ -312,7 +312,9 @@ struct rt_matrix {
   rt::DevBuf<double> r64, p64, q64, z64, xs, bs, ecur, Ecur, enew;
   rt::DevBuf<float> r32, p32, q32, z32, d32;
   rt::DevBuf<double> partA, partB;   // block partials of the reductions
-  rt::DevBuf<double> partC;          // second level of the partial reductions
+  rt::DevBuf<double> partC;          // block maxima of the componentwise residual measure
+  rt::DevBuf<double> partF;          // second level of the partial reductions
+  rt::DevBuf<float> w32;             // weights 1/(a_ii |x_i|) of the FP32 inner solve
   rt::DevBuf<double> scal;           // device scalars (see solve.hip)
   rt::DevBuf<int32_t> stop;          // PCG stop flag: set on the device when the loop ends
   // Residual carried between outer iterations: after a Newton step, r64 holds
@@ -322,7 +324,8 @@ struct rt_matrix {
   rt::DevBuf<double> bs_prev;
   rt::DevBuf<int32_t> xmis;
   bool resid_ok = false;
-  bool r64_valid = false;            // set by solve_sorted: r64 = b - A x on return
+  bool r64_valid = false;            // set by solve_sorted: r64 = b - A x on return (the
+                                     // recursive residual after FP64 CG: equal up to rounding)
 };
 
 namespace rt {

@@ -10,6 +10,13 @@
 //        vectors and arithmetic) to a relative reduction inner_tol (or just
 //        enough to reach tol); x += d in FP64; r = b - A x in FP64 } until
 //        ||r||_2 <= tol ||b||_2 -- the classical iterative refinement.
+// Componentwise test (cw_tol > 0): both precisions also require
+// max_i |r_i| / (a_ii |x_i|) <= cw_tol, the largest relative change of one
+// unknown that a Jacobi sweep would still make.  A normwise test alone is
+// blind to unknowns many decades below the largest: on a radiation front E
+// spans eight decades, and rows near 1e-8 can keep relative errors of 1e-9
+// under ||r|| <= 1e-14 ||b||.  The FP32 inner solve then measures its
+// residual with the weights 1/(a_ii |x_i|) of the refinement's start.
 //
 // Scalars (alpha, beta, r.z, ...) stay on the device; block partials of the
 // dot products are combined in FP64 by a one-block kernel in a fixed order.
@@ -32,7 +39,10 @@
 namespace rt {
 namespace {
 
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_ITS, S_STOP, S_COUNT };
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_ITS, S_STOP, S_CW, S_COUNT };
+// componentwise measure of the update kernel: none, |r_i| w_i / |x_i| with
+// w = 1/diag (the iterate's own measure), or |r_i| w_i with fixed weights
+enum { CW_NONE = 0, CW_X = 1, CW_W = 2 };
 enum { FIN_ALPHA = 0, FIN_BETA, FIN_RZ, FIN_RR, FIN_BB };
 enum { PROF_SPMV64 = 0, PROF_SPMV32 = 1, PROF_RESID64 = 2, PROF_KINDS = 3 };
 
@@ -42,9 +52,16 @@ enum { PROF_SPMV64 = 0, PROF_SPMV32 = 1, PROF_RESID64 = 2, PROF_KINDS = 3 };
 // FIN_ALPHA sets it on breakdown (p.Ap not positive).  FIN_RZ starts a loop.
 __global__ void __launch_bounds__(kBlock)
 k_finalize(int op, int np, const double* __restrict__ pa, const double* __restrict__ pb,
-           double* __restrict__ s, int32_t* __restrict__ stop, double thr2) {
+           const double* __restrict__ pc, double* __restrict__ s, int32_t* __restrict__ stop,
+           double thr2, double cwthr) {
   __shared__ double red[kBlock / kWave];
   if ((op == FIN_ALPHA || op == FIN_BETA) && *stop) return;
+  // pc (else NULL): block maxima of the componentwise measure
+  double c = 0.0;
+  if (pc) {
+    for (int k = threadIdx.x; k < np; k += kBlock) c = fmax(c, pc[k]);
+    c = block_max(c, red);
+  }
   // four independent running sums per thread keep four loads in flight; they
   // are combined in a fixed order, so the result is the same on every run
   double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -78,12 +95,13 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
         *stop = 1;
       }
       break;
-    case FIN_BETA:   // a = ||r||^2, b = r.z (new)
+    case FIN_BETA:   // a = ||r||^2, b = r.z (new), c = componentwise measure
       s[S_RR] = a;
       s[S_BETA] = b / s[S_RZ];
       s[S_RZ] = b;
       s[S_ITS] += 1.0;
-      if (!(a > thr2)) {
+      if (pc) s[S_CW] = c;
+      if (!(a > thr2) && (!pc || !(c > cwthr))) {
         s[S_STOP] = 1.0;
         *stop = 1;
       }
@@ -97,6 +115,7 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
       break;
     case FIN_RR:
       s[S_RR] = a;
+      if (pc) s[S_CW] = c;
       break;
     case FIN_BB:
       s[S_BB] = a;
@@ -119,21 +138,25 @@ inline int vec_blocks(int64_t n) {
 // second reduction level: nb2 blocks each sum a contiguous chunk of pa (and pb)
 __global__ void __launch_bounds__(kBlock)
 k_partial_reduce(int np, int chunk, const double* __restrict__ pa, const double* __restrict__ pb,
-                 double* __restrict__ out, const int32_t* __restrict__ stop) {
+                 const double* __restrict__ pc, double* __restrict__ out,
+                 const int32_t* __restrict__ stop) {
   __shared__ double red[kBlock / kWave];
   if (stop && *stop) return;
   const int lo = blockIdx.x * chunk;
   const int hi = lo + chunk < np ? lo + chunk : np;
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0;
   for (int i = lo + threadIdx.x; i < hi; i += kBlock) {
     a += pa[i];
     if (pb) b += pb[i];
+    if (pc) c = fmax(c, pc[i]);
   }
   a = block_sum(a, red);
   b = block_sum(b, red);
+  if (pc) c = block_max(c, red);
   if (threadIdx.x == 0) {
     out[blockIdx.x] = a;
     out[gridDim.x + blockIdx.x] = b;
+    out[2 * gridDim.x + blockIdx.x] = c;
   }
 }
 
@@ -180,28 +203,41 @@ k_dot(int64_t n, const T* __restrict__ a, const T* __restrict__ b, double* __res
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// x += alpha p; r -= alpha q; partA = r.r; (Jacobi) partB = r.(dinv r)
-template <typename T, bool JAC>
+// x += alpha p; r -= alpha q; partA = r.r; (Jacobi) partB = r.(dinv r);
+// CW != CW_NONE: partC = the block maximum of the componentwise measure, with
+// w = dinv (CW_X: |r_i| w_i / |x_i| of the updated x) or fixed weights (CW_W)
+template <typename T, bool JAC, int CW>
 __global__ void __launch_bounds__(kBlock)
 k_update(int64_t n, const double* __restrict__ s, T* __restrict__ x, T* __restrict__ r,
          const T* __restrict__ p, const T* __restrict__ q, const T* __restrict__ dinv,
-         double* __restrict__ partA, double* __restrict__ partB, const int32_t* __restrict__ stop) {
+         const T* __restrict__ w, double* __restrict__ partA, double* __restrict__ partB,
+         double* __restrict__ partC, const int32_t* __restrict__ stop) {
   __shared__ double red[kBlock / kWave];
   if (*stop) return;
   const T alpha = (T)s[S_ALPHA];
-  double rr = 0.0, rz = 0.0;
+  double rr = 0.0, rz = 0.0, cw = 0.0;
   RT_VEC_LOOP(i) {
-    x[i] += alpha * p[i];
+    const T xi = x[i] + alpha * p[i];
+    x[i] = xi;
     const T ri = r[i] - alpha * q[i];
     r[i] = ri;
     rr += (double)ri * (double)ri;
     if (JAC) rz += (double)ri * (double)(dinv[i] * ri);
+    if (CW == CW_X) {
+      const double ax = fabs((double)xi);
+      const double t = fabs((double)ri) * (double)w[i];
+      cw = fmax(cw, ax > 0.0 ? t / ax : (ri == T(0) ? 0.0 : INFINITY));
+    } else if (CW == CW_W) {
+      cw = fmax(cw, fabs((double)ri) * (double)w[i]);
+    }
   }
   rr = block_sum(rr, red);
   if (JAC) rz = block_sum(rz, red);
+  if (CW != CW_NONE) cw = block_max(cw, red);
   if (threadIdx.x == 0) {
     partA[blockIdx.x] = rr;
     if (JAC) partB[blockIdx.x] = rz;
+    if (CW != CW_NONE) partC[blockIdx.x] = cw;
   }
 }
 
@@ -221,13 +257,16 @@ k_pupdate(int64_t n, const double* __restrict__ s, const T* __restrict__ r,
 
 // Initial residual from the previous one: for the same matrix and x, b - A x =
 // (b_prev - A x) + (b - b_prev).  r = r + (b - b_prev) (r32: its FP32 copy),
-// partA = r.r, partB = b.b.
+// partA = r.r, partB = b.b, partC = the block maximum of the componentwise
+// measure |r_i| / (a_ii |x_i|) (x, diag), w32 (else NULL) its weights.
 __global__ void __launch_bounds__(kBlock)
 k_resid_shift(int64_t n, const double* __restrict__ b, const double* __restrict__ b_prev,
-              double* __restrict__ r, float* __restrict__ r32, double* __restrict__ partA,
-              double* __restrict__ partB) {
+              const double* __restrict__ x, const double* __restrict__ diag,
+              double* __restrict__ r, float* __restrict__ r32, float* __restrict__ w32,
+              double* __restrict__ partA, double* __restrict__ partB,
+              double* __restrict__ partC) {
   __shared__ double red[kBlock / kWave];
-  double rr = 0.0, bb = 0.0;
+  double rr = 0.0, bb = 0.0, cw = 0.0;
   RT_VEC_LOOP(i) {
     const double bi = b[i];
     const double ri = r[i] + (bi - b_prev[i]);
@@ -235,12 +274,17 @@ k_resid_shift(int64_t n, const double* __restrict__ b, const double* __restrict_
     if (r32) r32[i] = (float)ri;
     rr += ri * ri;
     bb += bi * bi;
+    const double xi = x[i], di = diag[i];
+    cw = fmax(cw, cw_term(ri, di, xi));
+    if (w32) w32[i] = cw_weight(di, xi);
   }
   rr = block_sum(rr, red);
   bb = block_sum(bb, red);
+  cw = block_max(cw, red);
   if (threadIdx.x == 0) {
     partA[blockIdx.x] = rr;
     partB[blockIdx.x] = bb;
+    partC[blockIdx.x] = cw;
   }
 }
 
@@ -282,28 +326,39 @@ struct Prof {
   }
 };
 
+// Device buffers of one solve: work vectors of the fine level (n entries
+// each; the FP32 ones only for mixed precision), block partials, the Krylov
+// scalars and the stop flag.
+struct Work {
+  double *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *z64 = nullptr;
+  float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *z32 = nullptr, *d32 = nullptr,
+        *w32 = nullptr;
+  double *partA = nullptr, *partB = nullptr, *partC = nullptr, *partF = nullptr, *scal = nullptr;
+  int32_t* stop = nullptr;
+};
+
 template <typename T> struct Sel;
 template <> struct Sel<double> {
   static const double* val(const Level& L) { return L.val64.p; }
   static const double* diag(const Level& L) { return L.diag64.p; }
   static const double* dinv(const Level& L) { return L.dinv64.p; }
-  static double* p(rt_matrix* A) { return A->p64.p; }
-  static double* q(rt_matrix* A) { return A->q64.p; }
-  static double* z(rt_matrix* A) { return A->z64.p; }
+  static double* p(const Work& W) { return W.p64; }
+  static double* q(const Work& W) { return W.q64; }
+  static double* z(const Work& W) { return W.z64; }
   static constexpr int kind = PROF_SPMV64;
 };
 template <> struct Sel<float> {
   static const float* val(const Level& L) { return L.val32.p; }
   static const float* diag(const Level& L) { return L.diag32.p; }
   static const float* dinv(const Level& L) { return L.dinv32.p; }
-  static float* p(rt_matrix* A) { return A->p32.p; }
-  static float* q(rt_matrix* A) { return A->q32.p; }
-  static float* z(rt_matrix* A) { return A->z32.p; }
+  static float* p(const Work& W) { return W.p32; }
+  static float* q(const Work& W) { return W.q32; }
+  static float* z(const Work& W) { return W.z32; }
   static constexpr int kind = PROF_SPMV32;
 };
 
-int read_scalar(rt_ctx* ctx, rt_matrix* A, int idx, double* out) {
-  RT_CHECK(ctx->sync_read(A->scal.p + idx, sizeof(double)));
+int read_scalar(rt_ctx* ctx, const Work& W, int idx, double* out) {
+  RT_CHECK(ctx->sync_read(W.scal + idx, sizeof(double)));
   *out = ctx->host[0];
   return RT_OK;
 }
@@ -313,63 +368,83 @@ int read_scalar(rt_ctx* ctx, rt_matrix* A, int idx, double* out) {
 #define RT_PARTIAL_FOLD_MIN (4 * kMaxPartials)
 #endif
 
-int finalize(rt_ctx* ctx, rt_matrix* A, int op, int np, const double* pa, const double* pb,
-             double thr2 = 0.0) {
+// pc (else NULL): block maxima of the componentwise measure; the loop stops
+// only when it is <= cwthr as well
+int finalize(rt_ctx* ctx, const Work& W, int op, int np, const double* pa, const double* pb,
+             double thr2 = 0.0, const double* pc = nullptr, double cwthr = 0.0) {
   const bool in_loop = op == FIN_ALPHA || op == FIN_BETA;
   if (np > RT_PARTIAL_FOLD_MIN) {
     // first fold the partials into at most kMaxPartials values per array
     const int nb2 = std::min(kMaxPartials, std::max(1, np / 8));
     const int chunk = (np + nb2 - 1) / nb2;
     hipLaunchKernelGGL(k_partial_reduce, dim3(nb2), dim3(kBlock), 0, ctx->stream, np, chunk, pa,
-                       pb, A->partC.p, in_loop ? A->stop.p : nullptr);
+                       pb, pc, W.partF, in_loop ? W.stop : nullptr);
     RT_LAUNCH_CHECK();
-    pa = A->partC.p;
-    pb = pb ? A->partC.p + nb2 : nullptr;
+    pa = W.partF;
+    pb = pb ? W.partF + nb2 : nullptr;
+    pc = pc ? W.partF + 2 * nb2 : nullptr;
     np = nb2;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, ctx->stream, op, np, pa, pb,
-                     A->scal.p, A->stop.p, thr2);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, ctx->stream, op, np, pa, pb, pc,
+                     W.scal, W.stop, thr2, cwthr);
   RT_LAUNCH_CHECK();
   return RT_OK;
 }
 
+// Componentwise test of a PCG loop: the update kernel's measure (mode), its
+// weights and the threshold (infinity: measured, never binding).
+struct CwTest {
+  int mode = CW_NONE;
+  const void* w = nullptr;
+  double thr = INFINITY;
+};
+
 // One PCG iteration, queued; a no-op on the device once the stop flag is set.
 template <typename T>
-int pcg_iteration(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double thr2) {
+int pcg_iteration(rt_ctx* ctx, rt_matrix* A, const Work& W, bool amg, T* x, T* r, double thr2, const CwTest& cw) {
   using S = Sel<T>;
   hipStream_t st = ctx->stream;
   const Level& L = A->levels[0];
   const int64_t n = L.n;
-  T* p = S::p(A);
-  T* q = S::q(A);
-  T* z = S::z(A);
-  const int32_t* stop = A->stop.p;
+  T* p = S::p(W);
+  T* q = S::q(W);
+  T* z = S::z(W);
+  const int32_t* stop = W.stop;
   const int gv = vec_blocks(n);
   int nbk = 0;
   Prof pf(ctx, S::kind);
   RT_CHECK(pf.begin());
   RT_CHECK((launch_spmv_level<T, SP_DOT>(st, L, S::val(L), S::diag(L), p, nullptr, nullptr, q,
-                                         nullptr, A->partA.p, &nbk, level_shape<T>(L), nullptr,
+                                         nullptr, W.partA, &nbk, level_shape<T>(L), nullptr,
                                          stop)));
   RT_CHECK(pf.end());
-  RT_CHECK(finalize(ctx, A, FIN_ALPHA, nbk, A->partA.p, nullptr));
+  RT_CHECK(finalize(ctx, W, FIN_ALPHA, nbk, W.partA, nullptr));
+  const T* w = static_cast<const T*>(cw.w);
+  double* pc = cw.mode == CW_NONE ? nullptr : W.partC;
+#define RT_UPD(JAC_, CW_)                                                                      \
+  hipLaunchKernelGGL((k_update<T, JAC_, CW_>), dim3(gv), dim3(kBlock), 0, st, n, W.scal, x, r, \
+                     p, q, JAC_ ? S::dinv(L) : nullptr, w, W.partA,                          \
+                     JAC_ ? W.partB : nullptr, pc, stop)
   if (amg) {
-    hipLaunchKernelGGL((k_update<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r, p,
-                       q, nullptr, A->partA.p, nullptr, stop);
+    if (cw.mode == CW_X) RT_UPD(false, CW_X);
+    else if (cw.mode == CW_W) RT_UPD(false, CW_W);
+    else RT_UPD(false, CW_NONE);
     RT_LAUNCH_CHECK();
     RT_CHECK(vcycle<T>(ctx, A, r, z, stop));
-    hipLaunchKernelGGL(k_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, A->partB.p, stop);
+    hipLaunchKernelGGL(k_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, W.partB, stop);
   } else {
-    hipLaunchKernelGGL((k_update<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, x, r, p,
-                       q, S::dinv(L), A->partA.p, A->partB.p, stop);
+    if (cw.mode == CW_X) RT_UPD(true, CW_X);
+    else if (cw.mode == CW_W) RT_UPD(true, CW_W);
+    else RT_UPD(true, CW_NONE);
   }
+#undef RT_UPD
   RT_LAUNCH_CHECK();
-  RT_CHECK(finalize(ctx, A, FIN_BETA, gv, A->partA.p, A->partB.p, thr2));
+  RT_CHECK(finalize(ctx, W, FIN_BETA, gv, W.partA, W.partB, thr2, pc, cw.thr));
   if (amg)
-    hipLaunchKernelGGL((k_pupdate<T, false>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
+    hipLaunchKernelGGL((k_pupdate<T, false>), dim3(gv), dim3(kBlock), 0, st, n, W.scal, r,
                        nullptr, z, p, stop);
   else
-    hipLaunchKernelGGL((k_pupdate<T, true>), dim3(gv), dim3(kBlock), 0, st, n, A->scal.p, r,
+    hipLaunchKernelGGL((k_pupdate<T, true>), dim3(gv), dim3(kBlock), 0, st, n, W.scal, r,
                        S::dinv(L), nullptr, p, stop);
   RT_LAUNCH_CHECK();
   return RT_OK;
@@ -387,38 +462,41 @@ int next_chunk(double rr_prev, int its_prev, double rr, int its, double thr2) {
 }
 
 // PCG iterations on A x = b given r = b - A x and s[S_RR] = ||r||^2 on entry.
-// Stops when ||r||^2 <= thr2 or after max_it iterations.
+// Stops when ||r||^2 <= thr2 (and the componentwise measure, cw0 on entry,
+// is <= cw.thr) or after max_it iterations; *cw_out: the measure at the end.
 template <typename T>
-int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double thr2,
-             int max_it, int* its_out, double* rr_out) {
+int pcg_core(rt_ctx* ctx, rt_matrix* A, const Work& W, bool amg, T* x, T* r, double rr0, double thr2,
+             int max_it, int* its_out, double* rr_out, const CwTest& cw = CwTest{},
+             double cw0 = 0.0, double* cw_out = nullptr) {
   using S = Sel<T>;
   hipStream_t st = ctx->stream;
   const Level& L = A->levels[0];
   const int64_t n = L.n;
-  T* p = S::p(A);
-  T* z = S::z(A);
+  T* p = S::p(W);
+  T* z = S::z(W);
   const int gv = vec_blocks(n);
   *its_out = 0;
   *rr_out = rr0;
-  if (rr0 <= thr2 || max_it <= 0) return RT_OK;
+  if (cw_out) *cw_out = cw0;
+  if ((rr0 <= thr2 && !(cw0 > cw.thr)) || max_it <= 0) return RT_OK;
   if (amg) {
     RT_CHECK(vcycle<T>(ctx, A, r, z));
-    hipLaunchKernelGGL(k_copy_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, p, A->partB.p);
+    hipLaunchKernelGGL(k_copy_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, p, W.partB);
   } else {
     hipLaunchKernelGGL(k_init_jacobi<T>, dim3(gv), dim3(kBlock), 0, st, n, S::dinv(L), r, p,
-                       A->partB.p);
+                       W.partB);
   }
   RT_LAUNCH_CHECK();
-  RT_CHECK(finalize(ctx, A, FIN_RZ, gv, A->partB.p, nullptr));   // clears the stop flag
+  RT_CHECK(finalize(ctx, W, FIN_RZ, gv, W.partB, nullptr));   // clears the stop flag
   const size_t spans0 = ctx->prof_spans.size();
   double rr = rr0, rr_prev = rr0;
   int its = 0, its_prev = 0, queued = 0, chunk = 1;
   bool stopped = false, bad = false;
   while (queued < max_it) {
     const int k = std::min(chunk, max_it - queued);
-    for (int j = 0; j < k; ++j) RT_CHECK(pcg_iteration<T>(ctx, A, amg, x, r, thr2));
+    for (int j = 0; j < k; ++j) RT_CHECK(pcg_iteration<T>(ctx, A, W, amg, x, r, thr2, cw));
     queued += k;
-    RT_CHECK(ctx->sync_read(A->scal.p, sizeof(double) * S_COUNT));
+    RT_CHECK(ctx->sync_read(W.scal, sizeof(double) * S_COUNT));
     const double* hs = ctx->host;
     rr = hs[S_RR];
     its = (int)hs[S_ITS];
@@ -430,8 +508,10 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, bool amg, T* x, T* r, double rr0, double
       *rr_out = rr;
       return RT_E_DEVICE;
     }
+    if (cw_out && its > 0) *cw_out = hs[S_CW];
     if (stopped) break;
-    chunk = next_chunk(rr_prev, its_prev, rr, its, thr2);
+    // while the componentwise test still binds, go by one iteration at a time
+    chunk = rr > thr2 ? next_chunk(rr_prev, its_prev, rr, its, thr2) : 1;
     rr_prev = rr;
     its_prev = its;
   }
@@ -450,68 +530,98 @@ int ensure_work(rt_matrix* A, bool mixed) {
   for (auto* b : {&A->r64, &A->p64, &A->q64, &A->z64}) RT_CHECK(b->reserve(n));
   RT_CHECK(A->partA.reserve(max_partials(n)));
   RT_CHECK(A->partB.reserve(max_partials(n)));
-  RT_CHECK(A->partC.reserve(2 * kMaxPartials));
+  RT_CHECK(A->partC.reserve(max_partials(n)));
+  RT_CHECK(A->partF.reserve(3 * kMaxPartials));
   RT_CHECK(A->scal.reserve(S_COUNT));
   RT_CHECK(A->stop.reserve(1));
   if (mixed)
-    for (auto* b : {&A->r32, &A->p32, &A->q32, &A->z32, &A->d32}) RT_CHECK(b->reserve(n));
+    for (auto* b : {&A->r32, &A->p32, &A->q32, &A->z32, &A->d32, &A->w32}) RT_CHECK(b->reserve(n));
   return RT_OK;
 }
 
-// r = b - A x in FP64 (optionally also r32), returns ||r||^2
-int residual64(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, float* r32,
-               double* rr) {
+// The matrix's own work buffers (after ensure_work)
+Work work_of(rt_matrix* A) {
+  Work W;
+  W.r64 = A->r64.p;
+  W.p64 = A->p64.p;
+  W.q64 = A->q64.p;
+  W.z64 = A->z64.p;
+  W.r32 = A->r32.p;
+  W.p32 = A->p32.p;
+  W.q32 = A->q32.p;
+  W.z32 = A->z32.p;
+  W.d32 = A->d32.p;
+  W.w32 = A->w32.p;
+  W.partA = A->partA.p;
+  W.partB = A->partB.p;
+  W.partC = A->partC.p;
+  W.partF = A->partF.p;
+  W.scal = A->scal.p;
+  W.stop = A->stop.p;
+  return W;
+}
+
+// r = b - A x in FP64 (optionally also r32 and the componentwise weights w32);
+// returns ||r||^2 and the componentwise measure max_i |r_i| / (a_ii |x_i|)
+int residual64(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, const double* x, float* r32,
+               float* w32, double* rr, double* cw) {
   const Level& L = A->levels[0];
   int nbk = 0;
   Prof pf(ctx, PROF_RESID64);
   RT_CHECK(pf.begin());
   RT_CHECK((launch_spmv_level<double, SP_RESID>(ctx->stream, L, L.val64.p, L.diag64.p, x, b,
-                                                nullptr, A->r64.p, r32, A->partA.p, &nbk,
-                                                L.shape64)));
+                                                nullptr, W.r64, r32, W.partA, &nbk,
+                                                L.shape64, nullptr, nullptr, W.partC, w32)));
   RT_CHECK(pf.end());
-  RT_CHECK(finalize(ctx, A, FIN_RR, nbk, A->partA.p, nullptr));
-  return read_scalar(ctx, A, S_RR, rr);
+  RT_CHECK(finalize(ctx, W, FIN_RR, nbk, W.partA, nullptr, 0.0, W.partC));
+  RT_CHECK(ctx->sync_read(W.scal, sizeof(double) * S_COUNT));
+  *rr = ctx->host[S_RR];
+  *cw = ctx->host[S_CW];
+  return RT_OK;
 }
 
-}  // namespace
-
-int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt_solve_opts* o,
-                 rt_solve_stats* stt, const double* b_prev, const int32_t* mismatch) {
+// The solve on sorted vectors with the buffers of W (see solve_sorted);
+// *resid_valid: W.r64 holds b - A x on return.
+int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double* x,
+               const rt_solve_opts* o, rt_solve_stats* stt, const double* b_prev,
+               const int32_t* mismatch, bool* resid_valid) {
   hipStream_t st = ctx->stream;
   const int64_t n = A->n;
   const bool mixed = o->precision == RT_PREC_MIXED;
-  A->r64_valid = false;
-  if (mixed && !A->has_fp32) {
-    set_error("rt_solve: mixed precision needs a matrix assembled with build_fp32 = 1");
-    return RT_E_STATE;
-  }
+  *resid_valid = false;
   const bool amg = o->precond == 1 && A->levels.size() > 1;
-  RT_CHECK(ensure_work(A, mixed));
   *stt = rt_solve_stats{};
   if (n == 0) return RT_OK;
   const int gv = vec_blocks(n);
-  double bb = 0.0, rr = 0.0;
-  bool have_r = false;   // r64 (and r32) hold b - A x, rr = ||r||^2
+  const Level& L0 = A->levels[0];
+  // componentwise test: its threshold, infinity when only measured
+  const bool use_cw = o->cw_tol > 0.0;
+  const double cwthr = use_cw ? o->cw_tol : INFINITY;
+  float* w32 = mixed && use_cw ? W.w32 : nullptr;
+  double bb = 0.0, rr = 0.0, cw = 0.0;
+  bool have_r = false;   // r64 (and r32) hold b - A x, rr = ||r||^2, cw its measure
   if (b_prev) {
-    hipLaunchKernelGGL(k_resid_shift, dim3(gv), dim3(kBlock), 0, st, n, b, b_prev, A->r64.p,
-                       mixed ? A->r32.p : nullptr, A->partA.p, A->partB.p);
+    hipLaunchKernelGGL(k_resid_shift, dim3(gv), dim3(kBlock), 0, st, n, b, b_prev, x,
+                       L0.diag64.p, W.r64, mixed ? W.r32 : nullptr, w32, W.partA,
+                       W.partB, W.partC);
     RT_LAUNCH_CHECK();
-    RT_CHECK(finalize(ctx, A, FIN_RR, gv, A->partA.p, nullptr));
-    RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
+    RT_CHECK(finalize(ctx, W, FIN_RR, gv, W.partA, nullptr, 0.0, W.partC));
+    RT_CHECK(finalize(ctx, W, FIN_BB, gv, W.partB, nullptr));
     RT_CHECK_HIP(hipMemcpyAsync(ctx->host + S_COUNT, mismatch, sizeof(int32_t),
                                 hipMemcpyDeviceToHost, st));
-    RT_CHECK(ctx->sync_read(A->scal.p, sizeof(double) * S_COUNT));
+    RT_CHECK(ctx->sync_read(W.scal, sizeof(double) * S_COUNT));
     int32_t mis = 0;
     std::memcpy(&mis, ctx->host + S_COUNT, sizeof(int32_t));
     bb = ctx->host[S_BB];
     rr = ctx->host[S_RR];
+    cw = ctx->host[S_CW];
     have_r = mis == 0;
   } else {
-    hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, A->partB.p,
+    hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, st, n, b, b, W.partB,
                        nullptr);
     RT_LAUNCH_CHECK();
-    RT_CHECK(finalize(ctx, A, FIN_BB, gv, A->partB.p, nullptr));
-    RT_CHECK(read_scalar(ctx, A, S_BB, &bb));
+    RT_CHECK(finalize(ctx, W, FIN_BB, gv, W.partB, nullptr));
+    RT_CHECK(read_scalar(ctx, W, S_BB, &bb));
   }
   if (!std::isfinite(bb)) {
     set_error("rt_solve: right-hand side is not finite");
@@ -525,39 +635,64 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
   const double thr2 = o->tol * o->tol * bb;
   int status = RT_OK;
   if (!mixed) {
-    if (!have_r) RT_CHECK(residual64(ctx, A, b, x, nullptr, &rr));
+    if (!have_r) RT_CHECK(residual64(ctx, A, W, b, x, nullptr, nullptr, &rr, &cw));
     int its = 0;
-    RT_CHECK(pcg_core<double>(ctx, A, amg, x, A->r64.p, rr, thr2, o->max_iter, &its, &rr));
+    const CwTest t{CW_X, L0.dinv64.p, cwthr};
+    RT_CHECK(pcg_core<double>(ctx, A, W, amg, x, W.r64, rr, thr2, o->max_iter, &its, &rr, t, cw,
+                              &cw));
     stt->iterations = its;
-    if (rr > thr2) status = RT_NOT_CONVERGED;
   } else {
-    if (!have_r) RT_CHECK(residual64(ctx, A, b, x, A->r32.p, &rr));
+    if (!have_r) RT_CHECK(residual64(ctx, A, W, b, x, W.r32, w32, &rr, &cw));
     int total = 0, refine = 0;
-    while (rr > thr2 && total < o->max_iter && refine < o->max_refine) {
-      // reduce by inner_tol, or just enough (with margin) to reach tol
-      double red = std::max(o->inner_tol, 0.3 * std::sqrt(thr2 / rr));
-      hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->d32.p);
+    while ((rr > thr2 || cw > cwthr) && total < o->max_iter && refine < o->max_refine) {
+      // reduce by inner_tol, or just enough (with margin) to reach tol; the
+      // same for the componentwise measure when it is tested
+      const double red = std::max(o->inner_tol, 0.3 * std::sqrt(thr2 / rr));
+      CwTest t{};
+      if (use_cw) t = CwTest{CW_W, w32, std::max(o->inner_tol, 0.3 * cwthr / cw) * cw};
+      hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, W.d32);
       RT_LAUNCH_CHECK();
       int its = 0;
       double rr_in = 0.0;
-      RT_CHECK(pcg_core<float>(ctx, A, amg, A->d32.p, A->r32.p, rr, red * red * rr,
-                               o->max_iter - total, &its, &rr_in));
+      RT_CHECK(pcg_core<float>(ctx, A, W, amg, W.d32, W.r32, rr, red * red * rr,
+                               o->max_iter - total, &its, &rr_in, t, cw));
       total += its;
-      hipLaunchKernelGGL(k_add_f32, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->d32.p, x);
+      hipLaunchKernelGGL(k_add_f32, dim3(grid_for(n)), dim3(kBlock), 0, st, n, W.d32, x);
       RT_LAUNCH_CHECK();
-      RT_CHECK(residual64(ctx, A, b, x, A->r32.p, &rr));
+      RT_CHECK(residual64(ctx, A, W, b, x, W.r32, w32, &rr, &cw));
       ++refine;
       if (its == 0) break;
     }
     stt->iterations = total;
     stt->refinements = refine;
-    if (rr > thr2) status = RT_NOT_CONVERGED;
   }
+  if (rr > thr2 || cw > cwthr) status = RT_NOT_CONVERGED;
   stt->rel_residual = std::sqrt(rr / bb);
-  A->r64_valid = true;
+  stt->cw_residual = cw;
+  // r64 now holds b - A x: the residual of an FP64 product (mixed), or the
+  // recursive residual of CG (FP64), which differs from it by rounding only
+  *resid_valid = true;
   if (status == RT_NOT_CONVERGED)
-    set_error("rt_solve: relative residual %.3e above tolerance %.3e", stt->rel_residual, o->tol);
+    set_error("rt_solve: relative residual %.3e (componentwise %.3e) above tolerance %.3e "
+              "(componentwise %.3e)", stt->rel_residual, cw, o->tol, o->cw_tol);
   return status;
+}
+
+}  // namespace
+
+int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt_solve_opts* o,
+                 rt_solve_stats* stt, const double* b_prev, const int32_t* mismatch) {
+  const bool mixed = o->precision == RT_PREC_MIXED;
+  A->r64_valid = false;
+  if (mixed && !A->has_fp32) {
+    set_error("rt_solve: mixed precision needs a matrix assembled with build_fp32 = 1");
+    return RT_E_STATE;
+  }
+  RT_CHECK(ensure_work(A, mixed));
+  bool valid = false;
+  const int s = solve_work(ctx, A, work_of(A), b, x, o, stt, b_prev, mismatch, &valid);
+  A->r64_valid = valid;
+  return s;
 }
 
 int collect_profile(rt_ctx* ctx, rt_solve_stats* s) {
@@ -569,6 +704,8 @@ int collect_profile(rt_ctx* ctx, rt_solve_stats* s) {
   s->spmv_seconds = sec[PROF_SPMV64];
   s->spmv32_calls = calls[PROF_SPMV32];
   s->spmv32_seconds = sec[PROF_SPMV32];
+  s->resid_calls = calls[PROF_RESID64];
+  s->resid_seconds = sec[PROF_RESID64];
   return RT_OK;
 }
 
@@ -601,7 +738,7 @@ int check_solve_opts(const rt_solve_opts* o) {
     set_error("unknown preconditioner %d", o->precond);
     return RT_E_ARG;
   }
-  if (!(o->tol >= 0.0) || o->max_iter < 0 ||
+  if (!(o->tol >= 0.0) || o->max_iter < 0 || !(o->cw_tol >= 0.0) ||
       (o->precision == RT_PREC_MIXED && (!(o->inner_tol > 0.0) || o->inner_tol >= 1.0))) {
     set_error("invalid tolerance or iteration limit");
     return RT_E_ARG;

@@ -29,9 +29,26 @@ namespace rt {
 enum SpmvMode {
   SP_PLAIN = 0,   // y = A x
   SP_DOT = 1,     // y = A x, part[block] = sum x.y
-  SP_RESID = 2,   // y = b - A x (optionally y32 = (float) y), part[block] = sum y.y
+  SP_RESID = 2,   // y = b - A x (optionally y32 = (float) y), part[block] = sum y.y;
+                  // optionally pmax[block] = max_i |y_i| / (a_ii |x_i|) and
+                  // w32 = 1 / (a_ii |x_i|) (see cw_term)
   SP_SMOOTH = 3,  // y = x + s (b - A x)
 };
+
+// Componentwise residual measure of row i: |r_i| / (a_ii |x_i|), the relative
+// change of x_i that one Jacobi sweep would make.  A row with x_i = 0 counts
+// as converged when r_i = 0 and as unconverged (infinity) otherwise.
+__device__ __forceinline__ double cw_term(double r, double aii, double x) {
+  const double ax = aii * fabs(x);
+  return ax > 0.0 ? fabs(r) / ax : (r == 0.0 ? 0.0 : INFINITY);
+}
+// Weight w_i with |r_i| w_i = cw_term for a fixed x (the FP32 inner solve of
+// the refinement loop measures its own residual with it); 0 where x_i = 0,
+// whose rows the FP64 test above still covers.
+__device__ __forceinline__ float cw_weight(double aii, double x) {
+  const double ax = aii * fabs(x);
+  return ax > 0.0 ? (float)fmin(1.0 / ax, 3.0e38) : 0.0f;
+}
 
 constexpr int kXcd = 8;
 
@@ -53,7 +70,7 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
        const T* __restrict__ val, const T* __restrict__ diag, const T* __restrict__ x,
        const T* __restrict__ b, const T* __restrict__ s, T* __restrict__ y,
        float* __restrict__ y32, double* __restrict__ part, const int32_t* __restrict__ tprob,
-       const int32_t* __restrict__ skip) {
+       const int32_t* __restrict__ skip, double* __restrict__ pmax, float* __restrict__ w32) {
   __shared__ double red[kBlock / kWave];
   constexpr int RPB = kBlock / G;
   const int lb = xcd_block(per);
@@ -63,7 +80,7 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
   }
   const int lane = threadIdx.x & (G - 1);
   const int64_t i = (int64_t)lb * RPB + threadIdx.x / G;
-  double acc = 0.0;
+  double acc = 0.0, cwm = 0.0;
   if (i < n) {
     const int64_t k0 = rp[i], k1 = rp[i + 1];
     const T xi = x[i];
@@ -102,6 +119,8 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
         y[i] = r;
         if (y32) y32[i] = (float)r;
         acc = (double)r * (double)r;
+        if (pmax) cwm = cw_term((double)r, (double)di, (double)xi);
+        if (w32) w32[i] = cw_weight((double)di, (double)xi);
       } else {
         y[i] = xi + si * (bi - ax);
       }
@@ -110,6 +129,10 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
   if (MODE == SP_DOT || MODE == SP_RESID) {
     const double t = block_sum(acc, red);
     if (threadIdx.x == 0 && part) part[lb] = t;
+  }
+  if (MODE == SP_RESID && pmax) {
+    const double m = block_max(cwm, red);
+    if (threadIdx.x == 0) pmax[lb] = m;
   }
 }
 
@@ -166,7 +189,8 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
              const int64_t* __restrict__ toff, const int32_t* __restrict__ tcols,
              const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ s,
              T* __restrict__ y, float* __restrict__ y32, double* __restrict__ part,
-             const int32_t* __restrict__ tprob, const int32_t* __restrict__ skip) {
+             const int32_t* __restrict__ tprob, const int32_t* __restrict__ skip,
+             double* __restrict__ pmax, float* __restrict__ w32) {
   RT_DYNAMIC_LDS(dyn_lds);
   T* xs = reinterpret_cast<T*>(dyn_lds);
   __shared__ int srp[kTileRows + 1];      // row bounds relative to the tile's aligned base
@@ -246,7 +270,7 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
     }
   }
   __syncthreads();
-  double acc = 0.0;
+  double acc = 0.0, cwm = 0.0;
   if (live) {
     const T ax = di * xi + sy[tid];
     if (MODE == SP_PLAIN) {
@@ -259,6 +283,8 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
       y[i] = r;
       if (y32) y32[i] = (float)r;
       acc = (double)r * (double)r;
+      if (pmax) cwm = cw_term((double)r, (double)di, (double)xi);
+      if (w32) w32[i] = cw_weight((double)di, (double)xi);
     } else {
       y[i] = xi + si * (bi - ax);
     }
@@ -266,6 +292,10 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   if (MODE == SP_DOT || MODE == SP_RESID) {
     const double tsum = block_sum(acc, red);
     if (tid == 0 && part) part[t] = tsum;
+  }
+  if (MODE == SP_RESID && pmax) {
+    const double m = block_max(cwm, red);
+    if (tid == 0) pmax[t] = m;
   }
 }
 
@@ -326,11 +356,14 @@ inline int spmv_rows_per_block(const Level& L, int shape) {
 // skip (else NULL): per-problem stop flags; blocks whose problem is flagged
 // do nothing.  tprob: the problem of every 256-row tile (batched systems), or
 // NULL for one problem (flag skip[0]).
+// pmax, w32 (SP_RESID only, else NULL): per-block maxima of the componentwise
+// residual measure and the per-row weights of cw_weight.
 template <typename T, int MODE>
 int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* diag, const T* x,
                       const T* b, const T* s, T* y, float* y32, double* part, int* nparts,
                       int shape = -1, const int32_t* tprob = nullptr,
-                      const int32_t* skip = nullptr) {
+                      const int32_t* skip = nullptr, double* pmax = nullptr,
+                      float* w32 = nullptr) {
   const int64_t n = L.n;
   shape = spmv_effective_shape(L, shape);
   const SpmvShape sh = kSpmvShapes[shape];
@@ -343,7 +376,7 @@ int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* dia
 #define RT_SPMV_T(G_, U_)                                                                     \
   hipLaunchKernelGGL((k_spmv_tiled<T, G_, U_, MODE>), dim3(grid), dim3(kBlock), lds, st, n, per, \
                      L.rp.p, L.lcol.p, val, diag, L.tile_off.p, L.tile_cols.p, x, b, s, y, y32,  \
-                     part, tprob, skip)
+                     part, tprob, skip, pmax, w32)
     switch (shape) {
       case 7: RT_SPMV_T(4, 4); break;
       case 8: RT_SPMV_T(8, 4); break;
@@ -358,7 +391,7 @@ int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* dia
   } else {
 #define RT_SPMV_S(G_, E_)                                                                       \
   hipLaunchKernelGGL((k_spmv<T, G_, E_, MODE>), dim3(grid), dim3(kBlock), 0, st, n, per, L.rp.p, \
-                     L.col.p, val, diag, x, b, s, y, y32, part, tprob, skip)
+                     L.col.p, val, diag, x, b, s, y, y32, part, tprob, skip, pmax, w32)
     switch (shape) {
       case 0: RT_SPMV_S(4, 4); break;
       case 1: RT_SPMV_S(4, 8); break;

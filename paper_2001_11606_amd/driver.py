@@ -62,6 +62,9 @@ class StepReport:
     spmv64_seconds: float = 0.0
     spmv32_calls: int = 0
     spmv32_seconds: float = 0.0
+    resid_calls: int = 0
+    resid_seconds: float = 0.0
+    cw_residual: list = field(default_factory=list)
 
 
 def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
@@ -112,6 +115,9 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
         rep.spmv64_seconds += st.solve.spmv_seconds
         rep.spmv32_calls += st.solve.spmv32_calls
         rep.spmv32_seconds += st.solve.spmv32_seconds
+        rep.resid_calls += st.solve.resid_calls
+        rep.resid_seconds += st.solve.resid_seconds
+        rep.cw_residual.append(st.solve.cw_residual)
         if fixed_outer is None and st.delta_e < eps_e and st.delta_E < eps_E:
             break
     if sorted_state:

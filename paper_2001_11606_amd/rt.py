@@ -67,7 +67,7 @@ class rt_matrix_info(ctypes.Structure):
 
 class rt_solve_opts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("precond", c_int), ("tol", c_dbl), ("max_iter", c_int),
-                ("inner_tol", c_dbl), ("max_refine", c_int)]
+                ("inner_tol", c_dbl), ("max_refine", c_int), ("cw_tol", c_dbl)]
 
 
 class rt_gmres_opts(ctypes.Structure):
@@ -77,7 +77,8 @@ class rt_gmres_opts(ctypes.Structure):
 class rt_solve_stats(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("refinements", c_int), ("rel_residual", c_dbl),
                 ("seconds", c_dbl), ("spmv_calls", c_int), ("spmv_seconds", c_dbl),
-                ("spmv32_calls", c_int), ("spmv32_seconds", c_dbl)]
+                ("spmv32_calls", c_int), ("spmv32_seconds", c_dbl), ("cw_residual", c_dbl),
+                ("resid_calls", c_int), ("resid_seconds", c_dbl)]
 
 
 class rt_newton_opts(ctypes.Structure):
@@ -407,8 +408,8 @@ def _ptr(t, dtype=None) -> int:
 
 
 def solve_opts(precision=RT_PREC_FP64, precond=PRECOND_JACOBI, tol=1e-10, max_iter=1000,
-               inner_tol=1e-4, max_refine=20) -> rt_solve_opts:
-    return rt_solve_opts(precision, precond, tol, max_iter, inner_tol, max_refine)
+               inner_tol=1e-4, max_refine=20, cw_tol=0.0) -> rt_solve_opts:
+    return rt_solve_opts(precision, precond, tol, max_iter, inner_tol, max_refine, cw_tol)
 
 
 RT_SMOOTHER_L1_JACOBI, RT_SMOOTHER_CHEBYSHEV = 0, 1

@@ -94,6 +94,17 @@ def check_case(ctx, name, prob):
         s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50))
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: solve prec={prec} precond={precond} err={e} its={st.iterations}"
+    # the componentwise stopping test: a positive right-hand side over eight
+    # decades, every unknown to the bar (relative), Jacobi FP64 and AMG mixed
+    bpos = sysm.A.diagonal() * 10.0 ** np.random.default_rng(23).uniform(-8.0, 0.0, nin)
+    xpos = linsolve.solve(sysm.A, bpos, tol=1e-15)
+    for prec, precond, tol, bar in ((0, 0, 1e-14, 1e-12), (1, 1, 1e-12, 1e-10)):
+        x = np.zeros(nin)
+        s, st = rt.rt_solve(ctx, c.A, p(bpos), p(x),
+                            rt.solve_opts(prec, precond, tol, 3000, 1e-4, 60, tol))
+        e = np.max(np.abs(x - xpos) / xpos)
+        assert s == 0 and e <= bar and st.cw_residual <= tol, \
+            f"{name}: componentwise prec={prec} err={e} cw={st.cw_residual}"
     # the V-cycle with the Chebyshev smoother (degrees 2 and 3), FP64 and mixed
     cc = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8,
                                          smoother=rt.RT_SMOOTHER_CHEBYSHEV, smoother_degree=3))

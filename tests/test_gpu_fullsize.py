@@ -113,6 +113,43 @@ def test_fullsize_solve_residual(ctx, full, precision, tol):
     assert rel <= 1.05 * tol
 
 
+_REF = {}
+
+
+def _step(ctx, dp, nb, solve, outer):
+    from paper_2001_11606_amd import driver, rt
+    e, E, A, rep = driver.time_step(ctx, dp, nb, amg=rt.amg_opts(max_levels=1), solve=solve,
+                                    fixed_outer=outer)
+    rt.rt_matrix_free(A)
+    ctx._owned = [o for o in ctx._owned if o[1] != A]
+    return e, E, rep
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_fullsize_bench_accuracy(ctx, full, precision):
+    """The step bench.py times (its outer iterations, preconditioner and both
+    stopping tolerances, in either precision) against the same step solved to
+    1e-14 in both measures in FP64: every particle's e and E within 1e-10
+    relative."""
+    import bench
+    from paper_2001_11606_amd import rt
+    name, prob, dp, nb, A, sam, rows, ghosts = full
+    if name not in _REF:
+        say(f"[fullsize accuracy] {name}: FP64 reference step to 1e-14")
+        e, E, rep = _step(ctx, dp, nb, rt.solve_opts(0, 0, 1e-14, 20000, 1e-4, 60, 1e-14),
+                          bench.BENCH_OUTER)
+        assert rep.status == rt.RT_OK
+        _REF[name] = (e, E)
+    eR, ER = _REF[name]
+    say(f"[fullsize accuracy] {name} precision={precision} at the bench's options")
+    e, E, rep = _step(ctx, dp, nb, bench.bench_solve_opts(precision), bench.BENCH_OUTER)
+    assert rep.status == rt.RT_OK
+    dE = float(((E - ER).abs() / ER.abs()).max())
+    de = float(((e - eR).abs() / eR.abs()).max())
+    say(f"  krylov {rep.krylov} refinements {rep.refinements}: max rel diff E {dE:.2e} e {de:.2e}")
+    assert dE <= 1e-10 and de <= 1e-10, (dE, de)
+
+
 def test_fullsize_material_sampled(ctx, full):
     """After one outer iteration the material energies of sampled particles are
     the roots of their own material equations for the returned E."""

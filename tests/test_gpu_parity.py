@@ -131,6 +131,73 @@ def _newton_case(ctx, name, precision, precond, outer):
     return err_e, err_E, rep, ref
 
 
+@pytest.mark.parametrize("name", ["marshak3d_16", "densitystep3d_16", "mms2d_64", "wendland3d_9",
+                                  "densitystep3d_12_coldpatch"])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_solve_componentwise(ctx, systems, name, precision, precond):
+    """With the componentwise test every unknown is accurate, not only the
+    largest: b = diag(A) 10^u with u uniform in [-8, 0] gives a positive
+    solution spanning about eight decades, and the pointwise relative error
+    against the oracle's solve (itself accurate per unknown) is held to
+    1e-12 (FP64, tolerances 1e-14) or 1e-10 (mixed, tolerances 1e-12)."""
+    import torch
+    from paper_2001_11606_amd import rt
+    prob, (ptr, idx, fz, sysm) = _get(systems, name)
+    nin = prob.n_interior
+    say(f"[solve componentwise] {name} precision={precision} precond={precond}")
+    b = sysm.A.diagonal() * 10.0 ** np.random.default_rng(23).uniform(-8.0, 0.0, nin)
+    x_ref = linsolve.solve(sysm.A, b, tol=1e-15)
+    assert np.all(x_ref > 0.0)
+    dp, nb, A = gpu_system(ctx, prob)
+    tol, bar = (1e-14, 1e-12) if precision == 0 else (1e-12, 1e-10)
+    bt = torch.tensor(b, device=ctx.device)
+    xt = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
+    status, st = ctx.solve(A, bt, xt, rt.solve_opts(precision, precond, tol, 4000, 1e-4, 60, tol))
+    assert status == rt.RT_OK, rt.rt_last_error()
+    x = xt.cpu().numpy()
+    err = np.max(np.abs(x - x_ref) / x_ref)
+    assert st.cw_residual <= tol
+    assert err <= bar, (err, st.iterations, st.refinements, st.cw_residual)
+
+
+def test_componentwise_option_errors(ctx, systems):
+    from paper_2001_11606_amd import rt
+    import torch
+    prob, _ = _get(systems, "marshak3d_16")
+    dp, nb, A = gpu_system(ctx, prob)
+    b = torch.ones(prob.n_interior, dtype=torch.float64, device=ctx.device)
+    x = torch.zeros_like(b)
+    for cw in (-1e-12, float("nan")):
+        with pytest.raises(rt.RtError) as ei:
+            ctx.solve(A, b, x, rt.solve_opts(0, 0, 1e-12, 100, 1e-4, 10, cw))
+        assert ei.value.code == rt.RT_E_ARG
+
+
+@pytest.mark.parametrize("name", ["marshak3d_16", "densitystep3d_16", "mms2d_64",
+                                  "densitystep3d_12_coldpatch"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_newton_componentwise(ctx, name, precision):
+    """Three outer iterations with the componentwise test on: pointwise
+    relative errors in e and E against the oracle, 1e-12 (FP64) or 1e-10
+    (mixed)."""
+    from paper_2001_11606_amd import driver, rt
+    prob = CASES[name]()
+    say(f"[newton componentwise] {name} precision={precision}")
+    ref = ostep.time_step(prob.copy(), fixed_outer=3, inner_tol_e=1e-14, solve_tol=1e-15)
+    dp = driver.upload(prob, ctx.device)
+    nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel, period=dp.period)
+    tol, bar = (1e-14, 1e-12) if precision == 0 else (1e-12, 1e-10)
+    e, E, A, rep = driver.time_step(ctx, dp, nb,
+                                    solve=rt.solve_opts(precision, 0, tol, 4000, 1e-4, 60, tol),
+                                    fixed_outer=3)
+    assert rep.status == rt.RT_OK
+    e, E = e.cpu().numpy(), E.cpu().numpy()
+    err_e = np.max(np.abs(e - ref.e) / np.abs(ref.e))
+    err_E = np.max(np.abs(E - ref.E) / np.abs(ref.E))
+    assert err_e <= bar and err_E <= bar, (err_e, err_E, rep.krylov, rep.refinements)
+
+
 @pytest.mark.parametrize("name", ["mms2d_64", "mms3d_12", "densitystep3d_16", "marshak3d_16",
                                   "infinite3d_10", "densitystep3d_16_levermore", "wendland2d_24",
                                   "wendland3d_9", "periodic2d_16", "periodic3d_13",

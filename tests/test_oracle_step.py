@@ -49,6 +49,73 @@ def test_pcg_matches_dense():
     assert np.max(np.abs(xc - xd)) / np.max(np.abs(xd)) < 1e-13
 
 
+def _marshak_system(n):
+    p = synth.config4(n=n)
+    ptr, idx = neighbors.build(p.pos, p.h, 2.0)
+    fz = operator.frozen(p, ptr, idx)
+    s = operator.assemble(p, ptr, idx, fz)
+    return p, fz, s, operator.rhs(p, fz, s, p.e[:p.n_interior], p.E[:p.n_interior])
+
+
+def _mp_solve(A, b):
+    mpmath.mp.dps = 40
+    M = mpmath.matrix(A.toarray().tolist())
+    return np.array([float(v) for v in mpmath.lu_solve(M, mpmath.matrix(b.tolist()))])
+
+
+def test_solve_accurate_per_unknown_vs_mpmath():
+    """The oracle's solve matches a 40-digit LU solve of the same FP64 system
+    in every unknown to 2e-15 relative: on the radiation-front system (E over
+    three decades at this size) and on a diagonally dominant M-matrix whose
+    solution spans twelve decades, where an error of 1e-16 of the largest
+    unknown would be an error of 1e-4 in the smallest."""
+    p, fz, s, b = _marshak_system(6)
+    xe = _mp_solve(s.A, b)
+    assert xe.max() / xe.min() > 1e3
+    x = linsolve.solve(s.A, b)
+    assert np.max(np.abs(x - xe) / xe) < 2e-15
+    assert linsolve.componentwise(s.A, x, linsolve.residual_ext(s.A, x, b)) < 1e-15
+    import scipy.sparse as sps
+    rng = np.random.default_rng(5)
+    n = 120
+    off = -rng.uniform(0.0, 0.3, n - 1)
+    A = sps.diags([off, np.zeros(n), off], [-1, 0, 1]).tolil()
+    A.setdiag(1.0 + rng.uniform(0.0, 0.2, n) - np.asarray(A.sum(axis=1)).ravel())
+    A = A.tocsr()
+    b = A @ (10.0 ** np.linspace(0.0, -12.0, n))
+    xe = _mp_solve(A, b)
+    assert xe.max() / xe.min() > 1e11
+    x = linsolve.solve(A, b)
+    assert np.max(np.abs(x - xe) / xe) < 2e-15
+    # the PCG path with the componentwise stop (the normwise one alone leaves
+    # errors near 1e-11 in the smallest unknowns here)
+    xc = linsolve.pcg_jacobi(A, b, tol=1e-14, cw_tol=1e-14)[0]
+    assert np.max(np.abs(xc - xe) / xe) < 1e-13
+
+
+def test_pcg_componentwise_stop_on_a_front():
+    """PCG (the path of larger systems) continued until the componentwise
+    measure is met agrees per unknown with the dense solve refined in extended
+    precision; stopped on the normwise test alone it is allowed to stop
+    earlier, never later."""
+    p, fz, s, b = _marshak_system(14)
+    assert p.n_interior > 2000
+    x = linsolve.solve(s.A, b)
+    xd = linsolve.dense(s.A, b)
+    xd = xd + linsolve.dense(s.A, linsolve.residual_ext(s.A, xd, b))
+    assert np.max(np.abs(x - xd) / np.abs(xd)) < 1e-13
+    _, its_norm, _ = linsolve.pcg_jacobi(s.A, b, tol=1e-14)
+    _, its_cw, _ = linsolve.pcg_jacobi(s.A, b, tol=1e-14, cw_tol=1e-14)
+    assert its_cw >= its_norm
+
+
+def test_componentwise_measure_edge_cases():
+    A = __import__("scipy.sparse", fromlist=["csr_matrix"]).csr_matrix(np.diag([2.0, 4.0, 1.0]))
+    x = np.array([1.0, 0.0, 0.0])
+    assert linsolve.componentwise(A, x, np.array([0.2, 0.0, 0.0])) == pytest.approx(0.1)
+    assert linsolve.componentwise(A, x, np.array([0.2, 1e-300, 0.0])) == np.inf
+
+
 def _quartic_root(e_prev, P, rho, cv, sig, dt, c=1.0, a=1.0):
     f = lambda e: rho / dt * (e - e_prev) + c * sig * a * (e / cv) ** 4 - P
     hi = e_prev + dt * P / rho
