@@ -305,6 +305,27 @@ typedef struct {
 int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
              const rt_solve_opts* opts, rt_solve_stats* stats);
 
+/* rt_solve_noalloc: rt_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, options, results and errors as rt_solve, but
+ * the call makes no device allocation and no hipMalloc/hipFree: the gathered
+ * b and x, the Krylov work vectors, block partials and scalars live in one
+ * static device array of the library (256 MiB per GPU, set up by rt_create
+ * and held until the process ends).  Scratch needed: 256-byte-aligned pieces
+ * of 8 bytes x 6n (+ 4 bytes x 6n in RT_PREC_MIXED) plus 3 arrays of block
+ * partials of about n/4 + 4096 doubles, about 54 bytes per unknown in FP64
+ * and 78 in mixed precision: n up to 4,968,256 unknowns in FP64 and
+ * 3,439,552 in mixed precision; a larger matrix is rejected with RT_E_ARG
+ * and a message giving the bytes needed.  The matrix (and its
+ * AMG hierarchy) must come from rt_assemble, whose buffers the V-cycle uses;
+ * the residual rt_newton_step carries between outer iterations is left as
+ * it was.  No per-product timings are recorded (stats->spmv_* are 0).
+ * Every call on one GPU uses the same array and leaves its contents behind:
+ * calls that overlap on one GPU (other streams, other contexts or threads)
+ * race, and so do calls on one matrix overlapping with rt_solve or
+ * rt_newton_step.                                                           */
+int rt_solve_noalloc(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
+                     const rt_solve_opts* opts, rt_solve_stats* stats);
 
 /* ---- one outer iteration of Algorithm 1 ------------------------------------
  * e, E: n_interior doubles, user order, device, holding the iterate

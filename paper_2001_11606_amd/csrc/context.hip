@@ -28,6 +28,36 @@ ReleaseState& release_state() {
   return st;
 }
 
+// Device scratch of the entry point that allocates nothing (rt_solve_noalloc):
+// one array per GPU, in the code object, held until the process ends.  Its
+// name is a host-side stand-in for the device array; the device address is
+// looked up once per device, with that device current, and kept here.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+}  // namespace
+
+int scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return RT_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error("scratch: hipGetSymbolAddress failed on device %d: %s", device,
+              hipGetErrorString(e));
+    return RT_E_DEVICE;
+  }
+  g_scratch_ptr[device] = ptr;
+  return RT_OK;
+}
+
+void* scratch_base(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 
 namespace {
 struct Cached {
@@ -198,6 +228,7 @@ int rt_create(rt_ctx** ctx, int device, void* hip_stream) {
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(device));
+  RT_CHECK(rt::scratch_setup(device));   // the scratch array's address on this device
   rt_ctx* c = new rt_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;

@@ -163,6 +163,11 @@ struct DevBuf {
   }
 };
 
+// Device scratch of rt_solve_noalloc (context.hip): one array per GPU.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+int scratch_setup(int device);    // look up the array's address on a device (current)
+void* scratch_base(int device);   // that address, NULL before scratch_setup
+
 constexpr int kBlock = 256;            // threads per block (4 wavefronts)
 constexpr int kMaxPartials = 2048;     // cap on blocks of reduction kernels
 constexpr int kTileRows = kBlock;      // rows per tile of the tiled SpMV format

@@ -748,6 +748,112 @@ int check_solve_opts(const rt_solve_opts* o) {
 
 }  // namespace rt
 
+namespace rt {
+namespace {
+
+// Bytes of scratch the no-allocation solve carves for n unknowns: the gathered
+// b and x, four FP64 work vectors (six FP32 ones in mixed precision), three
+// arrays of block partials, the fold buffer, the scalars and the stop flag,
+// each piece 256-byte aligned.
+struct Carve {
+  char* base;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    used = (used + 255) / 256 * 256;
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += (count ? count : 1) * sizeof(T);
+    return p;
+  }
+};
+
+Work carve_work(Carve& c, int64_t n, bool mixed, double** bs, double** xs) {
+  Work W;
+  *bs = c.take<double>(n);
+  *xs = c.take<double>(n);
+  W.r64 = c.take<double>(n);
+  W.p64 = c.take<double>(n);
+  W.q64 = c.take<double>(n);
+  W.z64 = c.take<double>(n);
+  if (mixed) {
+    W.r32 = c.take<float>(n);
+    W.p32 = c.take<float>(n);
+    W.q32 = c.take<float>(n);
+    W.z32 = c.take<float>(n);
+    W.d32 = c.take<float>(n);
+    W.w32 = c.take<float>(n);
+  }
+  W.partA = c.take<double>(max_partials(n));
+  W.partB = c.take<double>(max_partials(n));
+  W.partC = c.take<double>(max_partials(n));
+  W.partF = c.take<double>(3 * kMaxPartials);
+  W.scal = c.take<double>(S_COUNT);
+  W.stop = c.take<int32_t>(1);
+  return W;
+}
+
+}  // namespace
+}  // namespace rt
+
+// rt_solve for callers that cannot allocate: every buffer of the solve comes
+// from the device's scratch array; the matrix's own work buffers and the
+// residual it carries between outer iterations are left untouched.
+extern "C" int rt_solve_noalloc(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
+                                const rt_solve_opts* opts, rt_solve_stats* stats) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !A || (A->n > 0 && (!b || !x))) {
+    set_error("rt_solve_noalloc: NULL argument");
+    return RT_E_ARG;
+  }
+  RT_CHECK(check_solve_opts(opts));
+  if (A->levels.empty()) {
+    set_error("rt_solve_noalloc: matrix not assembled");
+    return RT_E_STATE;
+  }
+  const bool mixed = opts->precision == RT_PREC_MIXED;
+  if (mixed && !A->has_fp32) {
+    set_error("rt_solve_noalloc: mixed precision needs a matrix assembled with build_fp32 = 1");
+    return RT_E_STATE;
+  }
+  const int64_t n = A->n;
+  Carve size{nullptr};
+  double *bs = nullptr, *xs = nullptr;
+  (void)carve_work(size, n, mixed, &bs, &xs);
+  if (size.used > kScratchBytes) {
+    set_error("rt_solve_noalloc: %lld unknowns need %zu bytes of scratch in %s, above the "
+              "%zu-byte scratch array", (long long)n, size.used,
+              mixed ? "mixed precision" : "FP64", kScratchBytes);
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  char* base = static_cast<char*>(scratch_base(ctx->device));
+  if (!base) {
+    set_error("rt_solve_noalloc: no scratch address for device %d", ctx->device);
+    return RT_E_STATE;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  rt_solve_stats local{};
+  rt_solve_stats* stt = stats ? stats : &local;
+  *stt = rt_solve_stats{};
+  if (n == 0) return RT_OK;
+  Carve carve{base};
+  const Work W = carve_work(carve, n, mixed, &bs, &xs);
+  // no event timings: recording them would create events
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  int s = gather_sorted(ctx, A->nb, n, b, bs);
+  if (s == RT_OK) s = gather_sorted(ctx, A->nb, n, x, xs);
+  bool valid = false;
+  if (s == RT_OK) s = solve_work(ctx, A, W, bs, xs, opts, stt, nullptr, nullptr, &valid);
+  ctx->profiling = prof;
+  if (s < 0) return s;
+  RT_CHECK(scatter_user(ctx, A->nb, n, xs, x));
+  RT_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return s;
+}
+
 extern "C" int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
                         const rt_solve_opts* opts, rt_solve_stats* stats) {
   using namespace rt;

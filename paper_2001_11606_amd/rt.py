@@ -145,6 +145,8 @@ _SIGS = {
                                      c_int, ctypes.POINTER(rt_newton_stats)]),
     "rt_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
                          ctypes.POINTER(rt_solve_stats)]),
+    "rt_solve_noalloc": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
+                                 ctypes.POINTER(rt_solve_stats)]),
     "rt_solve_gmres": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_gmres_opts),
                                ctypes.POINTER(rt_solve_stats)]),
     "rt_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
@@ -369,6 +371,13 @@ def rt_batch_newton_step(ctx: int, B: int, nprob: int, e: int, E: int, ell: int,
 def rt_solve(ctx: int, A: int, b: int, x: int, opts: rt_solve_opts) -> tuple:
     st = rt_solve_stats()
     s = _check("rt_solve", load().rt_solve(ctx, A, b, x, ctypes.byref(opts), ctypes.byref(st)))
+    return s, st
+
+
+def rt_solve_noalloc(ctx: int, A: int, b: int, x: int, opts: rt_solve_opts) -> tuple:
+    st = rt_solve_stats()
+    s = _check("rt_solve_noalloc", load().rt_solve_noalloc(ctx, A, b, x, ctypes.byref(opts),
+                                                           ctypes.byref(st)))
     return s, st
 
 

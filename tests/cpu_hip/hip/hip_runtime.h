@@ -32,6 +32,8 @@
 
 #define __global__
 #define __device__
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) (&(x))
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
@@ -343,6 +345,11 @@ inline hipError_t hipGetDevice(int* d) {
 }
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "cpuhip error"; }
+// a device symbol's address is the host object's own address here
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  *p = const_cast<void*>(sym);
+  return hipSuccess;
+}
 inline hipError_t hipEventCreate(hipEvent_t* e) {
   *e = (hipEvent_t) new double(0);
   return hipSuccess;
