@@ -260,6 +260,7 @@ def run_ensemble(args):
             tuned = rt.rt_batch_tune(ctx.handle, B, 5)
         rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_FP64, tuned.chosen[0][0])
         rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_MIXED, tuned.chosen[0][1])
+        rt.rt_batch_set_spmv_shape(B, rt.RT_PRODUCT_RESIDUAL, tuned.chosen[0][2])
         e, E = e0.clone(), E0.clone()
         nopts = rt.newton_opts(rt.solve_opts(precision, 0, args.tol, 5000, args.inner_tol, 30))
         s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), 0,
@@ -628,7 +629,7 @@ def run_single(args):
             # SpMV shapes are tuned once per problem, outside the timed region
             tune = ctx.tune(A, reps=5)
             shapes = tune["chosen"]
-            log(f"[bench] tuned SpMV shapes {[(tune['shapes'][a], tune['shapes'][b]) for a, b in shapes]}")
+            log(f"[bench] tuned SpMV shapes {[[tune['shapes'][c] if c >= 0 else None for c in ch] for ch in shapes]}")
         release(ctx, nb, A)
     torch.cuda.synchronize()
 
@@ -656,16 +657,19 @@ def run_single(args):
     nnz_off = info.nnz - info.n
     tile_cols = info.level_tile_cols[0]
     sh = tune["shapes"] if tune else None
-    s64, s32 = (shapes[0] if shapes else (None, None))
+    s64, s32, sres = (shapes[0] if shapes else (None, None, None))
+    if sres is not None and sres < 0:
+        sres = s64
     tiled32 = bool(tile_cols) and (sh is None or sh[s32][2])
     tiled64 = bool(tile_cols) and (sh is None or sh[s64][2])
+    tiledr = bool(tile_cols) and (sh is None or sh[sres][2])
     k32 = (("k_spmv_tiled<float, %d, %d, SP_DOT>" % tuple(sh[s32][:2])) if tiled32 and sh
            else "k_spmv_tiled<float> (default shape)" if tiled32 else "k_spmv<float> (plain CSR)")
-    k64r = (("k_spmv_tiled<double, %d, %d, SP_RESID>" % tuple(sh[s64][:2])) if tiled64 and sh
-            else "k_spmv_tiled<double> SP_RESID" if tiled64 else "k_spmv<double> SP_RESID")
+    k64r = (("k_spmv_tiled<double, %d, %d, SP_RESID>" % tuple(sh[sres][:2])) if tiledr and sh
+            else "k_spmv_tiled<double> SP_RESID" if tiledr else "k_spmv<double> SP_RESID")
     roof32 = _kernel_roof(k32, spmv_bytes(4, nnz_off, n_rows, tile_cols if tiled32 else 0),
                           sum(r.spmv32_calls for r in reps), sum(r.spmv32_seconds for r in reps))
-    roof_res = _kernel_roof(k64r, resid_bytes(nnz_off, n_rows, tile_cols if tiled64 else 0,
+    roof_res = _kernel_roof(k64r, resid_bytes(nnz_off, n_rows, tile_cols if tiledr else 0,
                                               args.cw_tol > 0),
                             sum(r.resid_calls for r in reps), sum(r.resid_seconds for r in reps))
     kernels = [k for k in (roof_res, roof32) if k]
@@ -715,9 +719,9 @@ def run_single(args):
     t2 = time.perf_counter()
     Ab = ctx.assemble(nbb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                       dp.limiter_k, amg=amg)
-    for lvl, (a64, a32) in enumerate((shapes or [])[:ctx.matrix_info(Ab).levels]):
-        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_FP64, a64)
-        rt.rt_matrix_set_spmv_shape(Ab, lvl, rt.RT_PREC_MIXED, a32)
+    for lvl, chosen in enumerate((shapes or [])[:ctx.matrix_info(Ab).levels]):
+        for prod, sh_ in zip((rt.RT_PREC_FP64, rt.RT_PREC_MIXED, rt.RT_PRODUCT_RESIDUAL), chosen):
+            rt.rt_matrix_set_spmv_shape(Ab, lvl, prod, sh_)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     eb = torch.empty(nin, dtype=torch.float64, device=ctx.device)
@@ -761,7 +765,8 @@ def run_single(args):
         "spmv_tune": None if tune is None else {
             "shapes_g_e": tune["shapes"], "chosen": tune["chosen"],
             "level0_us_fp64": [round(t, 1) for t in tune["us"][0][0]],
-            "level0_us_fp32": [round(t, 1) for t in tune["us"][0][1]]},
+            "level0_us_fp32": [round(t, 1) for t in tune["us"][0][1]],
+            "level0_us_fp64_residual": [round(t, 1) for t in tune["us"][0][2]]},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

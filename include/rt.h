@@ -234,29 +234,35 @@ void rt_matrix_free(rt_matrix* A);
  * instead.
  * rt_spmv_shapes writes the (G, E, tiled) of up to max shapes (any pointer
  * may be NULL) and returns how many exist.  rt_matrix_tune times the Krylov-loop product on every
- * level of A with every shape, in FP64 and, when A holds FP32 copies, FP32:
- * one untimed launch, then reps launches between HIP events on the library
- * stream.  It keeps the fastest shape per level and precision for all later
- * products of A and writes the timings (microseconds per product; 0 = not
- * timed) and choices (-1 = none) to *rep when rep is not NULL.  It
- * synchronises the stream and allocates one temporary vector.
+ * level of A with every shape, in FP64 and, when A holds FP32 copies, FP32,
+ * and (with FP32 copies, fine level only) the FP64 residual product b - A x
+ * of the mixed-precision refinement loop: one untimed launch, then reps
+ * launches between HIP events on the library stream.  It keeps the fastest
+ * shape per level and product for all later products of A and writes the
+ * timings (microseconds per product; 0 = not timed) and choices (-1 = none)
+ * to *rep when rep is not NULL.  It synchronises the stream and allocates
+ * temporary vectors.
  * rt_matrix_set_spmv_shape forces a shape (index into the table; -1 restores
  * the default, picked from the level's longest row: tiled shapes with two
  * rows in flight on tiled levels, else the smallest plain shape whose one
- * pass covers the row).  Results of a product do not depend on the shape beyond the order
+ * pass covers the row; the residual product's default is the FP64 product's
+ * shape).  Results of a product do not depend on the shape beyond the order
  * of floating-point additions within a row.                                  */
 #define RT_MAX_LEVELS 16
-#define RT_MAX_SHAPES 16
+#define RT_MAX_SHAPES 24
+#define RT_PRODUCT_RESIDUAL 2     /* rt_matrix_set_spmv_shape: the FP64 residual product */
 typedef struct {
   int levels;                                 /* levels timed                  */
   int shapes;                                 /* shapes timed per level        */
-  double us[RT_MAX_LEVELS][2][RT_MAX_SHAPES]; /* [level][0 FP64, 1 FP32][shape] */
-  int chosen[RT_MAX_LEVELS][2];
+  double us[RT_MAX_LEVELS][3][RT_MAX_SHAPES]; /* [level][0 FP64, 1 FP32, 2 FP64
+                                                 residual][shape]              */
+  int chosen[RT_MAX_LEVELS][3];
 } rt_tune_report;
 
 int rt_spmv_shapes(int* g, int* ent, int* tiled, int max);
 int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep);
-/* precision: RT_PREC_FP64 selects the FP64 product, RT_PREC_MIXED the FP32 one */
+/* precision: RT_PREC_FP64 selects the FP64 product, RT_PREC_MIXED the FP32 one,
+ * RT_PRODUCT_RESIDUAL the FP64 residual product of the refinement loop      */
 int rt_matrix_set_spmv_shape(rt_matrix* A, int level, int precision, int shape);
 
 /* ---- linear solve (Sec. 3.2, the D^-1 operator) ---------------------------

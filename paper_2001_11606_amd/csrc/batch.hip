@@ -537,14 +537,14 @@ int b_solve(rt_ctx* ctx, rt_batch* B, const rt_solve_opts* o, int graph_k, rt_so
   RT_LAUNCH_CHECK();
   RT_CHECK(b_seg(ctx, B, BOP_BB, kTileRows, B->partA.p, nullptr, o->tol * o->tol));
   const int32_t* outer_done = B->flags.p + F_OUTER * np;
-  const int rpb64 = spmv_rows_per_block(L, L.shape64);
+  const int rpb64 = spmv_rows_per_block(L, resid_shape(L));
   std::vector<int32_t> fl;
   bool all = false;
   int refine = 0;
   for (;;) {
     RT_CHECK((launch_spmv_level<double, SP_RESID>(st, L, L.val64.p, L.diag64.p, B->xs.p, B->bs.p,
                                                   nullptr, B->r64.p, mixed ? B->r32.p : nullptr,
-                                                  B->partA.p, nullptr, L.shape64, B->tprob.p,
+                                                  B->partA.p, nullptr, resid_shape(L), B->tprob.p,
                                                   refine > 0 ? outer_done : nullptr)));
     RT_CHECK(b_seg(ctx, B, BOP_OUTER, rpb64, B->partA.p, nullptr, 0.0, mixed ? 1 : 0,
                    o->inner_tol));
@@ -778,10 +778,14 @@ int rt_batch_tune(rt_ctx* ctx, rt_batch* B, int reps, rt_tune_report* rep) {
 int rt_batch_set_spmv_shape(rt_batch* B, int precision, int shape) {
   using namespace rt;
   clear_error();
-  if (!B || (precision != RT_PREC_FP64 && precision != RT_PREC_MIXED) || shape < -1 ||
-      shape >= kNumSpmvShapes) {
+  if (!B || (precision != RT_PREC_FP64 && precision != RT_PREC_MIXED &&
+             precision != RT_PRODUCT_RESIDUAL) || shape < -1 || shape >= kNumSpmvShapes) {
     set_error("rt_batch_set_spmv_shape: bad batch, precision or shape");
     return RT_E_ARG;
+  }
+  if (precision == RT_PRODUCT_RESIDUAL) {   // not part of the replayed PCG graphs
+    B->L.shape_res = shape;
+    return RT_OK;
   }
   (precision == RT_PREC_FP64 ? B->L.shape64 : B->L.shape32) = shape;
   const int slot = precision == RT_PREC_FP64 ? 0 : 1;

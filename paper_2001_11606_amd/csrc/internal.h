@@ -274,6 +274,7 @@ struct Level {
   int64_t n = 0, nnz = 0;       // nnz = off-diagonal entries
   int64_t max_row = 0;          // longest off-diagonal row
   int shape64 = -1, shape32 = -1;   // SpMV row-group shape per precision (-1: by max_row)
+  int shape_res = -1;               // shape of the FP64 residual product (-1: shape64)
   // tiled form (see the file comment); tiled == false: plain CSR products only
   bool tiled = false;
   int64_t ntiles = 0, tile_cols_total = 0;
@@ -296,6 +297,8 @@ template <typename T>
 inline int level_shape(const Level& L) {
   return sizeof(T) == sizeof(double) ? L.shape64 : L.shape32;
 }
+// shape of the FP64 residual product b - A x of the refinement loop
+inline int resid_shape(const Level& L) { return L.shape_res >= 0 ? L.shape_res : L.shape64; }
 }  // namespace rt
 
 struct rt_matrix {

@@ -571,7 +571,7 @@ int residual64(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, const 
   RT_CHECK(pf.begin());
   RT_CHECK((launch_spmv_level<double, SP_RESID>(ctx->stream, L, L.val64.p, L.diag64.p, x, b,
                                                 nullptr, W.r64, r32, W.partA, &nbk,
-                                                L.shape64, nullptr, nullptr, W.partC, w32)));
+                                                resid_shape(L), nullptr, nullptr, W.partC, w32)));
   RT_CHECK(pf.end());
   RT_CHECK(finalize(ctx, W, FIN_RR, nbk, W.partA, nullptr, 0.0, W.partC));
   RT_CHECK(ctx->sync_read(W.scal, sizeof(double) * S_COUNT));

@@ -205,19 +205,12 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   const int64_t i = r0 + tid;
   if (skip && r0 < n && skip[tprob ? tprob[t] : 0]) return;   // a finished problem's tile
   const bool live = i < n;   // grids are padded to a multiple of the XCD count
-  T di = 0, xi = 0, bi = 0, si = 0;
   if (tid == 0) sbase = r0 < n ? rp[r0] & ~(int64_t)3 : 0;
   __syncthreads();
   const int64_t base_e = sbase;   // entries of a tile number far below 2^31
   if (r0 < n) {
     srp[tid] = (int)(rp[live ? i : n] - base_e);
     if (tid == 0) srp[kTileRows] = (int)(rp[r0 + kTileRows < n ? r0 + kTileRows : n] - base_e);
-    if (live) {
-      di = diag[i];
-      xi = x[i];
-      if (MODE == SP_RESID || MODE == SP_SMOOTH) bi = b[i];
-      if (MODE == SP_SMOOTH) si = s[i];
-    }
     const int64_t u0 = toff[t], u1 = toff[t + 1];
     for (int64_t k = tid; k < u1 - u0; k += kBlock) xs[k] = x[tcols[u0 + k]];
   } else {
@@ -272,6 +265,13 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   __syncthreads();
   double acc = 0.0, cwm = 0.0;
   if (live) {
+    // the row's own data is loaded only now, so that its registers are free
+    // while the entries stream
+    const T di = diag[i];
+    const T xi = x[i];
+    T bi = 0, si = 0;
+    if (MODE == SP_RESID || MODE == SP_SMOOTH) bi = b[i];
+    if (MODE == SP_SMOOTH) si = s[i];
     const T ax = di * xi + sy[tid];
     if (MODE == SP_PLAIN) {
       y[i] = ax;
@@ -310,7 +310,8 @@ constexpr SpmvShape kSpmvShapes[] = {{4, 4, false},  {4, 8, false},  {8, 8, fals
                                      {8, 12, false}, {16, 6, false}, {32, 6, false},
                                      {64, 4, false}, {4, 4, true},   {8, 4, true},
                                      {16, 4, true},  {32, 4, true},  {64, 4, true},
-                                     {8, 2, true},   {16, 2, true},  {32, 2, true}};
+                                     {8, 2, true},   {16, 2, true},  {32, 2, true},
+                                     {8, 1, true},   {16, 1, true},  {32, 1, true}};
 constexpr int kNumSpmvShapes = sizeof(kSpmvShapes) / sizeof(kSpmvShapes[0]);
 constexpr int kFirstTiledShape = 7;
 
@@ -385,7 +386,10 @@ int launch_spmv_level(hipStream_t st, const Level& L, const T* val, const T* dia
       case 11: RT_SPMV_T(64, 4); break;
       case 12: RT_SPMV_T(8, 2); break;
       case 13: RT_SPMV_T(16, 2); break;
-      default: RT_SPMV_T(32, 2); break;
+      case 14: RT_SPMV_T(32, 2); break;
+      case 15: RT_SPMV_T(8, 1); break;
+      case 16: RT_SPMV_T(16, 1); break;
+      default: RT_SPMV_T(32, 1); break;
     }
 #undef RT_SPMV_T
   } else {

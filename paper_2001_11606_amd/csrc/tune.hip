@@ -1,8 +1,9 @@
 // SpMV shape autotuning: every level of a hierarchy is multiplied with each
 // row-group shape in FP64 and (when built) FP32, and the fastest shape is
-// kept per level and precision.  The timed launch is the one the Krylov loop
-// issues (y = A x with the per-block x.y partials), on the library stream,
-// bracketed by HIP events.
+// kept per level and precision; on the fine level the FP64 residual product
+// of the refinement loop is timed and chosen on its own.  The timed launches
+// are the ones the solver issues, on the library stream, bracketed by HIP
+// events.
 #include <algorithm>
 #include <cstring>
 
@@ -12,17 +13,21 @@
 namespace rt {
 namespace {
 
-template <typename T>
-int time_shape(rt_ctx* ctx, const Level& L, const T* val, const T* diag, T* y, double* part,
-               int shape, int reps, double* us) {
+// One untimed launch, then reps timed ones of the product in `mode`: the
+// Krylov loop's y = A x with x.y partials (SP_DOT), or the refinement's FP64
+// residual r = b - A x with its FP32 copy, partials and componentwise maxima
+// (SP_RESID, FP64 only).
+template <typename T, int MODE>
+int time_shape(rt_ctx* ctx, const Level& L, const T* val, const T* diag, T* y, float* y32,
+               double* part, double* pmax, int shape, int reps, double* us) {
   hipStream_t st = ctx->stream;
-  // one untimed launch, then reps timed ones
-  RT_CHECK((launch_spmv_level<T, SP_DOT>(st, L, val, diag, diag, nullptr, nullptr, y, nullptr, part,
-                                         nullptr, shape)));
+  auto launch = [&]() {
+    return launch_spmv_level<T, MODE>(st, L, val, diag, diag, diag, nullptr, y, y32, part, nullptr,
+                                      shape, nullptr, nullptr, pmax, nullptr);
+  };
+  RT_CHECK(launch());
   RT_CHECK_HIP(hipEventRecord(ctx->ev0, st));
-  for (int r = 0; r < reps; ++r)
-    RT_CHECK((launch_spmv_level<T, SP_DOT>(st, L, val, diag, diag, nullptr, nullptr, y, nullptr,
-                                           part, nullptr, shape)));
+  for (int r = 0; r < reps; ++r) RT_CHECK(launch());
   RT_CHECK_HIP(hipEventRecord(ctx->ev1, st));
   RT_CHECK_HIP(hipEventSynchronize(ctx->ev1));
   float ms = 0.f;
@@ -50,13 +55,14 @@ int rt_matrix_set_spmv_shape(rt_matrix* A, int level, int precision, int shape) 
   using namespace rt;
   clear_error();
   if (!A || level < 0 || level >= (int)A->levels.size() ||
-      (precision != RT_PREC_FP64 && precision != RT_PREC_MIXED) || shape < -1 ||
-      shape >= kNumSpmvShapes) {
+      (precision != RT_PREC_FP64 && precision != RT_PREC_MIXED &&
+       precision != RT_PRODUCT_RESIDUAL) || shape < -1 || shape >= kNumSpmvShapes) {
     set_error("rt_matrix_set_spmv_shape: bad matrix, level, precision or shape");
     return RT_E_ARG;
   }
   Level& L = A->levels[level];
-  (precision == RT_PREC_FP64 ? L.shape64 : L.shape32) = shape;
+  (precision == RT_PREC_FP64 ? L.shape64 : precision == RT_PREC_MIXED ? L.shape32 : L.shape_res) =
+      shape;
   return RT_OK;
 }
 
@@ -77,25 +83,33 @@ int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep) {
   r->shapes = std::min(kNumSpmvShapes, RT_MAX_SHAPES);
   int64_t nmax = 0;
   for (int l = 0; l < nl; ++l) nmax = std::max(nmax, A->levels[l].n);
-  DevBuf<double> y, part;
+  DevBuf<double> y, part, pmax;
+  DevBuf<float> y32;
   RT_CHECK(y.reserve(std::max<int64_t>(nmax, 1)));
+  RT_CHECK(y32.reserve(std::max<int64_t>(nmax, 1)));
   RT_CHECK(part.reserve(max_partials(nmax)));
+  RT_CHECK(pmax.reserve(max_partials(nmax)));
   for (int l = 0; l < nl; ++l) {
     Level& L = A->levels[l];
-    r->chosen[l][0] = r->chosen[l][1] = -1;
+    r->chosen[l][0] = r->chosen[l][1] = r->chosen[l][2] = -1;
     if (L.n == 0) continue;
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < 3; ++p) {
       if (p == 1 && !A->has_fp32) continue;
+      if (p == 2 && (l > 0 || !A->has_fp32)) continue;   // refinement residuals: fine level
       double best = 0.0;
       int arg = -1;
       for (int s = 0; s < r->shapes; ++s) {
         if (kSpmvShapes[s].tiled && !L.tiled) continue;
         double us = 0.0;
         if (p == 0)
-          RT_CHECK(time_shape<double>(ctx, L, L.val64.p, L.diag64.p, y.p, part.p, s, reps, &us));
+          RT_CHECK((time_shape<double, SP_DOT>(ctx, L, L.val64.p, L.diag64.p, y.p, nullptr, part.p,
+                                               nullptr, s, reps, &us)));
+        else if (p == 1)
+          RT_CHECK((time_shape<float, SP_DOT>(ctx, L, L.val32.p, L.diag32.p, (float*)y.p, nullptr,
+                                              part.p, nullptr, s, reps, &us)));
         else
-          RT_CHECK(time_shape<float>(ctx, L, L.val32.p, L.diag32.p, (float*)y.p, part.p, s, reps,
-                                     &us));
+          RT_CHECK((time_shape<double, SP_RESID>(ctx, L, L.val64.p, L.diag64.p, y.p, y32.p, part.p,
+                                                 pmax.p, s, reps, &us)));
         r->us[l][p][s] = us;
         if (arg < 0 || us < best) {
           best = us;
@@ -103,7 +117,7 @@ int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep) {
         }
       }
       r->chosen[l][p] = arg;
-      (p == 0 ? L.shape64 : L.shape32) = arg;
+      (p == 0 ? L.shape64 : p == 1 ? L.shape32 : L.shape_res) = arg;
     }
   }
   return RT_OK;

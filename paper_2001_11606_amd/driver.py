@@ -74,17 +74,18 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
               shapes: Optional[list] = None, sorted_state: bool = True):
     """One backward-Euler step.  Returns (e, E, A, report) with e, E the new
     interior energies (device tensors, user order).  shapes: per-level
-    (FP64, FP32) SpMV shape indices, e.g. the "chosen" list of Context.tune on
-    an earlier matrix of the same problem, applied after assembly.
+    (FP64, FP32[, FP64 residual]) SpMV shape indices (-1: default), e.g. the
+    "chosen" list of Context.tune on an earlier matrix of the same problem,
+    applied after assembly.
     sorted_state: keep e, E in the library's sorted order during the outer
     iterations (one conversion each way per step instead of per iteration)."""
     A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                      dp.limiter_k, amg=amg, A=A)
     if shapes:
         levels = ctx.matrix_info(A).levels
-        for lvl, (s64, s32) in enumerate(shapes[:levels]):
-            rt.rt_matrix_set_spmv_shape(A, lvl, rt.RT_PREC_FP64, s64)
-            rt.rt_matrix_set_spmv_shape(A, lvl, rt.RT_PREC_MIXED, s32)
+        for lvl, chosen in enumerate(shapes[:levels]):
+            for prod, s in zip((rt.RT_PREC_FP64, rt.RT_PREC_MIXED, rt.RT_PRODUCT_RESIDUAL), chosen):
+                rt.rt_matrix_set_spmv_shape(A, lvl, prod, s)
     nin = dp.n_interior
     import torch
     e_user = dp.arrays["e"][:nin].clone()

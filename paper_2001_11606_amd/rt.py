@@ -93,13 +93,14 @@ class rt_newton_stats(ctypes.Structure):
 
 
 RT_MAX_LEVELS = 16
-RT_MAX_SHAPES = 16
+RT_MAX_SHAPES = 24
+RT_PRODUCT_RESIDUAL = 2
 
 
 class rt_tune_report(ctypes.Structure):
     _fields_ = [("levels", c_int), ("shapes", c_int),
-                ("us", ((c_dbl * RT_MAX_SHAPES) * 2) * RT_MAX_LEVELS),
-                ("chosen", (c_int * 2) * RT_MAX_LEVELS)]
+                ("us", ((c_dbl * RT_MAX_SHAPES) * 3) * RT_MAX_LEVELS),
+                ("chosen", (c_int * 3) * RT_MAX_LEVELS)]
 
 
 # name -> (restype, argtypes)
@@ -525,13 +526,14 @@ class Context:
 
     def tune(self, A: int, reps: int = 5) -> dict:
         """Time every SpMV shape on every level; keeps the fastest per level and
-        precision.  Returns {"shapes": [(G, E)], "us": [[fp64 list, fp32 list]],
-        "chosen": [[fp64, fp32]]}."""
+        product.  Returns {"shapes": [(G, E, tiled)], "us": [[fp64 list, fp32
+        list, fp64 residual list]], "chosen": [[fp64, fp32, fp64 residual]]}
+        (-1 / zero timings: not timed)."""
         rep = rt_matrix_tune(self.handle, A, reps)
         return {"shapes": rt_spmv_shapes()[:rep.shapes],
-                "us": [[list(rep.us[l][p][:rep.shapes]) for p in range(2)]
+                "us": [[list(rep.us[l][p][:rep.shapes]) for p in range(3)]
                        for l in range(rep.levels)],
-                "chosen": [[rep.chosen[l][0], rep.chosen[l][1]] for l in range(rep.levels)]}
+                "chosen": [[rep.chosen[l][p] for p in range(3)] for l in range(rep.levels)]}
 
     def solve(self, A: int, b, x, opts: rt_solve_opts):
         torch = self.torch

@@ -127,7 +127,7 @@ def check_case(ctx, name, prob):
     # (the widest shapes are slow to emulate: every shuffle is a thread barrier here)
     for shape in (sweep if not QUICK else (0, 7)):
         for lvl in range(info.levels):
-            for prec in (0, 1):
+            for prec in (0, 1, 2):
                 rt.rt_matrix_set_spmv_shape(c.A, lvl, prec, shape)
         for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
             x = np.zeros(nin)

@@ -50,18 +50,18 @@ def _solve(ctx, A, b, precision, tol):
 
 
 @pytest.mark.parametrize("name", ["marshak3d_16", "mms2d_64"])
-@pytest.mark.parametrize("shape", range(15))
+@pytest.mark.parametrize("shape", range(18))
 def test_every_shape_solves(ctx, built, name, shape):
     from paper_2001_11606_amd import rt
     shapes = rt.rt_spmv_shapes()
-    assert len(shapes) == 15
+    assert len(shapes) == 18
     prob, b, x_ref, (dp, nb, A) = built[name]
     info = ctx.matrix_info(A)
     assert info.level_tile_cols[0] > 0, "the fine level of these cases is tiled"
     say(f"[shape] {name} shape={shapes[shape]} levels={info.levels} "
         f"tiled={[info.level_tile_cols[l] > 0 for l in range(info.levels)]}")
     for lvl in range(info.levels):
-        for prec in (rt.RT_PREC_FP64, rt.RT_PREC_MIXED):
+        for prec in (rt.RT_PREC_FP64, rt.RT_PREC_MIXED, rt.RT_PRODUCT_RESIDUAL):
             rt.rt_matrix_set_spmv_shape(A, lvl, prec, shape)
     try:
         scale = np.max(np.abs(x_ref))
@@ -71,7 +71,7 @@ def test_every_shape_solves(ctx, built, name, shape):
         assert np.max(np.abs(x32 - x_ref)) / scale <= 1e-10
     finally:
         for lvl in range(info.levels):
-            for prec in (rt.RT_PREC_FP64, rt.RT_PREC_MIXED):
+            for prec in (rt.RT_PREC_FP64, rt.RT_PREC_MIXED, rt.RT_PRODUCT_RESIDUAL):
                 rt.rt_matrix_set_spmv_shape(A, lvl, prec, -1)
 
 
@@ -84,12 +84,15 @@ def test_tune_reports_and_keeps_choice(ctx, built):
     assert len(rep["us"]) == info.levels
     for lvl in range(info.levels):
         tiled = info.level_tile_cols[lvl] > 0
-        for p in range(2):
+        # FP64 and FP32 products on every level, the FP64 residual on the fine one
+        for p in (range(3) if lvl == 0 else range(2)):
             for s, t in enumerate(rep["us"][lvl][p]):
                 assert (t > 0) if (tiled or not rep["shapes"][s][2]) else (t == 0)
             c = rep["chosen"][lvl][p]
             assert 0 <= c < len(rep["shapes"])
             assert rep["us"][lvl][p][c] == min(t for t in rep["us"][lvl][p] if t > 0)
+        if lvl > 0:
+            assert rep["chosen"][lvl][2] == -1
     x = _solve(ctx, A, b, rt.RT_PREC_MIXED, 1e-12)
     assert np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref)) <= 1e-10
 
@@ -97,7 +100,7 @@ def test_tune_reports_and_keeps_choice(ctx, built):
 def test_shape_arguments_rejected(ctx, built):
     from paper_2001_11606_amd import rt
     A = built["mms2d_64"][3][2]
-    for args in ((99, rt.RT_PREC_FP64, 0), (0, 7, 0), (0, rt.RT_PREC_FP64, 15),
-                 (0, rt.RT_PREC_FP64, -2)):
+    for args in ((99, rt.RT_PREC_FP64, 0), (0, 7, 0), (0, rt.RT_PREC_FP64, 18),
+                 (0, rt.RT_PREC_FP64, -2), (0, 3, 0)):
         with pytest.raises(rt.RtError):
             rt.rt_matrix_set_spmv_shape(A, *args)
