@@ -558,6 +558,35 @@ def _kernel_roof(name, nbytes, calls, seconds):
             "device_ms": round(1e3 * seconds, 3)}
 
 
+def precond_leg(ctx, dp, args, ref, steps=2):
+    """The same step with the aggregation V-cycle (strength-based aggregates,
+    up to eight levels) in place of Jacobi, mixed and FP64 at the same
+    tolerances: hierarchy sizes, iterations, mean solve time per step and the
+    largest relative difference from the 1e-14 FP64 step `ref` (e, E)."""
+    import torch
+    from paper_2001_11606_amd import rt
+    amg = rt.amg_opts(max_levels=8, build_fp32=1)
+    out = {}
+    for prec, key in ((rt.RT_PREC_MIXED, "mixed"), (rt.RT_PREC_FP64, "fp64")):
+        solve = bench_solve_opts(prec, 1, args.tol, args.cw_tol, args.inner_tol)
+        e, E, A, rep, nb = run_step(ctx, dp, solve, args.outer, amg)   # warm-up
+        release(ctx, nb, A)
+        t = []
+        for _ in range(steps):
+            e, E, A, rep, nb = run_step(ctx, dp, solve, args.outer, amg)
+            t.append(rep.solve_seconds)
+            info = ctx.matrix_info(A)
+            release(ctx, nb, A)
+        torch.cuda.synchronize()
+        out["levels"] = info.levels
+        out["level_n"] = list(info.level_n[:info.levels])
+        out[f"solve_s_{key}"] = round(sum(t) / len(t), 5)
+        out[f"krylov_{key}"] = rep.krylov
+        out[f"max_rel_err_E_{key}"] = _max_rel(E, ref[1])
+        out[f"max_rel_err_e_{key}"] = _max_rel(e, ref[0])
+    return out
+
+
 def densitystep_leg(ctx, args, steps=3):
     """Mixed against FP64 on the density-step recipe at 128^3 (2,097,152
     particles, tens of Krylov iterations per solve), same options as the main
@@ -588,6 +617,7 @@ def densitystep_leg(ctx, args, steps=3):
         out[f"max_rel_err_E_{key}"] = _max_rel(E, ER)
         out[f"max_rel_err_e_{key}"] = _max_rel(e, eR)
     out["ratio_fp64_over_mixed"] = round(res["fp64"] / res["mixed"], 3)
+    out["vcycle"] = precond_leg(ctx, dp, args, (eR, ER))
     del dp
     return out
 
@@ -705,6 +735,10 @@ def run_single(args):
                            rep64.spmv64_calls, rep64.spmv64_seconds)
         if r64:
             cmp["fp64_cg_product"] = r64
+    amg_leg = None
+    if not args.no_fp64 and args.precond == 0:
+        log("[bench] V-cycle leg")
+        amg_leg = precond_leg(ctx, dp, args, (eR, ER))
     c3 = None
     if args.workload == "marshak3d" and not args.no_densitystep:
         log("[bench] density-step leg (mixed vs FP64 at 128^3)")
@@ -760,7 +794,7 @@ def run_single(args):
                    "precond": "amg" if args.precond == 1 else "jacobi",
                    "tol": args.tol, "cw_tol": args.cw_tol, "inner_tol": args.inner_tol},
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp,
-        "mixed_vs_fp64_densitystep3d": c3, "phases": phases,
+        "vcycle": amg_leg, "mixed_vs_fp64_densitystep3d": c3, "phases": phases,
         "solve_particle_updates_per_s": solve_rate,
         "spmv_tune": None if tune is None else {
             "shapes_g_e": tune["shapes"], "chosen": tune["chosen"],

@@ -181,7 +181,16 @@ typedef struct {
 typedef struct {
   int max_levels;        /* AMG levels including the fine one; 1 = Jacobi only */
   int coarse_size;       /* stop coarsening at or below this many unknowns     */
-  double strength;       /* strength-of-connection threshold theta             */
+  double strength;       /* strength-of-connection threshold theta: a_ij couples
+                            i and j strongly when |a_ij| >= theta sqrt(m_i m_j),
+                            m_i the largest |a_ik| of row i; rows whose
+                            off-diagonal sum is below 5% of a_ii stay out of
+                            the coarse space; aggregates grow from one root per
+                            neighbour-search cell (Morton block of cells on
+                            coarser levels) over strong couplings.  theta <= 0:
+                            each cell / Morton block is one aggregate
+                            (geometric aggregation).  The hierarchy is rebuilt
+                            with every rt_assemble.                           */
   int build_fp32;        /* 1: also build the FP32 copies for RT_PREC_MIXED    */
   int tiled_spmv;        /* 1: also build the tiled product form of each level
                             (16-bit tile-local columns, x staged in LDS)      */
@@ -194,6 +203,10 @@ typedef struct {
                             interval [1/4, 1] that contains the upper part of
                             its spectrum, which lies in (0, 1])               */
   int smoother_degree;   /* 1..8, Chebyshev only                              */
+  int cycle;             /* 1: V-cycle; 2: W-cycle (on every level above the
+                            coarsest, two coarse corrections, the second from
+                            the residual of the first: the same symmetric
+                            operator as two steps of the coarse cycle)        */
 } rt_amg_opts;
 
 #define RT_SMOOTHER_L1_JACOBI 0
@@ -201,9 +214,10 @@ typedef struct {
 
 int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
                 const rt_amg_opts* amg /* NULL = defaults */, rt_matrix** A);
-/* AMG defaults: max_levels 8, coarse_size 256, strength 0.08, build_fp32 1,
- * tiled_spmv 1, smoother RT_SMOOTHER_L1_JACOBI, smoother_degree 2.
- * Errors: RT_E_ARG for an unknown smoother or a degree outside 1..8.       */
+/* AMG defaults: max_levels 8, coarse_size 256, strength 0.25, build_fp32 1,
+ * tiled_spmv 1, smoother RT_SMOOTHER_L1_JACOBI, smoother_degree 2, cycle 1.
+ * Errors: RT_E_ARG for an unknown smoother, a degree outside 1..8 or a cycle
+ * other than 1 or 2.                                                        */
 
 typedef struct {
   int64_t n;             /* unknowns = interior particles                     */

@@ -2,15 +2,31 @@
 //
 // The paper preconditions its Krylov solve with algebraic multigrid, set up
 // once per time step and reused for every outer iteration (Sec. 3.2); it
-// fixes no AMG parameters.  This hierarchy uses unsmoothed aggregation with
-// aggregates taken from the neighbour-search grid: level 1 aggregates the
-// interior particles of one cell, level l+1 aggregates the 2^dim cells of a
-// Morton block of level l.  Because particles are sorted by Morton cell key,
-// every aggregate is a contiguous run of rows at every level, so restriction
-// is a segmented sum, prolongation a broadcast, and a coarse row has at most
-// 3^dim entries.  The coarse operators are Galerkin products P^T A P with the
-// piecewise-constant P (sums of fine entries by aggregate pair), computed
-// with a fixed summation order.
+// fixes no AMG parameters.  This hierarchy uses aggregation (unsmoothed
+// piecewise-constant prolongation) built from the strength of the couplings:
+//
+//   strength: a_ij couples i and j strongly when
+//       |a_ij| >= theta sqrt(m_i m_j),   m_i = max_k |a_ik| (off-diagonal),
+//     the classical relative measure made symmetric; a row whose
+//     off-diagonal sum is below kCoupled a_ii is left out of the coarse space
+//     (one Jacobi sweep already reduces its error by more than 1/kCoupled), so
+//     a system dominated by its diagonal, such as cold material at a
+//     radiation front, is not coarsened at all;
+//   aggregates: candidate blocks are the neighbour-search cells on the fine
+//     level and Morton blocks of 2^dim cells on coarser ones.  In each of
+//     kAggRounds rounds every block elects as a root its first unassigned
+//     node with no strongly coupled assigned neighbour, and unassigned nodes
+//     join the strongest strongly coupled new root; then, twice, unassigned
+//     nodes join the aggregate of their strongest strongly coupled assigned
+//     neighbour, and the rest form their own.
+//     With theta <= 0 each candidate block is one aggregate (geometric
+//     aggregation).
+//
+// Aggregates are numbered in the order of their first (root) node, so coarse
+// levels keep the Morton locality; the members of every aggregate are listed
+// in ascending order, and restriction, the Galerkin products P^T A P (sums of
+// fine entries by aggregate pair) and the coarse diagonals are sums in that
+// fixed order.
 //
 // V-cycle (symmetric, so it is a valid CG preconditioner): pre-smoothing
 // from zero, residual, restriction, coarse correction, prolongation,
@@ -46,8 +62,12 @@ __device__ __forceinline__ T wave_min(T v) {
   return v;
 }
 
-// new-aggregate flags: level 0 groups equal cell codes, coarser levels equal
-// parent codes (code >> dim)
+constexpr double kCoupled = 0.05;   // off-diagonal row sum / a_ii below which a row stays fine
+constexpr int kAggRounds = 6;       // root elections per level
+constexpr int kStrG = 16;           // lanes per row of the strength kernels
+
+// candidate-block starts: level 0 groups equal cell codes, coarser levels
+// equal parent codes (code >> dim)
 __global__ void k_agg_flags(int64_t n, int shift, const uint64_t* __restrict__ code,
                             int32_t* __restrict__ flag) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -55,36 +75,215 @@ __global__ void k_agg_flags(int64_t n, int shift, const uint64_t* __restrict__ c
   flag[i] = (i == 0 || (code[i] >> shift) != (code[i - 1] >> shift)) ? 1 : 0;
 }
 
-__global__ void k_agg_finish(int64_t n, int shift, const uint64_t* __restrict__ code,
-                             const int32_t* __restrict__ flag, int32_t* __restrict__ pmap,
-                             int32_t* __restrict__ crange, uint64_t* __restrict__ ccode,
-                             int64_t nc) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t I = pmap[i] - 1;      // inclusive scan -> 0-based
-  pmap[i] = I;
-  if (flag[i]) {
-    crange[I] = (int32_t)i;
-    ccode[I] = code[i] >> shift;
-  }
-  if (i == n - 1) crange[nc] = (int32_t)n;
+__device__ __forceinline__ bool strong_pair(double aij, double mi, double mj, double theta) {
+  return aij > 0.0 && aij >= theta * sqrt(mi * mj);
 }
 
+// m_i = max_k |a_ik| and whether row i takes part in the coarse space
+__global__ void __launch_bounds__(kBlock)
+k_row_strength(int64_t n, const int64_t* __restrict__ rp, const double* __restrict__ val,
+               const double* __restrict__ diag, double* __restrict__ mrow,
+               int32_t* __restrict__ coupled) {
+  const int lane = threadIdx.x & (kStrG - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kStrG;
+  if (i >= n) return;   // whole groups leave together
+  double m = 0.0, sum = 0.0;
+  for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kStrG) {
+    const double a = fabs(val[k]);
+    m = fmax(m, a);
+    sum += a;
+  }
+  m = group_max<kStrG>(m);
+  sum = group_sum<kStrG>(sum);
+  if (lane == 0) {
+    mrow[i] = m;
+    coupled[i] = sum >= kCoupled * diag[i] ? 1 : 0;
+  }
+}
+
+// aggregation state: -2 left out, -1 unassigned, else the aggregate's root node.
+// A row starts unassigned when it takes part and has a strong coupling.
+__global__ void __launch_bounds__(kBlock)
+k_agg_init(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const double* __restrict__ mrow,
+           const int32_t* __restrict__ coupled, double theta, int32_t* __restrict__ agg) {
+  const int lane = threadIdx.x & (kStrG - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kStrG;
+  if (i >= n) return;
+  int cnt = 0;
+  if (coupled[i]) {
+    const double mi = mrow[i];
+    for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kStrG) {
+      const int32_t j = col[k];
+      if (coupled[j] && strong_pair(fabs(val[k]), mi, mrow[j], theta)) ++cnt;
+    }
+  }
+  cnt = group_sum<kStrG>(cnt);
+  if (lane == 0) agg[i] = cnt > 0 ? -1 : -2;
+}
+
+__global__ void k_fill_i32v(int64_t n, int32_t* __restrict__ p, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// every candidate block elects its first unassigned node none of whose strong
+// neighbours is assigned yet, so that a new aggregate does not start at the
+// edge of an existing one (the minimum is the same whatever the order of the
+// atomics); geometric: the block's first node
+__global__ void __launch_bounds__(kBlock)
+k_agg_elect(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+            const double* __restrict__ val, const double* __restrict__ mrow,
+            const int32_t* __restrict__ coupled, const int32_t* __restrict__ bid,
+            const int32_t* __restrict__ agg, double theta, int geometric,
+            int32_t* __restrict__ root) {
+  const int lane = threadIdx.x & (kStrG - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kStrG;
+  if (i >= n || agg[i] != -1) return;   // uniform over the group
+  int busy = 0;
+  if (!geometric) {
+    const double mi = mrow[i];
+    for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kStrG) {
+      const int32_t j = col[k];
+      if (agg[j] >= 0 && coupled[j] && strong_pair(fabs(val[k]), mi, mrow[j], theta)) busy = 1;
+    }
+    busy = group_max<kStrG>(busy);
+  }
+  if (lane == 0 && !busy) atomicMin(&root[bid[i] - 1], (int32_t)i);
+}
+
+// the strongest candidate over a group: larger coupling, then smaller index
+template <int G>
+__device__ __forceinline__ void group_best(double& v, int32_t& j) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const double w = __shfl_xor(v, o, G);
+    const int32_t q = __shfl_xor(j, o, G);
+    if (w > v || (w == v && q >= 0 && (j < 0 || q < j))) {
+      v = w;
+      j = q;
+    }
+  }
+}
+
+// one round: a new root forms its aggregate; an unassigned node joins the
+// strongest strongly coupled new root (geometric: its own block's root)
+__global__ void __launch_bounds__(kBlock)
+k_agg_assign(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+             const double* __restrict__ val, const double* __restrict__ mrow,
+             const int32_t* __restrict__ coupled, const int32_t* __restrict__ bid,
+             const int32_t* __restrict__ root, double theta, int geometric,
+             int32_t* __restrict__ agg) {
+  const int lane = threadIdx.x & (kStrG - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kStrG;
+  if (i >= n) return;
+  if (agg[i] != -1) return;   // uniform over the group
+  const int32_t ri = root[bid[i] - 1];
+  if (ri == (int32_t)i || geometric) {
+    if (lane == 0) agg[i] = ri;
+    return;
+  }
+  const double mi = mrow[i];
+  double bv = -1.0;
+  int32_t bj = -1;
+  for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kStrG) {
+    const int32_t j = col[k];
+    const double a = fabs(val[k]);
+    if (root[bid[j] - 1] == j && coupled[j] && strong_pair(a, mi, mrow[j], theta) &&
+        (a > bv || (a == bv && j < bj))) {
+      bv = a;
+      bj = j;
+    }
+  }
+  group_best<kStrG>(bv, bj);
+  if (lane == 0 && bj >= 0) agg[i] = bj;
+}
+
+// after the rounds: an unassigned node joins the aggregate of its strongest
+// strongly coupled assigned neighbour (as assigned before this pass); if it
+// has none it stays unassigned (last pass: forms its own)
+__global__ void __launch_bounds__(kBlock)
+k_agg_join(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const double* __restrict__ mrow,
+           const int32_t* __restrict__ coupled, double theta, int last,
+           const int32_t* __restrict__ agg_in, int32_t* __restrict__ agg_out) {
+  const int lane = threadIdx.x & (kStrG - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kStrG;
+  if (i >= n) return;
+  const int32_t ai = agg_in[i];
+  if (ai != -1) {
+    if (lane == 0) agg_out[i] = ai;
+    return;
+  }
+  const double mi = mrow[i];
+  double bv = -1.0;
+  int32_t bj = -1;
+  for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kStrG) {
+    const int32_t j = col[k];
+    const double a = fabs(val[k]);
+    if (agg_in[j] >= 0 && coupled[j] && strong_pair(a, mi, mrow[j], theta) &&
+        (a > bv || (a == bv && j < bj))) {
+      bv = a;
+      bj = j;
+    }
+  }
+  group_best<kStrG>(bv, bj);
+  if (lane == 0) agg_out[i] = bj >= 0 ? agg_in[bj] : (last ? (int32_t)i : -1);
+}
+
+// aggregates numbered by their root node: lead = root flags; rank (inclusive
+// scan of lead) gives the number; the coarse node takes its root's code
+__global__ void k_agg_lead(int64_t n, const int32_t* __restrict__ agg, int32_t* __restrict__ lead) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) lead[i] = agg[i] == (int32_t)i ? 1 : 0;
+}
+
+__global__ void k_agg_number(int64_t n, int shift, const int32_t* __restrict__ agg,
+                             const int32_t* __restrict__ rank, const uint64_t* __restrict__ code,
+                             int32_t* __restrict__ pmap, uint64_t* __restrict__ ccode,
+                             int32_t* __restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t a = agg[i];
+  const int32_t I = a >= 0 ? rank[a] - 1 : -1;
+  pmap[i] = I;
+  if (a == (int32_t)i) ccode[I] = code[i] >> shift;
+  if (I >= 0) atomicAdd(&cnt[I], 1);
+}
+
+__global__ void k_agg_members(int64_t n, const int32_t* __restrict__ pmap,
+                              int32_t* __restrict__ cur, int32_t* __restrict__ amem) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t I = pmap[i];
+  if (I >= 0) amem[atomicAdd(&cur[I], 1)] = (int32_t)i;
+}
+
+__global__ void k_i64_to_i32(int64_t n, const int64_t* __restrict__ a, int32_t* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
+}
+
+// Coarse row I = sum over the members of aggregate I (one wavefront per
+// coarse row, members in ascending order): the distinct coarse columns in
+// ascending order, each the sum of the members' entries mapping to it; the
+// entries mapping to I itself and the members' diagonals form the coarse
+// diagonal.  Entries of rows left out of the coarse space (pmap -1) drop out.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
-k_galerkin(int64_t nc, const int32_t* __restrict__ crange, const int64_t* __restrict__ rp,
-           const int32_t* __restrict__ col, const double* __restrict__ val,
-           const double* __restrict__ diag, const int32_t* __restrict__ pmap,
-           int64_t* __restrict__ cnt, const int64_t* __restrict__ crp, int32_t* __restrict__ ccol,
+k_galerkin(int64_t nc, const int64_t* __restrict__ crange, const int32_t* __restrict__ amem,
+           const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+           const double* __restrict__ val, const double* __restrict__ diag,
+           const int32_t* __restrict__ pmap, int64_t* __restrict__ cnt,
+           const int64_t* __restrict__ crp, int32_t* __restrict__ ccol,
            double* __restrict__ cval, double* __restrict__ cdiag) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   if (I >= nc) return;   // whole wavefront exits together
-  const int64_t f0 = crange[I], f1 = crange[I + 1];
-  const int64_t e0 = rp[f0], e1 = rp[f1];
+  const int64_t m0 = crange[I], m1 = crange[I + 1];
   double dsum = 0.0;
   if (FILL) {
-    for (int64_t i = f0 + lane; i < f1; i += kWave) dsum += diag[i];
+    for (int64_t q = m0 + lane; q < m1; q += kWave) dsum += diag[amem[q]];
     dsum = group_sum<kWave>(dsum);
   }
   int32_t last = -1;
@@ -92,16 +291,22 @@ k_galerkin(int64_t nc, const int32_t* __restrict__ crange, const int64_t* __rest
   int64_t count = 0;
   while (true) {
     int32_t m = INT_MAX;
-    for (int64_t k = e0 + lane; k < e1; k += kWave) {
-      const int32_t pc = pmap[col[k]];
-      if (pc > last && pc < m) m = pc;
+    for (int64_t q = m0; q < m1; ++q) {
+      const int32_t i = amem[q];
+      for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kWave) {
+        const int32_t pc = pmap[col[k]];
+        if (pc > last && pc < m) m = pc;
+      }
     }
     m = wave_min(m);
     if (m == INT_MAX) break;
     if (FILL) {
       double sum = 0.0;
-      for (int64_t k = e0 + lane; k < e1; k += kWave)
-        if (pmap[col[k]] == m) sum += val[k];
+      for (int64_t q = m0; q < m1; ++q) {
+        const int32_t i = amem[q];
+        for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kWave)
+          if (pmap[col[k]] == m) sum += val[k];
+      }
       sum = group_sum<kWave>(sum);
       if (m == (int32_t)I) {
         dsum += sum;
@@ -211,23 +416,38 @@ __global__ void k_scale(int64_t n, const T* __restrict__ s, const T* __restrict_
   if (i < n) x[i] = s[i] * b[i];
 }
 
+// bc[I] = sum of r over the members of aggregate I, in ascending order
 template <typename T>
-__global__ void k_restrict(int64_t nc, const int32_t* __restrict__ crange, const T* __restrict__ r,
+__global__ void k_restrict(int64_t nc, const int64_t* __restrict__ crange,
+                           const int32_t* __restrict__ amem, const T* __restrict__ r,
                            T* __restrict__ bc, const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
   int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (I >= nc) return;
   T s = 0;
-  for (int32_t i = crange[I]; i < crange[I + 1]; ++i) s += r[i];
+  for (int64_t q = crange[I]; q < crange[I + 1]; ++q) s += r[amem[q]];
   bc[I] = s;
 }
 
+// x += y
+template <typename T>
+__global__ void k_axpy1(int64_t n, const T* __restrict__ y, T* __restrict__ x,
+                        const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += y[i];
+}
+
+// x += P xc (rows left out of the coarse space get nothing)
 template <typename T>
 __global__ void k_prolong(int64_t n, const int32_t* __restrict__ pmap, const T* __restrict__ xc,
                           T* __restrict__ x, const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) x[i] += xc[pmap[i]];
+  if (i < n) {
+    const int32_t I = pmap[i];
+    if (I >= 0) x[i] += xc[I];
+  }
 }
 
 // Chebyshev step: d = c1 d + c2 D1^-1 r (c1 = 0 on the first step), then
@@ -254,6 +474,8 @@ template <> struct LevelBufs<double> {
   static double* t(Level& L) { return L.t64.p; }
   static double* r(Level& L) { return L.r64.p; }
   static double* d(Level& L) { return L.d64.p; }
+  static double* wr(Level& L) { return L.wr64.p; }
+  static double* wx(Level& L) { return L.wx64.p; }
 };
 template <> struct LevelBufs<float> {
   static const float* val(const Level& L) { return L.val32.p; }
@@ -264,52 +486,130 @@ template <> struct LevelBufs<float> {
   static float* t(Level& L) { return L.t32.p; }
   static float* r(Level& L) { return L.r32.p; }
   static float* d(Level& L) { return L.d32.p; }
+  static float* wr(Level& L) { return L.wr32.p; }
+  static float* wx(Level& L) { return L.wx32.p; }
 };
 
 // Values (and columns) of the coarse level C = P^T F P.
 int galerkin_fill(rt_ctx* ctx, const Level& F, Level& C) {
   hipLaunchKernelGGL((k_galerkin<true>), dim3(grid_for(C.n * kWave)), dim3(kBlock), 0,
-                     ctx->stream, C.n, F.crange.p, F.rp.p, F.col.p, F.val64.p, F.diag64.p,
-                     F.pmap.p, nullptr, C.rp.p, C.col.p, C.val64.p, C.diag64.p);
+                     ctx->stream, C.n, F.crange.p, F.amem.p, F.rp.p, F.col.p, F.val64.p,
+                     F.diag64.p, F.pmap.p, nullptr, C.rp.p, C.col.p, C.val64.p, C.diag64.p);
   RT_LAUNCH_CHECK();
   return RT_OK;
 }
 
-// Build level l+1 from level l: aggregation maps, coarse CSR structure, and
-// the coarse columns and values, so that the new level is complete before it
-// serves as the fine level of the next one.
-int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim) {
+// Aggregates of level l (L.pmap, L.crange, L.amem) and the codes of their
+// coarse nodes; returns the number of aggregates.
+int aggregate(rt_ctx* ctx, Level& L, int shift, double theta, DevBuf<uint64_t>& ccode,
+              int64_t* nc_out) {
   hipStream_t st = ctx->stream;
-  Level& L = A->levels[l];
   const int64_t n = L.n;
-  const int shift = l == 0 ? 0 : dim;
-  DevBuf<int32_t> flag;
-  RT_CHECK(flag.reserve(n));
+  const bool geometric = !(theta > 0.0);
+  DevBuf<int32_t> flag, bid, coupled, agg, agg2, root;
+  DevBuf<double> mrow;
+  for (auto* b : {&flag, &bid, &coupled, &agg, &agg2}) RT_CHECK(b->reserve(n));
+  RT_CHECK(mrow.reserve(n));
   RT_CHECK(L.pmap.reserve(n));
+  // candidate blocks: bid = 1-based block number of every node
   hipLaunchKernelGGL(k_agg_flags, dim3(grid_for(n)), dim3(kBlock), 0, st, n, shift, L.code.p,
                      flag.p);
   RT_LAUNCH_CHECK();
-  RT_CHECK((scan<int32_t, int32_t>(ctx, flag.p, L.pmap.p, n, true)));
-  RT_CHECK(ctx->sync_read(L.pmap.p + n - 1, sizeof(int32_t)));
+  RT_CHECK((scan<int32_t, int32_t>(ctx, flag.p, bid.p, n, true)));
+  RT_CHECK(ctx->sync_read(bid.p + n - 1, sizeof(int32_t)));
+  int32_t nblk = 0;
+  std::memcpy(&nblk, ctx->host, sizeof(int32_t));
+  RT_CHECK(root.reserve(nblk));
+  const int gs = grid_for(n * (int64_t)kStrG);
+  if (geometric) {
+    hipLaunchKernelGGL(k_fill_i32v, dim3(grid_for(n)), dim3(kBlock), 0, st, n, agg.p, -1);
+  } else {
+    hipLaunchKernelGGL(k_row_strength, dim3(gs), dim3(kBlock), 0, st, n, L.rp.p, L.val64.p,
+                       L.diag64.p, mrow.p, coupled.p);
+    RT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_agg_init, dim3(gs), dim3(kBlock), 0, st, n, L.rp.p, L.col.p, L.val64.p,
+                       mrow.p, coupled.p, theta, agg.p);
+  }
+  RT_LAUNCH_CHECK();
+  for (int round = 0; round < (geometric ? 1 : kAggRounds); ++round) {
+    hipLaunchKernelGGL(k_fill_i32v, dim3(grid_for(nblk)), dim3(kBlock), 0, st, (int64_t)nblk,
+                       root.p, INT_MAX);
+    hipLaunchKernelGGL(k_agg_elect, dim3(gs), dim3(kBlock), 0, st, n, L.rp.p, L.col.p, L.val64.p,
+                       mrow.p, coupled.p, bid.p, agg.p, theta, geometric ? 1 : 0, root.p);
+    hipLaunchKernelGGL(k_agg_assign, dim3(gs), dim3(kBlock), 0, st, n, L.rp.p, L.col.p,
+                       L.val64.p, mrow.p, coupled.p, bid.p, root.p, theta, geometric ? 1 : 0,
+                       agg.p);
+    RT_LAUNCH_CHECK();
+  }
+  int32_t* final_agg = agg.p;
+  if (!geometric) {   // two join passes reach nodes up to two strong couplings away
+    hipLaunchKernelGGL(k_agg_join, dim3(gs), dim3(kBlock), 0, st, n, L.rp.p, L.col.p, L.val64.p,
+                       mrow.p, coupled.p, theta, 0, agg.p, agg2.p);
+    hipLaunchKernelGGL(k_agg_join, dim3(gs), dim3(kBlock), 0, st, n, L.rp.p, L.col.p, L.val64.p,
+                       mrow.p, coupled.p, theta, 1, agg2.p, agg.p);
+    RT_LAUNCH_CHECK();
+  }
+  // numbering by root node, member counts
+  hipLaunchKernelGGL(k_agg_lead, dim3(grid_for(n)), dim3(kBlock), 0, st, n, final_agg, flag.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((scan<int32_t, int32_t>(ctx, flag.p, bid.p, n, true)));   // bid now holds the ranks
+  RT_CHECK(ctx->sync_read(bid.p + n - 1, sizeof(int32_t)));
   int32_t nc32 = 0;
   std::memcpy(&nc32, ctx->host, sizeof(int32_t));
   const int64_t nc = nc32;
+  *nc_out = nc;
+  if (nc == 0) return RT_OK;
+  DevBuf<int32_t> cnt;
+  DevBuf<int64_t> cnt64;
+  RT_CHECK(cnt.reserve(nc + 1));
+  RT_CHECK(cnt64.reserve(nc + 1));
+  RT_CHECK(ccode.reserve(nc));
+  hipLaunchKernelGGL(k_fill_i32v, dim3(grid_for(nc + 1)), dim3(kBlock), 0, st, nc + 1, cnt.p, 0);
+  hipLaunchKernelGGL(k_agg_number, dim3(grid_for(n)), dim3(kBlock), 0, st, n, shift, final_agg,
+                     bid.p, L.code.p, L.pmap.p, ccode.p, cnt.p);
+  RT_LAUNCH_CHECK();
+  // member lists: offsets (exclusive scan of the counts), then every member
+  // at its aggregate's next slot, then each list sorted ascending
+  RT_CHECK(L.crange.reserve(nc + 1));
+  RT_CHECK((scan<int32_t, int64_t>(ctx, cnt.p, L.crange.p, nc + 1, false)));
+  RT_CHECK(ctx->sync_read(L.crange.p + nc, sizeof(int64_t)));
+  int64_t nmem = 0;
+  std::memcpy(&nmem, ctx->host, sizeof(int64_t));
+  RT_CHECK(L.amem.reserve(std::max<int64_t>(nmem, 1)));
+  hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(nc)), dim3(kBlock), 0, st, nc, L.crange.p,
+                     cnt.p);   // cnt = next free slot per aggregate
+  hipLaunchKernelGGL(k_agg_members, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p, cnt.p,
+                     L.amem.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((row_sort<int32_t, int32_t>(ctx, L.crange.p, L.amem.p, nullptr, nc)));
+  return RT_OK;
+}
+
+// Build level l+1 from level l: aggregates, coarse CSR structure, and the
+// coarse columns and values, so that the new level is complete before it
+// serves as the fine level of the next one.  *stalled: the aggregation left
+// no coarse space or coarsened too little (no level added).
+int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim, bool* stalled) {
+  hipStream_t st = ctx->stream;
+  const int shift = l == 0 ? 0 : dim;
+  DevBuf<uint64_t> ccode;
+  int64_t nc = 0;
+  RT_CHECK(aggregate(ctx, A->levels[l], shift, A->amg.strength, ccode, &nc));
+  const int64_t n = A->levels[l].n;
+  *stalled = nc == 0 || nc * 10 > n * 9;
+  if (*stalled) return RT_OK;
   A->levels.emplace_back();
   Level& C = A->levels.back();
   Level& Lr = A->levels[l];   // re-fetch after emplace_back
   C.n = nc;
-  RT_CHECK(Lr.crange.reserve(nc + 1));
-  RT_CHECK(C.code.reserve(nc));
-  hipLaunchKernelGGL(k_agg_finish, dim3(grid_for(n)), dim3(kBlock), 0, st, n, shift, Lr.code.p,
-                     flag.p, Lr.pmap.p, Lr.crange.p, C.code.p, nc);
-  RT_LAUNCH_CHECK();
+  C.code = std::move(ccode);
   // coarse structure: count, scan
   DevBuf<int64_t> cnt;
   RT_CHECK(cnt.reserve(nc + 1));
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + nc, 0, sizeof(int64_t), st));
   hipLaunchKernelGGL((k_galerkin<false>), dim3(grid_for(nc * kWave)), dim3(kBlock), 0, st, nc,
-                     Lr.crange.p, Lr.rp.p, Lr.col.p, nullptr, nullptr, Lr.pmap.p, cnt.p, nullptr,
-                     nullptr, nullptr, nullptr);
+                     Lr.crange.p, Lr.amem.p, Lr.rp.p, Lr.col.p, nullptr, nullptr, Lr.pmap.p,
+                     cnt.p, nullptr, nullptr, nullptr, nullptr);
   RT_LAUNCH_CHECK();
   RT_CHECK(C.rp.reserve(nc + 1));
   RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, C.rp.p, nc + 1, false)));
@@ -318,18 +618,22 @@ int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim) {
   std::memcpy(&nnz, ctx->host, sizeof(int64_t));
   C.nnz = nnz;
   RT_CHECK(max_nonneg<int64_t>(ctx, cnt.p, nc, &C.max_row));
-  RT_CHECK(C.col.reserve(nnz));
+  RT_CHECK(C.col.reserve(std::max<int64_t>(nnz, 1)));
   RT_CHECK(C.val64.reserve(nnz + kSpmvPad));
   RT_CHECK(C.diag64.reserve(nc));
   return galerkin_fill(ctx, A->levels[l], C);
 }
 
-int level_vectors(Level& L, bool fp32) {
+int level_vectors(Level& L, bool fp32, bool wcycle) {
   for (auto* b : {&L.b64, &L.x64, &L.t64, &L.r64, &L.d64, &L.sinv64, &L.dinv64})
     RT_CHECK(b->reserve(L.n));
+  if (wcycle)
+    for (auto* b : {&L.wr64, &L.wx64}) RT_CHECK(b->reserve(L.n));
   if (fp32) {
     for (auto* b : {&L.b32, &L.x32, &L.t32, &L.r32, &L.d32, &L.sinv32, &L.dinv32})
       RT_CHECK(b->reserve(L.n));
+    if (wcycle)
+      for (auto* b : {&L.wr32, &L.wx32}) RT_CHECK(b->reserve(L.n));
     RT_CHECK(L.val32.reserve(L.nnz + kSpmvPad));
     RT_CHECK(L.diag32.reserve(L.n));
   }
@@ -343,44 +647,40 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
   const rt_neighbors* nb = A->nb;
   const bool fp32 = A->has_fp32;
   if (A->n == 0) return RT_OK;
-  // structure (depends only on the neighbour object): built on first use
-  if (A->levels.size() == 1 && A->amg.max_levels > 1 && A->levels[0].code.n == 0) {
-    Level& L0 = A->levels[0];
+  // The aggregates depend on the values (strength of the couplings), so the
+  // hierarchy is rebuilt with every assembly: once per time step.
+  A->levels.resize(1);
+  Level& L0 = A->levels[0];
+  if (A->amg.max_levels > 1 && L0.code.n == 0) {   // cell codes of the fine level
     RT_CHECK(L0.code.reserve(L0.n));
     RT_CHECK_HIP(hipMemcpyAsync(L0.code.p, nb->skeys.p, sizeof(uint64_t) * L0.n,
                                 hipMemcpyDeviceToDevice, st));
-    for (int l = 0; (int)A->levels.size() < A->amg.max_levels; ++l) {
-      const int64_t n = A->levels[l].n;
-      if (n <= A->amg.coarse_size) break;
-      RT_CHECK(build_next_level(ctx, A, l, nb->dim));
-      const int64_t nc = A->levels.back().n;
-      if (nc * 10 > n * 9 || nc == 0) {   // coarsening stalled: drop the level
-        A->levels.pop_back();
-        break;
-      }
-      if (A->amg.tiled_spmv) RT_CHECK(build_tiles(ctx, A->levels.back()));
-    }
   }
-  for (Level& L : A->levels) RT_CHECK(level_vectors(L, fp32));
-  // numeric: Galerkin products down the hierarchy, smoother scalings
-  for (size_t l = 0; l < A->levels.size(); ++l) {
+  for (int l = 0; (int)A->levels.size() < A->amg.max_levels; ++l) {
+    if (A->levels[l].n <= A->amg.coarse_size) break;
+    bool stalled = false;
+    RT_CHECK(build_next_level(ctx, A, l, nb->dim, &stalled));
+    if (stalled) break;
+    if (A->amg.tiled_spmv) RT_CHECK(build_tiles(ctx, A->levels.back()));
+  }
+  for (Level& L : A->levels) RT_CHECK(level_vectors(L, fp32, A->amg.cycle == 2));
+  // smoother scalings and FP32 copies of the coarse levels (the Galerkin
+  // products were formed while the levels were built)
+  for (size_t l = 1; l < A->levels.size(); ++l) {
     Level& L = A->levels[l];
-    if (l > 0) {
-      RT_CHECK(galerkin_fill(ctx, A->levels[l - 1], L));
-      if (fp32) {
-        if (L.nnz > 0)
-          hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz)), dim3(kBlock), 0, st, L.nnz,
-                             L.val64.p, L.val32.p);
-        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.n)), dim3(kBlock), 0, st, L.n, L.diag64.p,
-                           L.diag32.p);
-        RT_LAUNCH_CHECK();
-      }
-      hipLaunchKernelGGL(k_smoother, dim3(grid_for(L.n * 8)), dim3(kBlock), 0, st, L.n, L.rp.p,
-                         L.val64.p, L.diag64.p, L.sinv64.p, L.dinv64.p,
-                         fp32 ? L.sinv32.p : nullptr, fp32 ? L.dinv32.p : nullptr);
+    if (fp32) {
+      if (L.nnz > 0)
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz)), dim3(kBlock), 0, st, L.nnz,
+                           L.val64.p, L.val32.p);
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.n)), dim3(kBlock), 0, st, L.n, L.diag64.p,
+                         L.diag32.p);
       RT_LAUNCH_CHECK();
-    }   // level 0: the assembly kernel wrote its scalings
-  }
+    }
+    hipLaunchKernelGGL(k_smoother, dim3(grid_for(L.n * 8)), dim3(kBlock), 0, st, L.n, L.rp.p,
+                       L.val64.p, L.diag64.p, L.sinv64.p, L.dinv64.p,
+                       fp32 ? L.sinv32.p : nullptr, fp32 ? L.dinv32.p : nullptr);
+    RT_LAUNCH_CHECK();
+  }   // level 0: the assembly kernel wrote its scalings
   // coarsest level: dense inverse when small
   Level& Lc = A->levels.back();
   A->coarse_direct = A->levels.size() > 1 && Lc.n <= kDenseMax;
@@ -481,9 +781,19 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
                                            nullptr, nullptr, nullptr, level_shape<T>(L),
                                            nullptr, stop)));
   hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
-                     r, B::b(C), stop);
+                     L.amem.p, r, B::b(C), stop);
   RT_LAUNCH_CHECK();
   RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::b(C), B::x(C), stop));
+  if (A->amg.cycle == 2 && l + 2 < A->levels.size()) {
+    // W-cycle: a second coarse correction from the residual of the first
+    RT_CHECK((launch_spmv_level<T, SP_RESID>(st, C, B::val(C), B::diag(C), B::x(C), B::b(C),
+                                             nullptr, B::wr(C), nullptr, nullptr, nullptr,
+                                             level_shape<T>(C), nullptr, stop)));
+    RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::wr(C), B::wx(C), stop));
+    hipLaunchKernelGGL(k_axpy1<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, B::wx(C),
+                       B::x(C), stop);
+    RT_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p, B::x(C),
                      t, stop);
   RT_LAUNCH_CHECK();

@@ -454,11 +454,12 @@ int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
     fresh = true;
   }
   M->resid_ok = false;   // a new operator: no residual carries over
-  rt_amg_opts d{8, 256, 0.08, 1, 1, RT_SMOOTHER_L1_JACOBI, 2};
+  rt_amg_opts d{8, 256, 0.25, 1, 1, RT_SMOOTHER_L1_JACOBI, 2, 1};
   if (amg && (amg->smoother < RT_SMOOTHER_L1_JACOBI || amg->smoother > RT_SMOOTHER_CHEBYSHEV ||
-              amg->smoother_degree < 1 || amg->smoother_degree > 8)) {
-    rt::set_error("rt_assemble: smoother %d of degree %d (smoother 0 or 1, degree 1..8)",
-                  amg->smoother, amg->smoother_degree);
+              amg->smoother_degree < 1 || amg->smoother_degree > 8 || amg->cycle < 1 ||
+              amg->cycle > 2)) {
+    rt::set_error("rt_assemble: smoother %d of degree %d, cycle %d (smoother 0 or 1, degree "
+                  "1..8, cycle 1 or 2)", amg->smoother, amg->smoother_degree, amg->cycle);
     if (fresh) delete M;
     return RT_E_ARG;
   }

@@ -268,8 +268,9 @@ struct rt_neighbors {
 
 namespace rt {
 // One level of the operator hierarchy.  Level 0 is the assembled fine system;
-// level l+1 aggregates contiguous runs of level-l rows (pmap is
-// non-decreasing; crange[I] is the first level-l row of aggregate I).
+// level l+1 has one node per aggregate of level-l nodes: pmap maps a node to
+// its aggregate (-1: left out of the coarse space), and the members of
+// aggregate I are amem[crange[I] .. crange[I+1]) in ascending order.
 struct Level {
   int64_t n = 0, nnz = 0;       // nnz = off-diagonal entries
   int64_t max_row = 0;          // longest off-diagonal row
@@ -286,12 +287,15 @@ struct Level {
   DevBuf<int32_t> col;
   DevBuf<double> val64, diag64, sinv64, dinv64;   // sinv = l1-Jacobi smoother, dinv = 1/diag
   DevBuf<float> val32, diag32, sinv32, dinv32;
-  DevBuf<uint64_t> code;        // Morton code of each node's cell block
-  DevBuf<int32_t> pmap;         // node -> aggregate on the next level
-  DevBuf<int32_t> crange;       // next-level aggregate -> first node (size n_next + 1)
+  DevBuf<uint64_t> code;        // Morton code of each node's cell block (candidate blocks)
+  DevBuf<int32_t> pmap;         // node -> aggregate on the next level (-1: none)
+  DevBuf<int64_t> crange;       // next-level aggregate -> offset of its members (n_next + 1)
+  DevBuf<int32_t> amem;         // members of the aggregates, ascending per aggregate
   // work vectors of this level (b: right-hand side, x: result, t, r: temporaries)
   DevBuf<double> b64, x64, t64, r64, d64;   // d: Chebyshev search direction
   DevBuf<float> b32, x32, t32, r32, d32;
+  DevBuf<double> wr64, wx64;   // W-cycle: residual and correction of the second visit
+  DevBuf<float> wr32, wx32;
 };
 template <typename T>
 inline int level_shape(const Level& L) {

@@ -56,7 +56,7 @@ class rt_step_inputs(ctypes.Structure):
 class rt_amg_opts(ctypes.Structure):
     _fields_ = [("max_levels", c_int), ("coarse_size", c_int), ("strength", c_dbl),
                 ("build_fp32", c_int), ("tiled_spmv", c_int), ("smoother", c_int),
-                ("smoother_degree", c_int)]
+                ("smoother_degree", c_int), ("cycle", c_int)]
 
 
 class rt_matrix_info(ctypes.Structure):
@@ -425,10 +425,11 @@ def solve_opts(precision=RT_PREC_FP64, precond=PRECOND_JACOBI, tol=1e-10, max_it
 RT_SMOOTHER_L1_JACOBI, RT_SMOOTHER_CHEBYSHEV = 0, 1
 
 
-def amg_opts(max_levels=8, coarse_size=256, strength=0.08, build_fp32=1,
-             tiled_spmv=1, smoother=RT_SMOOTHER_L1_JACOBI, smoother_degree=2) -> rt_amg_opts:
+def amg_opts(max_levels=8, coarse_size=256, strength=0.25, build_fp32=1,
+             tiled_spmv=1, smoother=RT_SMOOTHER_L1_JACOBI, smoother_degree=2,
+             cycle=1) -> rt_amg_opts:
     return rt_amg_opts(max_levels, coarse_size, strength, build_fp32, tiled_spmv, smoother,
-                       smoother_degree)
+                       smoother_degree, cycle)
 
 
 def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100,

@@ -190,6 +190,13 @@ inline int atomicCAS(int* p, int cmp, int v) {
   return cmp;
 }
 inline int atomicAdd(int* p, int v) { return std::atomic_ref<int>(*p).fetch_add(v); }
+inline int atomicMin(int* p, int v) {
+  std::atomic_ref<int> a(*p);
+  int cur = a.load();
+  while (v < cur && !a.compare_exchange_weak(cur, v)) {
+  }
+  return cur;
+}
 inline void __threadfence() {}
 
 template <typename T>

@@ -16,7 +16,8 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import synth  # noqa: E402
 from oracle import linsolve, neighbors, step as ostep  # noqa: E402
-from gpu_common import _cold_patch, _limited, _wendland, oracle_system, rowwise_rel_err  # noqa: E402
+from gpu_common import (_cold_patch, _diffusive, _limited, _wendland, oracle_system,  # noqa: E402
+                        rowwise_rel_err)
 from paper_2001_11606_amd import rt  # noqa: E402
 
 FIELDS = ("m", "rho", "cv", "sigma0_a", "sigma_s", "e", "E", "Q_e", "Q_E")
@@ -114,6 +115,14 @@ def check_case(ctx, name, prob):
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: chebyshev prec={prec} err={e} its={st.iterations}"
     cc.free()
+    # the W-cycle (two coarse corrections per level), FP64 and mixed
+    cw_ = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8, cycle=2))
+    for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
+        x = np.zeros(nin)
+        s, st = rt.rt_solve(ctx, cw_.A, p(b), p(x), rt.solve_opts(prec, 1, tol, 3000, 1e-4, 50))
+        e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+        assert s == 0 and e <= bar, f"{name}: w-cycle prec={prec} err={e} its={st.iterations}"
+    cw_.free()
     # GMRES on the unscaled operator, Jacobi and AMG, with and without restarts
     for precond, restart in (((1, 4),) if QUICK else ((0, 30), (1, 30), (1, 4))):
         x = np.zeros(nin)
@@ -266,6 +275,8 @@ def main():
         "larsen_wendland2d_12": _limited(_wendland(2, 12), synth.LIMITER_LARSEN),
         "levermore_wendland3d_6": _limited(_wendland(3, 6), synth.LIMITER_LEVERMORE),
         "coldpatch3d_8": _cold_patch(8),
+        "diffusive2d_16": _diffusive(synth.config1(n=16), 0.1),
+        "diffusive3d_8": _diffusive(synth.config3(n=8), 0.1),
         "periodic2d_16": synth.periodic_wendland(2, 16),
         "marshak3d_8": synth.config4(n=8),
         "ensemble2d": synth.config5_member(0, 400.0),

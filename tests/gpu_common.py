@@ -39,6 +39,16 @@ def _cold_patch(n):
     return prob
 
 
+def _diffusive(prob, dt):
+    """A workload with a longer time step, so that diffusion dominates the
+    diagonal (the coupling of a row grows with dt) and the strength-based
+    aggregation coarsens it; a manufactured problem takes the sources and
+    ghost values of its new first step."""
+    prob.dt = dt
+    prob.set_time(dt)
+    return prob
+
+
 def _wendland(dim, n):
     """The paper's Wendland kernel at h = 4 spacings (synth.wendland_lattice)."""
     return synth.wendland_lattice(dim, n)
@@ -79,6 +89,8 @@ def small_cases():
         "wendland2d_24_larsen": lambda: _limited(_wendland(2, 24), synth.LIMITER_LARSEN),
         "wendland3d_9_levermore": lambda: _limited(_wendland(3, 9), synth.LIMITER_LEVERMORE),
         "densitystep3d_12_coldpatch": lambda: _cold_patch(12),
+        "diffusive2d_48": lambda: _diffusive(synth.config1(n=48), 0.1),
+        "diffusive3d_16": lambda: _diffusive(synth.config3(n=16), 0.1),
         "marshak3d_16": lambda: synth.config4(n=16),
         "infinite3d_10": lambda: synth.config2_infinite(1.0, 0.01, n=10),
         "ensemble2d": lambda: synth.config5_member(0, 2500.0),
