@@ -206,8 +206,25 @@ typedef struct {
   int cycle;             /* 1: V-cycle; 2: W-cycle (on every level above the
                             coarsest, two coarse corrections, the second from
                             the residual of the first: the same symmetric
-                            operator as two steps of the coarse cycle)        */
+                            operator as two steps of the coarse cycle);
+                            3: K-cycle (on every coarse level but the
+                            coarsest, the two corrections are weighted as two
+                            steps of flexible CG, the weights formed from
+                            inner products on the device; the preconditioner
+                            then varies slightly with its argument)          */
+  int prolongation;      /* RT_PROLONG_PIECEWISE: constant over each aggregate;
+                            RT_PROLONG_SMOOTHED: smoothed aggregation,
+                            P = (I - 4/3 D1^-1 A) P0 with P0 the piecewise
+                            constant one and D1 the l1 diagonal (rows left out
+                            of the coarse space keep P = 0); the coarse
+                            operator is P^T A P either way                    */
 } rt_amg_opts;
+
+#define RT_PROLONG_PIECEWISE 0
+#define RT_PROLONG_SMOOTHED 1
+#define RT_CYCLE_V 1
+#define RT_CYCLE_W 2
+#define RT_CYCLE_K 3
 
 #define RT_SMOOTHER_L1_JACOBI 0
 #define RT_SMOOTHER_CHEBYSHEV 1
@@ -215,9 +232,10 @@ typedef struct {
 int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
                 const rt_amg_opts* amg /* NULL = defaults */, rt_matrix** A);
 /* AMG defaults: max_levels 8, coarse_size 256, strength 0.25, build_fp32 1,
- * tiled_spmv 1, smoother RT_SMOOTHER_L1_JACOBI, smoother_degree 2, cycle 1.
- * Errors: RT_E_ARG for an unknown smoother, a degree outside 1..8 or a cycle
- * other than 1 or 2.                                                        */
+ * tiled_spmv 1, smoother RT_SMOOTHER_L1_JACOBI, smoother_degree 2, cycle 1,
+ * prolongation RT_PROLONG_PIECEWISE.
+ * Errors: RT_E_ARG for an unknown smoother, a degree outside 1..8, a cycle
+ * other than 1, 2 or 3, or an unknown prolongation.                        */
 
 typedef struct {
   int64_t n;             /* unknowns = interior particles                     */
@@ -227,6 +245,8 @@ typedef struct {
   int64_t level_nnz[16];
   int64_t level_tile_cols[16]; /* distinct columns summed over the level's
                                   256-row tiles; 0 = level not tiled          */
+  int64_t level_p_nnz[16];  /* entries of the smoothed prolongation from this
+                               level to the next; 0 = piecewise constant     */
 } rt_matrix_info;
 
 int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info);

@@ -28,6 +28,11 @@
 // fine entries by aggregate pair) and the coarse diagonals are sums in that
 // fixed order.
 //
+// Smoothed aggregation (option): P = (I - 4/3 D1^-1 A) P0 smooths the
+// piecewise-constant P0 by one damped l1-Jacobi step, and the coarse
+// operator is the Galerkin product P^T (A P), both sparse products formed
+// by merging sorted rows over a wavefront in a fixed order.
+//
 // V-cycle (symmetric, so it is a valid CG preconditioner): pre-smoothing
 // from zero, residual, restriction, coarse correction, prolongation,
 // post-smoothing with the same smoother.  The l1 diagonal
@@ -39,6 +44,7 @@
 // with the residual recomputed as b - A x at every step).  The coarsest level is solved with a dense
 // FP64 inverse (Gauss-Jordan at setup) when small enough, otherwise with four
 // l1-Jacobi sweeps.
+#include <algorithm>
 #include <climits>
 #include <cstring>
 
@@ -328,6 +334,218 @@ k_galerkin(int64_t nc, const int64_t* __restrict__ crange, const int32_t* __rest
   }
 }
 
+// ---- smoothed aggregation ----------------------------------------------------
+// P = (I - omega D1^-1 A) P0 with the l1 diagonal D1: the spectrum of
+// D1^-1 A lies in (0, 1], so omega = 4/3 (the usual 4/(3 lambda_max) with the
+// bound lambda_max <= 1) damps the high end without an eigenvalue estimate.
+constexpr double kSaOmega = 4.0 / 3.0;
+constexpr int kMergeK = 16;   // input rows per lane of a merged row sum
+
+// Row i of P over the coarse-space rows: the distinct aggregates of i and its
+// neighbours, ascending, each with the value
+//   [J == pmap_i] (1 - omega s_i a_ii) - omega s_i sum_{k: pmap_k == J} a_ik,
+// s = 1/D1; a row left out of the coarse space (pmap_i < 0) stays empty.
+// One wavefront per row.
+template <bool FILL>
+__global__ void __launch_bounds__(kBlock)
+k_sa_prolong(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+             const double* __restrict__ val, const double* __restrict__ diag,
+             const double* __restrict__ sinv, const int32_t* __restrict__ pmap,
+             int64_t* __restrict__ cnt, const int64_t* __restrict__ prp,
+             int32_t* __restrict__ pcol, double* __restrict__ pval) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  if (i >= n) return;   // whole wavefront exits together
+  const int32_t pi = pmap[i];
+  if (pi < 0) {
+    if (!FILL && lane == 0) cnt[i] = 0;
+    return;
+  }
+  const double w = kSaOmega * sinv[i];
+  const int64_t k0 = rp[i], k1 = rp[i + 1];
+  int32_t last = -1;
+  int64_t out = FILL ? prp[i] : 0;
+  int64_t count = 0;
+  while (true) {
+    int32_t m = pi > last ? pi : INT_MAX;
+    for (int64_t k = k0 + lane; k < k1; k += kWave) {
+      const int32_t J = pmap[col[k]];
+      if (J > last && J < m) m = J;
+    }
+    m = wave_min(m);
+    if (m == INT_MAX) break;
+    if (FILL) {
+      double s = 0.0;
+      for (int64_t k = k0 + lane; k < k1; k += kWave)
+        if (pmap[col[k]] == m) s -= w * val[k];
+      s = group_sum<kWave>(s);
+      if (m == pi) s += 1.0 - w * diag[i];
+      if (lane == 0) {
+        pcol[out] = m;
+        pval[out] = s;
+      }
+      ++out;
+    } else {
+      ++count;
+    }
+    last = m;
+  }
+  if (!FILL && lane == 0) cnt[i] = count;
+}
+
+// Merged weighted sum of sorted sparse rows over a wavefront: the lane holds
+// up to kMergeK input rows (cursor cur[q] up to e[q], weight w[q]).  Each step
+// takes the smallest head column over the wavefront and adds every head at
+// that column (a row holds a column once), lanes combined in a fixed order;
+// the sum at column dcol (if >= 0) goes to *dsum instead of the output.
+// Counts the output columns (FILL false) or writes them from `out` on.
+template <bool FILL>
+__device__ __forceinline__ void merge_rows(int nq, const double* w, int64_t* cur, const int64_t* e,
+                                           const int32_t* __restrict__ col,
+                                           const double* __restrict__ val, int32_t dcol,
+                                           int64_t out, int32_t* __restrict__ ocol,
+                                           double* __restrict__ oval, int64_t* count,
+                                           double* dsum) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int64_t c = 0;
+  double d = 0.0;
+  while (true) {
+    int32_t m = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < kMergeK; ++q)
+      if (q < nq && cur[q] < e[q]) {
+        const int32_t cq = col[cur[q]];
+        m = cq < m ? cq : m;
+      }
+    m = wave_min(m);
+    if (m == INT_MAX) break;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMergeK; ++q)
+      if (q < nq && cur[q] < e[q] && col[cur[q]] == m) {
+        if (FILL) s += w[q] * val[cur[q]];
+        ++cur[q];
+      }
+    if (FILL) s = group_sum<kWave>(s);
+    if (m == dcol) {
+      d += s;
+    } else {
+      if (FILL && lane == 0) {
+        ocol[out] = m;
+        oval[out] = s;
+      }
+      ++out;
+      ++c;
+    }
+  }
+  *count = c;
+  *dsum = d;
+}
+
+// Row i of A P = a_ii P_i + sum_k a_ik P_k (rows outside the coarse space,
+// unused by the coarse operator, stay empty).  Lane l takes the row's
+// entries l, l + 64, ... with the diagonal as entry number len.
+template <bool FILL>
+__global__ void __launch_bounds__(kBlock)
+k_sa_ap(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+        const double* __restrict__ val, const double* __restrict__ diag,
+        const int32_t* __restrict__ pmap, const int64_t* __restrict__ prp,
+        const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+        int64_t* __restrict__ cnt, const int64_t* __restrict__ aprp,
+        int32_t* __restrict__ apcol, double* __restrict__ apval) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  if (i >= n) return;
+  if (pmap[i] < 0) {
+    if (!FILL && lane == 0) cnt[i] = 0;
+    return;
+  }
+  const int64_t k0 = rp[i];
+  const int len = (int)(rp[i + 1] - k0);
+  double w[kMergeK];
+  int64_t cur[kMergeK], e[kMergeK];
+  int nq = 0;
+#pragma unroll
+  for (int q = 0; q < kMergeK; ++q) {
+    const int t = lane + q * kWave;
+    w[q] = 0.0;
+    cur[q] = e[q] = 0;
+    if (t <= len) {
+      const int32_t k = t < len ? col[k0 + t] : (int32_t)i;
+      w[q] = t < len ? val[k0 + t] : diag[i];
+      cur[q] = prp[k];
+      e[q] = prp[k + 1];
+      nq = q + 1;
+    }
+  }
+  int64_t count = 0;
+  double dsum = 0.0;
+  merge_rows<FILL>(nq, w, cur, e, pcol, pval, -1, FILL ? aprp[i] : 0, apcol, apval, &count,
+                   &dsum);
+  if (!FILL && lane == 0) cnt[i] = count;
+}
+
+// Coarse row I of P^T (A P): the rows of A P listed in column I of P (its
+// transpose's row I), weighted by P's entries; the coarse diagonal apart.
+template <bool FILL>
+__global__ void __launch_bounds__(kBlock)
+k_sa_rap(int64_t nc, const int64_t* __restrict__ ptrp, const int32_t* __restrict__ ptrow,
+         const double* __restrict__ ptval, const int64_t* __restrict__ aprp,
+         const int32_t* __restrict__ apcol, const double* __restrict__ apval,
+         int64_t* __restrict__ cnt, const int64_t* __restrict__ crp, int32_t* __restrict__ ccol,
+         double* __restrict__ cval, double* __restrict__ cdiag) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  if (I >= nc) return;
+  const int64_t t0 = ptrp[I];
+  const int len = (int)(ptrp[I + 1] - t0);
+  double w[kMergeK];
+  int64_t cur[kMergeK], e[kMergeK];
+  int nq = 0;
+#pragma unroll
+  for (int q = 0; q < kMergeK; ++q) {
+    const int t = lane + q * kWave;
+    w[q] = 0.0;
+    cur[q] = e[q] = 0;
+    if (t < len) {
+      const int32_t i = ptrow[t0 + t];
+      w[q] = ptval[t0 + t];
+      cur[q] = aprp[i];
+      e[q] = aprp[i + 1];
+      nq = q + 1;
+    }
+  }
+  int64_t count = 0;
+  double dsum = 0.0;
+  merge_rows<FILL>(nq, w, cur, e, apcol, apval, (int32_t)I, FILL ? crp[I] : 0, ccol, cval,
+                   &count, &dsum);
+  if (lane == 0) {
+    if (FILL) cdiag[I] = dsum;
+    else cnt[I] = count;
+  }
+}
+
+// column counts of P, then its entries moved to their column's next slot
+__global__ void k_pt_count(int64_t n, const int64_t* __restrict__ prp,
+                           const int32_t* __restrict__ pcol, int32_t* __restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t q = prp[i]; q < prp[i + 1]; ++q) atomicAdd(&cnt[pcol[q]], 1);
+}
+
+__global__ void k_pt_fill(int64_t n, const int64_t* __restrict__ prp,
+                          const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+                          int32_t* __restrict__ cur, int32_t* __restrict__ ptrow,
+                          double* __restrict__ ptval) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t q = prp[i]; q < prp[i + 1]; ++q) {
+    const int32_t slot = atomicAdd(&cur[pcol[q]], 1);
+    ptrow[slot] = (int32_t)i;
+    ptval[slot] = pval[q];
+  }
+}
+
 // l1-Jacobi smoother scaling and Jacobi inverse diagonal of a coarse level,
 // plus FP32 copies; 8 lanes per row (coarse rows hold at most 3^dim entries).
 __global__ void __launch_bounds__(kBlock)
@@ -429,6 +647,34 @@ __global__ void k_restrict(int64_t nc, const int64_t* __restrict__ crange,
   bc[I] = s;
 }
 
+// bc = P^T r with the transpose's rows (fine rows ascending)
+template <typename T, typename PV>
+__global__ void k_restrict_p(int64_t nc, const int64_t* __restrict__ ptrp,
+                             const int32_t* __restrict__ ptrow, const PV* __restrict__ ptv,
+                             const T* __restrict__ r, T* __restrict__ bc,
+                             const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  T s = 0;
+  for (int64_t t = ptrp[I]; t < ptrp[I + 1]; ++t) s += (T)ptv[t] * r[ptrow[t]];
+  bc[I] = s;
+}
+
+// x += P xc
+template <typename T, typename PV>
+__global__ void k_prolong_p(int64_t n, const int64_t* __restrict__ prp,
+                            const int32_t* __restrict__ pcol, const PV* __restrict__ pv,
+                            const T* __restrict__ xc, T* __restrict__ x,
+                            const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int64_t q = prp[i]; q < prp[i + 1]; ++q) s += (T)pv[q] * xc[pcol[q]];
+  x[i] += s;
+}
+
 // x += y
 template <typename T>
 __global__ void k_axpy1(int64_t n, const T* __restrict__ y, T* __restrict__ x,
@@ -464,6 +710,104 @@ __global__ void k_cheb(int64_t n, T c1, T c2, const T* __restrict__ s, const T* 
   xout[i] = (xin ? xin[i] : T(0)) + di;
 }
 
+// ---- K-cycle -------------------------------------------------------------------
+// Krylov-accelerated coarse correction: on a level C that is not the
+// coarsest, the correction from its right-hand side r is two steps of a
+// flexible conjugate-gradient iteration on A_C preconditioned by the cycle of
+// the levels below:
+//   v1 = cycle(r), rho1 = v1.r, alpha1 = v1.A v1, rt = r - (rho1/alpha1) A v1,
+//   v2 = cycle(rt), gamma = v2.A v1, beta = v2.A v2, rho2 = v2.rt,
+//   alpha2 = beta - gamma^2/alpha1,
+//   x = (rho1/alpha1 - gamma rho2/(alpha1 alpha2)) v1 + (rho2/alpha2) v2,
+// the second direction being v2 made A-orthogonal to v1.  The inner products
+// are formed and turned into weights on the device.
+constexpr int kKdotBlocks = 128;
+
+// Block partials (double) of u.a, u.b and u.c over [0, n) at part[blk],
+// part[nb + blk] and part[2 nb + blk], nb = gridDim.x; b, c NULL: zero.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_kdots(int64_t n, const T* __restrict__ u, const T* __restrict__ a, const T* __restrict__ b,
+        const T* __restrict__ c, double* __restrict__ part, const int32_t* __restrict__ stop) {
+  __shared__ double red[kBlock / kWave];
+  if (stop && *stop) return;
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double ui = (double)u[i];
+    sa += ui * (double)a[i];
+    if (b) sb += ui * (double)b[i];
+    if (c) sc += ui * (double)c[i];
+  }
+  sa = block_sum(sa, red);
+  sb = block_sum(sb, red);
+  sc = block_sum(sc, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sa;
+    part[gridDim.x + blockIdx.x] = sb;
+    part[2 * gridDim.x + blockIdx.x] = sc;
+  }
+}
+
+// One block: the K-cycle weights from nb block partials of three inner
+// products.  Phase 1 (rho1, alpha1): kc[0] = rho1, kc[1] = alpha1,
+// kc[2] = rho1/alpha1 (0 unless alpha1 > 0).  Phase 2 (gamma, beta, rho2):
+// kc[3], kc[4] = the weights of v1 and v2; when alpha2 is not positive
+// against beta (v2 A-parallel to v1 within rounding) the second direction is
+// dropped.
+__global__ void __launch_bounds__(kBlock)
+k_kcoef(int phase, int nb, const double* __restrict__ part, double* __restrict__ kc,
+        const int32_t* __restrict__ stop) {
+  __shared__ double red[kBlock / kWave];
+  if (stop && *stop) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    s0 += part[k];
+    s1 += part[nb + k];
+    s2 += part[2 * nb + k];
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  s2 = block_sum(s2, red);
+  if (threadIdx.x != 0) return;
+  if (phase == 1) {
+    kc[0] = s0;
+    kc[1] = s1;
+    kc[2] = (s1 > 0.0 && isfinite(s1) && isfinite(s0)) ? s0 / s1 : 0.0;
+  } else {
+    const double rho1 = kc[0], a1 = kc[1], gam = s0, beta = s1, rho2 = s2;
+    double c1 = kc[2], c2 = 0.0;
+    if (a1 > 0.0 && isfinite(a1)) {
+      const double a2 = beta - gam * gam / a1;
+      if (a2 > 1e-12 * beta && isfinite(a2) && isfinite(rho2)) {
+        c2 = rho2 / a2;
+        c1 = rho1 / a1 - gam * c2 / a1;
+      }
+    }
+    kc[3] = c1;
+    kc[4] = c2;
+  }
+}
+
+// out = r - kc[2] w
+template <typename T>
+__global__ void k_kresid(int64_t n, const double* __restrict__ kc, const T* __restrict__ r,
+                         const T* __restrict__ w, T* __restrict__ out,
+                         const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = r[i] - (T)kc[2] * w[i];
+}
+
+// x = kc[3] v1 + kc[4] v2 (x may alias v1)
+template <typename T>
+__global__ void k_kcomb(int64_t n, const double* __restrict__ kc, const T* v1,
+                        const T* __restrict__ v2, T* x, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (T)kc[3] * v1[i] + (T)kc[4] * v2[i];
+}
+
 template <typename T> struct LevelBufs;
 template <> struct LevelBufs<double> {
   static const double* val(const Level& L) { return L.val64.p; }
@@ -476,6 +820,9 @@ template <> struct LevelBufs<double> {
   static double* d(Level& L) { return L.d64.p; }
   static double* wr(Level& L) { return L.wr64.p; }
   static double* wx(Level& L) { return L.wx64.p; }
+  static double* kw(Level& L) { return L.kw64.p; }
+  static const double* pv(const Level& L) { return L.p_val.p; }
+  static const double* ptv(const Level& L) { return L.pt_val.p; }
 };
 template <> struct LevelBufs<float> {
   static const float* val(const Level& L) { return L.val32.p; }
@@ -488,6 +835,9 @@ template <> struct LevelBufs<float> {
   static float* d(Level& L) { return L.d32.p; }
   static float* wr(Level& L) { return L.wr32.p; }
   static float* wx(Level& L) { return L.wx32.p; }
+  static float* kw(Level& L) { return L.kw32.p; }
+  static const float* pv(const Level& L) { return L.p_val32.p; }
+  static const float* ptv(const Level& L) { return L.pt_val32.p; }
 };
 
 // Values (and columns) of the coarse level C = P^T F P.
@@ -585,6 +935,103 @@ int aggregate(rt_ctx* ctx, Level& L, int shift, double theta, DevBuf<uint64_t>& 
   return RT_OK;
 }
 
+// Smoothed prolongation from F to C (aggregates already in F.pmap, nc of
+// them) and the coarse operator P^T A P into C.  *ok = false (nothing
+// changed in C) when a row of F or a column of P is longer than the merged
+// sums take (64 kMergeK entries); the caller then keeps P piecewise constant.
+int build_smoothed(rt_ctx* ctx, Level& F, Level& C, int64_t nc, bool* ok) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = F.n;
+  *ok = false;
+  if (F.max_row + 1 > (int64_t)kWave * kMergeK) return RT_OK;
+  // P: count, offsets, fill
+  DevBuf<int64_t> cnt;
+  RT_CHECK(cnt.reserve(n + 1));
+  RT_CHECK_HIP(hipMemsetAsync(cnt.p + n, 0, sizeof(int64_t), st));
+  const int gw = grid_for(n * (int64_t)kWave);
+  hipLaunchKernelGGL((k_sa_prolong<false>), dim3(gw), dim3(kBlock), 0, st, n, F.rp.p, F.col.p,
+                     F.val64.p, F.diag64.p, F.sinv64.p, F.pmap.p, cnt.p, nullptr, nullptr,
+                     nullptr);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(F.p_rp.reserve(n + 1));
+  RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, F.p_rp.p, n + 1, false)));
+  RT_CHECK(ctx->sync_read(F.p_rp.p + n, sizeof(int64_t)));
+  int64_t nnzp = 0;
+  std::memcpy(&nnzp, ctx->host, sizeof(int64_t));
+  F.p_nnz = nnzp;
+  RT_CHECK(F.p_col.reserve(std::max<int64_t>(nnzp, 1)));
+  RT_CHECK(F.p_val.reserve(std::max<int64_t>(nnzp, 1)));
+  hipLaunchKernelGGL((k_sa_prolong<true>), dim3(gw), dim3(kBlock), 0, st, n, F.rp.p, F.col.p,
+                     F.val64.p, F.diag64.p, F.sinv64.p, F.pmap.p, nullptr, F.p_rp.p, F.p_col.p,
+                     F.p_val.p);
+  RT_LAUNCH_CHECK();
+  // P^T: column counts, offsets, entries by atomic slots, then each column
+  // sorted by fine row (a fixed order)
+  DevBuf<int32_t> ccnt;
+  RT_CHECK(ccnt.reserve(nc + 1));
+  hipLaunchKernelGGL(k_fill_i32v, dim3(grid_for(nc + 1)), dim3(kBlock), 0, st, nc + 1, ccnt.p, 0);
+  hipLaunchKernelGGL(k_pt_count, dim3(grid_for(n)), dim3(kBlock), 0, st, n, F.p_rp.p, F.p_col.p,
+                     ccnt.p);
+  RT_LAUNCH_CHECK();
+  int32_t maxcol = 0;
+  RT_CHECK(max_nonneg<int32_t>(ctx, ccnt.p, nc, &maxcol));
+  if ((int64_t)maxcol > (int64_t)kWave * kMergeK) return RT_OK;
+  RT_CHECK(F.pt_rp.reserve(nc + 1));
+  RT_CHECK((scan<int32_t, int64_t>(ctx, ccnt.p, F.pt_rp.p, nc + 1, false)));
+  RT_CHECK(F.pt_row.reserve(std::max<int64_t>(nnzp, 1)));
+  RT_CHECK(F.pt_val.reserve(std::max<int64_t>(nnzp, 1)));
+  hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(nc)), dim3(kBlock), 0, st, nc, F.pt_rp.p,
+                     ccnt.p);   // ccnt = next free slot per column
+  hipLaunchKernelGGL(k_pt_fill, dim3(grid_for(n)), dim3(kBlock), 0, st, n, F.p_rp.p, F.p_col.p,
+                     F.p_val.p, ccnt.p, F.pt_row.p, F.pt_val.p);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((row_sort<int32_t, double>(ctx, F.pt_rp.p, F.pt_row.p, F.pt_val.p, nc)));
+  // A P (temporary)
+  DevBuf<int64_t> aprp;
+  DevBuf<int32_t> apcol;
+  DevBuf<double> apval;
+  RT_CHECK(aprp.reserve(n + 1));
+  hipLaunchKernelGGL((k_sa_ap<false>), dim3(gw), dim3(kBlock), 0, st, n, F.rp.p, F.col.p,
+                     F.val64.p, F.diag64.p, F.pmap.p, F.p_rp.p, F.p_col.p, F.p_val.p, cnt.p,
+                     nullptr, nullptr, nullptr);
+  RT_LAUNCH_CHECK();
+  RT_CHECK((scan<int64_t, int64_t>(ctx, cnt.p, aprp.p, n + 1, false)));
+  RT_CHECK(ctx->sync_read(aprp.p + n, sizeof(int64_t)));
+  int64_t nnzap = 0;
+  std::memcpy(&nnzap, ctx->host, sizeof(int64_t));
+  RT_CHECK(apcol.reserve(std::max<int64_t>(nnzap, 1)));
+  RT_CHECK(apval.reserve(std::max<int64_t>(nnzap, 1)));
+  hipLaunchKernelGGL((k_sa_ap<true>), dim3(gw), dim3(kBlock), 0, st, n, F.rp.p, F.col.p,
+                     F.val64.p, F.diag64.p, F.pmap.p, F.p_rp.p, F.p_col.p, F.p_val.p, nullptr,
+                     aprp.p, apcol.p, apval.p);
+  RT_LAUNCH_CHECK();
+  // P^T (A P): the coarse rows
+  DevBuf<int64_t> rcnt;
+  RT_CHECK(rcnt.reserve(nc + 1));
+  RT_CHECK_HIP(hipMemsetAsync(rcnt.p + nc, 0, sizeof(int64_t), st));
+  const int gc = grid_for(nc * (int64_t)kWave);
+  hipLaunchKernelGGL((k_sa_rap<false>), dim3(gc), dim3(kBlock), 0, st, nc, F.pt_rp.p, F.pt_row.p,
+                     F.pt_val.p, aprp.p, apcol.p, apval.p, rcnt.p, nullptr, nullptr, nullptr,
+                     nullptr);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(C.rp.reserve(nc + 1));
+  RT_CHECK((scan<int64_t, int64_t>(ctx, rcnt.p, C.rp.p, nc + 1, false)));
+  RT_CHECK(ctx->sync_read(C.rp.p + nc, sizeof(int64_t)));
+  int64_t nnz = 0;
+  std::memcpy(&nnz, ctx->host, sizeof(int64_t));
+  C.nnz = nnz;
+  RT_CHECK(max_nonneg<int64_t>(ctx, rcnt.p, nc, &C.max_row));
+  RT_CHECK(C.col.reserve(std::max<int64_t>(nnz, 1)));
+  RT_CHECK(C.val64.reserve(nnz + kSpmvPad));
+  RT_CHECK(C.diag64.reserve(nc));
+  hipLaunchKernelGGL((k_sa_rap<true>), dim3(gc), dim3(kBlock), 0, st, nc, F.pt_rp.p, F.pt_row.p,
+                     F.pt_val.p, aprp.p, apcol.p, apval.p, nullptr, C.rp.p, C.col.p, C.val64.p,
+                     C.diag64.p);
+  RT_LAUNCH_CHECK();
+  *ok = true;
+  return RT_OK;
+}
+
 // Build level l+1 from level l: aggregates, coarse CSR structure, and the
 // coarse columns and values, so that the new level is complete before it
 // serves as the fine level of the next one.  *stalled: the aggregation left
@@ -603,7 +1050,14 @@ int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim, bool* stalled) {
   Level& Lr = A->levels[l];   // re-fetch after emplace_back
   C.n = nc;
   C.code = std::move(ccode);
-  // coarse structure: count, scan
+  Lr.smoothed = false;
+  if (A->amg.prolongation == RT_PROLONG_SMOOTHED) {
+    bool ok = false;
+    RT_CHECK(build_smoothed(ctx, Lr, C, nc, &ok));
+    Lr.smoothed = ok;
+    if (ok) return RT_OK;
+  }
+  // piecewise-constant prolongation: coarse structure: count, scan
   DevBuf<int64_t> cnt;
   RT_CHECK(cnt.reserve(nc + 1));
   RT_CHECK_HIP(hipMemsetAsync(cnt.p + nc, 0, sizeof(int64_t), st));
@@ -624,16 +1078,24 @@ int build_next_level(rt_ctx* ctx, rt_matrix* A, int l, int dim, bool* stalled) {
   return galerkin_fill(ctx, A->levels[l], C);
 }
 
-int level_vectors(Level& L, bool fp32, bool wcycle) {
+// Work vectors of a level; cycle 2 (W) adds the second visit's residual and
+// correction, cycle 3 (K) also A v1 and the inner products' partials.
+int level_vectors(Level& L, bool fp32, int cycle) {
   for (auto* b : {&L.b64, &L.x64, &L.t64, &L.r64, &L.d64, &L.sinv64, &L.dinv64})
     RT_CHECK(b->reserve(L.n));
-  if (wcycle)
+  if (cycle >= 2)
     for (auto* b : {&L.wr64, &L.wx64}) RT_CHECK(b->reserve(L.n));
+  if (cycle == 3) {
+    RT_CHECK(L.kw64.reserve(L.n));
+    RT_CHECK(L.kpart.reserve(3 * kKdotBlocks));
+    RT_CHECK(L.kc.reserve(8));
+  }
   if (fp32) {
     for (auto* b : {&L.b32, &L.x32, &L.t32, &L.r32, &L.d32, &L.sinv32, &L.dinv32})
       RT_CHECK(b->reserve(L.n));
-    if (wcycle)
+    if (cycle >= 2)
       for (auto* b : {&L.wr32, &L.wx32}) RT_CHECK(b->reserve(L.n));
+    if (cycle == 3) RT_CHECK(L.kw32.reserve(L.n));
     RT_CHECK(L.val32.reserve(L.nnz + kSpmvPad));
     RT_CHECK(L.diag32.reserve(L.n));
   }
@@ -656,18 +1118,17 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
     RT_CHECK_HIP(hipMemcpyAsync(L0.code.p, nb->skeys.p, sizeof(uint64_t) * L0.n,
                                 hipMemcpyDeviceToDevice, st));
   }
+  RT_CHECK(level_vectors(L0, fp32, A->amg.cycle));   // level 0: assembly wrote its scalings
   for (int l = 0; (int)A->levels.size() < A->amg.max_levels; ++l) {
     if (A->levels[l].n <= A->amg.coarse_size) break;
     bool stalled = false;
     RT_CHECK(build_next_level(ctx, A, l, nb->dim, &stalled));
     if (stalled) break;
-    if (A->amg.tiled_spmv) RT_CHECK(build_tiles(ctx, A->levels.back()));
-  }
-  for (Level& L : A->levels) RT_CHECK(level_vectors(L, fp32, A->amg.cycle == 2));
-  // smoother scalings and FP32 copies of the coarse levels (the Galerkin
-  // products were formed while the levels were built)
-  for (size_t l = 1; l < A->levels.size(); ++l) {
-    Level& L = A->levels[l];
+    Level& L = A->levels.back();
+    if (A->amg.tiled_spmv) RT_CHECK(build_tiles(ctx, L));
+    // vectors, FP32 copy and smoother scalings of the new level now: the
+    // smoothed prolongation out of it reads its l1 scaling
+    RT_CHECK(level_vectors(L, fp32, A->amg.cycle));
     if (fp32) {
       if (L.nnz > 0)
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz)), dim3(kBlock), 0, st, L.nnz,
@@ -680,7 +1141,19 @@ int amg_setup(rt_ctx* ctx, rt_matrix* A) {
                        L.val64.p, L.diag64.p, L.sinv64.p, L.dinv64.p,
                        fp32 ? L.sinv32.p : nullptr, fp32 ? L.dinv32.p : nullptr);
     RT_LAUNCH_CHECK();
-  }   // level 0: the assembly kernel wrote its scalings
+  }
+  for (Level& L : A->levels) {
+    if (fp32 && L.smoothed) {   // FP32 copies of P and P^T for the FP32 V-cycle
+      const int64_t np = std::max<int64_t>(L.p_nnz, 1);
+      RT_CHECK(L.p_val32.reserve(np));
+      RT_CHECK(L.pt_val32.reserve(np));
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(np)), dim3(kBlock), 0, st, np, L.p_val.p,
+                         L.p_val32.p);
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(np)), dim3(kBlock), 0, st, np, L.pt_val.p,
+                         L.pt_val32.p);
+      RT_LAUNCH_CHECK();
+    }
+  }
   // coarsest level: dense inverse when small
   Level& Lc = A->levels.back();
   A->coarse_direct = A->levels.size() > 1 && Lc.n <= kDenseMax;
@@ -735,6 +1208,43 @@ static int cheb_smooth(hipStream_t st, rt_matrix* A, Level& L, int degree, const
 
 template <typename T>
 static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
+                        const int32_t* stop);
+
+// The K-cycle's coarse correction on level c (not the coarsest): from b(c)
+// into x(c).  wr, wx hold the second visit's residual and correction, kw the
+// product A v1; t(c) is free between the visits and takes A v2.
+template <typename T>
+static int kcycle_correct(rt_ctx* ctx, rt_matrix* A, size_t c, const int32_t* stop) {
+  using B = LevelBufs<T>;
+  hipStream_t st = ctx->stream;
+  Level& C = A->levels[c];
+  const int64_t n = C.n;
+  const int nb = std::min<int>(kKdotBlocks, std::max(1, grid_for(n)));
+  RT_CHECK(vcycle_level<T>(ctx, A, c, B::b(C), B::x(C), stop));
+  RT_CHECK((launch_spmv_level<T, SP_PLAIN>(st, C, B::val(C), B::diag(C), B::x(C), nullptr,
+                                           nullptr, B::kw(C), nullptr, nullptr, nullptr,
+                                           level_shape<T>(C), nullptr, stop)));
+  hipLaunchKernelGGL(k_kdots<T>, dim3(nb), dim3(kBlock), 0, st, n, B::x(C), B::b(C), B::kw(C),
+                     nullptr, C.kpart.p, stop);
+  hipLaunchKernelGGL(k_kcoef, dim3(1), dim3(kBlock), 0, st, 1, nb, C.kpart.p, C.kc.p, stop);
+  hipLaunchKernelGGL(k_kresid<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, C.kc.p, B::b(C),
+                     B::kw(C), B::wr(C), stop);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(vcycle_level<T>(ctx, A, c, B::wr(C), B::wx(C), stop));
+  RT_CHECK((launch_spmv_level<T, SP_PLAIN>(st, C, B::val(C), B::diag(C), B::wx(C), nullptr,
+                                           nullptr, B::t(C), nullptr, nullptr, nullptr,
+                                           level_shape<T>(C), nullptr, stop)));
+  hipLaunchKernelGGL(k_kdots<T>, dim3(nb), dim3(kBlock), 0, st, n, B::wx(C), B::kw(C), B::t(C),
+                     B::wr(C), C.kpart.p, stop);
+  hipLaunchKernelGGL(k_kcoef, dim3(1), dim3(kBlock), 0, st, 2, nb, C.kpart.p, C.kc.p, stop);
+  hipLaunchKernelGGL(k_kcomb<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, C.kc.p, B::x(C),
+                     B::wx(C), B::x(C), stop);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
+template <typename T>
+static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
                         const int32_t* stop) {
   using B = LevelBufs<T>;
   hipStream_t st = ctx->stream;
@@ -780,10 +1290,17 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
                                            nullptr, nullptr, nullptr, level_shape<T>(L),
                                            nullptr, stop)));
-  hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
-                     L.amem.p, r, B::b(C), stop);
+  if (L.smoothed)
+    hipLaunchKernelGGL((k_restrict_p<T, T>), dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n,
+                       L.pt_rp.p, L.pt_row.p, B::ptv(L), r, B::b(C), stop);
+  else
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
+                       L.amem.p, r, B::b(C), stop);
   RT_LAUNCH_CHECK();
-  RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::b(C), B::x(C), stop));
+  if (A->amg.cycle == 3 && l + 2 < A->levels.size())
+    RT_CHECK(kcycle_correct<T>(ctx, A, l + 1, stop));
+  else
+    RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::b(C), B::x(C), stop));
   if (A->amg.cycle == 2 && l + 2 < A->levels.size()) {
     // W-cycle: a second coarse correction from the residual of the first
     RT_CHECK((launch_spmv_level<T, SP_RESID>(st, C, B::val(C), B::diag(C), B::x(C), B::b(C),
@@ -794,8 +1311,12 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
                        B::x(C), stop);
     RT_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p, B::x(C),
-                     t, stop);
+  if (L.smoothed)
+    hipLaunchKernelGGL((k_prolong_p<T, T>), dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.p_rp.p,
+                       L.p_col.p, B::pv(L), B::x(C), t, stop);
+  else
+    hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p,
+                       B::x(C), t, stop);
   RT_LAUNCH_CHECK();
   if (cheb) return cheb_smooth<T>(st, A, L, A->amg.smoother_degree, b, t, out, stop);
   RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), t, b, B::sinv(L), out,

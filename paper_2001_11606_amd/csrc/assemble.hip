@@ -454,12 +454,14 @@ int rt_assemble(rt_ctx* ctx, const rt_neighbors* nb, const rt_step_inputs* in,
     fresh = true;
   }
   M->resid_ok = false;   // a new operator: no residual carries over
-  rt_amg_opts d{8, 256, 0.25, 1, 1, RT_SMOOTHER_L1_JACOBI, 2, 1};
+  rt_amg_opts d{8, 256, 0.25, 1, 1, RT_SMOOTHER_L1_JACOBI, 2, 1, RT_PROLONG_PIECEWISE};
   if (amg && (amg->smoother < RT_SMOOTHER_L1_JACOBI || amg->smoother > RT_SMOOTHER_CHEBYSHEV ||
               amg->smoother_degree < 1 || amg->smoother_degree > 8 || amg->cycle < 1 ||
-              amg->cycle > 2)) {
-    rt::set_error("rt_assemble: smoother %d of degree %d, cycle %d (smoother 0 or 1, degree "
-                  "1..8, cycle 1 or 2)", amg->smoother, amg->smoother_degree, amg->cycle);
+              amg->cycle > 3 || amg->prolongation < RT_PROLONG_PIECEWISE ||
+              amg->prolongation > RT_PROLONG_SMOOTHED)) {
+    rt::set_error("rt_assemble: smoother %d of degree %d, cycle %d, prolongation %d (smoother 0 "
+                  "or 1, degree 1..8, cycle 1, 2 or 3, prolongation 0 or 1)", amg->smoother,
+                  amg->smoother_degree, amg->cycle, amg->prolongation);
     if (fresh) delete M;
     return RT_E_ARG;
   }
@@ -489,6 +491,7 @@ int rt_matrix_get_info(const rt_matrix* A, rt_matrix_info* info) {
     info->level_n[l] = A->levels[l].n;
     info->level_nnz[l] = A->levels[l].nnz + A->levels[l].n;
     info->level_tile_cols[l] = A->levels[l].tiled ? A->levels[l].tile_cols_total : 0;
+    info->level_p_nnz[l] = A->levels[l].smoothed ? A->levels[l].p_nnz : 0;
   }
   return RT_OK;
 }

@@ -291,11 +291,24 @@ struct Level {
   DevBuf<int32_t> pmap;         // node -> aggregate on the next level (-1: none)
   DevBuf<int64_t> crange;       // next-level aggregate -> offset of its members (n_next + 1)
   DevBuf<int32_t> amem;         // members of the aggregates, ascending per aggregate
+  // smoothed prolongation to the next level (smoothed == false: piecewise
+  // constant over pmap): P in CSR (rows = nodes, ascending columns) and its
+  // transpose (rows = next-level nodes, ascending fine rows), FP64 and FP32
+  bool smoothed = false;
+  int64_t p_nnz = 0;            // entries of P (and of P^T)
+  DevBuf<int64_t> p_rp, pt_rp;
+  DevBuf<int32_t> p_col, pt_row;
+  DevBuf<double> p_val, pt_val;
+  DevBuf<float> p_val32, pt_val32;
   // work vectors of this level (b: right-hand side, x: result, t, r: temporaries)
   DevBuf<double> b64, x64, t64, r64, d64;   // d: Chebyshev search direction
   DevBuf<float> b32, x32, t32, r32, d32;
-  DevBuf<double> wr64, wx64;   // W-cycle: residual and correction of the second visit
+  DevBuf<double> wr64, wx64;   // W- and K-cycle: residual and correction of the second visit
   DevBuf<float> wr32, wx32;
+  DevBuf<double> kw64;         // K-cycle: A times the first correction
+  DevBuf<float> kw32;
+  DevBuf<double> kpart;        // K-cycle: block partials of its inner products
+  DevBuf<double> kc;           // K-cycle: its inner products and weights
 };
 template <typename T>
 inline int level_shape(const Level& L) {

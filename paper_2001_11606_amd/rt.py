@@ -56,13 +56,14 @@ class rt_step_inputs(ctypes.Structure):
 class rt_amg_opts(ctypes.Structure):
     _fields_ = [("max_levels", c_int), ("coarse_size", c_int), ("strength", c_dbl),
                 ("build_fp32", c_int), ("tiled_spmv", c_int), ("smoother", c_int),
-                ("smoother_degree", c_int), ("cycle", c_int)]
+                ("smoother_degree", c_int), ("cycle", c_int), ("prolongation", c_int)]
 
 
 class rt_matrix_info(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("levels", c_int),
                 ("level_n", c_i64 * 16), ("level_nnz", c_i64 * 16),
-                ("level_tile_cols", c_i64 * 16)]
+                ("level_tile_cols", c_i64 * 16),
+                ("level_p_nnz", c_i64 * 16)]
 
 
 class rt_solve_opts(ctypes.Structure):
@@ -425,11 +426,15 @@ def solve_opts(precision=RT_PREC_FP64, precond=PRECOND_JACOBI, tol=1e-10, max_it
 RT_SMOOTHER_L1_JACOBI, RT_SMOOTHER_CHEBYSHEV = 0, 1
 
 
+RT_PROLONG_PIECEWISE, RT_PROLONG_SMOOTHED = 0, 1
+RT_CYCLE_V, RT_CYCLE_W, RT_CYCLE_K = 1, 2, 3
+
+
 def amg_opts(max_levels=8, coarse_size=256, strength=0.25, build_fp32=1,
              tiled_spmv=1, smoother=RT_SMOOTHER_L1_JACOBI, smoother_degree=2,
-             cycle=1) -> rt_amg_opts:
+             cycle=1, prolongation=RT_PROLONG_PIECEWISE) -> rt_amg_opts:
     return rt_amg_opts(max_levels, coarse_size, strength, build_fp32, tiled_spmv, smoother,
-                       smoother_degree, cycle)
+                       smoother_degree, cycle, prolongation)
 
 
 def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100,
@@ -462,6 +467,14 @@ class Context:
         if self.handle:
             rt_destroy(self.handle)
             self.handle = 0
+
+    def free(self, *handles):
+        """Release matrices and neighbour lists of this context before close()."""
+        lib = load()
+        drop = {h.handle if isinstance(h, Neighbors) else h for h in handles}
+        for kind, h in [o for o in self._owned if o[1] in drop]:
+            (lib.rt_matrix_free if kind == "A" else lib.rt_neighbors_free)(h)
+        self._owned = [o for o in self._owned if o[1] not in drop]
 
     def __enter__(self):
         return self

@@ -115,14 +115,28 @@ def check_case(ctx, name, prob):
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: chebyshev prec={prec} err={e} its={st.iterations}"
     cc.free()
-    # the W-cycle (two coarse corrections per level), FP64 and mixed
-    cw_ = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8, cycle=2))
+    # the W-cycle (two coarse corrections per level) with smoothed
+    # aggregation, FP64 and mixed
+    cw_ = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8, cycle=2,
+                                          prolongation=rt.RT_PROLONG_SMOOTHED))
+    winfo = rt.rt_matrix_get_info(cw_.A)
+    assert winfo.levels == 1 or winfo.level_p_nnz[0] > 0, f"{name}: smoothed prolongation not built"
     for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
         x = np.zeros(nin)
         s, st = rt.rt_solve(ctx, cw_.A, p(b), p(x), rt.solve_opts(prec, 1, tol, 3000, 1e-4, 50))
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
-        assert s == 0 and e <= bar, f"{name}: w-cycle prec={prec} err={e} its={st.iterations}"
+        assert s == 0 and e <= bar, f"{name}: w-cycle sa prec={prec} err={e} its={st.iterations}"
     cw_.free()
+    # the K-cycle (coarse corrections weighted by inner products), FP64 and
+    # mixed, with the Chebyshev smoother
+    kc_ = Case(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8, cycle=rt.RT_CYCLE_K,
+                                          smoother=rt.RT_SMOOTHER_CHEBYSHEV))
+    for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
+        x = np.zeros(nin)
+        s, st = rt.rt_solve(ctx, kc_.A, p(b), p(x), rt.solve_opts(prec, 1, tol, 3000, 1e-4, 50))
+        e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+        assert s == 0 and e <= bar, f"{name}: k-cycle prec={prec} err={e} its={st.iterations}"
+    kc_.free()
     # GMRES on the unscaled operator, Jacobi and AMG, with and without restarts
     for precond, restart in (((1, 4),) if QUICK else ((0, 30), (1, 30), (1, 4))):
         x = np.zeros(nin)

@@ -6,7 +6,8 @@
   keeps one level (Jacobi); geometric aggregation (theta = 0) coarsens it.
 * The hierarchy solves: FP64 and mixed V-cycle-preconditioned solves match
   the oracle on every workload family of the parity tests' sizes, with
-  strength-based and with geometric aggregation.
+  strength-based and with geometric aggregation, with the smoothed
+  prolongation, and with the K-cycle.
 """
 import numpy as np
 import pytest
@@ -47,8 +48,9 @@ def test_strength_leaves_diagonal_rows_fine(ctx):
 @pytest.mark.parametrize("name", ["mms2d_64", "diffusive2d_48", "diffusive3d_16", "mms3d_12",
                                   "densitystep3d_16", "wendland2d_24", "wendland3d_9",
                                   "periodic3d_13", "densitystep3d_12_coldpatch", "ensemble2d"])
-@pytest.mark.parametrize("strength", [0.25, 0.0])
-def test_vcycle_solves_match_oracle(ctx, name, strength):
+@pytest.mark.parametrize("strength,prolong,cycle", [(0.25, 0, 1), (0.0, 0, 1), (0.25, 1, 1),
+                                                    (0.25, 0, 3)])
+def test_vcycle_solves_match_oracle(ctx, name, strength, prolong, cycle):
     import torch
     from paper_2001_11606_amd import rt
     prob = CASES[name]()
@@ -57,7 +59,8 @@ def test_vcycle_solves_match_oracle(ctx, name, strength):
     b = sysm.A.diagonal() * 10.0 ** np.random.default_rng(29).uniform(-4.0, 0.0, nin)
     x_ref = linsolve.solve(sysm.A, b, tol=1e-15)
     dp, nb, A = gpu_system(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=32,
-                                                      strength=strength))
+                                                      strength=strength, prolongation=prolong,
+                                                      cycle=cycle))
     info = ctx.matrix_info(A)
     its = []
     for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
@@ -68,5 +71,5 @@ def test_vcycle_solves_match_oracle(ctx, name, strength):
         err = np.max(np.abs(xt.cpu().numpy() - x_ref) / np.abs(x_ref))
         assert err <= bar, (prec, err, st.iterations)
         its.append(st.iterations)
-    say(f"[amg] {name} strength={strength}: levels {info.levels} sizes "
+    say(f"[amg] {name} strength={strength} smoothed={prolong} cycle={cycle}: levels {info.levels} sizes "
         f"{list(info.level_n[:info.levels])} iterations fp64/mixed {its}")
