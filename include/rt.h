@@ -340,6 +340,13 @@ typedef struct {
                               FP64 product (MIXED) or the CG recursion (FP64) */
   int resid_calls;         /* FP64 residual products b - A x timed (profiling on) */
   double resid_seconds;
+  double init_rel_residual; /* ||b - A x0|| / ||b|| at the start: from an FP64
+                              product, or from the residual rt_newton_step
+                              carries over from its last solve              */
+  int replacements;        /* FP64: times CG's recursive residual was replaced
+                              by a computed b - A x (after more than 32 CG
+                              steps since the last computed one, counting
+                              steps carried over by rt_newton_step)          */
 } rt_solve_stats;
 
 int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
@@ -389,6 +396,11 @@ typedef struct {
   double material_tol;
   int material_max_iter;
   int state_order;
+  int recompute_residual;  /* 0: an outer iteration after the first starts its
+                              solve from the last solve's residual plus the
+                              change of b (no product); 1: from b - A x formed
+                              by an FP64 product.  rt_batch_newton_step always
+                              forms it and ignores this field.                */
 } rt_newton_opts;
 
 typedef struct {

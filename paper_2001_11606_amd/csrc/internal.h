@@ -351,6 +351,8 @@ struct rt_matrix {
   bool resid_ok = false;
   bool r64_valid = false;            // set by solve_sorted: r64 = b - A x on return (the
                                      // recursive residual after FP64 CG: equal up to rounding)
+  int rec_steps = 0;                 // CG steps r64 has been carried by the recursion since
+                                     // it was last formed by a product (FP64 path)
 };
 
 namespace rt {

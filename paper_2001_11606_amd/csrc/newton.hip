@@ -223,8 +223,10 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   }
   RT_CHECK(check_solve_opts(&opts->solve));
   if (!(opts->material_tol > 0.0) || opts->material_max_iter < 1 ||
-      (opts->state_order != 0 && opts->state_order != 1)) {
-    set_error("rt_newton_step: material_tol must be > 0, material_max_iter >= 1, state_order 0 or 1");
+      (opts->state_order != 0 && opts->state_order != 1) ||
+      (opts->recompute_residual != 0 && opts->recompute_residual != 1)) {
+    set_error("rt_newton_step: material_tol must be > 0, material_max_iter >= 1, state_order "
+              "and recompute_residual 0 or 1");
     return RT_E_ARG;
   }
   RT_CHECK_HIP(hipSetDevice(ctx->device));
@@ -257,7 +259,7 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   // Outer iterations after the first start from the last solution with the
   // same matrix, so the last solve's residual b^l - A E^{l+1} turns into the
   // new initial residual by adding b^{l+1} - b^l: no product needed.
-  const bool carry = ell > 0 && A->resid_ok;
+  const bool carry = ell > 0 && A->resid_ok && !opts->recompute_residual;
   A->resid_ok = false;
   if (carry) {
     std::swap(A->bs, A->bs_prev);   // bs_prev: the last right-hand side

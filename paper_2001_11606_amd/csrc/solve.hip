@@ -580,11 +580,19 @@ int residual64(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, const 
   return RT_OK;
 }
 
+// FP64 CG steps after which the recursive residual is replaced by a
+// computed one: the recursion's drift from b - A x grows with the steps
+// taken (and carried between outer iterations); one product per 32 steps
+// keeps it at rounding level for about 3% more products on long solves.
+constexpr int kReplaceSteps = 32;
+
 // The solve on sorted vectors with the buffers of W (see solve_sorted);
-// *resid_valid: W.r64 holds b - A x on return.
+// *resid_valid: W.r64 holds b - A x on return.  *rec_steps: on entry, the
+// CG steps the residual carried in W.r64 (with b_prev) has been updated by
+// recursion since a product formed it; on return, the same for W.r64.
 int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double* x,
                const rt_solve_opts* o, rt_solve_stats* stt, const double* b_prev,
-               const int32_t* mismatch, bool* resid_valid) {
+               const int32_t* mismatch, bool* resid_valid, int* rec_steps) {
   hipStream_t st = ctx->stream;
   const int64_t n = A->n;
   const bool mixed = o->precision == RT_PREC_MIXED;
@@ -635,14 +643,31 @@ int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double
   const double thr2 = o->tol * o->tol * bb;
   int status = RT_OK;
   if (!mixed) {
+    int rec = have_r ? *rec_steps : 0;
     if (!have_r) RT_CHECK(residual64(ctx, A, W, b, x, nullptr, nullptr, &rr, &cw));
-    int its = 0;
+    stt->init_rel_residual = std::sqrt(rr / bb);
     const CwTest t{CW_X, L0.dinv64.p, cwthr};
-    RT_CHECK(pcg_core<double>(ctx, A, W, amg, x, W.r64, rr, thr2, o->max_iter, &its, &rr, t, cw,
-                              &cw));
-    stt->iterations = its;
+    int total = 0;
+    for (int pass = 0;; ++pass) {
+      int its = 0;
+      RT_CHECK(pcg_core<double>(ctx, A, W, amg, x, W.r64, rr, thr2, o->max_iter - total, &its,
+                                &rr, t, cw, &cw));
+      total += its;
+      rec += its;
+      if (rec <= kReplaceSteps || pass == 2) break;
+      // residual replacement; CG restarts from the computed residual if it
+      // misses the tolerance
+      RT_CHECK(residual64(ctx, A, W, b, x, nullptr, nullptr, &rr, &cw));
+      rec = 0;
+      ++stt->replacements;
+      if (!(rr > thr2 || cw > cwthr) || total >= o->max_iter) break;
+    }
+    stt->iterations = total;
+    *rec_steps = rec;
   } else {
     if (!have_r) RT_CHECK(residual64(ctx, A, W, b, x, W.r32, w32, &rr, &cw));
+    stt->init_rel_residual = std::sqrt(rr / bb);
+    *rec_steps = 0;
     int total = 0, refine = 0;
     while ((rr > thr2 || cw > cwthr) && total < o->max_iter && refine < o->max_refine) {
       // reduce by inner_tol, or just enough (with margin) to reach tol; the
@@ -690,8 +715,10 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt
   }
   RT_CHECK(ensure_work(A, mixed));
   bool valid = false;
-  const int s = solve_work(ctx, A, work_of(A), b, x, o, stt, b_prev, mismatch, &valid);
+  int rec = A->rec_steps;
+  const int s = solve_work(ctx, A, work_of(A), b, x, o, stt, b_prev, mismatch, &valid, &rec);
   A->r64_valid = valid;
+  A->rec_steps = rec;
   return s;
 }
 
@@ -845,7 +872,8 @@ extern "C" int rt_solve_noalloc(rt_ctx* ctx, rt_matrix* A, const double* b, doub
   int s = gather_sorted(ctx, A->nb, n, b, bs);
   if (s == RT_OK) s = gather_sorted(ctx, A->nb, n, x, xs);
   bool valid = false;
-  if (s == RT_OK) s = solve_work(ctx, A, W, bs, xs, opts, stt, nullptr, nullptr, &valid);
+  int rec = 0;
+  if (s == RT_OK) s = solve_work(ctx, A, W, bs, xs, opts, stt, nullptr, nullptr, &valid, &rec);
   ctx->profiling = prof;
   if (s < 0) return s;
   RT_CHECK(scatter_user(ctx, A->nb, n, xs, x));

@@ -65,20 +65,25 @@ class StepReport:
     resid_calls: int = 0
     resid_seconds: float = 0.0
     cw_residual: list = field(default_factory=list)
+    init_rel_residual: list = field(default_factory=list)
+    replacements: list = field(default_factory=list)
 
 
 def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
               amg: Optional[rt.rt_amg_opts] = None, solve: Optional[rt.rt_solve_opts] = None,
               eps_e: float = 1e-8, eps_E: float = 1e-8, material_tol: float = 1e-14,
               max_outer: int = 50, fixed_outer: Optional[int] = None,
-              shapes: Optional[list] = None, sorted_state: bool = True):
+              shapes: Optional[list] = None, sorted_state: bool = True,
+              recompute_residual: bool = False):
     """One backward-Euler step.  Returns (e, E, A, report) with e, E the new
     interior energies (device tensors, user order).  shapes: per-level
     (FP64, FP32[, FP64 residual]) SpMV shape indices (-1: default), e.g. the
     "chosen" list of Context.tune on an earlier matrix of the same problem,
     applied after assembly.
     sorted_state: keep e, E in the library's sorted order during the outer
-    iterations (one conversion each way per step instead of per iteration)."""
+    iterations (one conversion each way per step instead of per iteration).
+    recompute_residual: start every solve from b - A x formed by a product
+    instead of the residual carried over from the last outer iteration."""
     A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                      dp.limiter_k, amg=amg, A=A)
     if shapes:
@@ -97,7 +102,8 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
     else:
         e, E = e_user, E_user
     solve = solve or rt.solve_opts()
-    nopts = rt.newton_opts(solve, material_tol, state_order=1 if sorted_state else 0)
+    nopts = rt.newton_opts(solve, material_tol, state_order=1 if sorted_state else 0,
+                           recompute_residual=1 if recompute_residual else 0)
     rep = StepReport()
     n_outer = fixed_outer if fixed_outer is not None else max_outer
     for ell in range(n_outer):
@@ -119,6 +125,8 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
         rep.resid_calls += st.solve.resid_calls
         rep.resid_seconds += st.solve.resid_seconds
         rep.cw_residual.append(st.solve.cw_residual)
+        rep.init_rel_residual.append(st.solve.init_rel_residual)
+        rep.replacements.append(st.solve.replacements)
         if fixed_outer is None and st.delta_e < eps_e and st.delta_E < eps_E:
             break
     if sorted_state:

@@ -79,12 +79,13 @@ class rt_solve_stats(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("refinements", c_int), ("rel_residual", c_dbl),
                 ("seconds", c_dbl), ("spmv_calls", c_int), ("spmv_seconds", c_dbl),
                 ("spmv32_calls", c_int), ("spmv32_seconds", c_dbl), ("cw_residual", c_dbl),
-                ("resid_calls", c_int), ("resid_seconds", c_dbl)]
+                ("resid_calls", c_int), ("resid_seconds", c_dbl),
+                ("init_rel_residual", c_dbl), ("replacements", c_int)]
 
 
 class rt_newton_opts(ctypes.Structure):
     _fields_ = [("solve", rt_solve_opts), ("material_tol", c_dbl), ("material_max_iter", c_int),
-                ("state_order", c_int)]
+                ("state_order", c_int), ("recompute_residual", c_int)]
 
 
 class rt_newton_stats(ctypes.Structure):
@@ -438,8 +439,9 @@ def amg_opts(max_levels=8, coarse_size=256, strength=0.25, build_fp32=1,
 
 
 def newton_opts(solve: rt_solve_opts, material_tol=1e-14, material_max_iter=100,
-                state_order=0) -> rt_newton_opts:
-    return rt_newton_opts(solve, material_tol, material_max_iter, state_order)
+                state_order=0, recompute_residual=0) -> rt_newton_opts:
+    return rt_newton_opts(solve, material_tol, material_max_iter, state_order,
+                          recompute_residual)
 
 
 @dataclass

@@ -231,20 +231,24 @@ def test_deterministic(ctx):
     assert outs[0] == outs[1]
 
 
-def test_deep_hierarchy_repeated_setup(ctx):
+@pytest.mark.parametrize("name,strength", [("marshak3d_16", 0.0), ("diffusive3d_16", 0.25)])
+def test_deep_hierarchy_repeated_setup(ctx, name, strength):
     """Several set-ups of a many-level hierarchy in one process (device memory
     recycled between them): every coarse level must be complete before it is
-    coarsened again, and AMG-preconditioned solves must match the oracle."""
+    coarsened again, and AMG-preconditioned solves must match the oracle.
+    The Marshak rows are dominated by their diagonals, so the strength test
+    would keep them on one level: there the aggregation is geometric."""
     import torch
     from paper_2001_11606_amd import rt
-    prob = CASES["marshak3d_16"]()
+    prob = CASES[name]()
     ptr, idx, fz, sysm = oracle_system(prob)
     nin = prob.n_interior
     b = np.random.default_rng(5).standard_normal(nin) * sysm.A.diagonal()
     x_ref = linsolve.dense(sysm.A, b)
     for rep in range(3):
-        say(f"[deep hierarchy] marshak3d_16 set-up {rep}")
-        dp, nb, A = gpu_system(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8))
+        say(f"[deep hierarchy] {name} strength {strength} set-up {rep}")
+        dp, nb, A = gpu_system(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=8,
+                                                          strength=strength))
         assert ctx.matrix_info(A).levels >= 4
         bt = torch.tensor(b, device=ctx.device)
         for prec, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
