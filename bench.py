@@ -23,6 +23,8 @@ with per-step sources; --steps 1000 runs one full cycle).
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 from concurrent.futures import ThreadPoolExecutor
 import json
 import os
@@ -66,6 +68,19 @@ def make_problem(workload: str, n: int):
     if workload == "wendland3d":
         return synth.wendland_lattice(3, n)
     raise SystemExit(f"unknown workload {workload}")
+
+
+@contextlib.contextmanager
+def paused_gc():
+    """The interpreter's cyclic garbage collector off while steps are timed,
+    after one collection: a full pass over the problem generators' objects
+    once stalled the host for about 50 ms between two library calls."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def run_step(ctx, dp, solve, outer, amg, shapes=None):
@@ -279,12 +294,13 @@ def run_ensemble(args):
     for w in range(max(1, args.warmup)):
         log(f"[bench] warmup step {w}")
         step(rt.RT_PREC_MIXED)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        e, E, st, _ = step(rt.RT_PREC_MIXED)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    with paused_gc():
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            e, E, st, _ = step(rt.RT_PREC_MIXED)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t1) / args.steps
     value = ntot / (ms * 1e-3)
     # batched solve alone, mixed vs FP64, on one kept batch
     e, E, st, B = step(rt.RT_PREC_MIXED, keep=True)
@@ -368,8 +384,6 @@ def run_coswave(args):
     nin = prob.n_interior
     V = prob.m / prob.rho
     start = float(np.sum(prob.m * prob.e) + np.sum(V * prob.E))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     done = [0]
 
     def progress(t, e, E):
@@ -377,9 +391,12 @@ def run_coswave(args):
         if done[0] % 100 == 0:
             log(f"[bench] step {done[0]} t={t:.3e}")
 
-    t, reps = driver.run_fixed(ctx, dp, prob.dt, args.steps, callback=progress, **kw)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with paused_gc():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, reps = driver.run_fixed(ctx, dp, prob.dt, args.steps, callback=progress, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     log(f"[bench] {args.steps} steps in {wall:.2f} s")
     out = {
         "metric": "particle-updates/s", "value": nin * args.steps / wall,
@@ -448,10 +465,11 @@ def run_config2(args):
         log(f"[bench] config2 warmup run {w}")
         run(2)
     log(f"[bench] timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps, dp = run(args.steps)
-    wall = time.perf_counter() - t0
+    with paused_gc():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps, dp = run(args.steps)
+        wall = time.perf_counter() - t0
     outer = sum(r.outer for r in reps)
     nm = prob.copy()
     nm.set_time(args.steps * prob.dt)
@@ -665,16 +683,17 @@ def run_single(args):
 
     log(f"[bench] timing {args.steps} steps")
     reps = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        e, E, A, rep, nb = one(solve32, profile=True)
-        reps.append(rep)
-        info = ctx.matrix_info(A)
-        if s + 1 < args.steps:
-            release(ctx, nb, A)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with paused_gc():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            e, E, A, rep, nb = one(solve32, profile=True)
+            reps.append(rep)
+            info = ctx.matrix_info(A)
+            if s + 1 < args.steps:
+                release(ctx, nb, A)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
     nin = prob.n_interior
     value = nin * args.outer * args.steps / elapsed

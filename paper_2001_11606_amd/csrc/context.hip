@@ -176,8 +176,11 @@ int rt_ctx::sync_read(const void* dev, size_t bytes) {
 
 int rt_ctx::prof_mark(size_t* idx) {
   if (prof_used == prof_ev.size()) {
+    // timing only (read after the stream is synchronised): no system-scope
+    // fence, whose cache writeback and invalidation would slow the product
+    // that follows and inflate the timings
     hipEvent_t e;
-    RT_CHECK_HIP(hipEventCreate(&e));
+    RT_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     prof_ev.push_back(e);
   }
   RT_CHECK_HIP(hipEventRecord(prof_ev[prof_used], stream));

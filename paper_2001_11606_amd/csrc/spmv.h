@@ -59,6 +59,26 @@ __device__ __forceinline__ int xcd_block(int per) {
   return (p % kXcd) * per + p / kXcd;
 }
 
+#ifndef RT_SPMV_STAGE
+#define RT_SPMV_STAGE 8
+#endif
+#ifndef RT_SPMV_EAGER_TAIL
+#define RT_SPMV_EAGER_TAIL 1
+#endif
+#ifndef RT_SPMV_NT_STORE
+#define RT_SPMV_NT_STORE 1
+#endif
+
+// a product's per-row output, written once and read by a later kernel
+template <typename T>
+__device__ __forceinline__ void out_store(T* p, T v) {
+#if RT_SPMV_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ T stream_load(const T* p) {
   return __builtin_nontemporal_load(p);
@@ -136,54 +156,92 @@ k_spmv(int64_t n, int per, const int64_t* __restrict__ rp, const int32_t* __rest
   }
 }
 
-// 16-byte chunks of four consecutive entries
+// A lane's four entries of one pass over a row (a pass covers the 4G
+// entries from a 4-aligned base gb).  Every load instruction of a group of G
+// lanes reads one contiguous run: FP32 lanes hold four consecutive entries
+// (16 bytes at 4 lane); FP64 lanes hold two pairs, entries 2 lane and
+// 2G + 2 lane (16 bytes each), so that each 16-byte load is contiguous across
+// the lanes rather than strided by 32 bytes.  Loads of entries at or past
+// the row's end k1 are skipped; dot() adds only entries in [k0, k1).
 typedef float rt_f32x4 __attribute__((vector_size(16)));
 typedef double rt_f64x2 __attribute__((vector_size(16)));
 typedef unsigned short rt_u16x4 __attribute__((vector_size(8)));
+typedef unsigned short rt_u16x2 __attribute__((vector_size(4)));
 
-template <typename T>
-struct Chunk4;
-template <>
-struct Chunk4<float> {
+template <typename T, int G>
+struct LaneSeg;
+template <int G>
+struct LaneSeg<float, G> {
   rt_f32x4 v;
-  __device__ __forceinline__ void load(const float* p) {
-    v = stream_load(reinterpret_cast<const rt_f32x4*>(p));
+  rt_u16x4 c;
+  int k;   // first entry
+  __device__ __forceinline__ void load(const float* vt, const uint16_t* lt, int gb, int lane,
+                                       int k1) {
+    k = gb + 4 * lane;
+    if (k < k1) {
+      v = stream_load(reinterpret_cast<const rt_f32x4*>(vt + k));
+      c = stream_load(reinterpret_cast<const rt_u16x4*>(lt + k));
+    }
   }
-  __device__ __forceinline__ float operator[](int j) const { return v[j]; }
-};
-template <>
-struct Chunk4<double> {
-  rt_f64x2 lo, hi;
-  __device__ __forceinline__ void load(const double* p) {
-    lo = stream_load(reinterpret_cast<const rt_f64x2*>(p));
-    hi = stream_load(reinterpret_cast<const rt_f64x2*>(p + 2));
-  }
-  __device__ __forceinline__ double operator[](int j) const { return j < 2 ? lo[j] : hi[j - 2]; }
-};
-
-// sum over the entries of chunk kb..kb+3 that lie in [k0, k1)
-template <typename T>
-__device__ __forceinline__ T chunk_dot(const Chunk4<T>& v, rt_u16x4 lc, int kb, int k0, int k1,
-                                       const T* xs) {
-  T s = 0;
+  __device__ __forceinline__ float dot(int k0, int k1, const float* xs) const {
+    float s = 0.f;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const bool in = kb + j >= k0 && kb + j < k1;
-    const T w = in ? v[j] : T(0);
-    s += w * xs[in ? (int)lc[j] : 0];
+    for (int j = 0; j < 4; ++j) {
+      const bool in = k + j >= k0 && k + j < k1;
+      s += in ? v[j] * xs[in ? c[j] : 0] : 0.f;   // (the index of an unloaded entry is not read)
+    }
+    return s;
   }
-  return s;
-}
+};
+template <int G>
+struct LaneSeg<double, G> {
+  rt_f64x2 a, b;
+  rt_u16x2 ca, cb;
+  int k;   // first entry of the first pair; the second starts at k + 2G
+  __device__ __forceinline__ void load(const double* vt, const uint16_t* lt, int gb, int lane,
+                                       int k1) {
+    k = gb + 2 * lane;
+    if (k < k1) {
+      a = stream_load(reinterpret_cast<const rt_f64x2*>(vt + k));
+      ca = stream_load(reinterpret_cast<const rt_u16x2*>(lt + k));
+    }
+    if (k + 2 * G < k1) {
+      b = stream_load(reinterpret_cast<const rt_f64x2*>(vt + k + 2 * G));
+      cb = stream_load(reinterpret_cast<const rt_u16x2*>(lt + k + 2 * G));
+    }
+  }
+  __device__ __forceinline__ double dot(int k0, int k1, const double* xs) const {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const bool in = k + j >= k0 && k + j < k1;
+      s += in ? a[j] * xs[in ? ca[j] : 0] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int e = k + 2 * G + j;
+      const bool in = e >= k0 && e < k1;
+      s += in ? b[j] * xs[in ? cb[j] : 0] : 0.0;
+    }
+    return s;
+  }
+};
 
 // Tiled product: one block per tile of kTileRows rows (one row per thread for
 // the row data and the output).  The tile's distinct columns are staged from
 // x into LDS, then groups of G lanes walk the rows, UNR rows per group at a
-// time (their loads all in flight together), each lane loading four consecutive entries (values and 16-bit local
-// columns) as one aligned chunk starting at (k0 & ~3); entries of the chunk
-// outside the row get weight zero.  Row sums go through LDS so that the
+// time (their loads all in flight together), in passes of 4G entries from
+// the 4-aligned base (k0 & ~3), each lane holding four entries of a pass
+// (values and 16-bit local columns, laid out by LaneSeg); entries outside
+// the row add nothing.  Row sums go through LDS so that the
 // output and the dot-product terms are written by one thread per row.
+#ifdef RT_SPMV_WAVES
+#define RT_SPMV_OCC __attribute__((amdgpu_waves_per_eu(RT_SPMV_WAVES)))
+#else
+#define RT_SPMV_OCC
+#endif
 template <typename T, int G, int UNR, int MODE>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) RT_SPMV_OCC
 k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t* __restrict__ lcol,
              const T* __restrict__ val, const T* __restrict__ diag,
              const int64_t* __restrict__ toff, const int32_t* __restrict__ tcols,
@@ -196,6 +254,9 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   __shared__ int srp[kTileRows + 1];      // row bounds relative to the tile's aligned base
   __shared__ int64_t sbase;
   __shared__ T sy[kTileRows];
+  constexpr bool kNeedB = MODE == SP_RESID || MODE == SP_SMOOTH;
+  // the rows' own data, fetched while the columns are staged
+  __shared__ T sdx[(kNeedB ? 3 : 2) + (MODE == SP_SMOOTH ? 1 : 0)][kTileRows];
   __shared__ double red[kBlock / kWave];
   constexpr int NG = kBlock / G;   // row groups per block; UNR rows per group in flight
   static_assert(kTileRows % (NG * UNR) == 0, "tile rows must split evenly over the groups");
@@ -211,8 +272,33 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   if (r0 < n) {
     srp[tid] = (int)(rp[live ? i : n] - base_e);
     if (tid == 0) srp[kTileRows] = (int)(rp[r0 + kTileRows < n ? r0 + kTileRows : n] - base_e);
-    const int64_t u0 = toff[t], u1 = toff[t + 1];
-    for (int64_t k = tid; k < u1 - u0; k += kBlock) xs[k] = x[tcols[u0 + k]];
+    if (live) {
+      sdx[0][tid] = diag[i];
+      sdx[1][tid] = x[i];
+      if (kNeedB) sdx[2][tid] = b[i];
+      if (MODE == SP_SMOOTH) sdx[kNeedB ? 3 : 2][tid] = s[i];
+    }
+    // columns staged kStage per thread at a time: all index loads, then all
+    // gathers, so that a thread keeps kStage gathers in flight
+    constexpr int kStage = RT_SPMV_STAGE;
+    const int64_t u0 = toff[t];
+    const int cnt = (int)(toff[t + 1] - u0);
+    for (int k0 = 0; k0 < cnt; k0 += kStage * kBlock) {
+      int32_t c[kStage];
+#pragma unroll
+      for (int q = 0; q < kStage; ++q) {
+        const int k = k0 + q * kBlock + tid;
+        c[q] = k < cnt ? tcols[u0 + k] : -1;
+      }
+      T xv[kStage];
+#pragma unroll
+      for (int q = 0; q < kStage; ++q) xv[q] = c[q] >= 0 ? x[c[q]] : T(0);
+#pragma unroll
+      for (int q = 0; q < kStage; ++q) {
+        const int k = k0 + q * kBlock + tid;
+        if (k < cnt) xs[k] = xv[q];
+      }
+    }
   } else {
     srp[tid] = 0;
     if (tid == 0) srp[kTileRows] = 0;
@@ -222,38 +308,42 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   const T* vt = val + base_e;
   const uint16_t* lt = lcol + base_e;
   for (int base = 0; base < kTileRows; base += NG * UNR) {
-    int k0[UNR], k1[UNR], kb[UNR];
-    Chunk4<T> v[UNR];
-    rt_u16x4 lc[UNR];
+    int k0[UNR], k1[UNR], gb[UNR];
+    LaneSeg<T, G> v[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int rr = base + u * NG + grp;
       k0[u] = srp[rr];
       k1[u] = srp[rr + 1];
-      kb[u] = (k0[u] & ~3) + 4 * lane;
+      gb[u] = k0[u] & ~3;   // the group's pass base (4-aligned)
     }
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      if (kb[u] < k1[u]) {
-        v[u].load(vt + kb[u]);
-        lc[u] = stream_load(reinterpret_cast<const rt_u16x4*>(lt + kb[u]));
-      }
-    }
-    T sum[UNR];
+    for (int u = 0; u < UNR; ++u) v[u].load(vt, lt, gb[u], lane, k1[u]);
+#if RT_SPMV_EAGER_TAIL
+    // the second pass of every row in flight with the first
+    LaneSeg<T, G> v2[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
-      // (an empty row reads nothing: xs[0] is staged only in a tile with columns)
-      sum[u] = kb[u] < k1[u] && k0[u] < k1[u]
-                   ? chunk_dot<T>(v[u], lc[u], kb[u], k0[u], k1[u], xs)
-                   : T(0);
-    // rows longer than one pass of the group
+      if (gb[u] + 4 * G < k1[u]) v2[u].load(vt, lt, gb[u] + 4 * G, lane, k1[u]);
+    constexpr int kFirstTail = 2;
+#else
+    constexpr int kFirstTail = 1;
+#endif
+    T sum[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) sum[u] = v[u].dot(k0[u], k1[u], xs);
+#if RT_SPMV_EAGER_TAIL
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      if (gb[u] + 4 * G < k1[u]) sum[u] += v2[u].dot(k0[u], k1[u], xs);
+#endif
+    // rows longer than the passes above
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      for (int kk = kb[u] + 4 * G; kk < k1[u]; kk += 4 * G) {
-        Chunk4<T> w;
-        w.load(vt + kk);
-        const rt_u16x4 l2 = stream_load(reinterpret_cast<const rt_u16x4*>(lt + kk));
-        sum[u] += chunk_dot<T>(w, l2, kk, k0[u], k1[u], xs);
+      for (int pb = gb[u] + kFirstTail * 4 * G; pb < k1[u]; pb += 4 * G) {
+        LaneSeg<T, G> w;
+        w.load(vt, lt, pb, lane, k1[u]);
+        sum[u] += w.dot(k0[u], k1[u], xs);
       }
     }
 #pragma unroll
@@ -265,28 +355,26 @@ k_spmv_tiled(int64_t n, int per, const int64_t* __restrict__ rp, const uint16_t*
   __syncthreads();
   double acc = 0.0, cwm = 0.0;
   if (live) {
-    // the row's own data is loaded only now, so that its registers are free
-    // while the entries stream
-    const T di = diag[i];
-    const T xi = x[i];
+    const T di = sdx[0][tid];
+    const T xi = sdx[1][tid];
     T bi = 0, si = 0;
-    if (MODE == SP_RESID || MODE == SP_SMOOTH) bi = b[i];
-    if (MODE == SP_SMOOTH) si = s[i];
+    if (kNeedB) bi = sdx[2][tid];
+    if (MODE == SP_SMOOTH) si = sdx[kNeedB ? 3 : 2][tid];
     const T ax = di * xi + sy[tid];
     if (MODE == SP_PLAIN) {
-      y[i] = ax;
+      out_store(y + i, ax);
     } else if (MODE == SP_DOT) {
-      y[i] = ax;
+      out_store(y + i, ax);
       acc = (double)xi * (double)ax;
     } else if (MODE == SP_RESID) {
       const T r = bi - ax;
-      y[i] = r;
-      if (y32) y32[i] = (float)r;
+      out_store(y + i, r);
+      if (y32) out_store(y32 + i, (float)r);
       acc = (double)r * (double)r;
       if (pmax) cwm = cw_term((double)r, (double)di, (double)xi);
-      if (w32) w32[i] = cw_weight((double)di, (double)xi);
+      if (w32) out_store(w32 + i, cw_weight((double)di, (double)xi));
     } else {
-      y[i] = xi + si * (bi - ax);
+      out_store(y + i, xi + si * (bi - ax));
     }
   }
   if (MODE == SP_DOT || MODE == SP_RESID) {

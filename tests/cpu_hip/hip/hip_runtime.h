@@ -39,6 +39,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define __builtin_nontemporal_load(p) (*(p))
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
 // dynamic LDS: a heap buffer of the launch's byte count (bounds seen by ASan)
 #define RT_DYNAMIC_LDS(name) unsigned char* name = cpuhip::g_dyn_lds
 #define RT_UNIFORM(x) (x)
@@ -361,6 +362,8 @@ inline hipError_t hipEventCreate(hipEvent_t* e) {
   *e = (hipEvent_t) new double(0);
   return hipSuccess;
 }
+#define hipEventDisableSystemFence 0x20000000
+inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
 inline hipError_t hipEventDestroy(hipEvent_t e) {
   delete (double*)e;
   return hipSuccess;
