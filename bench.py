@@ -127,24 +127,26 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_spmv_tiled_marshak3d_16.8M_counters
 
 
 def profiled_traffic(workload: str, n: int, kernel: str):
-    """HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE,
+    """HBM bytes per launch of a product kernel (FETCH_SIZE and WRITE_SIZE,
     each scaled by its reading for a plain copy of known size) from the
-    committed counter summary -- only for the workload it was taken on, the
-    same kernel instance, and while the kernel source is unchanged (hash).
-    Returns (traffic, request-count estimate) or (None, None)."""
+    committed counter summary -- only for the workload it was taken on, a
+    kernel instance it lists, and while the kernel source is unchanged (hash);
+    else None."""
     import hashlib
     if workload != "marshak3d" or n != 256 or not os.path.exists(COUNTERS):
-        return None, None
-    vals = {}
+        return None
+    sha, traffic = None, {}
     for line in open(COUNTERS):
-        k, _, v = line.strip().partition(": ")
-        if v:
-            vals[k] = v
+        line = line.strip()
+        if line.startswith("spmv_source_sha256: "):
+            sha = line.split(": ", 1)[1]
+        elif line.startswith("traffic ") and ": " in line:
+            name, _, v = line[len("traffic "):].rpartition(": ")
+            traffic[name] = float(v)
     src = os.path.join(ROOT, "paper_2001_11606_amd", "csrc", "spmv.h")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("spmv_source_sha256") != sha or vals.get("traffic_kernel") != kernel:
-        return None, None
-    return float(vals["traffic_bytes_per_launch"]), float(vals["traffic_rdreq128_bytes_per_launch"])
+    if sha != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return traffic.get(kernel)
 
 
 def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
@@ -525,6 +527,9 @@ def main():
                     help="ensemble: PCG iterations per replayed HIP graph (0: none)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default SpMV shapes instead of tuning them during warm-up")
+    ap.add_argument("--shapes", default=None,
+                    help="fine-level SpMV shape indices FP64,FP32,RESIDUAL (rt_spmv_shapes order) "
+                         "used instead of tuning, e.g. to profile the tuned run's kernels")
     args = ap.parse_args()
     if args.precond is None:
         args.precond = 1 if args.workload == "config2" else 0
@@ -663,6 +668,10 @@ def run_single(args):
 
     shapes = None
     tune = None
+    if args.shapes:
+        shapes = [[int(v) for v in args.shapes.split(",")]]
+        tune = {"shapes": rt.rt_spmv_shapes(), "chosen": shapes, "pinned": True}
+        args.no_tune = True
 
     def one(solve, profile=False):
         ctx.set_profiling(profile)
@@ -722,12 +731,13 @@ def run_single(args):
                                               args.cw_tol > 0),
                             sum(r.resid_calls for r in reps), sum(r.resid_seconds for r in reps))
     kernels = [k for k in (roof_res, roof32) if k]
+    for k in kernels:
+        k["traffic"] = profiled_traffic(args.workload, args.n, k["kernel"])
     roof = None
     if kernels:
         dom = max(kernels, key=lambda k: k["device_ms"])   # most device time per step
-        traffic, traffic_req = profiled_traffic(args.workload, args.n, dom["kernel"])
         roof = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dom["frac"], "traffic": traffic, "traffic_rdreq128": traffic_req,
+                "frac": dom["frac"], "traffic": dom["traffic"],
                 "kernel": dom["kernel"], "bytes_per_launch": dom["bytes_per_launch"],
                 "avg_launch_us": dom["avg_launch_us"], "launches": dom["launches"],
                 "stream_copy_gbs": round(copy_gbs, 1), "tile_cols": tile_cols,
@@ -815,11 +825,13 @@ def run_single(args):
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp,
         "vcycle": amg_leg, "mixed_vs_fp64_densitystep3d": c3, "phases": phases,
         "solve_particle_updates_per_s": solve_rate,
-        "spmv_tune": None if tune is None else {
-            "shapes_g_e": tune["shapes"], "chosen": tune["chosen"],
-            "level0_us_fp64": [round(t, 1) for t in tune["us"][0][0]],
-            "level0_us_fp32": [round(t, 1) for t in tune["us"][0][1]],
-            "level0_us_fp64_residual": [round(t, 1) for t in tune["us"][0][2]]},
+        "spmv_tune": None if tune is None else (
+            {"shapes_g_e": tune["shapes"], "chosen": tune["chosen"], "pinned": True}
+            if tune.get("pinned") else {
+                "shapes_g_e": tune["shapes"], "chosen": tune["chosen"],
+                "level0_us_fp64": [round(t, 1) for t in tune["us"][0][0]],
+                "level0_us_fp32": [round(t, 1) for t in tune["us"][0][1]],
+                "level0_us_fp64_residual": [round(t, 1) for t in tune["us"][0][2]]}),
     }
     print(json.dumps(out), flush=True)
     ctx.close()
