@@ -39,11 +39,12 @@
 namespace rt {
 namespace {
 
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_ITS, S_STOP, S_CW, S_COUNT };
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RR0, S_BB, S_BAD, S_ITS, S_STOP, S_CW, S_RZ_PREV,
+       S_COUNT };
 // componentwise measure of the update kernel: none, |r_i| w_i / |x_i| with
 // w = 1/diag (the iterate's own measure), or |r_i| w_i with fixed weights
 enum { CW_NONE = 0, CW_X = 1, CW_W = 2 };
-enum { FIN_ALPHA = 0, FIN_BETA, FIN_RZ, FIN_RR, FIN_BB };
+enum { FIN_ALPHA = 0, FIN_BETA, FIN_RZ, FIN_RR, FIN_BB, FIN_RESUME };
 enum { PROF_SPMV64 = 0, PROF_SPMV32 = 1, PROF_RESID64 = 2, PROF_KINDS = 3 };
 
 // One block: combine the partials and update the scalars.  In the loop
@@ -98,6 +99,7 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
     case FIN_BETA:   // a = ||r||^2, b = r.z (new), c = componentwise measure
       s[S_RR] = a;
       s[S_BETA] = b / s[S_RZ];
+      s[S_RZ_PREV] = s[S_RZ];
       s[S_RZ] = b;
       s[S_ITS] += 1.0;
       if (pc) s[S_CW] = c;
@@ -119,6 +121,23 @@ k_finalize(int op, int np, const double* __restrict__ pa, const double* __restri
       break;
     case FIN_BB:
       s[S_BB] = a;
+      break;
+    case FIN_RESUME:   // a = r.z of a residual that replaced the recursive one
+      // The loop that stopped kept its last search direction and, in
+      // S_RZ_PREV, the r.z it was formed with: beta continues from it, but
+      // only while the replacement agrees with the recursion (S_RZ, the
+      // recursive r.z it stopped at, within 25%).  The FP32 operator's own
+      // error can make the two differ by far more than rounding; then
+      // beta = 0, a restart (p = z).
+      s[S_BETA] = s[S_RZ_PREV] > 0.0 && isfinite(s[S_RZ_PREV]) && a >= 0.75 * s[S_RZ] &&
+                          a <= 1.25 * s[S_RZ]
+                      ? a / s[S_RZ_PREV]
+                      : 0.0;
+      s[S_RZ] = a;
+      s[S_BAD] = 0.0;
+      s[S_ITS] = 0.0;
+      s[S_STOP] = 0.0;
+      *stop = 0;
       break;
   }
 }
@@ -172,6 +191,18 @@ k_init_jacobi(int64_t n, const T* __restrict__ dinv, const T* __restrict__ r, T*
     p[i] = z;
     acc += (double)r[i] * (double)z;
   }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// part = r.(D^-1 r): the r.z of a Jacobi-preconditioned residual
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_rz_jacobi(int64_t n, const T* __restrict__ dinv, const T* __restrict__ r,
+            double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  double acc = 0.0;
+  RT_VEC_LOOP(i) acc += (double)r[i] * (double)(dinv[i] * r[i]);
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
@@ -467,7 +498,7 @@ int next_chunk(double rr_prev, int its_prev, double rr, int its, double thr2) {
 template <typename T>
 int pcg_core(rt_ctx* ctx, rt_matrix* A, const Work& W, bool amg, T* x, T* r, double rr0, double thr2,
              int max_it, int* its_out, double* rr_out, const CwTest& cw = CwTest{},
-             double cw0 = 0.0, double* cw_out = nullptr) {
+             double cw0 = 0.0, double* cw_out = nullptr, bool resume = false) {
   using S = Sel<T>;
   hipStream_t st = ctx->stream;
   const Level& L = A->levels[0];
@@ -479,7 +510,25 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, const Work& W, bool amg, T* x, T* r, dou
   *rr_out = rr0;
   if (cw_out) *cw_out = cw0;
   if ((rr0 <= thr2 && !(cw0 > cw.thr)) || max_it <= 0) return RT_OK;
-  if (amg) {
+  if (resume) {
+    // the last loop on this system ended at a residual replacement: its
+    // search direction p carries over, p = z + beta p with the new r.z
+    if (amg) {
+      RT_CHECK(vcycle<T>(ctx, A, r, z));
+      hipLaunchKernelGGL(k_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, W.partB, nullptr);
+    } else {
+      hipLaunchKernelGGL(k_rz_jacobi<T>, dim3(gv), dim3(kBlock), 0, st, n, S::dinv(L), r,
+                         W.partB);
+    }
+    RT_LAUNCH_CHECK();
+    RT_CHECK(finalize(ctx, W, FIN_RESUME, gv, W.partB, nullptr));   // clears the stop flag
+    if (amg)
+      hipLaunchKernelGGL((k_pupdate<T, false>), dim3(gv), dim3(kBlock), 0, st, n, W.scal, r,
+                         nullptr, z, p, W.stop);
+    else
+      hipLaunchKernelGGL((k_pupdate<T, true>), dim3(gv), dim3(kBlock), 0, st, n, W.scal, r,
+                         S::dinv(L), nullptr, p, W.stop);
+  } else if (amg) {
     RT_CHECK(vcycle<T>(ctx, A, r, z));
     hipLaunchKernelGGL(k_copy_dot<T>, dim3(gv), dim3(kBlock), 0, st, n, r, z, p, W.partB);
   } else {
@@ -487,7 +536,7 @@ int pcg_core(rt_ctx* ctx, rt_matrix* A, const Work& W, bool amg, T* x, T* r, dou
                        W.partB);
   }
   RT_LAUNCH_CHECK();
-  RT_CHECK(finalize(ctx, W, FIN_RZ, gv, W.partB, nullptr));   // clears the stop flag
+  if (!resume) RT_CHECK(finalize(ctx, W, FIN_RZ, gv, W.partB, nullptr));   // clears the stop flag
   const size_t spans0 = ctx->prof_spans.size();
   double rr = rr0, rr_prev = rr0;
   int its = 0, its_prev = 0, queued = 0, chunk = 1;
@@ -669,6 +718,11 @@ int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double
     stt->init_rel_residual = std::sqrt(rr / bb);
     *rec_steps = 0;
     int total = 0, refine = 0;
+    // After the first inner solve each one continues the last: the FP64
+    // residual replaces CG's recursive one (reliable update) and the search
+    // direction carries over, so the refinements do not restart the Krylov
+    // space.
+    bool resume = false;
     while ((rr > thr2 || cw > cwthr) && total < o->max_iter && refine < o->max_refine) {
       // reduce by inner_tol, or just enough (with margin) to reach tol; the
       // same for the componentwise measure when it is tested
@@ -680,8 +734,9 @@ int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double
       int its = 0;
       double rr_in = 0.0;
       RT_CHECK(pcg_core<float>(ctx, A, W, amg, W.d32, W.r32, rr, red * red * rr,
-                               o->max_iter - total, &its, &rr_in, t, cw));
+                               o->max_iter - total, &its, &rr_in, t, cw, nullptr, resume));
       total += its;
+      resume = its > 0;
       hipLaunchKernelGGL(k_add_f32, dim3(grid_for(n)), dim3(kBlock), 0, st, n, W.d32, x);
       RT_LAUNCH_CHECK();
       RT_CHECK(residual64(ctx, A, W, b, x, W.r32, w32, &rr, &cw));
