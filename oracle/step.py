@@ -51,6 +51,32 @@ def material_update(prob, fz, E_new, e_start, tol):
                           prob.dt, prob.c, prob.a, e_start, tol=tol)
 
 
+def be_residual(prob, fz, ptr, idx, e: np.ndarray, E: np.ndarray):
+    """The backward-Euler system G = [m, r] of Sec. 2.2 (the starting point of
+    the nonlinear elimination) at the interior state (e, E), the opacities
+    and diffusion coefficients frozen at the start of the step as in the rest
+    of the step (ghost radiation energies fixed at prob.E):
+
+        m_i = rho_i/dt (e_i - e_i^{n-1}) + c sigma_a,i (B_i - E_i) - Q_e,i
+        r_i = (E_i - E_i^{n-1})/dt + sum_j V_j (D_i + D_j) F_ij (E_i - E_j)
+              + c sigma_a,i (E_i - B_i) - Q_E,i,
+
+    B = a (e/c_v)^4, the diffusion term the Brookshaw pair sum of Sec. 2.3
+    over every neighbour (not the assembled matrix).  Returns (m, r)."""
+    nin = prob.n_interior
+    sl = slice(0, nin)
+    B = prob.a * (e / prob.cv[sl]) ** 4
+    ca = prob.c * fz.sigma_a[sl]
+    m = prob.rho[sl] / prob.dt * (e - prob.e[sl]) + ca * (B - E) - prob.Q_e[sl]
+    Efull = prob.E.copy()
+    Efull[sl] = E
+    I, J, _, F = operator.pair_geometry(prob, ptr, idx)
+    a = fz.V[J] * (fz.D[I] + fz.D[J]) * F
+    lap = np.bincount(I, weights=a * (Efull[I] - Efull[J]), minlength=prob.n_total)[sl]
+    r = (E - prob.E[sl]) / prob.dt + lap + ca * (E - B) - prob.Q_E[sl]
+    return m, r
+
+
 def rel_change(new, old) -> float:
     return float(np.max(np.abs(new - old) / np.abs(new))) if new.size else 0.0
 

@@ -270,3 +270,71 @@ def test_infinite_medium_vs_paper(case):
     assert 0.5 < l1_e / g["l1_material"] < 2.5 and 0.5 < l1_r / g["l1_radiation"] < 2.5
     assert abs(l1_e / l1_r - g["l1_material"] / g["l1_radiation"]) < 0.1
     assert abs((es[-1] + Es[-1]) - (g["e0"] + g["E0"])) <= 1e-13
+
+def _be_parts(prob):
+    ptr, idx = neighbors.build(prob.pos, prob.h, 2.0, prob.period)
+    fz = operator.frozen(prob, ptr, idx)
+    return ptr, idx, fz
+
+
+@pytest.mark.parametrize("e0,E0,dt", [(1.0, 1e-16, 0.1), (1e-4, 1.0, 1e-3)])
+def test_be_residual_zero_at_the_scalar_root(e0, E0, dt):
+    """G of Sec. 2.2 vanishes at the exact backward-Euler step of the infinite
+    medium (40-digit root of the scalar system; no diffusion in a uniform
+    state) and has the signs of its terms off it."""
+    prob = _infinite_problem(e0, E0, dt)
+    ptr, idx, fz = _be_parts(prob)
+    e_ref, E_ref = _scalar_be_step(e0, E0, dt, 1.0)
+    nin = prob.n_interior
+    e = np.full(nin, float(e_ref))
+    E = np.full(nin, float(E_ref))
+    m, r = step.be_residual(prob, fz, ptr, idx, e, E)
+    scale_m = max(e0, float(e_ref)) / dt
+    scale_r = max(E0, float(E_ref)) / dt + float(e_ref) ** 4
+    assert np.max(np.abs(m)) <= 1e-13 * scale_m and np.max(np.abs(r)) <= 1e-13 * scale_r
+    # off the root, the signs of the derivatives: dm/de >= rho/dt, dr/dE >=
+    # 1/dt, dm/dE = -c sigma_a
+    m2, _ = step.be_residual(prob, fz, ptr, idx, e * (1 + 1e-6), E)
+    m3, r3 = step.be_residual(prob, fz, ptr, idx, e, E * (1 + 1e-6))
+    assert np.all(m2 > m) and np.all(r3 > r) and np.all(m3 < m)
+
+
+@pytest.mark.parametrize("name", ["mms2d", "densitystep3d", "marshak3d"])
+def test_be_residual_matches_the_assembled_system(name):
+    """V_i r_i(e, E) = (A E - b(e, E))_i: the pair-sum residual against the
+    assembled matrix and Algorithm 1's right-hand side evaluated at the same
+    state (two separate paths of the oracle), at a perturbed state."""
+    prob = {"mms2d": lambda: synth.config1(n=16), "densitystep3d": lambda: synth.config3(n=8),
+            "marshak3d": lambda: synth.config4(n=10)}[name]()
+    ptr, idx, fz = _be_parts(prob)
+    sysm = operator.assemble(prob, ptr, idx, fz)
+    nin = prob.n_interior
+    rng = np.random.default_rng(5)
+    e = prob.e[:nin] * (1 + 0.01 * rng.standard_normal(nin))
+    E = prob.E[:nin] * (1 + 0.01 * rng.standard_normal(nin))
+    m, r = step.be_residual(prob, fz, ptr, idx, e, E)
+    b = operator.rhs(prob, fz, sysm, e, E)
+    ref = sysm.A @ E - b
+    scale = np.abs(sysm.A).dot(np.abs(E)) + np.abs(b)
+    assert np.max(np.abs(fz.V[:nin] * r - ref) / scale) <= 1e-13
+    B = prob.a * (e / prob.cv[:nin]) ** 4
+    m_ref = (prob.rho[:nin] / prob.dt * (e - prob.e[:nin])
+             + prob.c * fz.sigma_a[:nin] * (B - E) - prob.Q_e[:nin])
+    assert np.array_equal(m, m_ref)
+
+
+def test_be_residual_small_after_algorithm_1():
+    """Algorithm 1 iterated to a tight outer tolerance reaches the root of G:
+    both residuals far below their terms, and far below those of the state
+    after one outer iteration."""
+    prob = synth.config1(n=16)
+    ptr, idx, fz = _be_parts(prob)
+    nin = prob.n_interior
+    one = step.time_step(prob.copy(), ptr, idx, fixed_outer=1, solve_tol=1e-15)
+    full = step.time_step(prob.copy(), ptr, idx, eps_e=1e-14, eps_E=1e-14, solve_tol=1e-15)
+    m1, r1 = step.be_residual(prob, fz, ptr, idx, one.e, one.E)
+    mf, rf = step.be_residual(prob, fz, ptr, idx, full.e, full.E)
+    scale_r = np.max(np.abs(prob.E[:nin])) / prob.dt
+    assert np.max(np.abs(rf)) <= 1e-9 * scale_r
+    assert np.max(np.abs(rf)) <= 1e-3 * np.max(np.abs(r1))
+    assert np.max(np.abs(mf)) <= 1e-9 * np.max(np.abs(prob.rho[:nin] * full.e / prob.dt))
