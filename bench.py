@@ -708,6 +708,12 @@ def run_single(args):
     value = nin * args.outer * args.steps / elapsed
     log(f"[bench] {ms_step:.1f} ms/step, krylov {reps[-1].krylov}, refinements "
         f"{reps[-1].refinements}, status {reps[-1].status}")
+    # the backward-Euler residual G (Sec. 2.2) of the last timed step's final
+    # state (after the timed region: one more FP64 product)
+    g_last = ctx.newton_residual(A, e, E, 0)
+    newton_residual = {"rad_rel": g_last.rad_rel, "rad_norm": g_last.rad_norm,
+                       "mat_rel": g_last.mat_rel,
+                       "starting_rad_rel": [round(v, 16) for v in reps[-1].init_rel_residual]}
     release(ctx, nb, A)
 
     # per-kernel rooflines of the products, from the HIP events of the timed steps
@@ -825,6 +831,7 @@ def run_single(args):
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": cmp,
         "vcycle": amg_leg, "mixed_vs_fp64_densitystep3d": c3, "phases": phases,
         "solve_particle_updates_per_s": solve_rate,
+        "newton_residual": newton_residual,
         "spmv_tune": None if tune is None else (
             {"shapes_g_e": tune["shapes"], "chosen": tune["chosen"], "pinned": True}
             if tune.get("pinned") else {

@@ -417,6 +417,28 @@ typedef struct {
 int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, int ell,
                    const rt_newton_opts* opts, rt_newton_stats* stats);
 
+/* ---- residual of the backward-Euler system (Sec. 2.2) ----------------------
+ * G = [m, r] at the state (e, E) (n_interior doubles each, device; user
+ * order, or the neighbour object's sorted order with state_order 1), with the
+ * matrix's frozen data of the step (rt_assemble):
+ *   m_i = rho_i/dt (e_i - e_i^{n-1}) + c sigma_a,i (B_i - E_i) - Q_e,i,
+ *   r_i = (E_i - E_i^{n-1})/dt - <d(c lambda/sigma_t dE)>_i + c sigma_a,i (E_i - B_i) - Q_E,i,
+ * B = a (e/c_v)^4.  Evaluated in FP64 as V r = A E - b(e, E), b the
+ * right-hand side of the outer iteration taken at the state itself.  The
+ * starting residual of every rt_newton_step solve (rt_solve_stats.
+ * init_rel_residual) is rad_rel of the state that call starts from; this call
+ * gives it for any state, e.g. the step's last one, at the cost of one FP64
+ * product.  It drops the residual rt_newton_step carries over.
+ * Errors: RT_E_ARG (NULL argument, state_order not 0 or 1).                */
+typedef struct {
+  double rad_norm;   /* ||V r||_2 = ||A E - b(e, E)||_2                        */
+  double rad_rel;    /* rad_norm / ||b(e, E)||_2                              */
+  double mat_rel;    /* max_i |m_i| / (rho_i |e_i| / dt)                      */
+} rt_be_residual;
+
+int rt_newton_residual(rt_ctx* ctx, rt_matrix* A, const double* e, const double* E,
+                       int state_order, rt_be_residual* out);
+
 /* Interior per-particle vectors between user order and the library's sorted
  * order (n = n_interior doubles, device; in and out must not overlap).      */
 int rt_to_sorted(rt_ctx* ctx, const rt_neighbors* nb, const double* user, double* sorted);

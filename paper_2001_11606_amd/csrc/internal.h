@@ -372,6 +372,10 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
                  const rt_solve_opts* o, rt_solve_stats* st, const double* b_prev = nullptr,
                  const int32_t* mismatch = nullptr);
 int amg_setup(rt_ctx* ctx, rt_matrix* A);
+// ||b - A x||^2 (an FP64 product, into the matrix's r64) and ||b||^2; the
+// residual the Newton step carries is dropped
+int residual_norms(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, double* rr,
+                   double* bb);
 int check_solve_opts(const rt_solve_opts* o);
 int collect_profile(rt_ctx* ctx, rt_solve_stats* s);
 int gather_sorted(rt_ctx* ctx, const rt_neighbors* nb, int64_t n, const double* user,

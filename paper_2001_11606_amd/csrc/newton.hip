@@ -40,6 +40,41 @@ __global__ void k_rhs(int64_t n, double dt, double c, double a, const double* __
   if (x_last && El != x_last[i]) atomicAdd(mismatch, 1);
 }
 
+// Block maxima of the material residual of the backward-Euler system,
+// |m_i| / (rho_i |e_i| / dt) with m_i = rho_i/dt (e_i - e_i^{n-1})
+// + c sigma_a,i (a T_i^4 - E_i) - Q_e,i (Sec. 2.2); a row with e_i = 0
+// counts |m_i| dt / rho_i.
+__global__ void __launch_bounds__(kBlock)
+k_mat_resid(int64_t n, double dt, double c, double a, const double* __restrict__ e,
+            const double* __restrict__ E, const double* __restrict__ e_prev,
+            const double* __restrict__ rho, const double* __restrict__ cv,
+            const double* __restrict__ sa, const double* __restrict__ Qe,
+            double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double T = e[i] / cv[i];
+    const double T2 = T * T;
+    const double m = rho[i] / dt * (e[i] - e_prev[i]) + c * sa[i] * (a * (T2 * T2) - E[i]) - Qe[i];
+    const double scale = rho[i] / dt * (e[i] != 0.0 ? fabs(e[i]) : 1.0);
+    v = fabs(m) / scale;
+    if (!(v == v)) v = INFINITY;   // a NaN residual counts as unbounded
+  }
+  v = block_max(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// one block: out[0] = the largest of np values
+__global__ void __launch_bounds__(kBlock)
+k_max_of(int np, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[kBlock / kWave];
+  double v = 0.0;
+  for (int k = threadIdx.x; k < np; k += kBlock) v = fmax(v, part[k]);
+  v = block_max(v, red);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
 enum { R_DE = 0, R_DEE, R_ITS, R_BAD, R_NONPHYS, R_EN, R_EN0, R_WIDTH };
 
 struct MatArgs {
@@ -307,6 +342,55 @@ extern "C" int rt_newton_step(rt_ctx* ctx, rt_matrix* A, double* e, double* E, i
   else if (status == RT_NOT_CONVERGED && rt_last_error()[0] == 0)
     set_error("rt_newton_step: a material solve did not converge");
   return status;
+}
+
+extern "C" int rt_newton_residual(rt_ctx* ctx, rt_matrix* A, const double* e, const double* E,
+                                  int state_order, rt_be_residual* out) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !A || !out || (A->n > 0 && (!e || !E))) {
+    set_error("rt_newton_residual: NULL argument");
+    return RT_E_ARG;
+  }
+  if (state_order != 0 && state_order != 1) {
+    set_error("rt_newton_residual: state_order must be 0 or 1");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt::StreamScope release_scope(ctx->stream);
+  *out = rt_be_residual{};
+  const int64_t n = A->n;
+  if (n == 0) return RT_OK;
+  hipStream_t st = ctx->stream;
+  for (auto* b : {&A->ecur, &A->Ecur, &A->bs}) RT_CHECK(b->reserve(n));
+  const double* es = e;
+  const double* Es = E;
+  if (state_order == 0) {
+    RT_CHECK(gather_sorted(ctx, A->nb, n, e, A->ecur.p));
+    RT_CHECK(gather_sorted(ctx, A->nb, n, E, A->Ecur.p));
+    es = A->ecur.p;
+    Es = A->Ecur.p;
+  }
+  // b(e, E): Algorithm 1's right-hand side at the state itself, so that
+  // A E - b = V r (the f terms cancel)
+  hipLaunchKernelGGL(k_rhs, dim3(grid_for(n)), dim3(kBlock), 0, st, n, A->dt, A->c, A->a, A->V.p,
+                     A->sa.p, A->f.p, A->cv.p, A->E_prev.p, A->QE.p, A->g.p, es, Es, A->bs.p,
+                     nullptr, nullptr);
+  RT_LAUNCH_CHECK();
+  double rr = 0.0, bb = 0.0;
+  RT_CHECK(residual_norms(ctx, A, A->bs.p, Es, &rr, &bb));
+  const int nbk = grid_for(n);
+  DevBuf<double> part;
+  RT_CHECK(part.reserve(nbk + 1));
+  hipLaunchKernelGGL(k_mat_resid, dim3(nbk), dim3(kBlock), 0, st, n, A->dt, A->c, A->a, es, Es,
+                     A->e_prev.p, A->rho.p, A->cv.p, A->sa.p, A->Qe.p, part.p);
+  hipLaunchKernelGGL(k_max_of, dim3(1), dim3(kBlock), 0, st, nbk, part.p, part.p + nbk);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(ctx->sync_read(part.p + nbk, sizeof(double)));
+  out->rad_norm = std::sqrt(rr);
+  out->rad_rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+  out->mat_rel = ctx->host[0];
+  return RT_OK;
 }
 
 extern "C" int rt_to_sorted(rt_ctx* ctx, const rt_neighbors* nb, const double* user,

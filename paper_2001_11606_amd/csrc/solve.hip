@@ -760,6 +760,22 @@ int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double
 
 }  // namespace
 
+int residual_norms(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, double* rr,
+                   double* bb) {
+  A->resid_ok = false;
+  A->r64_valid = false;
+  RT_CHECK(ensure_work(A, false));
+  const Work W = work_of(A);
+  double cw = 0.0;
+  RT_CHECK(residual64(ctx, A, W, b, x, nullptr, nullptr, rr, &cw));
+  const int gv = vec_blocks(A->n);
+  hipLaunchKernelGGL(k_dot<double>, dim3(gv), dim3(kBlock), 0, ctx->stream, A->n, b, b, W.partB,
+                     nullptr);
+  RT_LAUNCH_CHECK();
+  RT_CHECK(finalize(ctx, W, FIN_BB, gv, W.partB, nullptr));
+  return read_scalar(ctx, W, S_BB, bb);
+}
+
 int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x, const rt_solve_opts* o,
                  rt_solve_stats* stt, const double* b_prev, const int32_t* mismatch) {
   const bool mixed = o->precision == RT_PREC_MIXED;

@@ -67,6 +67,7 @@ class StepReport:
     cw_residual: list = field(default_factory=list)
     init_rel_residual: list = field(default_factory=list)
     replacements: list = field(default_factory=list)
+    final_residual: Optional[tuple] = None   # (rad_rel, mat_rel) of the step's last state
 
 
 def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
@@ -74,7 +75,7 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
               eps_e: float = 1e-8, eps_E: float = 1e-8, material_tol: float = 1e-14,
               max_outer: int = 50, fixed_outer: Optional[int] = None,
               shapes: Optional[list] = None, sorted_state: bool = True,
-              recompute_residual: bool = False):
+              recompute_residual: bool = False, final_residual: bool = False):
     """One backward-Euler step.  Returns (e, E, A, report) with e, E the new
     interior energies (device tensors, user order).  shapes: per-level
     (FP64, FP32[, FP64 residual]) SpMV shape indices (-1: default), e.g. the
@@ -83,7 +84,10 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
     sorted_state: keep e, E in the library's sorted order during the outer
     iterations (one conversion each way per step instead of per iteration).
     recompute_residual: start every solve from b - A x formed by a product
-    instead of the residual carried over from the last outer iteration."""
+    instead of the residual carried over from the last outer iteration.
+    final_residual: also evaluate the backward-Euler residual G at the step's
+    last state (one more FP64 product); the starting states' relative
+    radiation residuals are the solves' init_rel_residual."""
     A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
                      dp.limiter_k, amg=amg, A=A)
     if shapes:
@@ -129,6 +133,9 @@ def time_step(ctx: rt.Context, dp: DeviceProblem, nb: rt.Neighbors, A: int = 0,
         rep.replacements.append(st.solve.replacements)
         if fixed_outer is None and st.delta_e < eps_e and st.delta_E < eps_E:
             break
+    if final_residual:
+        g = ctx.newton_residual(A, e, E, 1 if sorted_state else 0)
+        rep.final_residual = (g.rad_rel, g.mat_rel)
     if sorted_state:
         rt.rt_to_user(ctx.handle, nb.handle, e.data_ptr(), e_user.data_ptr())
         rt.rt_to_user(ctx.handle, nb.handle, E.data_ptr(), E_user.data_ptr())

@@ -88,6 +88,10 @@ class rt_newton_opts(ctypes.Structure):
                 ("state_order", c_int), ("recompute_residual", c_int)]
 
 
+class rt_be_residual(ctypes.Structure):
+    _fields_ = [("rad_norm", c_dbl), ("rad_rel", c_dbl), ("mat_rel", c_dbl)]
+
+
 class rt_newton_stats(ctypes.Structure):
     _fields_ = [("delta_e", c_dbl), ("delta_E", c_dbl), ("energy", c_dbl), ("energy_prev", c_dbl),
                 ("material_iterations", c_int), ("nonphysical", c_i64), ("solve", rt_solve_stats),
@@ -154,6 +158,8 @@ _SIGS = {
                                ctypes.POINTER(rt_solve_stats)]),
     "rt_newton_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, ctypes.POINTER(rt_newton_opts),
                                ctypes.POINTER(rt_newton_stats)]),
+    "rt_newton_residual": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int,
+                                   ctypes.POINTER(rt_be_residual)]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -395,6 +401,13 @@ def gmres_opts(precond=PRECOND_JACOBI, tol=1e-10, max_iter=1000, restart=30) -> 
     return rt_gmres_opts(precond, tol, max_iter, restart)
 
 
+def rt_newton_residual(ctx: int, A: int, e: int, E: int, state_order: int = 0) -> rt_be_residual:
+    out = rt_be_residual()
+    _check("rt_newton_residual", load().rt_newton_residual(ctx, A, e, E, state_order,
+                                                           ctypes.byref(out)))
+    return out
+
+
 def rt_newton_step(ctx: int, A: int, e: int, E: int, ell: int, opts: rt_newton_opts) -> tuple:
     st = rt_newton_stats()
     s = _check("rt_newton_step", load().rt_newton_step(ctx, A, e, E, ell, ctypes.byref(opts),
@@ -559,6 +572,11 @@ class Context:
         torch = self.torch
         return rt_solve_gmres(self.handle, A, _ptr(b, torch.float64), _ptr(x, torch.float64),
                               opts)
+
+    def newton_residual(self, A: int, e, E, state_order: int = 0) -> rt_be_residual:
+        torch = self.torch
+        return rt_newton_residual(self.handle, A, _ptr(e, torch.float64), _ptr(E, torch.float64),
+                                  state_order)
 
     def newton_step(self, A: int, e, E, ell: int, opts: rt_newton_opts):
         torch = self.torch

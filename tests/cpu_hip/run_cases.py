@@ -15,7 +15,7 @@ sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.dirname(HERE))
 
 import synth  # noqa: E402
-from oracle import linsolve, neighbors, step as ostep  # noqa: E402
+from oracle import linsolve, neighbors, operator, step as ostep  # noqa: E402
 from gpu_common import (_cold_patch, _diffusive, _limited, _wendland, oracle_system,  # noqa: E402
                         rowwise_rel_err)
 from paper_2001_11606_amd import rt  # noqa: E402
@@ -193,6 +193,15 @@ def check_case(ctx, name, prob):
     rt.rt_to_user(ctx, c.nb, p(Es), p(Eu))
     assert np.max(np.abs(eu - e_) / e_) <= 1e-13 and np.max(np.abs(Eu - E_) / E_) <= 1e-13, \
         f"{name}: sorted-order state"
+    # the backward-Euler residual G at the state reached, against the oracle's
+    gres = rt.rt_newton_residual(ctx, c.A, p(e_), p(E_), 0)
+    m_o, r_o = ostep.be_residual(prob, fz, ptr, idx, e_, E_)
+    b_o = operator.rhs(prob, fz, sysm, e_, E_)
+    rad = float(np.linalg.norm(fz.V[:nin] * r_o))
+    mat = float(np.max(np.abs(m_o) / (prob.rho[:nin] / prob.dt * np.abs(e_))))
+    bn = float(np.linalg.norm(b_o))
+    assert abs(gres.rad_norm - rad) <= 1e-12 * bn and abs(gres.rad_rel - rad / bn) <= 1e-12 \
+        and abs(gres.mat_rel - mat) <= 1e-12, f"{name}: residual {gres.rad_norm} {rad} {gres.mat_rel} {mat}"
     say(f"ok {name}: n={prob.n_total} pairs={info.nnz} levels={info.levels} "
         f"err(values)={err:.1e} newton=({ee:.1e},{eE:.1e})")
     c.free()
