@@ -642,6 +642,39 @@ def densitystep_leg(ctx, args, steps=3):
     out["ratio_fp64_over_mixed"] = round(res["fp64"] / res["mixed"], 3)
     out["vcycle"] = precond_leg(ctx, dp, args, (eR, ER))
     del dp
+    out["depth_tune"] = depth_leg(ctx, args)
+    return out
+
+
+def depth_leg(ctx, args, reps=3):
+    """The V-cycle depth tuner on the density-step matrix at 128^3: FP64 CG
+    to the bench's tolerances on b = 1 from zero at every depth (1 = Jacobi),
+    at the configuration's dt and at dt = 0.025 (diffusion number about 9,
+    where the hierarchy pays); mean solve times, iterations and the depth
+    kept."""
+    import torch
+    from paper_2001_11606_amd import driver, rt
+    out = {}
+    for dt in (None, 0.025):
+        prob = make_problem("densitystep3d", 128)
+        if dt:
+            prob.dt = dt
+        dp = driver.upload(prob, ctx.device)
+        nb = ctx.build_neighbors(dp.pos, dp.h, prob.n_interior, prob.kernel)
+        A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=rt.amg_opts(max_levels=8))
+        nin = prob.n_interior
+        b = torch.ones(nin, dtype=torch.float64, device=ctx.device)
+        x0 = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
+        rep = ctx.tune_depth(A, b, x0, bench_solve_opts(rt.RT_PREC_FP64, 1, args.tol, args.cw_tol,
+                                                        args.inner_tol), reps=reps)
+        out[f"dt_{prob.dt:g}"] = {
+            "levels": rep.depths,
+            "solve_ms": [round(1e3 * rep.seconds[d], 3) for d in range(rep.depths)],
+            "iterations": list(rep.iterations[:rep.depths]),
+            "chosen_depth": rep.chosen}
+        ctx.free(A, nb)
+        del dp
     return out
 
 

@@ -299,6 +299,7 @@ int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep);
  * RT_PRODUCT_RESIDUAL the FP64 residual product of the refinement loop      */
 int rt_matrix_set_spmv_shape(rt_matrix* A, int level, int precision, int shape);
 
+
 /* ---- linear solve (Sec. 3.2, the D^-1 operator) ---------------------------
  * Solves A x = b (the V-scaled system above) by preconditioned CG, stopping
  * when ||b - A x||_2 <= tol ||b||_2 evaluated in FP64 and, if cw_tol > 0,
@@ -351,6 +352,30 @@ typedef struct {
 
 int rt_solve(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
              const rt_solve_opts* opts, rt_solve_stats* stats);
+
+/* V-cycle depth.  rt_matrix_tune_depth solves A x = b from x0 (n_interior
+ * doubles each, device, user order; x0 is not changed) with opts (precond
+ * must be 1) using the first d levels of the hierarchy, for every d from 1
+ * (Jacobi) to the number of levels, reps times each, and keeps the depth with
+ * the least mean solve time (rt_solve_stats.seconds) among those that
+ * converged; the deepest level used is then smoothed instead of being solved
+ * directly unless it is the hierarchy's last.  *rep (may be NULL) receives
+ * every depth's mean time, iterations and status and the choice.  The depth
+ * holds for later solves and V-cycles of A, also after re-assembly (clamped
+ * to the hierarchy's levels).  rt_matrix_set_cycle_depth sets it (0 = all
+ * levels).  Errors: RT_E_ARG (NULL arguments, reps < 1, precond not 1, a
+ * negative depth); a solve's own errors.                                    */
+typedef struct {
+  int depths;                      /* depths timed: 1 .. depths              */
+  double seconds[RT_MAX_LEVELS];   /* [d - 1]: mean wall time of a solve      */
+  int iterations[RT_MAX_LEVELS];   /* Krylov iterations of the last solve     */
+  int status[RT_MAX_LEVELS];       /* RT_OK or RT_NOT_CONVERGED               */
+  int chosen;                      /* the depth kept                          */
+} rt_depth_report;
+
+int rt_matrix_tune_depth(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x0,
+                         const rt_solve_opts* opts, int reps, rt_depth_report* rep);
+int rt_matrix_set_cycle_depth(rt_matrix* A, int depth);
 
 /* rt_solve_noalloc: rt_solve for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

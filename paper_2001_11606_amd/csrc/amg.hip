@@ -1250,8 +1250,9 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   hipStream_t st = ctx->stream;
   Level& L = A->levels[l];
   const int64_t n = L.n;
-  if (l + 1 == A->levels.size()) {
-    if (A->coarse_direct) {
+  const size_t nl = cycle_depth(A);
+  if (l + 1 == nl) {
+    if (A->coarse_direct && nl == A->levels.size()) {
       hipLaunchKernelGGL(k_coarse_solve<T>, dim3(grid_for(n * kWave)), dim3(kBlock), 0, st, n,
                          A->coarse_inv.p, b, out, stop);
       RT_LAUNCH_CHECK();
@@ -1297,11 +1298,11 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
     hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
                        L.amem.p, r, B::b(C), stop);
   RT_LAUNCH_CHECK();
-  if (A->amg.cycle == 3 && l + 2 < A->levels.size())
+  if (A->amg.cycle == 3 && l + 2 < nl)
     RT_CHECK(kcycle_correct<T>(ctx, A, l + 1, stop));
   else
     RT_CHECK(vcycle_level<T>(ctx, A, l + 1, B::b(C), B::x(C), stop));
-  if (A->amg.cycle == 2 && l + 2 < A->levels.size()) {
+  if (A->amg.cycle == 2 && l + 2 < nl) {
     // W-cycle: a second coarse correction from the residual of the first
     RT_CHECK((launch_spmv_level<T, SP_RESID>(st, C, B::val(C), B::diag(C), B::x(C), B::b(C),
                                              nullptr, B::wr(C), nullptr, nullptr, nullptr,

@@ -207,7 +207,7 @@ void givens(double a, double b, double* c, double* s) {
 int gmres_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
                  const rt_gmres_opts* o, rt_solve_stats* stt) {
   hipStream_t st = ctx->stream;
-  Gmres G{ctx, A, A->n, o->restart, o->precond == 1 && A->levels.size() > 1};
+  Gmres G{ctx, A, A->n, o->restart, o->precond == 1 && cycle_depth(A) > 1};
   RT_CHECK(A->partA.reserve(max_partials(A->n)));
   RT_CHECK(G.init());
   const int64_t n = A->n;

@@ -332,6 +332,7 @@ struct rt_matrix {
   // hierarchy: levels[0] is the fine operator
   std::vector<rt::Level> levels;
   bool coarse_direct = false;        // coarsest level solved with a dense inverse
+  int cycle_levels = 0;              // levels the V-cycle uses (0: all; set by the depth tuner)
   rt::DevBuf<double> coarse_inv;     // dense inverse of the coarsest operator (FP64)
   // Krylov work vectors (fine size)
   rt::DevBuf<double> r64, p64, q64, z64, xs, bs, ecur, Ecur, enew;
@@ -372,6 +373,11 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
                  const rt_solve_opts* o, rt_solve_stats* st, const double* b_prev = nullptr,
                  const int32_t* mismatch = nullptr);
 int amg_setup(rt_ctx* ctx, rt_matrix* A);
+// levels the V-cycle uses: all, or the tuned depth
+inline size_t cycle_depth(const rt_matrix* A) {
+  const size_t nl = A->levels.size();
+  return A->cycle_levels > 0 && (size_t)A->cycle_levels < nl ? (size_t)A->cycle_levels : nl;
+}
 // ||b - A x||^2 (an FP64 product, into the matrix's r64) and ||b||^2; the
 // residual the Newton step carries is dropped
 int residual_norms(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x, double* rr,

@@ -646,7 +646,7 @@ int solve_work(rt_ctx* ctx, rt_matrix* A, const Work& W, const double* b, double
   const int64_t n = A->n;
   const bool mixed = o->precision == RT_PREC_MIXED;
   *resid_valid = false;
-  const bool amg = o->precond == 1 && A->levels.size() > 1;
+  const bool amg = o->precond == 1 && cycle_depth(A) > 1;
   *stt = rt_solve_stats{};
   if (n == 0) return RT_OK;
   const int gv = vec_blocks(n);

@@ -123,4 +123,73 @@ int rt_matrix_tune(rt_ctx* ctx, rt_matrix* A, int reps, rt_tune_report* rep) {
   return RT_OK;
 }
 
+int rt_matrix_set_cycle_depth(rt_matrix* A, int depth) {
+  using namespace rt;
+  clear_error();
+  if (!A || depth < 0) {
+    set_error("rt_matrix_set_cycle_depth: NULL matrix or negative depth");
+    return RT_E_ARG;
+  }
+  A->cycle_levels = depth;
+  return RT_OK;
+}
+
+int rt_matrix_tune_depth(rt_ctx* ctx, rt_matrix* A, const double* b, const double* x0,
+                         const rt_solve_opts* opts, int reps, rt_depth_report* rep) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !A || !opts || reps < 1 || (A->n > 0 && (!b || !x0))) {
+    set_error("rt_matrix_tune_depth: NULL argument or reps < 1");
+    return RT_E_ARG;
+  }
+  if (opts->precond != 1) {
+    set_error("rt_matrix_tune_depth: the solve options must use the V-cycle (precond 1)");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt_depth_report local{};
+  rt_depth_report* r = rep ? rep : &local;
+  *r = rt_depth_report{};
+  const int nl = std::min<int>((int)A->levels.size(), RT_MAX_LEVELS);
+  r->depths = nl;
+  r->chosen = nl;
+  if (A->n == 0 || nl == 0) return RT_OK;
+  DevBuf<double> x;
+  {
+    rt::StreamScope scope(ctx->stream);
+    RT_CHECK(x.reserve(A->n));
+  }
+  const int keep = A->cycle_levels;
+  double best = 0.0;
+  int arg = -1;
+  for (int d = 1; d <= nl; ++d) {
+    A->cycle_levels = d;
+    double total = 0.0;
+    int status = RT_OK;
+    rt_solve_stats st{};
+    for (int k = 0; k < reps; ++k) {
+      RT_CHECK_HIP(hipMemcpyAsync(x.p, x0, sizeof(double) * A->n, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+      const int s = rt_solve(ctx, A, b, x.p, opts, &st);
+      if (s < 0) {
+        A->cycle_levels = keep;
+        return s;
+      }
+      if (s == RT_NOT_CONVERGED) status = RT_NOT_CONVERGED;
+      total += st.seconds;
+    }
+    r->seconds[d - 1] = total / reps;
+    r->iterations[d - 1] = st.iterations;
+    r->status[d - 1] = status;
+    if (status == RT_OK && (arg < 0 || r->seconds[d - 1] < best)) {
+      best = r->seconds[d - 1];
+      arg = d;
+    }
+  }
+  clear_error();   // a depth that did not converge is only left out
+  r->chosen = arg > 0 ? arg : nl;
+  A->cycle_levels = r->chosen == nl ? 0 : r->chosen;
+  return RT_OK;
+}
+
 }  // extern "C"

@@ -66,6 +66,11 @@ class rt_matrix_info(ctypes.Structure):
                 ("level_p_nnz", c_i64 * 16)]
 
 
+class rt_depth_report(ctypes.Structure):
+    _fields_ = [("depths", c_int), ("seconds", c_dbl * 16), ("iterations", c_int * 16),
+                ("status", c_int * 16), ("chosen", c_int)]
+
+
 class rt_solve_opts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("precond", c_int), ("tol", c_dbl), ("max_iter", c_int),
                 ("inner_tol", c_dbl), ("max_refine", c_int), ("cw_tol", c_dbl)]
@@ -160,6 +165,9 @@ _SIGS = {
                                ctypes.POINTER(rt_newton_stats)]),
     "rt_newton_residual": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int,
                                    ctypes.POINTER(rt_be_residual)]),
+    "rt_matrix_tune_depth": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
+                                     c_int, ctypes.POINTER(rt_depth_report)]),
+    "rt_matrix_set_cycle_depth": (c_int, [c_vp, c_int]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -401,6 +409,18 @@ def gmres_opts(precond=PRECOND_JACOBI, tol=1e-10, max_iter=1000, restart=30) -> 
     return rt_gmres_opts(precond, tol, max_iter, restart)
 
 
+def rt_matrix_tune_depth(ctx: int, A: int, b: int, x0: int, opts: rt_solve_opts,
+                         reps: int = 3) -> rt_depth_report:
+    rep = rt_depth_report()
+    _check("rt_matrix_tune_depth", load().rt_matrix_tune_depth(ctx, A, b, x0, ctypes.byref(opts),
+                                                               reps, ctypes.byref(rep)))
+    return rep
+
+
+def rt_matrix_set_cycle_depth(A: int, depth: int) -> None:
+    _check("rt_matrix_set_cycle_depth", load().rt_matrix_set_cycle_depth(A, depth))
+
+
 def rt_newton_residual(ctx: int, A: int, e: int, E: int, state_order: int = 0) -> rt_be_residual:
     out = rt_be_residual()
     _check("rt_newton_residual", load().rt_newton_residual(ctx, A, e, E, state_order,
@@ -572,6 +592,11 @@ class Context:
         torch = self.torch
         return rt_solve_gmres(self.handle, A, _ptr(b, torch.float64), _ptr(x, torch.float64),
                               opts)
+
+    def tune_depth(self, A: int, b, x0, opts: rt_solve_opts, reps: int = 3) -> rt_depth_report:
+        torch = self.torch
+        return rt_matrix_tune_depth(self.handle, A, _ptr(b, torch.float64),
+                                    _ptr(x0, torch.float64), opts, reps)
 
     def newton_residual(self, A: int, e, E, state_order: int = 0) -> rt_be_residual:
         torch = self.torch

@@ -137,6 +137,18 @@ def check_case(ctx, name, prob):
         e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
         assert s == 0 and e <= bar, f"{name}: k-cycle prec={prec} err={e} its={st.iterations}"
     kc_.free()
+    # the V-cycle on the first two levels only (the second smoothed, not
+    # solved), then the depth tuner
+    if info.levels >= 3:
+        rt.rt_matrix_set_cycle_depth(c.A, 2)
+        x = np.zeros(nin)
+        s, st = rt.rt_solve(ctx, c.A, p(b), p(x), rt.solve_opts(0, 1, 1e-14, 3000, 1e-4, 50))
+        e = np.max(np.abs(x - xref)) / np.max(np.abs(xref))
+        assert s == 0 and e <= 1e-12, f"{name}: depth 2 err={e}"
+        x0 = np.zeros(nin)
+        rep = rt.rt_matrix_tune_depth(ctx, c.A, p(b), p(x0), rt.solve_opts(0, 1, 1e-14, 3000), 1)
+        assert rep.depths == info.levels and 1 <= rep.chosen <= info.levels, f"{name}: depth tuner"
+        rt.rt_matrix_set_cycle_depth(c.A, 0)
     # GMRES on the unscaled operator, Jacobi and AMG, with and without restarts
     for precond, restart in (((1, 4),) if QUICK else ((0, 30), (1, 30), (1, 4))):
         x = np.zeros(nin)

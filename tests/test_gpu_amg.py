@@ -73,3 +73,40 @@ def test_vcycle_solves_match_oracle(ctx, name, strength, prolong, cycle):
         its.append(st.iterations)
     say(f"[amg] {name} strength={strength} smoothed={prolong} cycle={cycle}: levels {info.levels} sizes "
         f"{list(info.level_n[:info.levels])} iterations fp64/mixed {its}")
+
+
+@pytest.mark.parametrize("name", ["diffusive3d_16", "diffusive2d_48"])
+def test_depth_tuner_and_truncated_cycles(ctx, name):
+    """The V-cycle depth tuner times the solve at every depth and keeps a
+    converged one; solves with the chosen depth and with every forced depth
+    (the deepest level used then smoothed, not solved directly) match the
+    oracle."""
+    import torch
+    from paper_2001_11606_amd import rt
+    prob = CASES[name]()
+    sysm = oracle_system(prob)[3]
+    nin = prob.n_interior
+    b = sysm.A.diagonal() * 10.0 ** np.random.default_rng(31).uniform(-4.0, 0.0, nin)
+    x_ref = linsolve.solve(sysm.A, b, tol=1e-15)
+    dp, nb, A = gpu_system(ctx, prob, amg=rt.amg_opts(max_levels=8, coarse_size=32))
+    levels = ctx.matrix_info(A).levels
+    assert levels >= 3
+    bt = torch.tensor(b, device=ctx.device)
+    x0 = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
+    opts = rt.solve_opts(0, 1, 1e-12, 3000, 1e-4, 60, 1e-12)
+    rep = ctx.tune_depth(A, bt, x0, opts, reps=2)
+    say(f"[depth] {name}: levels {levels}, seconds {[round(rep.seconds[d] * 1e3, 2) for d in range(rep.depths)]} ms, "
+        f"iterations {list(rep.iterations[:rep.depths])}, chosen {rep.chosen}")
+    assert rep.depths == levels and 1 <= rep.chosen <= levels
+    assert all(rep.status[d] == rt.RT_OK for d in range(rep.depths))
+    assert rep.seconds[rep.chosen - 1] == min(rep.seconds[d] for d in range(rep.depths))
+    assert float(x0.abs().max()) == 0.0   # the initial guess is left as it was
+    for depth in [0] + list(range(1, levels + 1)):
+        if depth:
+            rt.rt_matrix_set_cycle_depth(A, depth)
+        xt = torch.zeros(nin, dtype=torch.float64, device=ctx.device)
+        s, st = ctx.solve(A, bt, xt, opts)
+        assert s == rt.RT_OK, rt.rt_last_error()
+        err = np.max(np.abs(xt.cpu().numpy() - x_ref) / np.abs(x_ref))
+        assert err <= 1e-10, (depth, err, st.iterations)
+    rt.rt_matrix_set_cycle_depth(A, 0)
