@@ -515,12 +515,20 @@ int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
  * problem padded with identity rows to a multiple of 256 rows, plus the
  * per-particle data of the Newton step; each problem keeps its own dt, c, a.
  * The batch copies what it needs: the matrices may be freed afterwards; after
- * re-assembling them, create a new batch.  Solves use Jacobi-preconditioned
- * CG (precond must be 0; cw_tol must be 0) with per-problem Krylov scalars and per-problem
+ * re-assembling them, create a new batch.  Solves use preconditioned CG
+ * (cw_tol must be 0) with per-problem Krylov scalars and per-problem
  * convergence: a problem that meets its tolerance stops while the others go
- * on.  graph_iters > 0 replays HIP graphs of that many PCG iterations between
- * host reads of the convergence flags (extra iterations of finished problems
- * are no-ops); 0 checks after every iteration.
+ * on.  precond 0: Jacobi.  precond 1: the V-cycle of the batch's hierarchy,
+ * which concatenates the problems' own aggregation hierarchies level by
+ * level (built by rt_batch_create when the matrices have more than one level
+ * and piecewise-constant prolongations; else precond 1 is Jacobi).  It is one
+ * block-diagonal V-cycle: every problem's own levels, smoother and
+ * aggregates; the last level of each problem is smoothed (l1-Jacobi, three
+ * sweeps on the batch's last level) rather than solved directly.
+ * graph_iters > 0 replays HIP graphs of that many Jacobi PCG iterations
+ * between host reads of the convergence flags (extra iterations of finished
+ * problems are no-ops); 0 checks after every iteration; V-cycle iterations
+ * are launched one by one.
  * Vectors (b, x, e, E) are the problems' interior vectors concatenated in
  * problem order, each in its own user order (problem p at the offset
  * sum_{q<p} n_interior(q)), device memory.  stats arrays hold nprob entries
@@ -530,8 +538,8 @@ int rt_batch_create(rt_ctx* ctx, int nprob, rt_matrix* const* mats, rt_batch** o
 void rt_batch_free(rt_batch* B);
 /* rows (padded), stored off-diagonal entries, tile columns (0 = untiled) */
 int rt_batch_get_info(const rt_batch* B, int64_t* rows, int64_t* nnz, int64_t* tile_cols);
-/* rt_matrix_tune / rt_matrix_set_spmv_shape on the concatenated operator
- * (one level: the report's level 0)                                        */
+/* rt_matrix_tune / rt_matrix_set_spmv_shape on the batch's hierarchy (level
+ * 0 the concatenated fine operator; the shape set applies to level 0)     */
 int rt_batch_tune(rt_ctx* ctx, rt_batch* B, int reps, rt_tune_report* rep);
 int rt_batch_set_spmv_shape(rt_batch* B, int precision, int shape);
 int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x,

@@ -1104,6 +1104,8 @@ int level_vectors(Level& L, bool fp32, int cycle) {
 
 }  // namespace
 
+int amg_level_vectors(Level& L, bool fp32, int cycle) { return level_vectors(L, fp32, cycle); }
+
 int amg_setup(rt_ctx* ctx, rt_matrix* A) {
   hipStream_t st = ctx->stream;
   const rt_neighbors* nb = A->nb;

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "internal.h"
@@ -45,7 +46,21 @@ struct rt_batch {
   std::vector<int64_t> row_off, uoff;   // host: padded row offsets, user offsets (nprob + 1)
   int64_t n = 0, nuser = 0, ntiles = 0;
   bool fp32 = false;
-  rt::Level L;                          // the concatenated fine level
+  // The batch's hierarchy: level 0 the concatenated fine level, level l >= 1
+  // the problems' level l concatenated (a problem whose hierarchy is shorter
+  // has no rows there); the V-cycle runs on it as on one matrix.  Its level
+  // vector never grows past RT_MAX_LEVELS, so L stays valid.
+  std::unique_ptr<rt_matrix> H;
+  rt::Level& L;                         // the concatenated fine level (H->levels[0])
+  rt::DevBuf<double> z64;               // V-cycle output of the batched AMG PCG
+  rt::DevBuf<float> z32;
+  rt_batch() : H(make_h()), L(H->levels[0]) {}
+  static rt_matrix* make_h() {
+    rt_matrix* h = new rt_matrix();
+    h->levels.reserve(RT_MAX_LEVELS);
+    h->levels.resize(1);
+    return h;
+  }
   rt::DevBuf<int64_t> d_row_off;
   rt::DevBuf<int32_t> tprob;            // problem of every tile
   rt::DevBuf<int32_t> perm;             // row -> concatenated user index (-1: padding)
@@ -138,6 +153,29 @@ __global__ void k_b_copy_cols(int64_t nnz, const int32_t* __restrict__ col, int6
 }
 
 __global__ void k_b_set_i64(int64_t* p, int64_t v) { *p = v; }
+
+// ---- the batch hierarchy: a problem's level copied in with offsets ----------
+__global__ void k_bh_rp(int64_t n, const int64_t* __restrict__ rp, int64_t eoff,
+                        int64_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = rp[i] + eoff;
+}
+// aggregate of a fine row on the batch's next level (-1 stays: no aggregate)
+__global__ void k_bh_pmap(int64_t n, const int32_t* __restrict__ src, int64_t coff,
+                          int32_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = src[i] >= 0 ? (int32_t)(src[i] + coff) : -1;
+}
+__global__ void k_bh_crange(int64_t nc, const int64_t* __restrict__ src, int64_t moff,
+                            int64_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nc) out[i] = src[i] + moff;
+}
+template <typename T>
+__global__ void k_bh_fill(int64_t n, T* __restrict__ p, T v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
 __global__ void k_b_fill_i32(int64_t n, int32_t* __restrict__ p, int32_t v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -269,7 +307,7 @@ k_b_update(int64_t n, int nprob, const int32_t* __restrict__ tprob,
     const T ri = r[i] - alpha * q[i];
     r[i] = ri;
     rr = (double)ri * (double)ri;
-    rz = (double)ri * (double)(dinv[i] * ri);
+    if (dinv) rz = (double)ri * (double)(dinv[i] * ri);
   }
   rr = block_sum(rr, red);
   rz = block_sum(rz, red);
@@ -279,16 +317,36 @@ k_b_update(int64_t n, int nprob, const int32_t* __restrict__ tprob,
   }
 }
 
+// p = z + beta p, z = D^-1 r (Jacobi) or the given z (the V-cycle's)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_b_pupdate(int64_t n, int nprob, const int32_t* __restrict__ tprob,
             const int32_t* __restrict__ done, const double* __restrict__ ps,
-            const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ p) {
+            const T* __restrict__ r, const T* __restrict__ dinv, const T* __restrict__ z,
+            T* __restrict__ p) {
   const int pr = tprob[blockIdx.x];
   if (done[pr]) return;
   const T beta = (T)ps[B_BETA * nprob + pr];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = dinv[i] * r[i] + beta * p[i];
+  if (i < n) p[i] = (z ? z[i] : dinv[i] * r[i]) + beta * p[i];
+}
+
+// tile partials of r.z for the problems not done; with p (else NULL) also p = z
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_b_rz(int64_t n, const int32_t* __restrict__ tprob, const int32_t* __restrict__ done,
+       const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ p,
+       double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  if (done[tprob[blockIdx.x]]) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double acc = 0.0;
+  if (i < n) {
+    acc = (double)r[i] * (double)z[i];
+    if (p) p[i] = z[i];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 // ---- Newton-step kernels -----------------------------------------------------
@@ -427,6 +485,7 @@ struct BSel<double> {
   static const double* dinv(const Level& L) { return L.dinv64.p; }
   static double* p(rt_batch* B) { return B->p64.p; }
   static double* q(rt_batch* B) { return B->q64.p; }
+  static double* z(rt_batch* B) { return B->z64.p; }
   static int shape(const Level& L) { return L.shape64; }
   static constexpr int slot = 0;
 };
@@ -437,13 +496,16 @@ struct BSel<float> {
   static const float* dinv(const Level& L) { return L.dinv32.p; }
   static float* p(rt_batch* B) { return B->p32.p; }
   static float* q(rt_batch* B) { return B->q32.p; }
+  static float* z(rt_batch* B) { return B->z32.p; }
   static int shape(const Level& L) { return L.shape32; }
   static constexpr int slot = 1;
 };
 
-// one PCG iteration for every problem not flagged done (kernels only)
+// one PCG iteration for every problem not flagged done (kernels only); amg:
+// preconditioned by the V-cycle of the batch hierarchy (on the context's
+// stream, which st must then be)
 template <typename T>
-int b_iteration(rt_ctx* ctx, hipStream_t st, rt_batch* B, T* x, T* r) {
+int b_iteration(rt_ctx* ctx, hipStream_t st, rt_batch* B, T* x, T* r, bool amg = false) {
   using S = BSel<T>;
   const Level& L = B->L;
   const int32_t* done = B->flags.p + F_INNER * B->nprob;
@@ -458,29 +520,44 @@ int b_iteration(rt_ctx* ctx, hipStream_t st, rt_batch* B, T* x, T* r) {
   RT_LAUNCH_CHECK();
   const unsigned nt = (unsigned)B->ntiles;
   hipLaunchKernelGGL((k_b_update<T>), dim3(nt), dim3(kBlock), 0, st, B->n, B->nprob, B->tprob.p,
-                     done, B->ps.p, x, r, S::p(B), S::q(B), S::dinv(L), B->partA.p, B->partB.p);
+                     done, B->ps.p, x, r, S::p(B), S::q(B), amg ? nullptr : S::dinv(L),
+                     B->partA.p, B->partB.p);
   RT_LAUNCH_CHECK();
+  if (amg) {
+    RT_CHECK(vcycle<T>(ctx, B->H.get(), r, S::z(B)));
+    hipLaunchKernelGGL((k_b_rz<T>), dim3(nt), dim3(kBlock), 0, st, B->n, B->tprob.p, done, r,
+                       S::z(B), (T*)nullptr, B->partB.p);
+    RT_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_b_seg, dim3(B->nprob), dim3(kBlock), 0, st, (int)BOP_BETA, B->nprob,
                      B->d_row_off.p, kTileRows, B->partA.p, B->partB.p, B->ps.p, B->flags.p, 0.0,
                      0, 0.0);
   RT_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_b_pupdate<T>), dim3(nt), dim3(kBlock), 0, st, B->n, B->nprob, B->tprob.p,
-                     done, B->ps.p, r, S::dinv(L), S::p(B));
+                     done, B->ps.p, r, S::dinv(L), amg ? S::z(B) : (const T*)nullptr, S::p(B));
   RT_LAUNCH_CHECK();
   return RT_OK;
 }
 
-// Jacobi PCG on every problem whose inner flag is clear; on entry r = b - A x
-// and the per-problem thresholds are set.  graph_k > 0 replays graphs of
-// graph_k iterations between host reads of the flags.
+// PCG (Jacobi, or amg: the batch hierarchy's V-cycle) on every problem whose
+// inner flag is clear; on entry r = b - A x and the per-problem thresholds
+// are set.  graph_k > 0 replays graphs of graph_k Jacobi iterations between
+// host reads of the flags (V-cycle iterations are launched one by one).
 template <typename T>
-int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k) {
+int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k, bool amg = false) {
   using S = BSel<T>;
   hipStream_t st = ctx->stream;
   const Level& L = B->L;
   const int32_t* done = B->flags.p + F_INNER * B->nprob;
-  hipLaunchKernelGGL((k_b_init_jacobi<T>), dim3((unsigned)B->ntiles), dim3(kBlock), 0, st, B->n,
-                     B->tprob.p, done, S::dinv(L), r, S::p(B), B->partB.p);
+  if (amg) {
+    graph_k = 0;
+    RT_CHECK(vcycle<T>(ctx, B->H.get(), r, S::z(B)));
+    hipLaunchKernelGGL((k_b_rz<T>), dim3((unsigned)B->ntiles), dim3(kBlock), 0, st, B->n,
+                       B->tprob.p, done, r, S::z(B), S::p(B), B->partB.p);
+  } else {
+    hipLaunchKernelGGL((k_b_init_jacobi<T>), dim3((unsigned)B->ntiles), dim3(kBlock), 0, st, B->n,
+                       B->tprob.p, done, S::dinv(L), r, S::p(B), B->partB.p);
+  }
   RT_LAUNCH_CHECK();
   RT_CHECK(b_seg(ctx, B, BOP_RZ, kTileRows, B->partB.p, nullptr));
   std::vector<int32_t> fl;
@@ -514,7 +591,7 @@ int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k) {
       RT_CHECK_HIP(hipGraphLaunch(B->graph[slot], st));
       launched += graph_k;
     } else {
-      RT_CHECK(b_iteration<T>(ctx, st, B, x, r));
+      RT_CHECK(b_iteration<T>(ctx, st, B, x, r, amg));
       launched += 1;
     }
     RT_CHECK(b_read_flags(ctx, B, F_INNER, &fl, &all));
@@ -528,6 +605,8 @@ int b_solve(rt_ctx* ctx, rt_batch* B, const rt_solve_opts* o, int graph_k, rt_so
   const int64_t n = B->n;
   const int np = B->nprob;
   const bool mixed = o->precision == RT_PREC_MIXED;
+  // the V-cycle when asked for and the batch has a hierarchy (else Jacobi)
+  const bool amg = o->precond == 1 && B->H->levels.size() > 1;
   const Level& L = B->L;
   hipLaunchKernelGGL(k_b_fill_i32, dim3(grid_for((int64_t)F_COUNT * np)), dim3(kBlock), 0, st,
                      (int64_t)F_COUNT * np, B->flags.p, 0);
@@ -551,13 +630,13 @@ int b_solve(rt_ctx* ctx, rt_batch* B, const rt_solve_opts* o, int graph_k, rt_so
     RT_CHECK(b_read_flags(ctx, B, F_OUTER, &fl, &all));
     if (all) break;
     if (!mixed) {
-      RT_CHECK(b_pcg<double>(ctx, B, B->xs.p, B->r64.p, o->max_iter, graph_k));
+      RT_CHECK(b_pcg<double>(ctx, B, B->xs.p, B->r64.p, o->max_iter, graph_k, amg));
       break;   // the recursive residual decided convergence
     }
     if (refine >= o->max_refine) break;
     hipLaunchKernelGGL((k_b_zero<float>), dim3(grid_for(n)), dim3(kBlock), 0, st, n, B->d32.p);
     RT_LAUNCH_CHECK();
-    RT_CHECK(b_pcg<float>(ctx, B, B->d32.p, B->r32.p, o->max_iter, graph_k));
+    RT_CHECK(b_pcg<float>(ctx, B, B->d32.p, B->r32.p, o->max_iter, graph_k, amg));
     hipLaunchKernelGGL(k_b_add_f32, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B->d32.p, B->xs.p);
     RT_LAUNCH_CHECK();
     ++refine;
@@ -583,6 +662,149 @@ int b_solve(rt_ctx* ctx, rt_batch* B, const rt_solve_opts* o, int graph_k, rt_so
     }
   }
   return status;
+}
+
+// The batch hierarchy from the problems' hierarchies (see rt_batch): level
+// l >= 1 concatenates every problem's level l; level 0 (the batch's padded
+// fine level) gains the l1 smoother scalings and, like every level above the
+// last, the aggregate maps to the next (a problem whose hierarchy ends at l
+// maps nothing: its rows there are smoothed only).  Built only when every
+// problem's prolongations are piecewise constant; otherwise the batch keeps
+// one level and its V-cycle is Jacobi.
+int build_hierarchy(rt_ctx* ctx, rt_batch* B) {
+  hipStream_t st = ctx->stream;
+  const int np = B->nprob;
+  rt_matrix* H = B->H.get();
+  H->n = B->n;
+  H->has_fp32 = B->fp32;
+  int D = 1;
+  for (rt_matrix* A : B->mats) {
+    const int la = std::min<int>((int)A->levels.size(), RT_MAX_LEVELS);
+    for (int l = 0; l + 1 < la; ++l)
+      if (A->levels[l].smoothed) return RT_OK;
+    D = std::max(D, la);
+  }
+  H->amg = rt_amg_opts{D, 0, 0.0, B->fp32 ? 1 : 0, 0, RT_SMOOTHER_L1_JACOBI, 2, 1,
+                       RT_PROLONG_PIECEWISE};
+  H->coarse_direct = false;
+  if (D == 1) return RT_OK;
+  const bool fp32 = B->fp32;
+  auto has = [&](int p, int l) { return (int)B->mats[p]->levels.size() > l; };
+  // row and entry offsets per level (level 0: the padded fine rows)
+  std::vector<std::vector<int64_t>> off(D, std::vector<int64_t>(np + 1, 0)),
+      eoff(D, std::vector<int64_t>(np + 1, 0));
+  off[0] = B->row_off;
+  for (int l = 1; l < D; ++l)
+    for (int p = 0; p < np; ++p) {
+      off[l][p + 1] = off[l][p] + (has(p, l) ? B->mats[p]->levels[l].n : 0);
+      eoff[l][p + 1] = eoff[l][p] + (has(p, l) ? B->mats[p]->levels[l].nnz : 0);
+    }
+  // level 0: l1 scalings (padding rows: 1, their residual is 0)
+  Level& L0 = B->L;
+  RT_CHECK(L0.sinv64.reserve(B->n));
+  hipLaunchKernelGGL(k_bh_fill<double>, dim3(grid_for(B->n)), dim3(kBlock), 0, st, B->n,
+                     L0.sinv64.p, 1.0);
+  if (fp32) {
+    RT_CHECK(L0.sinv32.reserve(B->n));
+    hipLaunchKernelGGL(k_bh_fill<float>, dim3(grid_for(B->n)), dim3(kBlock), 0, st, B->n,
+                       L0.sinv32.p, 1.0f);
+  }
+  RT_LAUNCH_CHECK();
+  for (int p = 0; p < np; ++p) {
+    const Level& S = B->mats[p]->levels[0];
+    RT_CHECK_HIP(hipMemcpyAsync(L0.sinv64.p + off[0][p], S.sinv64.p, sizeof(double) * S.n,
+                                hipMemcpyDeviceToDevice, st));
+    if (fp32)
+      RT_CHECK_HIP(hipMemcpyAsync(L0.sinv32.p + off[0][p], S.sinv32.p, sizeof(float) * S.n,
+                                  hipMemcpyDeviceToDevice, st));
+  }
+  // coarse levels
+  for (int l = 1; l < D; ++l) {
+    H->levels.emplace_back();
+    Level& C = H->levels.back();
+    C.n = off[l][np];
+    C.nnz = eoff[l][np];
+    for (int p = 0; p < np; ++p)
+      if (has(p, l)) C.max_row = std::max(C.max_row, B->mats[p]->levels[l].max_row);
+    RT_CHECK(C.rp.reserve(C.n + 1));
+    RT_CHECK(C.col.reserve(std::max<int64_t>(C.nnz, 1)));
+    RT_CHECK(C.val64.reserve(C.nnz + kSpmvPad));
+    for (auto* b : {&C.diag64, &C.sinv64, &C.dinv64}) RT_CHECK(b->reserve(C.n));
+    if (fp32) {
+      RT_CHECK(C.val32.reserve(C.nnz + kSpmvPad));
+      for (auto* b : {&C.diag32, &C.sinv32, &C.dinv32}) RT_CHECK(b->reserve(C.n));
+    }
+    for (int p = 0; p < np; ++p) {
+      if (!has(p, l)) continue;
+      const Level& S = B->mats[p]->levels[l];
+      const int64_t r0 = off[l][p], e0 = eoff[l][p];
+      if (S.n > 0)
+        hipLaunchKernelGGL(k_bh_rp, dim3(grid_for(S.n)), dim3(kBlock), 0, st, S.n, S.rp.p, e0,
+                           C.rp.p + r0);
+      if (S.nnz > 0)
+        hipLaunchKernelGGL(k_b_copy_cols, dim3(grid_for(S.nnz)), dim3(kBlock), 0, st, S.nnz,
+                           S.col.p, e0, r0, C.col.p);
+      RT_LAUNCH_CHECK();
+      auto cp = [&](void* dst, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+      };
+      RT_CHECK_HIP(cp(C.val64.p + e0, S.val64.p, sizeof(double) * S.nnz));
+      RT_CHECK_HIP(cp(C.diag64.p + r0, S.diag64.p, sizeof(double) * S.n));
+      RT_CHECK_HIP(cp(C.sinv64.p + r0, S.sinv64.p, sizeof(double) * S.n));
+      RT_CHECK_HIP(cp(C.dinv64.p + r0, S.dinv64.p, sizeof(double) * S.n));
+      if (fp32) {
+        RT_CHECK_HIP(cp(C.val32.p + e0, S.val32.p, sizeof(float) * S.nnz));
+        RT_CHECK_HIP(cp(C.diag32.p + r0, S.diag32.p, sizeof(float) * S.n));
+        RT_CHECK_HIP(cp(C.sinv32.p + r0, S.sinv32.p, sizeof(float) * S.n));
+        RT_CHECK_HIP(cp(C.dinv32.p + r0, S.dinv32.p, sizeof(float) * S.n));
+      }
+    }
+    hipLaunchKernelGGL(k_b_set_i64, dim3(1), dim3(1), 0, st, C.rp.p + C.n, C.nnz);
+    RT_LAUNCH_CHECK();
+  }
+  // aggregate maps from level l to l + 1
+  for (int l = 0; l + 1 < D; ++l) {
+    Level& F = H->levels[l];
+    const int64_t nc = H->levels[l + 1].n;
+    RT_CHECK(F.pmap.reserve(std::max<int64_t>(F.n, 1)));
+    hipLaunchKernelGGL(k_b_fill_i32, dim3(grid_for(F.n)), dim3(kBlock), 0, st, F.n, F.pmap.p, -1);
+    RT_LAUNCH_CHECK();
+    // members per problem: the last offset of its own map
+    std::vector<int64_t> members(np, 0), moff(np + 1, 0);
+    for (int p = 0; p < np; ++p) {
+      if (has(p, l + 1)) {
+        const Level& S = B->mats[p]->levels[l];
+        RT_CHECK(ctx->sync_read(S.crange.p + B->mats[p]->levels[l + 1].n, sizeof(int64_t)));
+        std::memcpy(&members[p], ctx->host, sizeof(int64_t));
+      }
+      moff[p + 1] = moff[p] + members[p];
+    }
+    RT_CHECK(F.crange.reserve(nc + 1));
+    RT_CHECK(F.amem.reserve(std::max<int64_t>(moff[np], 1)));
+    for (int p = 0; p < np; ++p) {
+      if (!has(p, l + 1)) continue;
+      const Level& S = B->mats[p]->levels[l];
+      const int64_t ncp = B->mats[p]->levels[l + 1].n;
+      if (S.n > 0)
+        hipLaunchKernelGGL(k_bh_pmap, dim3(grid_for(S.n)), dim3(kBlock), 0, st, S.n, S.pmap.p,
+                           off[l + 1][p], F.pmap.p + off[l][p]);
+      if (ncp > 0)
+        hipLaunchKernelGGL(k_bh_crange, dim3(grid_for(ncp)), dim3(kBlock), 0, st, ncp,
+                           S.crange.p, moff[p], F.crange.p + off[l + 1][p]);
+      if (members[p] > 0)
+        hipLaunchKernelGGL(k_b_copy_cols, dim3(grid_for(members[p])), dim3(kBlock), 0, st,
+                           members[p], S.amem.p, moff[p], off[l][p], F.amem.p);
+      RT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_b_set_i64, dim3(1), dim3(1), 0, st, F.crange.p + nc, moff[np]);
+    RT_LAUNCH_CHECK();
+    F.smoothed = false;
+  }
+  for (Level& L : H->levels) RT_CHECK(amg_level_vectors(L, fp32, 1));
+  RT_CHECK(B->z64.reserve(B->n));
+  if (fp32) RT_CHECK(B->z32.reserve(B->n));
+  RT_CHECK_HIP(hipStreamSynchronize(st));
+  return RT_OK;
 }
 
 }  // namespace
@@ -731,6 +953,7 @@ int rt_batch_create(rt_ctx* ctx, int nprob, rt_matrix* const* mats, rt_batch** o
     return fail(RT_E_DEVICE);
   }
   RT_B(build_tiles(ctx, L));
+  RT_B(build_hierarchy(ctx, B));
 #undef RT_B
   *out = B;
   return RT_OK;
@@ -760,13 +983,8 @@ int rt_batch_tune(rt_ctx* ctx, rt_batch* B, int reps, rt_tune_report* rep) {
     rt::set_error("rt_batch_tune: NULL argument");
     return RT_E_ARG;
   }
-  // the concatenated level is an ordinary one-level operator
-  rt_matrix view;
-  view.n = B->n;
-  view.has_fp32 = B->fp32;
-  view.levels.emplace_back(std::move(B->L));
-  const int s = rt_matrix_tune(ctx, &view, reps, rep);
-  B->L = std::move(view.levels[0]);
+  // the batch's hierarchy is an ordinary operator: every level is tuned
+  const int s = rt_matrix_tune(ctx, B->H.get(), reps, rep);
   for (auto& g : B->graph)
     if (g) {
       (void)hipGraphExecDestroy(g);
@@ -805,9 +1023,8 @@ int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x, const r
     return RT_E_ARG;
   }
   RT_CHECK(check_solve_opts(opts));
-  if (opts->precond != 0 || opts->cw_tol != 0.0) {
-    set_error("rt_batch_solve: batched solves use the Jacobi preconditioner (precond 0) and "
-              "the normwise test only (cw_tol 0)");
+  if (opts->cw_tol != 0.0) {
+    set_error("rt_batch_solve: batched solves use the normwise test only (cw_tol 0)");
     return RT_E_ARG;
   }
   if (opts->precision == RT_PREC_MIXED && !B->fp32) {
@@ -844,9 +1061,8 @@ int rt_batch_newton_step(rt_ctx* ctx, rt_batch* B, double* e, double* E, int ell
     return RT_E_ARG;
   }
   RT_CHECK(check_solve_opts(&opts->solve));
-  if (opts->solve.precond != 0 || opts->solve.cw_tol != 0.0) {
-    set_error("rt_batch_newton_step: batched solves use the Jacobi preconditioner (precond 0) "
-              "and the normwise test only (cw_tol 0)");
+  if (opts->solve.cw_tol != 0.0) {
+    set_error("rt_batch_newton_step: batched solves use the normwise test only (cw_tol 0)");
     return RT_E_ARG;
   }
   if (opts->solve.precision == RT_PREC_MIXED && !B->fp32) {

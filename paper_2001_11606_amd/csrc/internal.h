@@ -373,6 +373,8 @@ int solve_sorted(rt_ctx* ctx, rt_matrix* A, const double* b, double* x,
                  const rt_solve_opts* o, rt_solve_stats* st, const double* b_prev = nullptr,
                  const int32_t* mismatch = nullptr);
 int amg_setup(rt_ctx* ctx, rt_matrix* A);
+// work vectors of a level of a V-cycle (cycle: rt_amg_opts.cycle)
+int amg_level_vectors(Level& L, bool fp32, int cycle);
 // levels the V-cycle uses: all, or the tuned depth
 inline size_t cycle_depth(const rt_matrix* A) {
   const size_t nl = A->levels.size();

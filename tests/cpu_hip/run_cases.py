@@ -284,6 +284,55 @@ def check_batch(ctx):
     say(f"ok batch: {len(probs)} problems, rows={rows} nnz={nnz} tile_cols={tcols}")
 
 
+def check_batch_amg(ctx):
+    """An ensemble of diffusive problems with their own aggregation
+    hierarchies: batched V-cycle solves and Newton steps against the oracle."""
+    probs = []
+    for q, s_ in enumerate((150.0, 300.0, 700.0)):
+        pr = synth.config5_member(q, s_)
+        pr.dt = 0.1
+        probs.append(pr)
+    cases = [Case(ctx, pr, amg=rt.amg_opts(max_levels=8, coarse_size=16)) for pr in probs]
+    levels = [rt.rt_matrix_get_info(c.A).levels for c in cases]
+    assert max(levels) >= 3, f"batch amg: hierarchies {levels}"
+    B = rt.rt_batch_create(ctx, [c.A for c in cases])
+    offs = np.cumsum([0] + [pr.n_interior for pr in probs])
+    rng = np.random.default_rng(13)
+    bs, xref = [], []
+    for pr in probs:
+        sysm = oracle_system(pr)[3]
+        b = rng.standard_normal(pr.n_interior) * sysm.A.diagonal()
+        bs.append(b)
+        xref.append(linsolve.dense(sysm.A, b))
+    bcat = np.concatenate(bs)
+    its = {}
+    for prec, precond, tol, bar in ((0, 1, 1e-14, 1e-12), (1, 1, 1e-12, 1e-10), (0, 0, 1e-14, 1e-12)):
+        x = np.zeros(offs[-1])
+        s, st = rt.rt_batch_solve(ctx, B, len(probs), p(bcat), p(x),
+                                  rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50), 0)
+        assert s == 0, f"batch amg solve status {s}"
+        its[(prec, precond)] = [st[q].iterations for q in range(len(probs))]
+        for q in range(len(probs)):
+            xq = x[offs[q]:offs[q + 1]]
+            err = np.max(np.abs(xq - xref[q])) / np.max(np.abs(xref[q]))
+            assert err <= bar, f"batch amg solve prec={prec} precond={precond} problem {q}: {err}"
+    e = np.concatenate([pr.e[:pr.n_interior] for pr in probs]).copy()
+    E = np.concatenate([pr.E[:pr.n_interior] for pr in probs]).copy()
+    nopts = rt.newton_opts(rt.solve_opts(0, 1, 1e-14, 3000))
+    for ell in range(2):
+        s, st = rt.rt_batch_newton_step(ctx, B, len(probs), p(e), p(E), ell, nopts, 0)
+        assert s == 0, f"batch amg newton status {s}"
+    for q, pr in enumerate(probs):
+        ref = ostep.time_step(pr.copy(), fixed_outer=2, solve_tol=1e-15)
+        ee = np.max(np.abs(e[offs[q]:offs[q + 1]] - ref.e) / ref.e)
+        eE = np.max(np.abs(E[offs[q]:offs[q + 1]] - ref.E) / ref.E)
+        assert ee <= 1e-12 and eE <= 1e-12, f"batch amg newton problem {q}: {ee} {eE}"
+    rt.rt_batch_free(B)
+    for c in cases:
+        c.free()
+    say(f"ok batch amg: levels {levels}, iterations {its}")
+
+
 def pytest_approx(v, rel=1e-12):
     class _A:
         def __eq__(self, o):
@@ -324,6 +373,8 @@ def main():
         check_case(ctx, name, prob)
     if not only or "batch" in only.split(","):
         check_batch(ctx)
+    if not only or "batch_amg" in only.split(","):
+        check_batch_amg(ctx)
     check_cache(ctx)
     # error contract on the host
     pos = np.random.default_rng(0).uniform(0, 1, (3, 40))

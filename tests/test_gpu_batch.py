@@ -4,7 +4,9 @@ An ensemble of independent problems (the 2-D / 3-D mix of the ensemble
 workload, shrunk) is concatenated into one block-diagonal system.  Every
 problem's solution must match its own oracle solve (FP64 to 1e-12, mixed to
 1e-10, max-norm relative) whatever the graph replay length, and a batched
-Newton step must match the oracle's time step per problem.
+Newton step must match the oracle's time step per problem.  An ensemble of
+diffusive problems with their own aggregation hierarchies does the same with
+the batch's V-cycle (the problems' levels concatenated).
 """
 import numpy as np
 import pytest
@@ -138,9 +140,18 @@ def test_batch_tune_and_errors(ctx, ensemble):
     offs = _offsets(probs)
     b = torch.ones(offs[-1], dtype=torch.float64, device=ctx.device)
     x = torch.zeros_like(b)
-    with pytest.raises(rt.RtError):   # AMG is not offered for batches
+    # one-level matrices: the batch has no hierarchy and precond 1 is Jacobi
+    s1, st1 = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                rt.solve_opts(0, 1, 1e-10, 4000), 0)
+    x.zero_()
+    s0, st0 = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                rt.solve_opts(0, 0, 1e-10, 4000), 0)
+    assert s1 == s0 == rt.RT_OK
+    assert [st1[q].iterations for q in range(len(probs))] == [st0[q].iterations
+                                                               for q in range(len(probs))]
+    with pytest.raises(rt.RtError):   # the componentwise test is not offered for batches
         rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
-                          rt.solve_opts(0, 1, 1e-10, 100), 0)
+                          rt.solve_opts(0, 0, 1e-10, 100, 1e-4, 60, 1e-10), 0)
     with pytest.raises(rt.RtError):
         rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
                           rt.solve_opts(0, 0, 1e-10, 100), -1)
@@ -192,3 +203,77 @@ def test_full_ensemble_sampled_against_oracle(ctx):
             rt.rt_matrix_free(A)
             rt.rt_neighbors_free(nb.handle)
         ctx._owned.clear()
+
+
+AMG_SIZES = (150.0, 2200.0, 700.0, 5000.0, 300.0)
+
+
+@pytest.fixture(scope="module")
+def ensemble_amg(ctx):
+    from paper_2001_11606_amd import rt
+    probs = []
+    for q, size in enumerate(AMG_SIZES):
+        pr = synth.config5_member(q, size)
+        pr.dt = 0.1   # diffusion-dominated: the strength test coarsens the rows
+        probs.append(pr)
+    systems = [gpu_system(ctx, pr, amg=rt.amg_opts(max_levels=8, coarse_size=16)) for pr in probs]
+    levels = [ctx.matrix_info(A).levels for (_, _, A) in systems]
+    B = rt.rt_batch_create(ctx.handle, [A for (_, _, A) in systems])
+    yield probs, systems, B, levels
+    rt.rt_batch_free(B)
+
+
+@pytest.mark.parametrize("precision,tol,bar", [(0, 1e-14, 1e-12), (1, 1e-12, 1e-10)])
+def test_batch_amg_solve_matches_oracle(ctx, ensemble_amg, precision, tol, bar):
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B, levels = ensemble_amg
+    assert max(levels) >= 3, levels
+    offs = _offsets(probs)
+    bs, refs = _rhs(probs)
+    b = torch.tensor(np.concatenate(bs), device=ctx.device)
+    its = {}
+    for precond in (1, 0):
+        x = torch.zeros_like(b)
+        s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                  rt.solve_opts(precision, precond, tol, 4000, 1e-4, 60), 0)
+        assert s == rt.RT_OK, rt.rt_last_error()
+        its[precond] = [st[q].iterations for q in range(len(probs))]
+        xh = x.cpu().numpy()
+        for q in range(len(probs)):
+            err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
+            assert err <= bar, (precond, q, err)
+    say(f"[batch amg] precision={precision} levels {levels}: iterations V-cycle {its[1]}, "
+        f"Jacobi {its[0]}")
+    assert sum(its[1]) < sum(its[0])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_amg_newton_matches_oracle(ctx, ensemble_amg, precision):
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B, levels = ensemble_amg
+    offs = _offsets(probs)
+    e = torch.tensor(np.concatenate([pr.e[:pr.n_interior] for pr in probs]), device=ctx.device)
+    E = torch.tensor(np.concatenate([pr.E[:pr.n_interior] for pr in probs]), device=ctx.device)
+    tol = 1e-14 if precision == 0 else 1e-12
+    nopts = rt.newton_opts(rt.solve_opts(precision, 1, tol, 4000, 1e-4, 50))
+    for ell in range(3):
+        s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), ell,
+                                        nopts, 4)
+        assert s == rt.RT_OK, rt.rt_last_error()
+    eh, Eh = e.cpu().numpy(), E.cpu().numpy()
+    bar = 1e-12 if precision == 0 else 1e-10
+    for q, pr in enumerate(probs):
+        ref = ostep.time_step(pr.copy(), fixed_outer=3, inner_tol_e=1e-14, solve_tol=1e-15)
+        err_e = np.max(np.abs(eh[offs[q]:offs[q + 1]] - ref.e) / np.abs(ref.e))
+        err_E = np.max(np.abs(Eh[offs[q]:offs[q + 1]] - ref.E) / np.abs(ref.E))
+        assert err_e <= bar and err_E <= bar, (q, err_e, err_E)
+
+
+def test_batch_amg_tune(ctx, ensemble_amg):
+    from paper_2001_11606_amd import rt
+    probs, systems, B, levels = ensemble_amg
+    rep = rt.rt_batch_tune(ctx.handle, B, 2)
+    assert rep.levels == max(levels)
+    assert all(0 <= rep.chosen[l][0] < rep.shapes for l in range(rep.levels))
