@@ -44,33 +44,50 @@ __device__ __forceinline__ int first_bucket(int32_t c) {
   return (int)((((uint32_t)c >> 4) * 2654435761u) >> 24) & (kBuckets - 1);
 }
 
-// Insert the columns of entries [e0, e1) into keys (empty = -1); *count is the
-// number of distinct columns inserted; *overflow is set once it reaches
-// kTileMaxCols or a probe finds no free slot (then insertion stops).
-__device__ void tile_insert(int64_t e0, int64_t e1, const int32_t* __restrict__ col, int* keys,
-                            int* count, int* overflow) {
-  for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock) {
-    if (*(volatile int*)overflow) break;
-    const int c = col[k];
-    const int off = c & (kBucket - 1);
-    int b = first_bucket(c);
-    bool placed = false;
-    for (int step = 0; step < kBuckets && !placed; ++step, b = (b + 1) & (kBuckets - 1)) {
-      const int s = b * kBucket + off;
-      const int cur = ((volatile int*)keys)[s];
-      if (cur == c) {
+// Insert column c into keys (empty = -1); *count is the number of distinct
+// columns inserted; *overflow is set once it reaches kTileMaxCols or a probe
+// finds no free slot.
+__device__ __forceinline__ void tile_insert_one(int c, int* keys, int* count, int* overflow) {
+  const int off = c & (kBucket - 1);
+  int b = first_bucket(c);
+  bool placed = false;
+  for (int step = 0; step < kBuckets && !placed; ++step, b = (b + 1) & (kBuckets - 1)) {
+    const int s = b * kBucket + off;
+    const int cur = ((volatile int*)keys)[s];
+    if (cur == c) {
+      placed = true;
+    } else if (cur == -1) {
+      const int prev = atomicCAS(&keys[s], -1, c);
+      if (prev == -1) {
+        if (atomicAdd(count, 1) + 1 >= kTileMaxCols) *(volatile int*)overflow = 1;
         placed = true;
-      } else if (cur == -1) {
-        const int prev = atomicCAS(&keys[s], -1, c);
-        if (prev == -1) {
-          if (atomicAdd(count, 1) + 1 >= kTileMaxCols) *(volatile int*)overflow = 1;
-          placed = true;
-        } else if (prev == c) {
-          placed = true;
-        }
+      } else if (prev == c) {
+        placed = true;
       }
     }
-    if (!placed) *(volatile int*)overflow = 1;
+  }
+  if (!placed) *(volatile int*)overflow = 1;
+}
+
+// Insert the columns of entries [e0, e1) (insertion stops at an overflow).
+// A thread requests kTileBatch columns, one per block-wide stride, before it
+// hashes any of them: a tile's entries are then read in a few round trips
+// to memory rather than one per entry.
+constexpr int kTileBatch = 8;
+
+__device__ void tile_insert(int64_t e0, int64_t e1, const int32_t* __restrict__ col, int* keys,
+                            int* count, int* overflow) {
+  for (int64_t kb = e0 + threadIdx.x; kb < e1; kb += (int64_t)kBlock * kTileBatch) {
+    if (*(volatile int*)overflow) break;
+    int c[kTileBatch];
+#pragma unroll
+    for (int e = 0; e < kTileBatch; ++e) {
+      const int64_t k = kb + (int64_t)e * kBlock;
+      c[e] = k < e1 ? col[k] : -1;   // columns are >= 0
+    }
+#pragma unroll
+    for (int e = 0; e < kTileBatch; ++e)
+      if (c[e] >= 0) tile_insert_one(c[e], keys, count, overflow);
   }
 }
 
@@ -144,8 +161,17 @@ k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict
     }
   }
   __syncthreads();
-  for (int64_t k = e0 + threadIdx.x; k < e1; k += kBlock)
-    lcol[k] = (uint16_t)pos[tile_find(keys, col[k])];
+  for (int64_t kb = e0 + threadIdx.x; kb < e1; kb += (int64_t)kBlock * kTileBatch) {
+    int c[kTileBatch];
+#pragma unroll
+    for (int e = 0; e < kTileBatch; ++e) {
+      const int64_t k = kb + (int64_t)e * kBlock;
+      c[e] = k < e1 ? col[k] : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < kTileBatch; ++e)
+      if (c[e] >= 0) lcol[kb + (int64_t)e * kBlock] = (uint16_t)pos[tile_find(keys, c[e])];
+  }
 }
 
 // padded lists -> contiguous tile_cols (tile t at off[t])
