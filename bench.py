@@ -218,6 +218,52 @@ def cpu_baseline(workload: str, n_sample: int, outer: int, tol: float, cw_tol: f
             "host_cpus": ncpu, "cpu_model": model}
 
 
+def ensemble_vcycle_leg(ctx, dps, ntot, args):
+    """The batched V-cycle on the ensemble: every problem assembled with its
+    own aggregation hierarchy, the batch concatenating them level by level;
+    mixed solves of b = 1 with the V-cycle (iterations launched one by one,
+    and replayed from graphs) against Jacobi (graphs) on that batch, outside
+    the timed steps."""
+    import torch
+    from paper_2001_11606_amd import rt
+    amg = rt.amg_opts(build_fp32=1)
+    built = []
+    for dp in dps:
+        nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+        A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=amg)
+        built.append((nb, A))
+    levels = [ctx.matrix_info(A).levels for _, A in built]
+    B = rt.rt_batch_create(ctx.handle, [A for _, A in built])
+    ctx.free(*[h for nb, A in built for h in (A, nb)])
+    rep = rt.rt_batch_tune(ctx.handle, B, 3)
+    rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_FP64, rep.chosen[0][0])
+    rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_MIXED, rep.chosen[0][1])
+    rt.rt_batch_set_spmv_shape(B, rt.RT_PRODUCT_RESIDUAL, rep.chosen[0][2])
+    res = {}
+    runs = ((1, 0), (1, args.graph_iters), (0, args.graph_iters))
+    for precond, graph in runs + runs:   # the second round is timed
+        bt = torch.ones(ntot, dtype=torch.float64, device=ctx.device)
+        xt = torch.zeros_like(bt)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        s, sst = rt.rt_batch_solve(ctx.handle, B, len(dps), bt.data_ptr(), xt.data_ptr(),
+                                   rt.solve_opts(rt.RT_PREC_MIXED, precond, args.tol, 5000,
+                                                 args.inner_tol, 30), graph)
+        torch.cuda.synchronize()
+        if s != rt.RT_OK:
+            raise RuntimeError(f"ensemble V-cycle leg: status {s}")
+        res[(precond, graph)] = (time.perf_counter() - ta,
+                                 max(sst[q].iterations for q in range(len(dps))))
+    rt.rt_batch_free(B)
+    v0, vg, jg = (res[k] for k in runs)
+    return {"levels_min": min(levels), "levels_max": max(levels),
+            "solve_s_vcycle": round(v0[0], 5), "solve_s_vcycle_graph": round(vg[0], 5),
+            "solve_s_jacobi": round(jg[0], 5), "graph_iters": args.graph_iters,
+            "krylov_max_vcycle": v0[1], "krylov_max_jacobi": jg[1],
+            "ratio_jacobi_over_vcycle": round(jg[0] / min(v0[0], vg[0]), 3)}
+
+
 def run_ensemble(args):
     """The ensemble workload: 96 independent problems (2-D / 3-D, log-uniform
     sizes 8k-500k, about 1.1e7 particles), one step = per-problem neighbour
@@ -319,6 +365,7 @@ def run_ensemble(args):
         torch.cuda.synchronize()
         solve_t[prec] = time.perf_counter() - ta
     rt.rt_batch_free(B)
+    vleg = None if args.no_vcycle else ensemble_vcycle_leg(ctx, dps, ntot, args)
     sh = tuned.chosen[0][1]
     shapes = rt.rt_spmv_shapes()
     us32 = tuned.us[0][1][sh]
@@ -342,6 +389,8 @@ def run_ensemble(args):
                                                          solve_t[rt.RT_PREC_MIXED], 3)},
         "krylov_max": max(s.solve.iterations for s in st),
     }
+    if vleg is not None:
+        out["vcycle"] = vleg
     out["config"]["build_threads"] = nthreads
     print(json.dumps(out), flush=True)
     for c in wctx:
@@ -516,6 +565,8 @@ def main():
     ap.add_argument("--mixed", action="store_true",
                     help="coswave3d: FP32 inner CG with FP64 refinement instead of FP64 CG")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-vcycle", action="store_true",
+                    help="ensemble: skip the batched V-cycle leg")
     ap.add_argument("--no-densitystep", action="store_true",
                     help="marshak3d: skip the mixed-vs-FP64 leg on the density-step recipe")
     ap.add_argument("--cpu-n", type=int, default=64)

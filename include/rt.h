@@ -525,10 +525,11 @@ int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
  * block-diagonal V-cycle: every problem's own levels, smoother and
  * aggregates; the last level of each problem is smoothed (l1-Jacobi, three
  * sweeps on the batch's last level) rather than solved directly.
- * graph_iters > 0 replays HIP graphs of that many Jacobi PCG iterations
- * between host reads of the convergence flags (extra iterations of finished
- * problems are no-ops); 0 checks after every iteration; V-cycle iterations
- * are launched one by one.
+ * The V-cycle's fine-level products skip the problems that have stopped.
+ * graph_iters > 0 replays HIP graphs of that many PCG iterations (Jacobi or
+ * V-cycle) between host reads of the convergence flags (extra iterations of
+ * finished problems change none of their values); 0 checks after every
+ * iteration.
  * Vectors (b, x, e, E) are the problems' interior vectors concatenated in
  * problem order, each in its own user order (problem p at the offset
  * sum_{q<p} n_interior(q)), device memory.  stats arrays hold nprob entries

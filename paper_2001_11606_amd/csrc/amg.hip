@@ -1253,6 +1253,10 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   Level& L = A->levels[l];
   const int64_t n = L.n;
   const size_t nl = cycle_depth(A);
+  // a batch's levels: the products skip the chunks of stopped problems
+  const bool bskip = l < A->lvl_skip.size();
+  const int32_t* tp = bskip ? A->lvl_tprob[l] : nullptr;
+  const int32_t* sk = bskip ? A->lvl_skip[l] : stop;
   if (l + 1 == nl) {
     if (A->coarse_direct && nl == A->levels.size()) {
       hipLaunchKernelGGL(k_coarse_solve<T>, dim3(grid_for(n * kWave)), dim3(kBlock), 0, st, n,
@@ -1270,7 +1274,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
     for (int sweep = 0; sweep < 3; ++sweep) {
       RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), src, b, B::sinv(L),
                                                 dst, nullptr, nullptr, nullptr,
-                                                level_shape<T>(L), nullptr, stop)));
+                                                level_shape<T>(L), tp, sk)));
       T* tmp = src;
       src = dst;
       dst = tmp;
@@ -1292,7 +1296,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   }
   RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
                                            nullptr, nullptr, nullptr, level_shape<T>(L),
-                                           nullptr, stop)));
+                                           tp, sk)));
   if (L.smoothed)
     hipLaunchKernelGGL((k_restrict_p<T, T>), dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n,
                        L.pt_rp.p, L.pt_row.p, B::ptv(L), r, B::b(C), stop);
@@ -1324,7 +1328,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   if (cheb) return cheb_smooth<T>(st, A, L, A->amg.smoother_degree, b, t, out, stop);
   RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), t, b, B::sinv(L), out,
                                             nullptr, nullptr, nullptr, level_shape<T>(L),
-                                            nullptr, stop)));
+                                            tp, sk)));
   return RT_OK;
 }
 

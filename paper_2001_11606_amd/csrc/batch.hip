@@ -63,6 +63,10 @@ struct rt_batch {
   }
   rt::DevBuf<int64_t> d_row_off;
   rt::DevBuf<int32_t> tprob;            // problem of every tile
+  // coarse levels of the hierarchy, per 256-row chunk (levels concatenated):
+  // first and last problem with rows in it, and whether all of them stopped
+  rt::DevBuf<int32_t> crng, cdone, ciota;
+  int64_t nchunks = 0;
   rt::DevBuf<int32_t> perm;             // row -> concatenated user index (-1: padding)
   rt::DevBuf<double> pdt, pc, pa;       // per-problem dt, c, a
   rt::DevBuf<double> V, sa, f, rho, cv, m, e_prev, E_prev, Qe, QE, g;
@@ -73,6 +77,7 @@ struct rt_batch {
   hipStream_t cap = nullptr;            // stream the graphs are captured on
   hipGraphExec_t graph[2] = {nullptr, nullptr};   // [FP64, FP32] PCG iterations
   int graph_k[2] = {0, 0};
+  bool graph_amg[2] = {false, false};              // the iterations captured are V-cycle ones
   ~rt_batch() {
     for (auto& gx : graph)
       if (gx) (void)hipGraphExecDestroy(gx);
@@ -175,6 +180,21 @@ template <typename T>
 __global__ void k_bh_fill(int64_t n, T* __restrict__ p, T v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+__global__ void k_b_iota(int64_t n, int32_t* __restrict__ p) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+// chunk c is skipped when every problem from crng[2c] to crng[2c + 1] stopped
+__global__ void k_b_chunk_done(int64_t nch, const int32_t* __restrict__ crng,
+                               const int32_t* __restrict__ done, int32_t* __restrict__ cdone) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  int all = 1;
+  for (int p = crng[2 * c]; p <= crng[2 * c + 1] && all; ++p) all = done[p] != 0;
+  cdone[c] = all;
 }
 
 __global__ void k_b_fill_i32(int64_t n, int32_t* __restrict__ p, int32_t v) {
@@ -501,6 +521,15 @@ struct BSel<float> {
   static constexpr int slot = 1;
 };
 
+// the coarse-level chunk flags from the problems' inner flags
+static int b_chunk_flags(hipStream_t st, rt_batch* B) {
+  if (B->nchunks == 0) return RT_OK;
+  hipLaunchKernelGGL(k_b_chunk_done, dim3(grid_for(B->nchunks)), dim3(kBlock), 0, st, B->nchunks,
+                     B->crng.p, B->flags.p + F_INNER * B->nprob, B->cdone.p);
+  RT_LAUNCH_CHECK();
+  return RT_OK;
+}
+
 // one PCG iteration for every problem not flagged done (kernels only); amg:
 // preconditioned by the V-cycle of the batch hierarchy (on the context's
 // stream, which st must then be)
@@ -524,6 +553,7 @@ int b_iteration(rt_ctx* ctx, hipStream_t st, rt_batch* B, T* x, T* r, bool amg =
                      B->partA.p, B->partB.p);
   RT_LAUNCH_CHECK();
   if (amg) {
+    RT_CHECK(b_chunk_flags(st, B));
     RT_CHECK(vcycle<T>(ctx, B->H.get(), r, S::z(B)));
     hipLaunchKernelGGL((k_b_rz<T>), dim3(nt), dim3(kBlock), 0, st, B->n, B->tprob.p, done, r,
                        S::z(B), (T*)nullptr, B->partB.p);
@@ -541,8 +571,8 @@ int b_iteration(rt_ctx* ctx, hipStream_t st, rt_batch* B, T* x, T* r, bool amg =
 
 // PCG (Jacobi, or amg: the batch hierarchy's V-cycle) on every problem whose
 // inner flag is clear; on entry r = b - A x and the per-problem thresholds
-// are set.  graph_k > 0 replays graphs of graph_k Jacobi iterations between
-// host reads of the flags (V-cycle iterations are launched one by one).
+// are set.  graph_k > 0 replays graphs of graph_k iterations between host
+// reads of the flags.
 template <typename T>
 int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k, bool amg = false) {
   using S = BSel<T>;
@@ -550,7 +580,7 @@ int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k, bool am
   const Level& L = B->L;
   const int32_t* done = B->flags.p + F_INNER * B->nprob;
   if (amg) {
-    graph_k = 0;
+    RT_CHECK(b_chunk_flags(st, B));
     RT_CHECK(vcycle<T>(ctx, B->H.get(), r, S::z(B)));
     hipLaunchKernelGGL((k_b_rz<T>), dim3((unsigned)B->ntiles), dim3(kBlock), 0, st, B->n,
                        B->tprob.p, done, r, S::z(B), S::p(B), B->partB.p);
@@ -567,7 +597,7 @@ int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k, bool am
   while (!all && launched < max_it) {
     if (graph_k > 0 && launched + graph_k <= max_it) {
       const int slot = S::slot;
-      if (!B->graph[slot] || B->graph_k[slot] != graph_k) {
+      if (!B->graph[slot] || B->graph_k[slot] != graph_k || B->graph_amg[slot] != amg) {
         if (B->graph[slot]) {
           RT_CHECK_HIP(hipGraphExecDestroy(B->graph[slot]));
           B->graph[slot] = nullptr;
@@ -575,8 +605,14 @@ int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k, bool am
         if (!B->cap) RT_CHECK_HIP(hipStreamCreate(&B->cap));
         hipGraph_t g = nullptr;
         RT_CHECK_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+        // the V-cycle launches on the context's stream: the capture stream
+        // stands in for it while the iterations are recorded
+        hipStream_t own = ctx->stream;
+        ctx->stream = B->cap;
         int cs = RT_OK;
-        for (int k = 0; k < graph_k && cs == RT_OK; ++k) cs = b_iteration<T>(ctx, B->cap, B, x, r);
+        for (int k = 0; k < graph_k && cs == RT_OK; ++k)
+          cs = b_iteration<T>(ctx, B->cap, B, x, r, amg);
+        ctx->stream = own;
         const hipError_t ce = hipStreamEndCapture(B->cap, &g);
         if (cs != RT_OK) {
           if (g) (void)hipGraphDestroy(g);
@@ -587,6 +623,7 @@ int b_pcg(rt_ctx* ctx, rt_batch* B, T* x, T* r, int max_it, int graph_k, bool am
         (void)hipGraphDestroy(g);
         RT_CHECK_HIP(ie);
         B->graph_k[slot] = graph_k;
+        B->graph_amg[slot] = amg;
       }
       RT_CHECK_HIP(hipGraphLaunch(B->graph[slot], st));
       launched += graph_k;
@@ -803,6 +840,56 @@ int build_hierarchy(rt_ctx* ctx, rt_batch* B) {
   for (Level& L : H->levels) RT_CHECK(amg_level_vectors(L, fp32, 1));
   RT_CHECK(B->z64.reserve(B->n));
   if (fp32) RT_CHECK(B->z32.reserve(B->n));
+  // The V-cycle's products skip the rows of problems whose inner iteration
+  // has stopped: on the fine level by tile (one problem each), on a coarse
+  // level by 256-row chunk once every problem with rows in the chunk has
+  // stopped (k_b_chunk_done before each V-cycle).  Skipped rows of a level's
+  // residual and correction keep the last value written (zero before the
+  // first), and the levels, block-diagonal, carry them only into rows of the
+  // same stopped problems, which no update reads.
+  const int32_t* done = B->flags.p + F_INNER * np;
+  std::vector<int32_t> rng;
+  std::vector<int64_t> choff(D, 0);
+  int64_t maxch = 0;
+  for (int l = 1; l < D; ++l) {
+    const int64_t n = H->levels[l].n, nch = (n + kTileRows - 1) / kTileRows;
+    choff[l] = (int64_t)rng.size() / 2;
+    maxch = std::max(maxch, nch);
+    for (int64_t c = 0; c < nch; ++c) {
+      // problems owning the chunk's first and last rows (empty ones own none)
+      const int64_t a = c * kTileRows, z = std::min(n, a + kTileRows) - 1;
+      const auto& o = off[l];
+      rng.push_back((int32_t)(std::upper_bound(o.begin(), o.end(), a) - o.begin() - 1));
+      rng.push_back((int32_t)(std::upper_bound(o.begin(), o.end(), z) - o.begin() - 1));
+    }
+  }
+  B->nchunks = (int64_t)rng.size() / 2;
+  RT_CHECK(B->crng.reserve(std::max<size_t>(rng.size(), 2)));
+  RT_CHECK(B->cdone.reserve(std::max<int64_t>(B->nchunks, 1)));
+  RT_CHECK(B->ciota.reserve(std::max<int64_t>(maxch, 1)));
+  if (!rng.empty())
+    RT_CHECK_HIP(hipMemcpyAsync(B->crng.p, rng.data(), sizeof(int32_t) * rng.size(),
+                                hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_b_iota, dim3(grid_for(std::max<int64_t>(maxch, 1))), dim3(kBlock), 0, st,
+                     maxch, B->ciota.p);
+  hipLaunchKernelGGL(k_b_fill_i32, dim3(grid_for(std::max<int64_t>(B->nchunks, 1))), dim3(kBlock),
+                     0, st, B->nchunks, B->cdone.p, 0);
+  RT_LAUNCH_CHECK();
+  H->lvl_tprob.assign(D, B->ciota.p);
+  H->lvl_skip.assign(D, nullptr);
+  H->lvl_tprob[0] = B->tprob.p;
+  H->lvl_skip[0] = done;
+  for (int l = 1; l < D; ++l) H->lvl_skip[l] = B->cdone.p + choff[l];
+  for (int l = 0; l < D; ++l) {
+    Level& V = H->levels[l];
+    for (double* q : {V.r64.p, V.x64.p})
+      hipLaunchKernelGGL(k_bh_fill<double>, dim3(grid_for(V.n)), dim3(kBlock), 0, st, V.n, q, 0.0);
+    if (fp32)
+      for (float* q : {V.r32.p, V.x32.p})
+        hipLaunchKernelGGL(k_bh_fill<float>, dim3(grid_for(V.n)), dim3(kBlock), 0, st, V.n, q,
+                           0.0f);
+  }
+  RT_LAUNCH_CHECK();
   RT_CHECK_HIP(hipStreamSynchronize(st));
   return RT_OK;
 }

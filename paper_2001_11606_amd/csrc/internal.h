@@ -333,6 +333,11 @@ struct rt_matrix {
   std::vector<rt::Level> levels;
   bool coarse_direct = false;        // coarsest level solved with a dense inverse
   int cycle_levels = 0;              // levels the V-cycle uses (0: all; set by the depth tuner)
+  // a batch's hierarchy, per level (else empty): the map from 256-row chunks
+  // to flag slots and the flags themselves, set for chunks whose rows all
+  // belong to problems whose iteration has stopped; the V-cycle's products
+  // leave those chunks as they are
+  std::vector<const int32_t*> lvl_tprob, lvl_skip;
   rt::DevBuf<double> coarse_inv;     // dense inverse of the coarsest operator (FP64)
   // Krylov work vectors (fine size)
   rt::DevBuf<double> r64, p64, q64, z64, xs, bs, ecur, Ecur, enew;

@@ -305,13 +305,19 @@ def check_batch_amg(ctx):
         bs.append(b)
         xref.append(linsolve.dense(sysm.A, b))
     bcat = np.concatenate(bs)
-    its = {}
-    for prec, precond, tol, bar in ((0, 1, 1e-14, 1e-12), (1, 1, 1e-12, 1e-10), (0, 0, 1e-14, 1e-12)):
+    its, sols = {}, {}
+    for prec, precond, tol, bar, graph in ((0, 1, 1e-14, 1e-12, 0), (1, 1, 1e-12, 1e-10, 0),
+                                           (0, 0, 1e-14, 1e-12, 0), (0, 1, 1e-14, 1e-12, 3),
+                                           (1, 1, 1e-12, 1e-10, 3)):
         x = np.zeros(offs[-1])
         s, st = rt.rt_batch_solve(ctx, B, len(probs), p(bcat), p(x),
-                                  rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50), 0)
+                                  rt.solve_opts(prec, precond, tol, 3000, 1e-4, 50), graph)
         assert s == 0, f"batch amg solve status {s}"
-        its[(prec, precond)] = [st[q].iterations for q in range(len(probs))]
+        its[(prec, precond, graph)] = [st[q].iterations for q in range(len(probs))]
+        sols[(prec, precond, graph)] = x.copy()
+        if graph:   # replayed V-cycle iterations: the same iterates as launched one by one
+            assert its[(prec, precond, graph)] == its[(prec, precond, 0)], its
+            assert np.array_equal(x, sols[(prec, precond, 0)]), f"graph {graph} prec {prec}"
         for q in range(len(probs)):
             xq = x[offs[q]:offs[q + 1]]
             err = np.max(np.abs(xq - xref[q])) / np.max(np.abs(xref[q]))
@@ -320,7 +326,7 @@ def check_batch_amg(ctx):
     E = np.concatenate([pr.E[:pr.n_interior] for pr in probs]).copy()
     nopts = rt.newton_opts(rt.solve_opts(0, 1, 1e-14, 3000))
     for ell in range(2):
-        s, st = rt.rt_batch_newton_step(ctx, B, len(probs), p(e), p(E), ell, nopts, 0)
+        s, st = rt.rt_batch_newton_step(ctx, B, len(probs), p(e), p(E), ell, nopts, 2 * ell)
         assert s == 0, f"batch amg newton status {s}"
     for q, pr in enumerate(probs):
         ref = ostep.time_step(pr.copy(), fixed_outer=2, solve_tol=1e-15)

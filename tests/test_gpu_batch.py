@@ -6,7 +6,8 @@ problem's solution must match its own oracle solve (FP64 to 1e-12, mixed to
 1e-10, max-norm relative) whatever the graph replay length, and a batched
 Newton step must match the oracle's time step per problem.  An ensemble of
 diffusive problems with their own aggregation hierarchies does the same with
-the batch's V-cycle (the problems' levels concatenated).
+the batch's V-cycle (the problems' levels concatenated), whose iterations
+replayed from graphs must give bitwise the iterates of eager launches.
 """
 import numpy as np
 import pytest
@@ -232,20 +233,23 @@ def test_batch_amg_solve_matches_oracle(ctx, ensemble_amg, precision, tol, bar):
     offs = _offsets(probs)
     bs, refs = _rhs(probs)
     b = torch.tensor(np.concatenate(bs), device=ctx.device)
-    its = {}
-    for precond in (1, 0):
+    its, sols = {}, {}
+    for precond, graph in ((1, 0), (0, 0), (1, 4)):
         x = torch.zeros_like(b)
         s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
-                                  rt.solve_opts(precision, precond, tol, 4000, 1e-4, 60), 0)
+                                  rt.solve_opts(precision, precond, tol, 4000, 1e-4, 60), graph)
         assert s == rt.RT_OK, rt.rt_last_error()
-        its[precond] = [st[q].iterations for q in range(len(probs))]
-        xh = x.cpu().numpy()
+        its[(precond, graph)] = [st[q].iterations for q in range(len(probs))]
+        xh = sols[(precond, graph)] = x.cpu().numpy()
         for q in range(len(probs)):
             err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
-            assert err <= bar, (precond, q, err)
-    say(f"[batch amg] precision={precision} levels {levels}: iterations V-cycle {its[1]}, "
-        f"Jacobi {its[0]}")
-    assert sum(its[1]) < sum(its[0])
+            assert err <= bar, (precond, graph, q, err)
+    say(f"[batch amg] precision={precision} levels {levels}: iterations V-cycle {its[(1, 0)]}, "
+        f"Jacobi {its[(0, 0)]}")
+    assert sum(its[(1, 0)]) < sum(its[(0, 0)])
+    # V-cycle iterations replayed from graphs: the same iterates as launched one by one
+    assert its[(1, 4)] == its[(1, 0)]
+    assert np.array_equal(sols[(1, 4)], sols[(1, 0)])
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -260,7 +264,7 @@ def test_batch_amg_newton_matches_oracle(ctx, ensemble_amg, precision):
     nopts = rt.newton_opts(rt.solve_opts(precision, 1, tol, 4000, 1e-4, 50))
     for ell in range(3):
         s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), ell,
-                                        nopts, 4)
+                                        nopts, 4 * (ell % 2))
         assert s == rt.RT_OK, rt.rt_last_error()
     eh, Eh = e.cpu().numpy(), E.cpu().numpy()
     bar = 1e-12 if precision == 0 else 1e-10
