@@ -626,10 +626,13 @@ __global__ void k_coarse_solve(int64_t n, const double* __restrict__ M, const T*
   if (lane == 0) x[i] = (T)s;
 }
 
+// The vector passes below take one row per thread; stop (else NULL) holds
+// the flag of the block's 256-row chunk at tp[block] (tp NULL: one flag).
 template <typename T>
 __global__ void k_scale(int64_t n, const T* __restrict__ s, const T* __restrict__ b,
-                        T* __restrict__ x, const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
+                        T* __restrict__ x, const int32_t* __restrict__ tp,
+                        const int32_t* __restrict__ stop) {
+  if (stop && stop[tp ? tp[blockIdx.x] : 0]) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[i] = s[i] * b[i];
 }
@@ -638,8 +641,9 @@ __global__ void k_scale(int64_t n, const T* __restrict__ s, const T* __restrict_
 template <typename T>
 __global__ void k_restrict(int64_t nc, const int64_t* __restrict__ crange,
                            const int32_t* __restrict__ amem, const T* __restrict__ r,
-                           T* __restrict__ bc, const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
+                           T* __restrict__ bc, const int32_t* __restrict__ tp,
+                           const int32_t* __restrict__ stop) {
+  if (stop && stop[tp ? tp[blockIdx.x] : 0]) return;
   int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (I >= nc) return;
   T s = 0;
@@ -687,8 +691,9 @@ __global__ void k_axpy1(int64_t n, const T* __restrict__ y, T* __restrict__ x,
 // x += P xc (rows left out of the coarse space get nothing)
 template <typename T>
 __global__ void k_prolong(int64_t n, const int32_t* __restrict__ pmap, const T* __restrict__ xc,
-                          T* __restrict__ x, const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
+                          T* __restrict__ x, const int32_t* __restrict__ tp,
+                          const int32_t* __restrict__ stop) {
+  if (stop && stop[tp ? tp[blockIdx.x] : 0]) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) {
     const int32_t I = pmap[i];
@@ -1253,7 +1258,8 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
   Level& L = A->levels[l];
   const int64_t n = L.n;
   const size_t nl = cycle_depth(A);
-  // a batch's levels: the products skip the chunks of stopped problems
+  // a batch's levels: the products and vector passes skip the chunks of
+  // stopped problems
   const bool bskip = l < A->lvl_skip.size();
   const int32_t* tp = bskip ? A->lvl_tprob[l] : nullptr;
   const int32_t* sk = bskip ? A->lvl_skip[l] : stop;
@@ -1267,7 +1273,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
     // four l1-Jacobi sweeps from zero (a symmetric positive-definite operator)
     T* t = B::t(L);
     hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t,
-                       stop);
+                       tp, sk);
     RT_LAUNCH_CHECK();
     T* src = t;
     T* dst = out;
@@ -1284,6 +1290,9 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
     return RT_OK;
   }
   Level& C = A->levels[l + 1];
+  const bool cskip = l + 1 < A->lvl_skip.size();
+  const int32_t* tpc = cskip ? A->lvl_tprob[l + 1] : nullptr;
+  const int32_t* skc = cskip ? A->lvl_skip[l + 1] : stop;
   T* t = B::t(L);
   T* r = B::r(L);
   const bool cheb = A->amg.smoother == RT_SMOOTHER_CHEBYSHEV;
@@ -1291,7 +1300,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
     RT_CHECK(cheb_smooth<T>(st, A, L, A->amg.smoother_degree, b, nullptr, t, stop));
   } else {
     hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, B::sinv(L), b, t,
-                       stop);
+                       tp, sk);
     RT_LAUNCH_CHECK();
   }
   RT_CHECK((launch_spmv_level<T, SP_RESID>(st, L, B::val(L), B::diag(L), t, b, nullptr, r,
@@ -1302,7 +1311,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
                        L.pt_rp.p, L.pt_row.p, B::ptv(L), r, B::b(C), stop);
   else
     hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, st, C.n, L.crange.p,
-                       L.amem.p, r, B::b(C), stop);
+                       L.amem.p, r, B::b(C), tpc, skc);
   RT_LAUNCH_CHECK();
   if (A->amg.cycle == 3 && l + 2 < nl)
     RT_CHECK(kcycle_correct<T>(ctx, A, l + 1, stop));
@@ -1323,7 +1332,7 @@ static int vcycle_level(rt_ctx* ctx, rt_matrix* A, size_t l, const T* b, T* out,
                        L.p_col.p, B::pv(L), B::x(C), t, stop);
   else
     hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, n, L.pmap.p,
-                       B::x(C), t, stop);
+                       B::x(C), t, tp, sk);
   RT_LAUNCH_CHECK();
   if (cheb) return cheb_smooth<T>(st, A, L, A->amg.smoother_degree, b, t, out, stop);
   RT_CHECK((launch_spmv_level<T, SP_SMOOTH>(st, L, B::val(L), B::diag(L), t, b, B::sinv(L), out,

@@ -840,11 +840,11 @@ int build_hierarchy(rt_ctx* ctx, rt_batch* B) {
   for (Level& L : H->levels) RT_CHECK(amg_level_vectors(L, fp32, 1));
   RT_CHECK(B->z64.reserve(B->n));
   if (fp32) RT_CHECK(B->z32.reserve(B->n));
-  // The V-cycle's products skip the rows of problems whose inner iteration
-  // has stopped: on the fine level by tile (one problem each), on a coarse
-  // level by 256-row chunk once every problem with rows in the chunk has
-  // stopped (k_b_chunk_done before each V-cycle).  Skipped rows of a level's
-  // residual and correction keep the last value written (zero before the
+  // The V-cycle's products and vector passes skip the rows of problems whose
+  // inner iteration has stopped: on the fine level by tile (one problem
+  // each), on a coarse level by 256-row chunk once every problem with rows
+  // in the chunk has stopped (k_b_chunk_done before each V-cycle).  Skipped
+  // rows of a level's vectors keep the last value written (zero before the
   // first), and the levels, block-diagonal, carry them only into rows of the
   // same stopped problems, which no update reads.
   const int32_t* done = B->flags.p + F_INNER * np;
@@ -882,10 +882,10 @@ int build_hierarchy(rt_ctx* ctx, rt_batch* B) {
   for (int l = 1; l < D; ++l) H->lvl_skip[l] = B->cdone.p + choff[l];
   for (int l = 0; l < D; ++l) {
     Level& V = H->levels[l];
-    for (double* q : {V.r64.p, V.x64.p})
+    for (double* q : {V.r64.p, V.x64.p, V.t64.p, V.b64.p})
       hipLaunchKernelGGL(k_bh_fill<double>, dim3(grid_for(V.n)), dim3(kBlock), 0, st, V.n, q, 0.0);
     if (fp32)
-      for (float* q : {V.r32.p, V.x32.p})
+      for (float* q : {V.r32.p, V.x32.p, V.t32.p, V.b32.p})
         hipLaunchKernelGGL(k_bh_fill<float>, dim3(grid_for(V.n)), dim3(kBlock), 0, st, V.n, q,
                            0.0f);
   }
