@@ -35,6 +35,7 @@ constexpr int kHashBits = 12;
 constexpr int kHash = 1 << kHashBits;   // slots; > kTileMaxCols + kBlock, so never full
 static_assert(kHash >= kTileMaxCols + kBlock, "hash set must have room for in-flight inserts");
 static_assert(kTileRows == kBlock, "one tile per block, one row per thread");
+static_assert(kTileMaxCols <= 65536, "positions in a tile's list are 16-bit");
 
 constexpr int kBucket = 16;                   // slots per bucket = columns per block
 constexpr int kBuckets = kHash / kBucket;
@@ -116,7 +117,7 @@ k_tile_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict
             int* __restrict__ flag) {
   constexpr int PER = kHash / kBlock;   // consecutive slots per thread
   __shared__ int keys[kHash];
-  __shared__ int pos[kHash];
+  __shared__ uint16_t pos[kHash];   // positions < kTileMaxCols: 16 bits, so six blocks fit a CU
   __shared__ int wsum[kBlock / kWave];
   __shared__ int count, overflow;
   for (int s = threadIdx.x; s < kHash; s += kBlock) keys[s] = -1;
