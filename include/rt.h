@@ -521,7 +521,10 @@ int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
  * on.  precond 0: Jacobi.  precond 1: the V-cycle of the batch's hierarchy,
  * which concatenates the problems' own aggregation hierarchies level by
  * level (built by rt_batch_create when the matrices have more than one level
- * and piecewise-constant prolongations; else precond 1 is Jacobi).  It is one
+ * and piecewise-constant prolongations; else precond 1 is Jacobi).  Each
+ * problem contributes the levels of its own V-cycle depth at the time of
+ * rt_batch_create (all, unless rt_matrix_set_cycle_depth or
+ * rt_matrix_tune_depth set it on its matrix).  It is one
  * block-diagonal V-cycle: every problem's own levels, smoother and
  * aggregates; the last level of each problem is smoothed (l1-Jacobi, three
  * sweeps on the batch's last level) rather than solved directly.

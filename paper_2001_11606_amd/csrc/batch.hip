@@ -714,9 +714,11 @@ int build_hierarchy(rt_ctx* ctx, rt_batch* B) {
   rt_matrix* H = B->H.get();
   H->n = B->n;
   H->has_fp32 = B->fp32;
+  // each problem contributes the levels its own V-cycle uses (its depth, as
+  // set or tuned on its matrix), and is smoothed on the last of them
   int D = 1;
   for (rt_matrix* A : B->mats) {
-    const int la = std::min<int>((int)A->levels.size(), RT_MAX_LEVELS);
+    const int la = std::min<int>((int)cycle_depth(A), RT_MAX_LEVELS);
     for (int l = 0; l + 1 < la; ++l)
       if (A->levels[l].smoothed) return RT_OK;
     D = std::max(D, la);
@@ -726,7 +728,7 @@ int build_hierarchy(rt_ctx* ctx, rt_batch* B) {
   H->coarse_direct = false;
   if (D == 1) return RT_OK;
   const bool fp32 = B->fp32;
-  auto has = [&](int p, int l) { return (int)B->mats[p]->levels.size() > l; };
+  auto has = [&](int p, int l) { return (int)cycle_depth(B->mats[p]) > l; };
   // row and entry offsets per level (level 0: the padded fine rows)
   std::vector<std::vector<int64_t>> off(D, std::vector<int64_t>(np + 1, 0)),
       eoff(D, std::vector<int64_t>(np + 1, 0));

@@ -334,6 +334,18 @@ def check_batch_amg(ctx):
         eE = np.max(np.abs(E[offs[q]:offs[q + 1]] - ref.E) / ref.E)
         assert ee <= 1e-12 and eE <= 1e-12, f"batch amg newton problem {q}: {ee} {eE}"
     rt.rt_batch_free(B)
+    # each problem with its own V-cycle depth (0: every level)
+    for c, d in zip(cases, (1, 0, 2)):
+        rt.rt_matrix_set_cycle_depth(c.A, d)
+    B = rt.rt_batch_create(ctx, [c.A for c in cases])
+    x = np.zeros(offs[-1])
+    s, st = rt.rt_batch_solve(ctx, B, len(probs), p(bcat), p(x),
+                              rt.solve_opts(0, 1, 1e-14, 3000, 1e-4, 50), 0)
+    assert s == 0, f"batch amg depth solve status {s}"
+    for q in range(len(probs)):
+        err = np.max(np.abs(x[offs[q]:offs[q + 1]] - xref[q])) / np.max(np.abs(xref[q]))
+        assert err <= 1e-12, f"batch amg depth problem {q}: {err}"
+    rt.rt_batch_free(B)
     for c in cases:
         c.free()
     say(f"ok batch amg: levels {levels}, iterations {its}")

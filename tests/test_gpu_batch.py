@@ -281,3 +281,53 @@ def test_batch_amg_tune(ctx, ensemble_amg):
     rep = rt.rt_batch_tune(ctx.handle, B, 2)
     assert rep.levels == max(levels)
     assert all(0 <= rep.chosen[l][0] < rep.shapes for l in range(rep.levels))
+
+
+def test_batch_amg_depth_per_problem(ctx, ensemble_amg):
+    """Each problem enters the batch's hierarchy with its own V-cycle depth
+    (set on its matrix): the batch has as many levels as the deepest, every
+    problem still matches the oracle, and with every depth 1 the batch has no
+    hierarchy (precond 1 is Jacobi)."""
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, _, levels = ensemble_amg
+    mats = [A for (_, _, A) in systems]
+    depths = [1, 2, 0, 3, 2]   # 0: every level
+    offs = _offsets(probs)
+    bs, refs = _rhs(probs)
+    b = torch.tensor(np.concatenate(bs), device=ctx.device)
+    try:
+        for A, d in zip(mats, depths):
+            rt.rt_matrix_set_cycle_depth(A, d)
+        B = rt.rt_batch_create(ctx.handle, mats)
+        try:
+            used = [levels[q] if d == 0 else min(d, levels[q]) for q, d in enumerate(depths)]
+            assert rt.rt_batch_tune(ctx.handle, B, 1).levels == max(used)
+            its = {}
+            for precond in (1, 0):
+                x = torch.zeros_like(b)
+                s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                          rt.solve_opts(0, precond, 1e-14, 4000, 1e-4, 60), 0)
+                assert s == rt.RT_OK, rt.rt_last_error()
+                its[precond] = [st[q].iterations for q in range(len(probs))]
+                xh = x.cpu().numpy()
+                for q in range(len(probs)):
+                    err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
+                    assert err <= 1e-12, (precond, q, err)
+            say(f"[batch depth] depths {used}: iterations V-cycle {its[1]}, Jacobi {its[0]}")
+            # a problem of depth 1 takes two l1-Jacobi sweeps per application,
+            # the deeper ones their coarse corrections: none more than Jacobi
+            assert all(a <= j for a, j in zip(its[1], its[0]))
+            assert sum(its[1]) < sum(its[0])
+        finally:
+            rt.rt_batch_free(B)
+        for A in mats:
+            rt.rt_matrix_set_cycle_depth(A, 1)
+        B1 = rt.rt_batch_create(ctx.handle, mats)
+        try:
+            assert rt.rt_batch_tune(ctx.handle, B1, 1).levels == 1
+        finally:
+            rt.rt_batch_free(B1)
+    finally:
+        for A in mats:
+            rt.rt_matrix_set_cycle_depth(A, 0)
