@@ -334,6 +334,18 @@ def check_batch_amg(ctx):
         eE = np.max(np.abs(E[offs[q]:offs[q + 1]] - ref.E) / ref.E)
         assert ee <= 1e-12 and eE <= 1e-12, f"batch amg newton problem {q}: {ee} {eE}"
     rt.rt_batch_free(B)
+    # a problem with b = 0 stops before the first V-cycle: exactly zero
+    bz = bcat.copy()
+    bz[offs[1]:offs[2]] = 0.0
+    x = np.zeros(offs[-1])
+    s, st = rt.rt_batch_solve(ctx, B2 := rt.rt_batch_create(ctx, [c.A for c in cases]),
+                              len(probs), p(bz), p(x), rt.solve_opts(0, 1, 1e-14, 3000, 1e-4, 50), 2)
+    assert s == 0 and st[1].iterations == 0, f"batch amg zero rhs: {s}"
+    assert not np.any(x[offs[1]:offs[2]]), "batch amg zero rhs: nonzero solution"
+    for q in (0, 2):
+        err = np.max(np.abs(x[offs[q]:offs[q + 1]] - xref[q])) / np.max(np.abs(xref[q]))
+        assert err <= 1e-12, f"batch amg zero rhs problem {q}: {err}"
+    rt.rt_batch_free(B2)
     # each problem with its own V-cycle depth (0: every level)
     for c, d in zip(cases, (1, 0, 2)):
         rt.rt_matrix_set_cycle_depth(c.A, d)

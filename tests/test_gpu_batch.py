@@ -331,3 +331,31 @@ def test_batch_amg_depth_per_problem(ctx, ensemble_amg):
     finally:
         for A in mats:
             rt.rt_matrix_set_cycle_depth(A, 0)
+
+
+@pytest.mark.parametrize("graph", [0, 4])
+def test_batch_amg_zero_rhs_problem(ctx, ensemble_amg, graph):
+    """A problem with b = 0 has stopped before the first V-cycle (the skipped
+    rows of its levels are never written in the solve): its solution is
+    exactly zero, and the other problems still match the oracle."""
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, B, levels = ensemble_amg
+    offs = _offsets(probs)
+    bs, refs = _rhs(probs)
+    zero = 2
+    bs[zero] = np.zeros_like(bs[zero])
+    b = torch.tensor(np.concatenate(bs), device=ctx.device)
+    for precision, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
+        x = torch.zeros_like(b)
+        s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                  rt.solve_opts(precision, 1, tol, 4000, 1e-4, 60), graph)
+        assert s == rt.RT_OK, rt.rt_last_error()
+        xh = x.cpu().numpy()
+        assert st[zero].iterations == 0
+        assert not np.any(xh[offs[zero]:offs[zero + 1]])
+        for q in range(len(probs)):
+            if q == zero:
+                continue
+            err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
+            assert err <= bar, (precision, q, err)
