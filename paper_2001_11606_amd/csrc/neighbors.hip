@@ -259,6 +259,7 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
             int64_t* __restrict__ cnt, const int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
             int32_t* __restrict__ n_int_nbrs, uint64_t* __restrict__ masks, int mstride) {
   constexpr int NB = DIM == 3 ? 27 : 9;   // adjacent cells per flag
+  // candidates' positions and squared support radii (kappa h)^2
   __shared__ double cx[kNbrCand], cy[kNbrCand], cz[kNbrCand], ch[kNbrCand];
   __shared__ int32_t ct[kNbrCand];
   __shared__ int32_t rlo[2 * NB], roff[2 * NB + 1];
@@ -320,7 +321,8 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           cx[k] = q.x;
           cy[k] = q.y;
           cz[k] = q.z;
-          ch[k] = q.h;
+          const double kq = kappa * q.h;
+          ch[k] = kq * kq;
         }
       }
       __syncthreads();
@@ -347,7 +349,8 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           if (g >= ngroups) break;
           const int k = w * kWave + lane;
           // The pair test r^2 < (kappa max(h_i, h_j))^2 as max((kappa h_i)^2,
-          // (kappa h_j)^2): rounding is monotone, so both give the same bits.
+          // (kappa h_j)^2): rounding is monotone, so both give the same bits;
+          // each squared radius is formed once, when its particle is staged.
           // An empty lane has NaN coordinates: its r^2 never tests true.
           int32_t t = -1;
           double qx = __builtin_nan(""), qy = qx, qz = qx, tq = 0.0;
@@ -356,8 +359,7 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
             qx = cx[k];
             qy = cy[k];
             qz = cz[k];
-            const double kq = kappa * ch[k];
-            tq = kq * kq;
+            tq = ch[k];
           }
           const int ra = g * kCountRows;
           const int nr = RT_UNIFORM(nrows - ra < kCountRows ? nrows - ra : kCountRows);
@@ -367,20 +369,20 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           unsigned long long mine = 0ull;   // lane r keeps the mask word of row ra + r
           for (int r = 0; r < nr; ++r) {
             const int32_t s = s0 + r;
-            double xi, yi, zi, hi;
+            double xi, yi, zi, ti;
             if (staged) {
               xi = cx[ks0 + r];
               yi = cy[ks0 + r];
               zi = cz[ks0 + r];
-              hi = ch[ks0 + r];
+              ti = ch[ks0 + r];
             } else {
               const Rec4 q = load_rec4(sp4, s);
               xi = q.x;
               yi = q.y;
               zi = q.z;
-              hi = q.h;
+              const double ki = kappa * q.h;
+              ti = ki * ki;
             }
-            const double ki = kappa * hi;
             double d = axis_disp<PER>(xi - qx, box, 0);
             double r2 = d * d;
             d = axis_disp<PER>(yi - qy, box, 1);
@@ -389,7 +391,7 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
               d = axis_disp<PER>(zi - qz, box, 2);
               r2 = r2 + d * d;
             }
-            const double th2 = fmax(ki * ki, tq);
+            const double th2 = fmax(ti, tq);
             const bool hit = (t != s) & (r2 < th2);
             const unsigned long long bm = __ballot(hit);
             if (lane == r) mine = bm;
@@ -404,20 +406,21 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
       for (int r = wave; r < nrows; r += kBlock / kWave) {
         const int64_t s = rb + r;
         const int ks = roff[cslot] + (int)(s - rlo[cslot]) - c0;
-        double xi = 0.0, yi = 0.0, zi = 0.0, hi = 0.0;
+        double xi = 0.0, yi = 0.0, zi = 0.0, ti = 0.0;
         if (FROM_MASK) {
           // positions are not needed
         } else if (ks >= 0 && ks < mc) {
           xi = cx[ks];
           yi = cy[ks];
           zi = cz[ks];
-          hi = ch[ks];
+          ti = ch[ks];
         } else {
           const Rec4 q = load_rec4(sp4, s);
           xi = q.x;
           yi = q.y;
           zi = q.z;
-          hi = q.h;
+          const double ki = kappa * q.h;
+          ti = ki * ki;
         }
         int found = 0, fint = 0;
         int64_t out = FILL ? ptr[s] + rcount[r] : 0;
@@ -441,8 +444,7 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
                 d = axis_disp<PER>(zi - cz[k], box, 2);
                 r2 = r2 + d * d;
               }
-              const double th = kappa * fmax(hi, ch[k]);
-              hit = r2 < th * th;
+              hit = r2 < fmax(ti, ch[k]);   // the count pass's test, bit for bit
             }
           }
           const unsigned long long bm = __ballot(hit);
