@@ -352,10 +352,8 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
           // (kappa h_j)^2): rounding is monotone, so both give the same bits;
           // each squared radius is formed once, when its particle is staged.
           // An empty lane has NaN coordinates: its r^2 never tests true.
-          int32_t t = -1;
           double qx = __builtin_nan(""), qy = qx, qz = qx, tq = 0.0;
           if (k < mc) {
-            t = ct[k];
             qx = cx[k];
             qy = cy[k];
             qz = cz[k];
@@ -392,8 +390,11 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
               r2 = r2 + d * d;
             }
             const double th2 = fmax(ti, tq);
-            const bool hit = (t != s) & (r2 < th2);
-            const unsigned long long bm = __ballot(hit);
+            unsigned long long bm = __ballot(r2 < th2);
+            // the row itself is candidate ks0 + r of the chunk (its own cell's
+            // slot): its bit is cleared here rather than tested in every lane
+            const int kself = RT_UNIFORM(ks0 + r - w * kWave);
+            if (kself >= 0 && kself < kWave) bm &= ~(1ull << kself);
             if (lane == r) mine = bm;
           }
           if (lane < nr) {
