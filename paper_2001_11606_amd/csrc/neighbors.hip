@@ -479,9 +479,15 @@ k_nbr_cells(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, 
 // word of one row (kMaskWords lanes per row, 64 / kMaskWords rows per wave at a
 // time), so the work follows the hits, not the candidates.
 constexpr int kMaskWords = kNbrCand / kWave;   // mask words per staged chunk (8)
+#ifndef RT_FILL_BLOCK
+#define RT_FILL_BLOCK 128
+#endif
+// threads per block of the fill pass: a cell holds about 15 rows in 3-D, 8 rows
+// per wave step, so two waves are all a block's rows keep busy
+constexpr int kFillBlock = RT_FILL_BLOCK;
 
 template <int DIM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFillBlock)
 k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int nc1, int nc2,
                  PeriodicBox box, const int32_t* __restrict__ runs, const uint64_t* __restrict__ runkey,
                  const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend,
@@ -528,14 +534,14 @@ k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int 
   const int rr = lane / kMaskWords, q = lane % kMaskWords;
   for (int64_t rb = r0; rb < r1; rb += kNbrRows) {
     const int nrows = (int)(r1 - rb < kNbrRows ? r1 - rb : kNbrRows);
-    for (int r = tid; r < nrows; r += kBlock) {
+    for (int r = tid; r < nrows; r += kFillBlock) {
       rcount[r] = 0;
       rint[r] = 0;
     }
     for (int c0 = 0; c0 < m; c0 += kNbrCand) {
       const int mc = m - c0 < kNbrCand ? m - c0 : kNbrCand;
       __syncthreads();
-      for (int k = tid; k < mc; k += kBlock) {
+      for (int k = tid; k < mc; k += kFillBlock) {
         const int kk = c0 + k;
         int lo = 0, hi = 2 * NB;
         while (hi - lo > 1) {
@@ -547,7 +553,7 @@ k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int 
       }
       __syncthreads();
       const int words = (mc + kWave - 1) / kWave;
-      for (int base = wave * RPW; base < nrows; base += (kBlock / kWave) * RPW) {
+      for (int base = wave * RPW; base < nrows; base += (kFillBlock / kWave) * RPW) {
         const int r = base + rr;
         const bool live = r < nrows && q < words;
         const int64_t s = rb + r;
@@ -581,7 +587,7 @@ k_nbr_fill_masks(int64_t n, int64_t nin, int bits, int64_t ncells, int nc0, int 
       }
     }
     __syncthreads();
-    for (int r = tid; r < nrows; r += kBlock) n_int_nbrs[rb + r] = rint[r];
+    for (int r = tid; r < nrows; r += kFillBlock) n_int_nbrs[rb + r] = rint[r];
     __syncthreads();
   }
 }
@@ -835,7 +841,7 @@ int build_neighbors(rt_ctx* ctx, int dim, int64_t n, int64_t nin, const double* 
   RT_CHECK(nb->idx.reserve((size_t)npairs));
   if (use_masks) {
 #define RT_FILLM(D_)                                                                             \
-  hipLaunchKernelGGL((k_nbr_fill_masks<D_>), dim3(nruns), dim3(kBlock), 0, st, n, nin, bits, ncells, \
+  hipLaunchKernelGGL((k_nbr_fill_masks<D_>), dim3(nruns), dim3(kFillBlock), 0, st, n, nin, bits, ncells, \
                      nb->nc[0], nb->nc[1], nb->nc[2], box, runs.p, runkey.p, cstart.p, cend.p,    \
                      nb->ptr.p, nb->idx.p, nb->n_int_nbrs.p, masks.p, mstride)
     if (dim == 3) RT_FILLM(3);
