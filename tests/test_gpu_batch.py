@@ -359,3 +359,49 @@ def test_batch_amg_zero_rhs_problem(ctx, ensemble_amg, graph):
                 continue
             err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
             assert err <= bar, (precision, q, err)
+
+
+def test_full_ensemble_vcycle_sampled_against_oracle(ctx):
+    """The full 96-problem ensemble of the bench, each problem assembled with
+    its own aggregation hierarchy (1 to 7 levels, 2-D and 3-D mixed): one
+    batched mixed Newton step with the batch's V-cycle meets the tolerance
+    for every problem, and the three smallest problems match the oracle's
+    step to the mixed bar."""
+    import torch
+    from paper_2001_11606_amd import driver, rt
+    probs = synth.config5(96)
+    amg = rt.amg_opts(build_fp32=1)
+    handles = []
+    for pr in probs:
+        dp = driver.upload(pr, ctx.device)
+        nb = ctx.build_neighbors(dp.pos, dp.h, dp.n_interior, dp.kernel)
+        A = ctx.assemble(nb, dp.arrays, dp.dt, dp.c, dp.a, dp.opacity_exponent, dp.limiter,
+                         dp.limiter_k, amg=amg)
+        handles.append((nb, A))
+    levels = [ctx.matrix_info(A).levels for _, A in handles]
+    B = rt.rt_batch_create(ctx.handle, [A for _, A in handles])
+    try:
+        say(f"[full ensemble V-cycle] levels {min(levels)}..{max(levels)}")
+        assert max(levels) >= 3
+        offs = _offsets(probs)
+        e = torch.tensor(np.concatenate([pr.e[:pr.n_interior] for pr in probs]), device=ctx.device)
+        E = torch.tensor(np.concatenate([pr.E[:pr.n_interior] for pr in probs]), device=ctx.device)
+        tol = 1e-12
+        nopts = rt.newton_opts(rt.solve_opts(rt.RT_PREC_MIXED, 1, tol, 5000, 1e-4, 50))
+        s, st = rt.rt_batch_newton_step(ctx.handle, B, len(probs), e.data_ptr(), E.data_ptr(), 0,
+                                        nopts, 0)
+        assert s == rt.RT_OK, rt.rt_last_error()
+        assert all(st[q].solve.rel_residual <= tol for q in range(len(probs)))
+        eh, Eh = e.cpu().numpy(), E.cpu().numpy()
+        smallest = sorted(range(len(probs)), key=lambda q: probs[q].n_interior)[:3]
+        for q in smallest:
+            ref = ostep.time_step(probs[q].copy(), fixed_outer=1, inner_tol_e=1e-14,
+                                  solve_tol=1e-15)
+            err_e = np.max(np.abs(eh[offs[q]:offs[q + 1]] - ref.e) / np.abs(ref.e))
+            err_E = np.max(np.abs(Eh[offs[q]:offs[q + 1]] - ref.E) / np.abs(ref.E))
+            say(f"[full ensemble V-cycle] problem {q} ({probs[q].n_interior} particles, "
+                f"{levels[q]} levels): e {err_e:.1e} E {err_E:.1e}")
+            assert err_e <= 1e-10 and err_E <= 1e-10, (q, err_e, err_E)
+    finally:
+        rt.rt_batch_free(B)
+        ctx.free(*[h for nb, A in handles for h in (A, nb)])
