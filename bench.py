@@ -222,8 +222,9 @@ def ensemble_vcycle_leg(ctx, dps, ntot, args):
     """The batched V-cycle on the ensemble: every problem assembled with its
     own aggregation hierarchy, the batch concatenating them level by level;
     mixed solves of b = 1 with the V-cycle (iterations launched one by one,
-    and replayed from graphs) against Jacobi (graphs) on that batch, outside
-    the timed steps."""
+    and replayed from graphs) against Jacobi (graphs) on that batch, and
+    with the V-cycle on a batch whose problems each take the depth the
+    depth tuner chose on their own solve; outside the timed steps."""
     import torch
     from paper_2001_11606_amd import rt
     amg = rt.amg_opts(build_fp32=1)
@@ -234,34 +235,48 @@ def ensemble_vcycle_leg(ctx, dps, ntot, args):
                          dp.limiter_k, amg=amg)
         built.append((nb, A))
     levels = [ctx.matrix_info(A).levels for _, A in built]
+    opts = rt.solve_opts(rt.RT_PREC_MIXED, 1, args.tol, 5000, args.inner_tol, 30)
     B = rt.rt_batch_create(ctx.handle, [A for _, A in built])
+    # each problem's depth tuned on its own solve of b = 1, then a second
+    # batch built from the tuned matrices
+    depths = []
+    for (nb, A), dp in zip(built, dps):
+        bq = torch.ones(dp.n_interior, dtype=torch.float64, device=ctx.device)
+        depths.append(ctx.tune_depth(A, bq, torch.zeros_like(bq), opts, 2).chosen)
+    BT = rt.rt_batch_create(ctx.handle, [A for _, A in built])
     ctx.free(*[h for nb, A in built for h in (A, nb)])
-    rep = rt.rt_batch_tune(ctx.handle, B, 3)
-    rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_FP64, rep.chosen[0][0])
-    rt.rt_batch_set_spmv_shape(B, rt.RT_PREC_MIXED, rep.chosen[0][1])
-    rt.rt_batch_set_spmv_shape(B, rt.RT_PRODUCT_RESIDUAL, rep.chosen[0][2])
+    for b_ in (B, BT):
+        rep = rt.rt_batch_tune(ctx.handle, b_, 3)
+        rt.rt_batch_set_spmv_shape(b_, rt.RT_PREC_FP64, rep.chosen[0][0])
+        rt.rt_batch_set_spmv_shape(b_, rt.RT_PREC_MIXED, rep.chosen[0][1])
+        rt.rt_batch_set_spmv_shape(b_, rt.RT_PRODUCT_RESIDUAL, rep.chosen[0][2])
     res = {}
-    runs = ((1, 0), (1, args.graph_iters), (0, args.graph_iters))
-    for precond, graph in runs + runs:   # the second round is timed
+    runs = ((B, 1, 0), (B, 1, args.graph_iters), (B, 0, args.graph_iters), (BT, 1, 0))
+    for b_, precond, graph in runs + runs:   # the second round is timed
         bt = torch.ones(ntot, dtype=torch.float64, device=ctx.device)
         xt = torch.zeros_like(bt)
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        s, sst = rt.rt_batch_solve(ctx.handle, B, len(dps), bt.data_ptr(), xt.data_ptr(),
+        s, sst = rt.rt_batch_solve(ctx.handle, b_, len(dps), bt.data_ptr(), xt.data_ptr(),
                                    rt.solve_opts(rt.RT_PREC_MIXED, precond, args.tol, 5000,
                                                  args.inner_tol, 30), graph)
         torch.cuda.synchronize()
         if s != rt.RT_OK:
             raise RuntimeError(f"ensemble V-cycle leg: status {s}")
-        res[(precond, graph)] = (time.perf_counter() - ta,
-                                 max(sst[q].iterations for q in range(len(dps))))
+        res[(b_, precond, graph)] = (time.perf_counter() - ta,
+                                     max(sst[q].iterations for q in range(len(dps))))
     rt.rt_batch_free(B)
-    v0, vg, jg = (res[k] for k in runs)
+    rt.rt_batch_free(BT)
+    v0, vg, jg, vt = (res[k] for k in runs)
+    hist = {d: depths.count(d) for d in sorted(set(depths))}
     return {"levels_min": min(levels), "levels_max": max(levels),
             "solve_s_vcycle": round(v0[0], 5), "solve_s_vcycle_graph": round(vg[0], 5),
             "solve_s_jacobi": round(jg[0], 5), "graph_iters": args.graph_iters,
+            "solve_s_vcycle_tuned_depths": round(vt[0], 5),
+            "tuned_depth_counts": {str(d): c for d, c in hist.items()},
             "krylov_max_vcycle": v0[1], "krylov_max_jacobi": jg[1],
-            "ratio_jacobi_over_vcycle": round(jg[0] / min(v0[0], vg[0]), 3)}
+            "krylov_max_vcycle_tuned_depths": vt[1],
+            "ratio_jacobi_over_vcycle": round(jg[0] / min(v0[0], vg[0], vt[0]), 3)}
 
 
 def run_ensemble(args):
