@@ -224,7 +224,8 @@ def ensemble_vcycle_leg(ctx, dps, ntot, args):
     mixed solves of b = 1 with the V-cycle (iterations launched one by one,
     and replayed from graphs) against Jacobi (graphs) on that batch, and
     with the V-cycle on a batch whose problems each take the depth the
-    depth tuner chose on their own solve; outside the timed steps."""
+    depth tuner chose on their own solve, and at the depth the batch's own
+    tuner keeps; outside the timed steps."""
     import torch
     from paper_2001_11606_amd import rt
     amg = rt.amg_opts(build_fp32=1)
@@ -265,6 +266,19 @@ def ensemble_vcycle_leg(ctx, dps, ntot, args):
             raise RuntimeError(f"ensemble V-cycle leg: status {s}")
         res[(b_, precond, graph)] = (time.perf_counter() - ta,
                                      max(sst[q].iterations for q in range(len(dps))))
+    # the depth timed inside the batch
+    bt = torch.ones(ntot, dtype=torch.float64, device=ctx.device)
+    rep = rt.rt_batch_tune_depth(ctx.handle, B, bt.data_ptr(), torch.zeros_like(bt).data_ptr(),
+                                 opts, 0, 1)
+    for k in range(2):   # the second run is timed
+        xt = torch.zeros_like(bt)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        s, sst = rt.rt_batch_solve(ctx.handle, B, len(dps), bt.data_ptr(), xt.data_ptr(), opts, 0)
+        torch.cuda.synchronize()
+        if s != rt.RT_OK:
+            raise RuntimeError(f"ensemble V-cycle leg: status {s}")
+    vb = (time.perf_counter() - ta, max(sst[q].iterations for q in range(len(dps))))
     rt.rt_batch_free(B)
     rt.rt_batch_free(BT)
     v0, vg, jg, vt = (res[k] for k in runs)
@@ -276,7 +290,10 @@ def ensemble_vcycle_leg(ctx, dps, ntot, args):
             "tuned_depth_counts": {str(d): c for d, c in hist.items()},
             "krylov_max_vcycle": v0[1], "krylov_max_jacobi": jg[1],
             "krylov_max_vcycle_tuned_depths": vt[1],
-            "ratio_jacobi_over_vcycle": round(jg[0] / min(v0[0], vg[0], vt[0]), 3)}
+            "batch_depth_ms": [round(1e3 * rep.seconds[d], 2) for d in range(rep.depths)],
+            "batch_depth_chosen": rep.chosen, "solve_s_vcycle_batch_depth": round(vb[0], 5),
+            "krylov_max_vcycle_batch_depth": vb[1],
+            "ratio_jacobi_over_vcycle": round(jg[0] / min(v0[0], vg[0], vt[0], vb[0]), 3)}
 
 
 def run_ensemble(args):

@@ -548,6 +548,22 @@ int rt_batch_tune(rt_ctx* ctx, rt_batch* B, int reps, rt_tune_report* rep);
 int rt_batch_set_spmv_shape(rt_batch* B, int precision, int shape);
 int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x,
                    const rt_solve_opts* opts, int graph_iters, rt_solve_stats* stats);
+/* The depth of the batch's V-cycle: how many levels of its hierarchy the
+ * cycle uses (1: Jacobi instead of the V-cycle; 0: all).  A depth shorter
+ * than the hierarchy smooths on its last level.  rt_batch_tune_depth runs
+ * rt_batch_solve with opts (precond must be 1) and graph_iters at every
+ * depth from 1 to the hierarchy's levels, once untimed and then reps times
+ * (b, x0: concatenated device vectors as for rt_batch_solve; x0 is not
+ * changed), and keeps the depth whose solve took the least wall time among
+ * those that converged.  *rep (may be NULL) receives every depth's mean
+ * time, the largest per-problem iteration count and the status.  The
+ * depth holds for later batched solves and Newton steps of B.  For callers
+ * whose ensemble is solved in batches: a depth timed inside the batch, not
+ * one tuned per problem on its own solve.                                  */
+int rt_batch_tune_depth(rt_ctx* ctx, rt_batch* B, const double* b, const double* x0,
+                        const rt_solve_opts* opts, int graph_iters, int reps,
+                        rt_depth_report* rep);
+int rt_batch_set_cycle_depth(rt_batch* B, int depth);
 /* One outer iteration of Algorithm 1 for every problem (ell == 0 first does
  * the initial material solve), as rt_newton_step per problem.              */
 int rt_batch_newton_step(rt_ctx* ctx, rt_batch* B, double* e, double* E, int ell,

@@ -16,6 +16,7 @@
 // iterations can be replayed as HIP graphs of K iterations with a single
 // host read of the flags per graph.  Preconditioner: Jacobi.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -642,8 +643,8 @@ int b_solve(rt_ctx* ctx, rt_batch* B, const rt_solve_opts* o, int graph_k, rt_so
   const int64_t n = B->n;
   const int np = B->nprob;
   const bool mixed = o->precision == RT_PREC_MIXED;
-  // the V-cycle when asked for and the batch has a hierarchy (else Jacobi)
-  const bool amg = o->precond == 1 && B->H->levels.size() > 1;
+  // the V-cycle when asked for and the batch's depth is above 1 (else Jacobi)
+  const bool amg = o->precond == 1 && cycle_depth(B->H.get()) > 1;
   const Level& L = B->L;
   hipLaunchKernelGGL(k_b_fill_i32, dim3(grid_for((int64_t)F_COUNT * np)), dim3(kBlock), 0, st,
                      (int64_t)F_COUNT * np, B->flags.p, 0);
@@ -1101,6 +1102,87 @@ int rt_batch_set_spmv_shape(rt_batch* B, int precision, int shape) {
     B->graph[slot] = nullptr;
   }
   return RT_OK;
+}
+
+int rt_batch_set_cycle_depth(rt_batch* B, int depth) {
+  rt::clear_error();
+  if (!B || depth < 0) {
+    rt::set_error("rt_batch_set_cycle_depth: NULL batch or negative depth");
+    return RT_E_ARG;
+  }
+  B->H->cycle_levels = depth;
+  for (auto& g : B->graph)   // graphs hold the launches of the previous depth
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  return RT_OK;
+}
+
+int rt_batch_tune_depth(rt_ctx* ctx, rt_batch* B, const double* b, const double* x0,
+                        const rt_solve_opts* opts, int graph_iters, int reps,
+                        rt_depth_report* rep) {
+  using namespace rt;
+  clear_error();
+  if (!ctx || !B || !opts || !b || !x0 || reps < 1) {
+    set_error("rt_batch_tune_depth: NULL argument or reps < 1");
+    return RT_E_ARG;
+  }
+  if (opts->precond != 1) {
+    set_error("rt_batch_tune_depth: the solve options must use the V-cycle (precond 1)");
+    return RT_E_ARG;
+  }
+  RT_CHECK_HIP(hipSetDevice(ctx->device));
+  rt_depth_report local{};
+  rt_depth_report* r = rep ? rep : &local;
+  *r = rt_depth_report{};
+  const int nl = std::min<int>((int)B->H->levels.size(), RT_MAX_LEVELS);
+  r->depths = nl;
+  r->chosen = nl;
+  if (nl <= 1 || B->nuser == 0) return RT_OK;
+  DevBuf<double> x;
+  {
+    rt::StreamScope scope(ctx->stream);
+    RT_CHECK(x.reserve(B->nuser));
+  }
+  std::vector<rt_solve_stats> st(B->nprob);
+  const int keep = B->H->cycle_levels;
+  double best = 0.0;
+  int arg = -1;
+  for (int d = 1; d <= nl; ++d) {
+    RT_CHECK(rt_batch_set_cycle_depth(B, d));
+    double total = 0.0;
+    int status = RT_OK, its = 0;
+    for (int k = 0; k <= reps; ++k) {   // the first run (graph capture) is not timed
+      RT_CHECK_HIP(hipMemcpyAsync(x.p, x0, sizeof(double) * B->nuser, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+      RT_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+      const auto t0 = std::chrono::steady_clock::now();
+      const int s = rt_batch_solve(ctx, B, b, x.p, opts, graph_iters, st.data());
+      RT_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+      const double sec =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (s < 0) {
+        (void)rt_batch_set_cycle_depth(B, keep);
+        return s;
+      }
+      if (k == 0) continue;
+      if (s == RT_NOT_CONVERGED) status = RT_NOT_CONVERGED;
+      total += sec;
+      its = 0;
+      for (const rt_solve_stats& q : st) its = std::max(its, q.iterations);
+    }
+    r->seconds[d - 1] = total / reps;
+    r->iterations[d - 1] = its;
+    r->status[d - 1] = status;
+    if (status == RT_OK && (arg < 0 || r->seconds[d - 1] < best)) {
+      best = r->seconds[d - 1];
+      arg = d;
+    }
+  }
+  clear_error();   // a depth that did not converge is only left out
+  r->chosen = arg > 0 ? arg : nl;
+  return rt_batch_set_cycle_depth(B, r->chosen == nl ? 0 : r->chosen);
 }
 
 int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x, const rt_solve_opts* opts,

@@ -168,6 +168,9 @@ _SIGS = {
     "rt_matrix_tune_depth": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts),
                                      c_int, ctypes.POINTER(rt_depth_report)]),
     "rt_matrix_set_cycle_depth": (c_int, [c_vp, c_int]),
+    "rt_batch_tune_depth": (c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(rt_solve_opts), c_int,
+                                    c_int, ctypes.POINTER(rt_depth_report)]),
+    "rt_batch_set_cycle_depth": (c_int, [c_vp, c_int]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -419,6 +422,18 @@ def rt_matrix_tune_depth(ctx: int, A: int, b: int, x0: int, opts: rt_solve_opts,
 
 def rt_matrix_set_cycle_depth(A: int, depth: int) -> None:
     _check("rt_matrix_set_cycle_depth", load().rt_matrix_set_cycle_depth(A, depth))
+
+
+def rt_batch_tune_depth(ctx: int, B: int, b: int, x0: int, opts: rt_solve_opts, graph_iters: int,
+                        reps: int) -> rt_depth_report:
+    rep = rt_depth_report()
+    _check("rt_batch_tune_depth", load().rt_batch_tune_depth(ctx, B, b, x0, ctypes.byref(opts),
+                                                             graph_iters, reps, ctypes.byref(rep)))
+    return rep
+
+
+def rt_batch_set_cycle_depth(B: int, depth: int) -> None:
+    _check("rt_batch_set_cycle_depth", load().rt_batch_set_cycle_depth(B, depth))
 
 
 def rt_newton_residual(ctx: int, A: int, e: int, E: int, state_order: int = 0) -> rt_be_residual:

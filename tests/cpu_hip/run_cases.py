@@ -346,6 +346,21 @@ def check_batch_amg(ctx):
         err = np.max(np.abs(x[offs[q]:offs[q + 1]] - xref[q])) / np.max(np.abs(xref[q]))
         assert err <= 1e-12, f"batch amg zero rhs problem {q}: {err}"
     rt.rt_batch_free(B2)
+    # the batch's own depth tuner: every depth timed, the chosen one solves
+    B3 = rt.rt_batch_create(ctx, [c.A for c in cases])
+    x0 = np.zeros(offs[-1])
+    rep = rt.rt_batch_tune_depth(ctx, B3, p(bcat), p(x0), rt.solve_opts(0, 1, 1e-14, 3000, 1e-4, 50),
+                                 2, 1)
+    assert 1 <= rep.chosen <= rep.depths == max(levels), f"batch depth tuner: {rep.chosen}"
+    assert not np.any(x0), "batch depth tuner changed x0"
+    x = np.zeros(offs[-1])
+    s, st = rt.rt_batch_solve(ctx, B3, len(probs), p(bcat), p(x),
+                              rt.solve_opts(0, 1, 1e-14, 3000, 1e-4, 50), 0)
+    assert s == 0, f"batch tuned depth solve status {s}"
+    for q in range(len(probs)):
+        err = np.max(np.abs(x[offs[q]:offs[q + 1]] - xref[q])) / np.max(np.abs(xref[q]))
+        assert err <= 1e-12, f"batch tuned depth problem {q}: {err}"
+    rt.rt_batch_free(B3)
     # each problem with its own V-cycle depth (0: every level)
     for c, d in zip(cases, (1, 0, 2)):
         rt.rt_matrix_set_cycle_depth(c.A, d)

@@ -405,3 +405,46 @@ def test_full_ensemble_vcycle_sampled_against_oracle(ctx):
     finally:
         rt.rt_batch_free(B)
         ctx.free(*[h for nb, A in handles for h in (A, nb)])
+
+
+def test_batch_tune_depth(ctx, ensemble_amg):
+    """The batch's own depth tuner times the batched solve at every depth of
+    the concatenated hierarchy (1: Jacobi); every depth, the tuned one
+    included, solves to the oracle, and depth 1 takes Jacobi's iterations."""
+    import torch
+    from paper_2001_11606_amd import rt
+    probs, systems, _, levels = ensemble_amg
+    B = rt.rt_batch_create(ctx.handle, [A for (_, _, A) in systems])
+    try:
+        offs = _offsets(probs)
+        bs, refs = _rhs(probs)
+        b = torch.tensor(np.concatenate(bs), device=ctx.device)
+        x0 = torch.zeros_like(b)
+        opts = rt.solve_opts(0, 1, 1e-14, 4000, 1e-4, 60)
+        rep = rt.rt_batch_tune_depth(ctx.handle, B, b.data_ptr(), x0.data_ptr(), opts, 4, 1)
+        its = [rep.iterations[d] for d in range(rep.depths)]
+        say(f"[batch depth tuner] depths {rep.depths}: ms "
+            f"{[round(1e3 * rep.seconds[d], 2) for d in range(rep.depths)]}, iterations {its}, "
+            f"chosen {rep.chosen}")
+        assert rep.depths == max(levels) and 1 <= rep.chosen <= rep.depths
+        assert all(rep.status[d] == rt.RT_OK for d in range(rep.depths))
+        assert its[-1] < its[0]
+        assert not np.any(x0.cpu().numpy())   # x0 is not changed
+        x = torch.zeros_like(b)
+        s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                  rt.solve_opts(0, 0, 1e-14, 4000, 1e-4, 60), 0)
+        jac = [st[q].iterations for q in range(len(probs))]
+        for d in list(range(1, rep.depths + 1)) + [0]:
+            rt.rt_batch_set_cycle_depth(B, d)
+            x = torch.zeros_like(b)
+            s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                      opts, 0)
+            assert s == rt.RT_OK, rt.rt_last_error()
+            xh = x.cpu().numpy()
+            for q in range(len(probs)):
+                err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
+                assert err <= 1e-12, (d, q, err)
+            if d == 1:
+                assert [st[q].iterations for q in range(len(probs))] == jac
+    finally:
+        rt.rt_batch_free(B)
