@@ -528,7 +528,8 @@ int rt_fractional_change(rt_ctx* ctx, const rt_matrix* A, const double* e_new,
  * block-diagonal V-cycle: every problem's own levels, smoother and
  * aggregates; the last level of each problem is smoothed (l1-Jacobi, three
  * sweeps on the batch's last level) rather than solved directly.
- * The V-cycle's fine-level products skip the problems that have stopped.
+ * The V-cycle's products and vector passes skip the rows of problems that
+ * have stopped (on coarse levels, 256-row chunks all of whose problems have).
  * graph_iters > 0 replays HIP graphs of that many PCG iterations (Jacobi or
  * V-cycle) between host reads of the convergence flags (extra iterations of
  * finished problems change none of their values); 0 checks after every
@@ -559,7 +560,8 @@ int rt_batch_solve(rt_ctx* ctx, rt_batch* B, const double* b, double* x,
  * time, the largest per-problem iteration count and the status.  The
  * depth holds for later batched solves and Newton steps of B.  For callers
  * whose ensemble is solved in batches: a depth timed inside the batch, not
- * one tuned per problem on its own solve.                                  */
+ * one tuned per problem on its own solve.  rt_batch_set_cycle_depth sets
+ * the depth (negative: RT_E_ARG); both drop the batch's cached graphs.     */
 int rt_batch_tune_depth(rt_ctx* ctx, rt_batch* B, const double* b, const double* x0,
                         const rt_solve_opts* opts, int graph_iters, int reps,
                         rt_depth_report* rep);
