@@ -158,6 +158,15 @@ def test_batch_tune_and_errors(ctx, ensemble):
                           rt.solve_opts(0, 0, 1e-10, 100), -1)
     with pytest.raises(rt.RtError):
         rt.rt_batch_create(ctx.handle, [])
+    with pytest.raises(rt.RtError):   # negative depth
+        rt.rt_batch_set_cycle_depth(B, -1)
+    with pytest.raises(rt.RtError):   # the depth tuner times V-cycle solves only
+        rt.rt_batch_tune_depth(ctx.handle, B, b.data_ptr(), x.data_ptr(),
+                               rt.solve_opts(0, 0, 1e-10, 100), 0, 1)
+    # a batch without a hierarchy: one depth, nothing to tune
+    rep = rt.rt_batch_tune_depth(ctx.handle, B, b.data_ptr(), x.data_ptr(),
+                                 rt.solve_opts(0, 1, 1e-10, 100), 0, 1)
+    assert rep.depths == 1 and rep.chosen == 1
 
 
 def test_full_ensemble_sampled_against_oracle(ctx):
