@@ -457,3 +457,37 @@ def test_batch_tune_depth(ctx, ensemble_amg):
                 assert [st[q].iterations for q in range(len(probs))] == jac
     finally:
         rt.rt_batch_free(B)
+
+
+@pytest.mark.parametrize("sizes", [(700.0,), (700.0, 16.0)])
+def test_batch_amg_single_and_tiny(ctx, sizes):
+    """A batch of one diffusive problem, and one that adds a 16-particle
+    problem (a single level): the batched V-cycle solves each to the oracle."""
+    import torch
+    from paper_2001_11606_amd import rt
+    probs = []
+    for q, size in enumerate(sizes):
+        pr = synth.config5_member(2 * q, size)   # even members are 2-D
+        pr.dt = 0.1
+        probs.append(pr)
+    systems = [gpu_system(ctx, pr, amg=rt.amg_opts(max_levels=8, coarse_size=16)) for pr in probs]
+    levels = [ctx.matrix_info(A).levels for (_, _, A) in systems]
+    say(f"[batch amg edge] sizes {[pr.n_interior for pr in probs]} levels {levels}")
+    B = rt.rt_batch_create(ctx.handle, [A for (_, _, A) in systems])
+    try:
+        offs = _offsets(probs)
+        bs, refs = _rhs(probs)
+        b = torch.tensor(np.concatenate(bs), device=ctx.device)
+        for precision, tol, bar in ((0, 1e-14, 1e-12), (1, 1e-12, 1e-10)):
+            for graph in (0, 3):
+                x = torch.zeros_like(b)
+                s, st = rt.rt_batch_solve(ctx.handle, B, len(probs), b.data_ptr(), x.data_ptr(),
+                                          rt.solve_opts(precision, 1, tol, 4000, 1e-4, 60), graph)
+                assert s == rt.RT_OK, rt.rt_last_error()
+                xh = x.cpu().numpy()
+                for q in range(len(probs)):
+                    err = np.max(np.abs(xh[offs[q]:offs[q + 1]] - refs[q])) / np.max(np.abs(refs[q]))
+                    assert err <= bar, (precision, graph, q, err)
+    finally:
+        rt.rt_batch_free(B)
+        ctx.free(*[h for (_, nb, A) in systems for h in (A, nb)])
